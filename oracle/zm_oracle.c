@@ -1,0 +1,469 @@
+/*
+ * Z-Model high-order step: plain FP64 CPU oracle.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the slow, obviously-correct
+ * reference that the GPU library is checked against.  Only the test suite,
+ * the package smoke check and the benchmark's CPU-baseline leg may load it;
+ * the product path never calls it and shares no code, header or constant
+ * with it.
+ *
+ * What it computes (paper: Beatnik, Stewart & Bridges 2024):
+ *   - SurfaceMesh state (sec. 2): per mesh point a position z = (z1,z2,z3)
+ *     and two vorticity components w = (w1,w2) on a regular N1 x N2 mesh.
+ *   - Two-node-deep stencils for tangents and Laplacians (sec. 3.1,
+ *     SurfaceMesh) with periodic coordinate correction across the seam
+ *     (sec. 3.1, BoundaryCondition).
+ *   - The Birkhoff-Rott velocity of every point from the position and
+ *     vorticity of every other point (sec. 2, BRSolver), by brute-force
+ *     all pairs (sec. 3.2.1, exact integral calculation).
+ *   - The Z-Model derivatives of position and vorticity (sec. 2, ZModel)
+ *     and a third-order Runge-Kutta step with three derivative evaluations
+ *     (sec. 3.1, TimeIntegrator).
+ * The paper prints no equations; the formulas below are the reading this
+ * project fixes (vortex-sheet Biot-Savart law with algebraic
+ * desingularisation, Bernoulli-type vorticity law, SSP-RK3).  Each function
+ * states the definition it implements.
+ *
+ * Parity status of each function:
+ *   zmo_tangents / zmo_laplacian : pinned (modified-wavenumber closed form,
+ *                                  flat-grid identity, symmetry).
+ *   zmo_br_velocity             : pinned (flat-sheet eigenvalue -> -|k|/2,
+ *                                  linear Rayleigh-Taylor growth rate,
+ *                                  mirror / translation invariants,
+ *                                  high-precision brute force).
+ *   zmo_rhs (linear part)       : pinned by the linear growth rate.
+ *   zmo_rhs (|u|^2 and q/4 terms of the Bernoulli potential): the identity
+ *                                  q = g^{ab} w_a w_b is pinned; the choice
+ *                                  to keep |u|^2 and drop the mean-potential
+ *                                  time derivative is a reading of the
+ *                                  model -- parity unpinned.
+ *   zmo_rk3_step                : pinned (amplification factor, order 3).
+ *
+ * Arithmetic: plain double, 1.0/sqrt(s), Neumaier-compensated per-target
+ * sums in a fixed sequential source order, no FMA contraction (build with
+ * -ffp-contract=off).  Targets are split over OpenMP threads; the result
+ * does not depend on the thread count.
+ *
+ * Layout: structure-of-arrays planes.  Point index p = i2*n1 + i1.
+ * z has 3 planes (z[c*N + p]), w has 2 planes, velocities 3 planes.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#include <omp.h>
+
+typedef struct {
+    int32_t n1, n2;          /* mesh points along alpha_1, alpha_2           */
+    int32_t images;          /* K >= 0 extra periodic image layers           */
+    int32_t pad_;
+    double period1, period2; /* L1, L2 (parameter and x/y period)            */
+    double atwood;           /* A                                            */
+    double gravity;          /* g (gravity is -g e3)                         */
+    double eps;              /* desingularisation length                     */
+    double nu;               /* optional artificial viscosity on w           */
+    double dt;               /* time step                                    */
+} zmo_problem;
+
+/* ------------------------------------------------------------------ */
+/* helpers                                                             */
+/* ------------------------------------------------------------------ */
+
+static int wrap_index(int i, int n, int *wraps)
+{
+    int w = 0;
+    while (i < 0) { i += n; w -= 1; }
+    while (i >= n) { i -= n; w += 1; }
+    *wraps = w;
+    return i;
+}
+
+/* Position component c at (possibly out-of-range) mesh index (i1,i2):
+ * periodic in the index; z1 gains +-L1 per wrap along alpha_1, z2 gains
+ * +-L2 per wrap along alpha_2 (the periodic coordinate correction);
+ * z3 is plainly periodic. */
+static double z_at(const zmo_problem *P, const double *z, int c, int i1, int i2)
+{
+    const int n1 = P->n1, n2 = P->n2;
+    int w1, w2;
+    int j1 = wrap_index(i1, n1, &w1);
+    int j2 = wrap_index(i2, n2, &w2);
+    double v = z[(size_t)c * n1 * n2 + (size_t)j2 * n1 + j1];
+    if (c == 0 && w1 != 0) v = v + (double)w1 * P->period1;
+    if (c == 1 && w2 != 0) v = v + (double)w2 * P->period2;
+    return v;
+}
+
+/* A periodic scalar plane at a possibly out-of-range index. */
+static double f_at(const zmo_problem *P, const double *f, int i1, int i2)
+{
+    int w1, w2;
+    int j1 = wrap_index(i1, P->n1, &w1);
+    int j2 = wrap_index(i2, P->n2, &w2);
+    (void)w1; (void)w2;
+    return f[(size_t)j2 * P->n1 + j1];
+}
+
+/* Fourth-order central first difference from the four neighbours:
+ * D f = [8 (f(+1) - f(-1)) - (f(+2) - f(-2))] / (12 h). */
+static double d1_5pt(double fm2, double fm1, double fp1, double fp2, double h)
+{
+    return (8.0 * (fp1 - fm1) - (fp2 - fm2)) / (12.0 * h);
+}
+
+/* Fourth-order central second difference:
+ * D2 f = [-f(+2) + 16 f(+1) - 30 f(0) + 16 f(-1) - f(-2)] / (12 h^2). */
+static double d2_5pt(double fm2, double fm1, double f0, double fp1, double fp2, double h)
+{
+    return (-fp2 + 16.0 * fp1 - 30.0 * f0 + 16.0 * fm1 - fm2) / (12.0 * h * h);
+}
+
+typedef struct { double s, c; } neumaier;
+
+static void nm_add(neumaier *a, double x)
+{
+    double t = a->s + x;
+    if (fabs(a->s) >= fabs(x)) a->c += (a->s - t) + x;
+    else                       a->c += (x - t) + a->s;
+    a->s = t;
+}
+
+static double nm_value(const neumaier *a) { return a->s + a->c; }
+
+static int set_threads(int nthreads)
+{
+    if (nthreads > 0) return nthreads;
+    return omp_get_max_threads();
+}
+
+/* ------------------------------------------------------------------ */
+/* surface derivatives                                                 */
+/* ------------------------------------------------------------------ */
+
+/* Tangents T_a = dz/d(alpha_a) by the 5-point fourth-order stencil with the
+ * periodic coordinate correction.  t1, t2: 3 planes each. */
+void zmo_tangents(const zmo_problem *P, const double *z, double *t1, double *t2)
+{
+    const int n1 = P->n1, n2 = P->n2;
+    const size_t N = (size_t)n1 * n2;
+    const double h1 = P->period1 / n1, h2 = P->period2 / n2;
+    for (int i2 = 0; i2 < n2; ++i2)
+        for (int i1 = 0; i1 < n1; ++i1) {
+            size_t p = (size_t)i2 * n1 + i1;
+            for (int c = 0; c < 3; ++c) {
+                t1[c * N + p] = d1_5pt(z_at(P, z, c, i1 - 2, i2), z_at(P, z, c, i1 - 1, i2),
+                                       z_at(P, z, c, i1 + 1, i2), z_at(P, z, c, i1 + 2, i2), h1);
+                t2[c * N + p] = d1_5pt(z_at(P, z, c, i1, i2 - 2), z_at(P, z, c, i1, i2 - 1),
+                                       z_at(P, z, c, i1, i2 + 1), z_at(P, z, c, i1, i2 + 2), h2);
+            }
+        }
+}
+
+/* Surface quantities: tangents, the BR source strength
+ * gamma = w1 T2 - w2 T1 (3 planes), and q = |gamma|^2 / |T1 x T2|^2,
+ * the squared jump of tangential velocity across the sheet. */
+void zmo_surface(const zmo_problem *P, const double *z, const double *w,
+                 double *t1, double *t2, double *gamma, double *q)
+{
+    const size_t N = (size_t)P->n1 * P->n2;
+    zmo_tangents(P, z, t1, t2);
+    for (size_t p = 0; p < N; ++p) {
+        double a1 = t1[p], a2 = t1[N + p], a3 = t1[2 * N + p];
+        double b1 = t2[p], b2 = t2[N + p], b3 = t2[2 * N + p];
+        double w1 = w[p], w2 = w[N + p];
+        double g1 = w1 * b1 - w2 * a1;
+        double g2 = w1 * b2 - w2 * a2;
+        double g3 = w1 * b3 - w2 * a3;
+        gamma[p] = g1; gamma[N + p] = g2; gamma[2 * N + p] = g3;
+        double n1 = a2 * b3 - a3 * b2;
+        double n2 = a3 * b1 - a1 * b3;
+        double n3 = a1 * b2 - a2 * b1;
+        q[p] = (g1 * g1 + g2 * g2 + g3 * g3) / (n1 * n1 + n2 * n2 + n3 * n3);
+    }
+}
+
+/* Laplacian in the mesh parameters, sum over both axes of the fourth-order
+ * second difference; f is one periodic plane. */
+void zmo_laplacian(const zmo_problem *P, const double *f, double *out)
+{
+    const int n1 = P->n1, n2 = P->n2;
+    const double h1 = P->period1 / n1, h2 = P->period2 / n2;
+    for (int i2 = 0; i2 < n2; ++i2)
+        for (int i1 = 0; i1 < n1; ++i1) {
+            double a = d2_5pt(f_at(P, f, i1 - 2, i2), f_at(P, f, i1 - 1, i2), f_at(P, f, i1, i2),
+                              f_at(P, f, i1 + 1, i2), f_at(P, f, i1 + 2, i2), h1);
+            double b = d2_5pt(f_at(P, f, i1, i2 - 2), f_at(P, f, i1, i2 - 1), f_at(P, f, i1, i2),
+                              f_at(P, f, i1, i2 + 1), f_at(P, f, i1, i2 + 2), h2);
+            out[(size_t)i2 * n1 + i1] = a + b;
+        }
+}
+
+/* ------------------------------------------------------------------ */
+/* Birkhoff-Rott velocity                                              */
+/* ------------------------------------------------------------------ */
+
+/* Images of source index j seen from target index i along one axis with n
+ * points: the offset o = j - i reduced modulo n to the cell centred on the
+ * target.  Writes the image shifts (in periods, source moves by +s*L) and
+ * their weights; returns how many (1, or 2 when |o| = n/2 exactly, which
+ * only happens for even n: the two end images share weight 1/2 -- the
+ * trapezoid rule over the period cell centred on the target). */
+static int axis_images(int i, int j, int n, int shift[2], double weight[2])
+{
+    int d = ((j - i) % n + n) % n;   /* in [0, n) */
+    if (2 * d < n) {                 /* o = d */
+        shift[0] = (i + d - j) / n;
+        weight[0] = 1.0;
+        return 1;
+    }
+    if (2 * d > n) {                 /* o = d - n */
+        shift[0] = (i + d - n - j) / n;
+        weight[0] = 1.0;
+        return 1;
+    }
+    shift[0] = (i + d - j) / n;      /* o = +n/2 */
+    shift[1] = (i + d - n - j) / n;  /* o = -n/2 */
+    weight[0] = 0.5;
+    weight[1] = 0.5;
+    return 2;
+}
+
+/* One target: u = -(h1 h2 / 4 pi) sum_j sum_images c * (r x gamma_j) /
+ * (|r|^2 + eps^2)^(3/2), r = z_i - z_j - (S1 L1, S2 L2, 0).  Sources are
+ * visited in index order p_j = j2*n1 + j1; for each source the images are
+ * visited in the order (extra layer m2, m1 from -K..K) x (axis-2 image,
+ * axis-1 image). */
+static void br_one_target(const zmo_problem *P, const double *z, const double *gamma,
+                          int i1, int i2, double coef, double out[3])
+{
+    const int n1 = P->n1, n2 = P->n2, K = P->images;
+    const size_t N = (size_t)n1 * n2;
+    const double L1 = P->period1, L2 = P->period2;
+    const double eps2 = P->eps * P->eps;
+    const size_t pi_ = (size_t)i2 * n1 + i1;
+    const double zi1 = z[pi_], zi2 = z[N + pi_], zi3 = z[2 * N + pi_];
+    neumaier a1 = {0, 0}, a2 = {0, 0}, a3 = {0, 0};
+
+    for (int j2 = 0; j2 < n2; ++j2) {
+        int s2[2]; double c2[2];
+        int k2 = axis_images(i2, j2, n2, s2, c2);
+        for (int j1 = 0; j1 < n1; ++j1) {
+            int s1[2]; double c1[2];
+            int k1 = axis_images(i1, j1, n1, s1, c1);
+            const size_t pj = (size_t)j2 * n1 + j1;
+            const double zj1 = z[pj], zj2 = z[N + pj], zj3 = z[2 * N + pj];
+            const double g1 = gamma[pj], g2 = gamma[N + pj], g3 = gamma[2 * N + pj];
+            for (int m2 = -K; m2 <= K; ++m2)
+                for (int m1 = -K; m1 <= K; ++m1)
+                    for (int b = 0; b < k2; ++b)
+                        for (int a = 0; a < k1; ++a) {
+                            double c = c1[a] * c2[b];
+                            double S1 = (double)(s1[a] + m1), S2 = (double)(s2[b] + m2);
+                            double r1 = zi1 - zj1 - S1 * L1;
+                            double r2 = zi2 - zj2 - S2 * L2;
+                            double r3 = zi3 - zj3;
+                            double s = r1 * r1 + r2 * r2 + r3 * r3 + eps2;
+                            double inv = 1.0 / sqrt(s);
+                            double wgt = inv * inv * inv;
+                            double x1 = r2 * g3 - r3 * g2;
+                            double x2 = r3 * g1 - r1 * g3;
+                            double x3 = r1 * g2 - r2 * g1;
+                            double f = c * wgt;
+                            nm_add(&a1, f * x1);
+                            nm_add(&a2, f * x2);
+                            nm_add(&a3, f * x3);
+                        }
+        }
+    }
+    out[0] = coef * nm_value(&a1);
+    out[1] = coef * nm_value(&a2);
+    out[2] = coef * nm_value(&a3);
+}
+
+/* BR velocity of the listed targets (point indices), or of all points when
+ * targets == NULL.  u: 3 planes of length ntargets (or N).  gamma is the
+ * source strength from zmo_surface.  Returns 0, or -1 on bad arguments. */
+int zmo_br_from_gamma(const zmo_problem *P, const double *z, const double *gamma,
+                      int64_t ntargets, const int64_t *targets, double *u, int nthreads)
+{
+    if (!P || P->n1 < 1 || P->n2 < 1 || !(P->eps > 0.0) || P->images < 0) return -1;
+    const size_t N = (size_t)P->n1 * P->n2;
+    const int64_t nt = targets ? ntargets : (int64_t)N;
+    const double h1 = P->period1 / P->n1, h2 = P->period2 / P->n2;
+    const double coef = -(h1 * h2) / (4.0 * M_PI);
+    int bad = 0;
+#pragma omp parallel for schedule(dynamic, 16) num_threads(set_threads(nthreads)) reduction(|:bad)
+    for (int64_t t = 0; t < nt; ++t) {
+        int64_t p = targets ? targets[t] : t;
+        if (p < 0 || (size_t)p >= N) { bad = 1; continue; }
+        double o[3];
+        br_one_target(P, z, gamma, (int)(p % P->n1), (int)(p / P->n1), coef, o);
+        u[t] = o[0];
+        u[nt + t] = o[1];
+        u[2 * nt + t] = o[2];
+    }
+    return bad ? -1 : 0;
+}
+
+int zmo_br_velocity(const zmo_problem *P, const double *z, const double *w,
+                    int64_t ntargets, const int64_t *targets, double *u, int nthreads)
+{
+    if (!P || P->n1 < 1 || P->n2 < 1) return -1;
+    const size_t N = (size_t)P->n1 * P->n2;
+    double *buf = (double *)malloc(sizeof(double) * 10 * N);
+    if (!buf) return -1;
+    double *t1 = buf, *t2 = buf + 3 * N, *gamma = buf + 6 * N, *q = buf + 9 * N;
+    zmo_surface(P, z, w, t1, t2, gamma, q);
+    int rc = zmo_br_from_gamma(P, z, gamma, ntargets, targets, u, nthreads);
+    free(buf);
+    return rc;
+}
+
+/* ------------------------------------------------------------------ */
+/* Z-Model right-hand side                                             */
+/* ------------------------------------------------------------------ */
+
+/* Bernoulli-type potential V = A (|u|^2 - q/4 - 2 g z3). */
+static double bernoulli(const zmo_problem *P, double u1, double u2, double u3, double q, double z3)
+{
+    double uu = u1 * u1 + u2 * u2 + u3 * u3;
+    return P->atwood * ((uu - 0.25 * q) - (2.0 * P->gravity) * z3);
+}
+
+/* F(z, w) = (z_t, w_t) with z_t = u (BR velocity) and
+ * w_t = (D1 V, D2 V) + nu * Lap(w).  zt: 3 planes, wt: 2 planes. */
+int zmo_rhs(const zmo_problem *P, const double *z, const double *w,
+            double *zt, double *wt, int nthreads)
+{
+    if (!P || P->n1 < 1 || P->n2 < 1) return -1;
+    const int n1 = P->n1, n2 = P->n2;
+    const size_t N = (size_t)n1 * n2;
+    const double h1 = P->period1 / n1, h2 = P->period2 / n2;
+    double *buf = (double *)malloc(sizeof(double) * 13 * N);
+    if (!buf) return -1;
+    double *t1 = buf, *t2 = buf + 3 * N, *gamma = buf + 6 * N, *q = buf + 9 * N;
+    double *V = buf + 10 * N, *lap = buf + 11 * N;
+    zmo_surface(P, z, w, t1, t2, gamma, q);
+    int rc = zmo_br_from_gamma(P, z, gamma, 0, NULL, zt, nthreads);
+    if (rc) { free(buf); return rc; }
+    for (size_t p = 0; p < N; ++p)
+        V[p] = bernoulli(P, zt[p], zt[N + p], zt[2 * N + p], q[p], z[2 * N + p]);
+    for (int i2 = 0; i2 < n2; ++i2)
+        for (int i1 = 0; i1 < n1; ++i1) {
+            size_t p = (size_t)i2 * n1 + i1;
+            wt[p] = d1_5pt(f_at(P, V, i1 - 2, i2), f_at(P, V, i1 - 1, i2),
+                           f_at(P, V, i1 + 1, i2), f_at(P, V, i1 + 2, i2), h1);
+            wt[N + p] = d1_5pt(f_at(P, V, i1, i2 - 2), f_at(P, V, i1, i2 - 1),
+                               f_at(P, V, i1, i2 + 1), f_at(P, V, i1, i2 + 2), h2);
+        }
+    if (P->nu != 0.0) {
+        for (int c = 0; c < 2; ++c) {
+            zmo_laplacian(P, w + c * N, lap);
+            for (size_t p = 0; p < N; ++p) wt[c * N + p] = wt[c * N + p] + P->nu * lap[p];
+        }
+    }
+    free(buf);
+    return 0;
+}
+
+/* F at listed targets only.  The BR velocity is evaluated at each target and
+ * at its +-1, +-2 stencil neighbours along both axes (V is needed there).
+ * zt: 3 planes of length ntargets, wt: 2 planes of length ntargets. */
+int zmo_rhs_sampled(const zmo_problem *P, const double *z, const double *w,
+                    int64_t ntargets, const int64_t *targets,
+                    double *zt, double *wt, int nthreads)
+{
+    if (!P || P->n1 < 1 || P->n2 < 1 || ntargets < 0 || !targets) return -1;
+    const int n1 = P->n1, n2 = P->n2;
+    const size_t N = (size_t)n1 * n2;
+    const double h1 = P->period1 / n1, h2 = P->period2 / n2;
+    for (int64_t t = 0; t < ntargets; ++t)
+        if (targets[t] < 0 || (size_t)targets[t] >= N) return -1;
+    /* stencil points: 0 centre, 1..4 axis-1 offsets -2,-1,+1,+2, 5..8 axis-2 */
+    static const int off1[9] = {0, -2, -1, 1, 2, 0, 0, 0, 0};
+    static const int off2[9] = {0, 0, 0, 0, 0, -2, -1, 1, 2};
+    const int64_t ns = 9 * ntargets;
+    int64_t *pts = (int64_t *)malloc(sizeof(int64_t) * (size_t)(ns > 0 ? ns : 1));
+    double *us = (double *)malloc(sizeof(double) * 3 * (size_t)(ns > 0 ? ns : 1));
+    double *buf = (double *)malloc(sizeof(double) * 10 * N);
+    if (!pts || !us || !buf) { free(pts); free(us); free(buf); return -1; }
+    for (int64_t t = 0; t < ntargets; ++t) {
+        int i1 = (int)(targets[t] % n1), i2 = (int)(targets[t] / n1);
+        for (int k = 0; k < 9; ++k) {
+            int w1, w2;
+            int j1 = wrap_index(i1 + off1[k], n1, &w1);
+            int j2 = wrap_index(i2 + off2[k], n2, &w2);
+            pts[9 * t + k] = (int64_t)j2 * n1 + j1;
+        }
+    }
+    double *t1 = buf, *t2 = buf + 3 * N, *gamma = buf + 6 * N, *q = buf + 9 * N;
+    zmo_surface(P, z, w, t1, t2, gamma, q);
+    int rc = zmo_br_from_gamma(P, z, gamma, ns, pts, us, nthreads);
+    if (rc) { free(pts); free(us); free(buf); return rc; }
+    for (int64_t t = 0; t < ntargets; ++t) {
+        double V[9];
+        for (int k = 0; k < 9; ++k) {
+            int64_t s = 9 * t + k, p = pts[s];
+            V[k] = bernoulli(P, us[s], us[ns + s], us[2 * ns + s], q[p], z[2 * N + p]);
+        }
+        int64_t s0 = 9 * t;
+        zt[t] = us[s0];
+        zt[ntargets + t] = us[ns + s0];
+        zt[2 * ntargets + t] = us[2 * ns + s0];
+        wt[t] = d1_5pt(V[1], V[2], V[3], V[4], h1);
+        wt[ntargets + t] = d1_5pt(V[5], V[6], V[7], V[8], h2);
+        if (P->nu != 0.0) {
+            int i1 = (int)(targets[t] % n1), i2 = (int)(targets[t] / n1);
+            for (int c = 0; c < 2; ++c) {
+                const double *f = w + c * N;
+                double lap = d2_5pt(f_at(P, f, i1 - 2, i2), f_at(P, f, i1 - 1, i2), f_at(P, f, i1, i2),
+                                    f_at(P, f, i1 + 1, i2), f_at(P, f, i1 + 2, i2), h1)
+                           + d2_5pt(f_at(P, f, i1, i2 - 2), f_at(P, f, i1, i2 - 1), f_at(P, f, i1, i2),
+                                    f_at(P, f, i1, i2 + 1), f_at(P, f, i1, i2 + 2), h2);
+                wt[c * ntargets + t] = wt[c * ntargets + t] + P->nu * lap;
+            }
+        }
+    }
+    free(pts); free(us); free(buf);
+    return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* time integration                                                    */
+/* ------------------------------------------------------------------ */
+
+/* nsteps of the Shu-Osher strong-stability-preserving RK3 on y = (z, w):
+ *   y1 = y0 + dt F(y0)
+ *   y2 = 3/4 y0 + 1/4 (y1 + dt F(y1))
+ *   y3 = 1/3 y0 + 2/3 (y2 + dt F(y2))
+ * z (3 planes) and w (2 planes) are advanced in place. */
+int zmo_rk3_step(const zmo_problem *P, double *z, double *w, int nsteps, int nthreads)
+{
+    if (!P || P->n1 < 1 || P->n2 < 1 || nsteps < 0) return -1;
+    const size_t N = (size_t)P->n1 * P->n2;
+    const size_t M = 5 * N;            /* y = (z planes, w planes) */
+    const double dt = P->dt;
+    double *mem = (double *)malloc(sizeof(double) * 4 * M);
+    if (!mem) return -1;
+    double *y0 = mem, *y1 = mem + M, *y2 = mem + 2 * M, *F = mem + 3 * M;
+    for (int step = 0; step < nsteps; ++step) {
+        memcpy(y0, z, sizeof(double) * 3 * N);
+        memcpy(y0 + 3 * N, w, sizeof(double) * 2 * N);
+        int rc = zmo_rhs(P, y0, y0 + 3 * N, F, F + 3 * N, nthreads);
+        if (rc) { free(mem); return rc; }
+        for (size_t k = 0; k < M; ++k) y1[k] = y0[k] + dt * F[k];
+        rc = zmo_rhs(P, y1, y1 + 3 * N, F, F + 3 * N, nthreads);
+        if (rc) { free(mem); return rc; }
+        for (size_t k = 0; k < M; ++k) y2[k] = 0.75 * y0[k] + 0.25 * (y1[k] + dt * F[k]);
+        rc = zmo_rhs(P, y2, y2 + 3 * N, F, F + 3 * N, nthreads);
+        if (rc) { free(mem); return rc; }
+        for (size_t k = 0; k < M; ++k) {
+            double y3 = (1.0 / 3.0) * y0[k] + (2.0 / 3.0) * (y2[k] + dt * F[k]);
+            if (k < 3 * N) z[k] = y3; else w[k - 3 * N] = y3;
+        }
+    }
+    free(mem);
+    return 0;
+}
+
+int zmo_abi_version(void) { return 1; }
