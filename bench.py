@@ -1,0 +1,185 @@
+#!/usr/bin/env python3
+"""Throughput of the Z-Model high-order step on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+
+A step is one SSP-RK3 step: three evaluations of (surface derivatives ->
+all-pairs Birkhoff-Rott sweep -> tie correction -> reduction -> RK3 stage),
+each evaluation doing N^2 pair interactions.  Inputs are seeded synthetic
+rocket-rig interfaces resident in HBM before the timed region.  Prints one
+JSON line with the throughput, the pair kernel's place on its VALU roofline
+(timed with HIP events inside the library, on the stream it launches on) and
+the CPU oracle timed on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+import rocket_rig as rr  # noqa: E402
+
+METRIC = "BR pair-interactions/s & % VALU peak (FP32 vs FP64); served p50/p99 step ms"
+FLOPS_PER_PAIR = 27          # 3 sub, 3 fma, 1 rsqrt, 2 mul, 3 mul, 6 fma (fma = 2)
+PEAK_TFLOPS = {"fp64": 78.6, "fp32_pairs": 157.3}   # MI355X vector peaks
+DEFAULT_WORKLOAD = "periodic256_multimode8_fp64"
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=None, help="timed RK3 steps (default: the workload's)")
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default=DEFAULT_WORKLOAD, choices=sorted(rr.WORKLOADS))
+    ap.add_argument("--cpu-seconds", type=float, default=15.0,
+                    help="target CPU time of the oracle sample (0 = skip)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of this many MiB (counter calibration)")
+    return ap.parse_args()
+
+
+def copy_calibration(mib: int):
+    import torch
+    n = mib * (1 << 20) // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes_read": n * 8, "bytes_written": n * 8, "launches": 3}))
+
+
+def cpu_baseline(wl, zh, wh, gpu_u, target_seconds: float):
+    """Oracle BR velocity on seeded targets of the same state, sized to about
+    target_seconds of host time; also the GPU/oracle error on that sample."""
+    import oracle
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or os.cpu_count()
+    P = oracle.Problem(wl.n1, wl.n2, eps=wl.eps, atwood=wl.atwood, gravity=wl.gravity, dt=wl.dt)
+    probe = rr.sample_targets(wl.n, 32, seed=99)
+    t0 = time.perf_counter()
+    oracle.br_velocity(P, zh, wh, targets=probe, threads=threads)
+    per_target = (time.perf_counter() - t0) / probe.size
+    count = int(min(wl.n, max(64, target_seconds / max(per_target, 1e-9))))
+    tg = rr.sample_targets(wl.n, count, seed=wl.seed)
+    t0 = time.perf_counter()
+    ref = oracle.br_velocity(P, zh, wh, targets=tg, threads=threads)
+    dt = time.perf_counter() - t0
+    err = float(np.max(np.abs(gpu_u[:, tg] - ref)) / np.max(np.abs(ref)))
+    return {
+        "value": tg.size * wl.n / dt,
+        "unit": "pair-interactions/s",
+        "cores": threads,
+        "kind": "oracle",
+        "sample": f"BR velocity of {tg.size} seeded targets x {wl.n} sources "
+                  f"({tg.size * wl.n:.3e} pairs, {dt:.1f} s) at the final GPU state",
+        "seconds": dt,
+        "gpu_vs_oracle_max_rel_err": err,
+    }
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
+              "the multi-GPU sharding is a design note, not an implemented path", file=sys.stderr)
+        sys.exit(2)
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
+        return
+
+    import torch
+    import paper_2406_05490_amd as zm
+
+    wl = rr.WORKLOADS[args.workload]
+    if wl.precision != "fp64":
+        raise SystemExit(f"{wl.name}: precision {wl.precision} is not provided by this build")
+    steps = wl.steps if args.steps is None else args.steps
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    p = zm.Params(wl.n1, wl.n2, eps=wl.eps, atwood=wl.atwood, gravity=wl.gravity, dt=wl.dt)
+    z0, w0 = wl.state()
+    zd = torch.from_numpy(z0.ravel()).to(dev)
+    wd = torch.from_numpy(w0.ravel()).to(dev)
+    ctx = zm.Context(p)
+    ctx.init_state(zd, wd)
+    info = ctx.launch_info()
+    stream = ctx.stream
+
+    ctx.step(args.warmup)
+    torch.cuda.synchronize()
+    ctx.profile_read()                      # discard warm-up timings
+    ctx.profile_enable(True)
+
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    ctx.step(steps)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    gpu_s = ev0.elapsed_time(ev1) / 1e3
+    stats = ctx.profile_read()
+    ctx.profile_enable(False)
+
+    pairs_per_step = 3 * info.pairs_per_eval
+    elapsed = max(wall, gpu_s)
+    value = pairs_per_step * steps / elapsed
+    launches, pair_ms = stats["pairs"]
+    avg_pair_s = pair_ms / 1e3 / max(launches, 1)
+    achieved = FLOPS_PER_PAIR * info.pairs_per_eval / avg_pair_s / 1e12
+    peak = PEAK_TFLOPS[wl.precision]
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "pair-interactions/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": wl.name, "mesh": f"{wl.n1}x{wl.n2}", "points": wl.n,
+            "eps_over_h": wl.eps_over_h, "atwood": wl.atwood, "dt": wl.dt,
+            "precision": wl.precision, "image_layers": 0,
+            "pairs_per_step": pairs_per_step, "pair_kernel_workgroups": info.workgroups,
+            "source_splits": info.source_splits, "targets_per_lane": info.targets_per_lane,
+        },
+        "roofline": {
+            "kernel": "k_pairs_f64", "bound": "alu", "achieved": achieved, "peak": peak,
+            "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,
+            "flops_per_pair": FLOPS_PER_PAIR, "pairs_per_launch": info.pairs_per_eval,
+            "avg_launch_ms": avg_pair_s * 1e3, "launches": launches,
+        },
+        "kernel_ms": {k: {"launches": n, "total_ms": ms} for k, (n, ms) in stats.items()},
+        "pair_kernel_share": pair_ms / 1e3 / elapsed,
+    }
+
+    if args.cpu_seconds > 0:
+        zs = torch.empty_like(zd); ws = torch.empty_like(wd)
+        ctx.get_state(zs, ws)
+        ud = torch.empty_like(zd)
+        ctx.br_velocity(zs, ws, ud)
+        torch.cuda.synchronize()
+        zh = zs.cpu().numpy().reshape(3, -1); wh = ws.cpu().numpy().reshape(2, -1)
+        out["cpu_baseline"] = cpu_baseline(wl, zh, wh, ud.cpu().numpy().reshape(3, -1),
+                                           args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,188 @@
+/*
+ * zm.h -- C ABI of the MI355X Z-Model high-order step library (libzm.so).
+ *
+ * The library evaluates, on one AMD Instinct MI355X (gfx950), the hot path of
+ * the Z-Model Rayleigh-Taylor interface solver that the Beatnik
+ * mini-application is built on (Stewart & Bridges, 2024):
+ *
+ *   state      per mesh point a position z = (z1, z2, z3) and two vorticity
+ *              components w = (w1, w2) on a regular n1 x n2 mesh
+ *              (sec. 2, SurfaceMesh; sec. 3.1, ProblemManager);
+ *   BR velocity  the Birkhoff-Rott velocity of every point from the position
+ *              and vorticity of every point (sec. 2, BRSolver), evaluated by
+ *              brute force over all pairs (sec. 3.2.1, exact integral);
+ *   derivatives  surface tangents and Laplacians by two-node-deep stencils
+ *              with periodic coordinate correction (sec. 3.1, SurfaceMesh
+ *              and BoundaryCondition), and the position/vorticity time
+ *              derivatives (sec. 2, ZModel);
+ *   step       third-order Runge-Kutta, three derivative evaluations per
+ *              step (sec. 3.1, TimeIntegrator).
+ *
+ * The paper prints no equations.  The library implements this reading:
+ *   mesh       doubly periodic, period L_a, spacing h_a = L_a / n_a,
+ *              point index p = i2 * n1 + i1;
+ *   D_a f      [8 (f(i+1) - f(i-1)) - (f(i+2) - f(i-2))] / (12 h_a), indices
+ *              periodic, z1 (z2) gains +-L1 (+-L2) when the stencil crosses
+ *              the seam along axis 1 (2);
+ *   gamma      w1 T2 - w2 T1 with T_a = D_a z (BR source strength);
+ *   u_i        -(h1 h2 / 4 pi) sum_j sum_images c (r x gamma_j) /
+ *              (|r|^2 + eps^2)^(3/2),  r = z_i - z_j - (s1 L1, s2 L2, 0),
+ *              image chosen by the index offset j_a - i_a reduced into the
+ *              period cell centred on i; when n_a is even and the offset is
+ *              exactly n_a/2 both end images count with weight 1/2; with
+ *              image_layers = K > 0 the shifts (s1+m1, s2+m2),
+ *              m in [-K, K]^2, are all summed;
+ *   q          |gamma|^2 / |T1 x T2|^2;
+ *   V          A (|u|^2 - q/4 - 2 g z3);
+ *   F(z, w)    z_t = u,  w_t = (D_1 V, D_2 V) + nu Lap(w);
+ *   RK3        y1 = y0 + dt F(y0); y2 = 3/4 y0 + 1/4 (y1 + dt F(y1));
+ *              y3 = 1/3 y0 + 2/3 (y2 + dt F(y2))  (Shu-Osher SSP-RK3).
+ *
+ * Conventions for every entry point
+ *   - Device pointers (d_*) are caller-owned device memory on the device
+ *     current when the context was created, float64, 256-byte aligned,
+ *     structure-of-arrays planes: z is 3 planes of N = n1*n2 doubles
+ *     (z1 plane, z2 plane, z3 plane), w is 2 planes, u is 3 planes.
+ *   - The library never allocates device memory.  All scratch lives in the
+ *     caller's workspace of zm_workspace_bytes() bytes.
+ *   - Work is enqueued asynchronously on the stream given to zm_create (a
+ *     hipStream_t, or NULL for the null stream).  Results are visible after
+ *     that stream is synchronised.
+ *   - Arguments are validated before anything is enqueued; a rejected call
+ *     has no side effects.  No C++ exception crosses this interface.
+ *   - A context is not thread-safe; distinct contexts are independent.
+ */
+#ifndef ZM_H
+#define ZM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes -------------------------------------------------------- */
+typedef int32_t zm_status;
+#define ZM_OK               0
+#define ZM_ERR_INVALID_ARG (-1)  /* bad parameter or pointer                    */
+#define ZM_ERR_UNSUPPORTED (-2)  /* valid request this build does not provide   */
+#define ZM_ERR_WORKSPACE   (-3)  /* workspace missing, too small or misaligned  */
+#define ZM_ERR_HIP         (-4)  /* a HIP runtime call or kernel launch failed  */
+#define ZM_ERR_NONFINITE   (-5)  /* state became non-finite (check-finite flag) */
+#define ZM_ERR_CAPACITY    (-6)  /* request exceeds a fixed capacity            */
+
+/* ---- precision of the pair interactions ---------------------------------- */
+#define ZM_FP64        0  /* all arithmetic in float64                          */
+#define ZM_FP32_PAIRS  1  /* pair terms in float32, per-target sums, state and
+                             RK3 in float64 (reserved: not yet provided)        */
+
+/* ---- flags ---------------------------------------------------------------- */
+#define ZM_FLAG_CHECK_FINITE 0x1u /* zm_step checks the state after each call
+                                     and returns ZM_ERR_NONFINITE (this makes
+                                     zm_step wait for its own work)            */
+
+/* ---- parameters ------------------------------------------------------------ */
+typedef struct zm_params {
+    int32_t  n1, n2;           /* mesh points per axis, each >= 8               */
+    double   period1, period2; /* L1, L2 > 0 (parameter and x / y period)       */
+    double   atwood;           /* A = (rho+ - rho-) / (rho+ + rho-)             */
+    double   gravity;          /* g (acceleration -g e3)                        */
+    double   eps;              /* desingularisation length, > 0                 */
+    double   nu;               /* optional viscosity on w (0 = none), >= 0      */
+    double   dt;               /* time step, > 0 (zm_step only)                 */
+    int32_t  precision;        /* ZM_FP64 or ZM_FP32_PAIRS                      */
+    int32_t  image_layers;     /* K >= 0 extra periodic image layers            */
+    uint32_t flags;            /* ZM_FLAG_*                                     */
+    int32_t  reserved;         /* must be 0                                     */
+} zm_params;
+
+typedef struct zm_ctx zm_ctx;  /* opaque */
+
+/* Bytes of device workspace a context with these parameters needs (0 if the
+ * parameters are invalid).  Pure host function. */
+size_t zm_workspace_bytes(const zm_params *params);
+
+/* Create a context on the current device.  d_workspace: caller-owned device
+ * memory of at least zm_workspace_bytes(params) bytes, 256-byte aligned, kept
+ * alive and unused by the caller until zm_destroy.  hip_stream: the
+ * hipStream_t all work is enqueued on (NULL = null stream).  On success *out
+ * receives the context; on failure *out is set to NULL. */
+zm_status zm_create(zm_ctx **out, const zm_params *params,
+                    void *d_workspace, size_t workspace_bytes, void *hip_stream);
+
+/* Copy (d_z: 3 planes, d_w: 2 planes) into the context's state.  The inputs
+ * may be freed or reused once the stream has passed this call. */
+zm_status zm_init_state(zm_ctx *ctx, const double *d_z, const double *d_w);
+
+/* One Birkhoff-Rott evaluation (pure function of its inputs, including the
+ * tangents behind the source strength): d_u (3 planes) = u(d_z, d_w).
+ * d_u must not overlap d_z or d_w.  The context state is not touched. */
+zm_status zm_br_velocity(zm_ctx *ctx, const double *d_z, const double *d_w, double *d_u);
+
+/* One evaluation of F: d_zt (3 planes) = u, d_wt (2 planes) = D V + nu Lap w.
+ * Outputs must not overlap inputs.  The context state is not touched. */
+zm_status zm_rhs(zm_ctx *ctx, const double *d_z, const double *d_w,
+                 double *d_zt, double *d_wt);
+
+/* Advance the context state by nsteps >= 0 RK3 steps of size params.dt. */
+zm_status zm_step(zm_ctx *ctx, int32_t nsteps);
+
+/* Copy the context state out (d_z: 3 planes, d_w: 2 planes). */
+zm_status zm_get_state(zm_ctx *ctx, double *d_z, double *d_w);
+
+/* Wait for the context's outstanding work and release its host resources.
+ * The workspace may be freed afterwards.  NULL is accepted. */
+zm_status zm_destroy(zm_ctx *ctx);
+
+/* Static description of a status code. */
+const char *zm_status_string(zm_status status);
+
+/* Message of the last error on this context ("" if none; NULL ctx: the last
+ * error of a failed zm_create on this thread). */
+const char *zm_last_error(const zm_ctx *ctx);
+
+/* ---- launch configuration and per-kernel timing ------------------------- */
+
+typedef struct zm_launch_info {
+    int32_t targets_per_lane;   /* register-blocked targets per thread       */
+    int32_t patch_cols;         /* target patch: columns (axis 1)            */
+    int32_t patch_rows;         /* target patch: rows (axis 2)               */
+    int32_t source_splits;      /* source row ranges summed separately       */
+    int32_t workgroups;         /* pair-kernel workgroups per evaluation     */
+    int32_t threads_per_group;  /* 256                                        */
+    int64_t pairs_per_eval;     /* N^2 (2K+1)^2: algorithmic pair count      */
+} zm_launch_info;
+
+/* Launch shape the pair kernel uses for this context (depends on n1, n2, K
+ * and precision only). */
+zm_status zm_get_launch_info(const zm_ctx *ctx, zm_launch_info *out);
+
+#define ZM_KERNEL_SURFACE 0  /* tangents, source strength, q        */
+#define ZM_KERNEL_PAIRS   1  /* all-pairs BR sweep                   */
+#define ZM_KERNEL_TIES    2  /* split-tie correction (even n_a)      */
+#define ZM_KERNEL_REDUCE  3  /* sum of source splits, V              */
+#define ZM_KERNEL_UPDATE  4  /* D V, RK3 stage combination           */
+#define ZM_KERNEL_COUNT   5
+
+typedef struct zm_kernel_stats {
+    int64_t launches;           /* launches timed since the last read        */
+    double  total_ms;           /* summed duration from HIP events           */
+} zm_kernel_stats;
+
+/* Enable (on != 0) or disable per-kernel timing: each launch is bracketed by
+ * HIP events recorded on the context stream. */
+zm_status zm_profile_enable(zm_ctx *ctx, int32_t on);
+
+/* Wait for the timed launches, write ZM_KERNEL_COUNT entries to out (indexed
+ * by ZM_KERNEL_*) and reset the counters. */
+zm_status zm_profile_read(zm_ctx *ctx, zm_kernel_stats *out);
+
+/* Interface version (incremented on any ABI change). */
+int32_t zm_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ZM_H */

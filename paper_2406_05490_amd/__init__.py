@@ -1,0 +1,15 @@
+"""MI355X-native hot path of the Z-Model high-order step.
+
+The computation lives in ``libzm.so`` (hand-written HIP kernels for gfx950
+behind the C ABI in ``include/zm.h``); this package is its thin Python
+binding.  Importing it loads the library and fails loudly if it has not been
+built -- there is no CPU fallback.
+"""
+from ._zm import (  # noqa: F401
+    EXPORTS, KERNELS, LIB_PATH, Context, Params, ZMError,
+    ZM_ERR_CAPACITY, ZM_ERR_HIP, ZM_ERR_INVALID_ARG, ZM_ERR_NONFINITE,
+    ZM_ERR_UNSUPPORTED, ZM_ERR_WORKSPACE, ZM_FLAG_CHECK_FINITE, ZM_FP32_PAIRS,
+    ZM_FP64, ZM_OK, load, status_string, workspace_bytes,
+)
+
+load()

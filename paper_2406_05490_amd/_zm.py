@@ -1,0 +1,233 @@
+"""ctypes binding of libzm.so (include/zm.h): argument marshalling only.
+
+Every step of the computation runs in the HIP library; this module only
+converts torch tensors to device pointers and status codes to exceptions.
+Names follow the C entry points (``zm_create`` -> ``create`` etc.).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass, field
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libzm.so")
+
+ZM_OK = 0
+ZM_ERR_INVALID_ARG = -1
+ZM_ERR_UNSUPPORTED = -2
+ZM_ERR_WORKSPACE = -3
+ZM_ERR_HIP = -4
+ZM_ERR_NONFINITE = -5
+ZM_ERR_CAPACITY = -6
+
+ZM_FP64 = 0
+ZM_FP32_PAIRS = 1
+ZM_FLAG_CHECK_FINITE = 0x1
+
+KERNELS = ("surface", "pairs", "ties", "reduce", "update")
+
+
+class ZMError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"zm status {status}: {message}")
+        self.status = status
+
+
+class zm_params(ctypes.Structure):
+    _fields_ = [
+        ("n1", ctypes.c_int32), ("n2", ctypes.c_int32),
+        ("period1", ctypes.c_double), ("period2", ctypes.c_double),
+        ("atwood", ctypes.c_double), ("gravity", ctypes.c_double),
+        ("eps", ctypes.c_double), ("nu", ctypes.c_double), ("dt", ctypes.c_double),
+        ("precision", ctypes.c_int32), ("image_layers", ctypes.c_int32),
+        ("flags", ctypes.c_uint32), ("reserved", ctypes.c_int32),
+    ]
+
+
+class zm_launch_info(ctypes.Structure):
+    _fields_ = [
+        ("targets_per_lane", ctypes.c_int32), ("patch_cols", ctypes.c_int32),
+        ("patch_rows", ctypes.c_int32), ("source_splits", ctypes.c_int32),
+        ("workgroups", ctypes.c_int32), ("threads_per_group", ctypes.c_int32),
+        ("pairs_per_eval", ctypes.c_int64),
+    ]
+
+
+class zm_kernel_stats(ctypes.Structure):
+    _fields_ = [("launches", ctypes.c_int64), ("total_ms", ctypes.c_double)]
+
+
+# names declared in include/zm.h, in order
+EXPORTS = (
+    "zm_workspace_bytes", "zm_create", "zm_init_state", "zm_br_velocity", "zm_rhs",
+    "zm_step", "zm_get_state", "zm_destroy", "zm_status_string", "zm_last_error",
+    "zm_get_launch_info", "zm_profile_enable", "zm_profile_read", "zm_abi_version",
+)
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libzm.so; raises ImportError if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with "
+                          "`python -m paper_2406_05490_amd.build` (no fallback exists)")
+    # PyTorch ships its own HIP runtime.  Loading torch first makes the
+    # library's libamdhip64.so.7 dependency resolve to that same runtime, so
+    # torch's streams and allocations are valid in the library (a second
+    # HIP/HSA runtime in the process would not see torch's objects).
+    import torch  # noqa: F401
+    lib = ctypes.CDLL(path)
+    P = ctypes.POINTER(zm_params)
+    vp = ctypes.c_void_p
+    lib.zm_workspace_bytes.argtypes = [P]
+    lib.zm_workspace_bytes.restype = ctypes.c_size_t
+    lib.zm_create.argtypes = [ctypes.POINTER(vp), P, vp, ctypes.c_size_t, vp]
+    lib.zm_create.restype = ctypes.c_int32
+    lib.zm_init_state.argtypes = [vp, vp, vp]
+    lib.zm_init_state.restype = ctypes.c_int32
+    lib.zm_br_velocity.argtypes = [vp, vp, vp, vp]
+    lib.zm_br_velocity.restype = ctypes.c_int32
+    lib.zm_rhs.argtypes = [vp, vp, vp, vp, vp]
+    lib.zm_rhs.restype = ctypes.c_int32
+    lib.zm_step.argtypes = [vp, ctypes.c_int32]
+    lib.zm_step.restype = ctypes.c_int32
+    lib.zm_get_state.argtypes = [vp, vp, vp]
+    lib.zm_get_state.restype = ctypes.c_int32
+    lib.zm_destroy.argtypes = [vp]
+    lib.zm_destroy.restype = ctypes.c_int32
+    lib.zm_status_string.argtypes = [ctypes.c_int32]
+    lib.zm_status_string.restype = ctypes.c_char_p
+    lib.zm_last_error.argtypes = [vp]
+    lib.zm_last_error.restype = ctypes.c_char_p
+    lib.zm_get_launch_info.argtypes = [vp, ctypes.POINTER(zm_launch_info)]
+    lib.zm_get_launch_info.restype = ctypes.c_int32
+    lib.zm_profile_enable.argtypes = [vp, ctypes.c_int32]
+    lib.zm_profile_enable.restype = ctypes.c_int32
+    lib.zm_profile_read.argtypes = [vp, ctypes.POINTER(zm_kernel_stats)]
+    lib.zm_profile_read.restype = ctypes.c_int32
+    lib.zm_abi_version.argtypes = []
+    lib.zm_abi_version.restype = ctypes.c_int32
+    _lib = lib
+    return lib
+
+
+@dataclass
+class Params:
+    """Python mirror of zm_params."""
+    n1: int
+    n2: int
+    eps: float
+    atwood: float = 0.5
+    gravity: float = 1.0
+    dt: float = 1e-3
+    nu: float = 0.0
+    period1: float = 2.0
+    period2: float = 2.0
+    precision: int = ZM_FP64
+    image_layers: int = 0
+    flags: int = 0
+
+    def c(self) -> zm_params:
+        return zm_params(self.n1, self.n2, self.period1, self.period2, self.atwood,
+                         self.gravity, self.eps, self.nu, self.dt, self.precision,
+                         self.image_layers, self.flags, 0)
+
+    @property
+    def n(self) -> int:
+        return self.n1 * self.n2
+
+
+def status_string(status: int) -> str:
+    return load().zm_status_string(status).decode()
+
+
+def workspace_bytes(p: Params) -> int:
+    return int(load().zm_workspace_bytes(ctypes.byref(p.c())))
+
+
+def _ptr(t) -> int:
+    return 0 if t is None else int(t.data_ptr())
+
+
+def _check_f64_planes(t, planes: int, n: int, name: str):
+    import torch
+    if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous() or t.numel() != planes * n:
+        raise ValueError(f"{name}: need a contiguous float64 CUDA tensor of {planes} x {n} values")
+
+
+class Context:
+    """One zm_ctx with a workspace tensor it keeps alive."""
+
+    def __init__(self, p: Params, stream=None, device=None):
+        import torch
+        self.lib = load()
+        self.params = p
+        dev = torch.device("cuda", torch.cuda.current_device()) if device is None else device
+        nbytes = workspace_bytes(p)
+        if nbytes == 0:
+            raise ZMError(ZM_ERR_INVALID_ARG, "invalid parameters")
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+        self.stream = torch.cuda.current_stream(dev) if stream is None else stream
+        h = ctypes.c_void_p()
+        with torch.cuda.device(dev):
+            st = self.lib.zm_create(ctypes.byref(h), ctypes.byref(p.c()),
+                                    self.workspace.data_ptr(), nbytes, self.stream.cuda_stream)
+        if st != ZM_OK:
+            raise ZMError(st, self.lib.zm_last_error(None).decode())
+        self.handle = h
+
+    def _raise(self, st):
+        if st != ZM_OK:
+            raise ZMError(st, self.lib.zm_last_error(self.handle).decode())
+
+    def init_state(self, z, w):
+        _check_f64_planes(z, 3, self.params.n, "z"); _check_f64_planes(w, 2, self.params.n, "w")
+        self._raise(self.lib.zm_init_state(self.handle, _ptr(z), _ptr(w)))
+
+    def get_state(self, z, w):
+        _check_f64_planes(z, 3, self.params.n, "z"); _check_f64_planes(w, 2, self.params.n, "w")
+        self._raise(self.lib.zm_get_state(self.handle, _ptr(z), _ptr(w)))
+
+    def br_velocity(self, z, w, u):
+        _check_f64_planes(z, 3, self.params.n, "z"); _check_f64_planes(w, 2, self.params.n, "w")
+        _check_f64_planes(u, 3, self.params.n, "u")
+        self._raise(self.lib.zm_br_velocity(self.handle, _ptr(z), _ptr(w), _ptr(u)))
+
+    def rhs(self, z, w, zt, wt):
+        for t, k, nm in ((z, 3, "z"), (w, 2, "w"), (zt, 3, "zt"), (wt, 2, "wt")):
+            _check_f64_planes(t, k, self.params.n, nm)
+        self._raise(self.lib.zm_rhs(self.handle, _ptr(z), _ptr(w), _ptr(zt), _ptr(wt)))
+
+    def step(self, nsteps: int):
+        self._raise(self.lib.zm_step(self.handle, int(nsteps)))
+
+    def launch_info(self) -> zm_launch_info:
+        info = zm_launch_info()
+        self._raise(self.lib.zm_get_launch_info(self.handle, ctypes.byref(info)))
+        return info
+
+    def profile_enable(self, on: bool = True):
+        self._raise(self.lib.zm_profile_enable(self.handle, 1 if on else 0))
+
+    def profile_read(self) -> dict:
+        arr = (zm_kernel_stats * len(KERNELS))()
+        self._raise(self.lib.zm_profile_read(self.handle, arr))
+        return {k: (int(arr[i].launches), float(arr[i].total_ms)) for i, k in enumerate(KERNELS)}
+
+    def destroy(self):
+        if getattr(self, "handle", None) is not None:
+            st = self.lib.zm_destroy(self.handle)
+            self.handle = None
+            if st != ZM_OK:
+                raise ZMError(st, "destroy")
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass

@@ -1,0 +1,463 @@
+// Host runtime behind the C ABI declared in include/zm.h.
+//
+// A context owns no device memory: it carves the caller's workspace into
+// the RK3 state buffers and the per-evaluation scratch, and enqueues the
+// kernel sequence on the caller's stream.  Per derivative evaluation:
+//   k_surface -> k_pairs -> [k_ties] -> k_reduce -> k_update
+#include "zm.h"
+#include "zm_internal.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+namespace {
+
+constexpr size_t kAlign = 256;
+constexpr int kMaxSide = 16384;
+constexpr int kMaxImages = 16;
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+// Workspace regions, all 256-byte aligned, in bytes from the base.
+struct Layout {
+    size_t y0, y1, y2;   // 5N doubles each (z1 z2 z3 w1 w2)
+    size_t gam, q;       // 3N, N
+    size_t part;         // splits * 3N
+    size_t tie;          // 6N
+    size_t u, V;         // 3N, N
+    size_t flag;         // one int
+    size_t total;
+};
+
+Layout make_layout(const zm_params& p, const zm::PairShape& sh)
+{
+    const size_t N = (size_t)p.n1 * (size_t)p.n2;
+    const size_t d = sizeof(double);
+    Layout L;
+    size_t o = 0;
+    auto take = [&](size_t bytes) { size_t at = o; o = align_up(o + bytes); return at; };
+    L.y0 = take(5 * N * d);
+    L.y1 = take(5 * N * d);
+    L.y2 = take(5 * N * d);
+    L.gam = take(3 * N * d);
+    L.q = take(N * d);
+    L.part = take((size_t)sh.splits * 3 * N * d);
+    L.tie = take(6 * N * d);
+    L.u = take(3 * N * d);
+    L.V = take(N * d);
+    L.flag = take(sizeof(int));
+    L.total = o;
+    return L;
+}
+
+const char* validate(const zm_params* p)
+{
+    if (!p) return "params is NULL";
+    if (p->n1 < 8 || p->n2 < 8) return "n1 and n2 must be >= 8";
+    if (p->n1 > kMaxSide || p->n2 > kMaxSide) return "n1 and n2 must be <= 16384";
+    if (!(std::isfinite(p->period1) && p->period1 > 0.0)) return "period1 must be finite and > 0";
+    if (!(std::isfinite(p->period2) && p->period2 > 0.0)) return "period2 must be finite and > 0";
+    if (!(std::isfinite(p->eps) && p->eps > 0.0)) return "eps must be finite and > 0";
+    if (!(std::isfinite(p->dt) && p->dt > 0.0)) return "dt must be finite and > 0";
+    if (!(std::isfinite(p->nu) && p->nu >= 0.0)) return "nu must be finite and >= 0";
+    if (!std::isfinite(p->atwood)) return "atwood must be finite";
+    if (!std::isfinite(p->gravity)) return "gravity must be finite";
+    if (p->precision != ZM_FP64 && p->precision != ZM_FP32_PAIRS) return "unknown precision";
+    if (p->image_layers < 0 || p->image_layers > kMaxImages) return "image_layers must be in [0, 16]";
+    if (p->flags & ~ZM_FLAG_CHECK_FINITE) return "unknown flag bits";
+    if (p->reserved != 0) return "reserved must be 0";
+    return nullptr;
+}
+
+thread_local std::string g_create_error;
+
+struct Timed {
+    int kernel;
+    hipEvent_t start, stop;
+};
+
+}  // namespace
+
+struct zm_ctx {
+    zm_params prm;
+    zm::Mesh mesh;
+    zm::PairShape shape;
+    Layout layout;
+    hipStream_t stream = nullptr;
+    int device = 0;
+    char* ws = nullptr;
+    std::string err;
+    bool profiling = false;
+    std::vector<Timed> pending;
+    std::vector<hipEvent_t> spare;
+    zm_kernel_stats stats[ZM_KERNEL_COUNT];
+
+    double* at(size_t off) { return reinterpret_cast<double*>(ws + off); }
+    size_t N() const { return (size_t)mesh.N; }
+};
+
+namespace {
+
+zm_status fail(zm_ctx* c, zm_status st, const std::string& msg)
+{
+    if (c) c->err = msg;
+    return st;
+}
+
+zm_status hip_fail(zm_ctx* c, hipError_t e, const char* where)
+{
+    return fail(c, ZM_ERR_HIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+bool aligned(const void* p) { return p && ((uintptr_t)p % kAlign) == 0; }
+
+bool overlaps(const void* a, size_t na, const void* b, size_t nb)
+{
+    const uintptr_t x = (uintptr_t)a, y = (uintptr_t)b;
+    return x < y + nb && y < x + na;
+}
+
+// Makes the context's device current for the duration of a call.
+struct DeviceGuard {
+    int prev = -1;
+    bool ok = true;
+    explicit DeviceGuard(int dev)
+    {
+        if (hipGetDevice(&prev) != hipSuccess) { ok = false; return; }
+        if (prev != dev && hipSetDevice(dev) != hipSuccess) ok = false;
+    }
+    ~DeviceGuard()
+    {
+        int cur;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+hipEvent_t get_event(zm_ctx* c)
+{
+    if (!c->spare.empty()) {
+        hipEvent_t e = c->spare.back();
+        c->spare.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Enqueue one launch, bracketed by timing events when profiling is on.
+template <class F>
+hipError_t timed(zm_ctx* c, int kernel, F&& launch)
+{
+    if (!c->profiling) return launch();
+    hipEvent_t a = get_event(c), b = get_event(c);
+    if (!a || !b) return hipErrorOutOfMemory;
+    hipError_t e = hipEventRecord(a, c->stream);
+    if (e != hipSuccess) return e;
+    e = launch();
+    if (e != hipSuccess) return e;
+    e = hipEventRecord(b, c->stream);
+    if (e != hipSuccess) return e;
+    c->pending.push_back({kernel, a, b});
+    return hipSuccess;
+}
+
+// u (3 planes) = BR velocity of (z, w); optionally V as well.
+zm_status eval_velocity(zm_ctx* c, const double* z, const double* w, double* u, double* V)
+{
+    const zm::Mesh& m = c->mesh;
+    double* gam = c->at(c->layout.gam);
+    double* q = c->at(c->layout.q);
+    double* part = c->at(c->layout.part);
+    double* tie = c->at(c->layout.tie);
+    hipError_t e;
+    e = timed(c, ZM_KERNEL_SURFACE, [&] { return zm::launch_surface(m, z, w, gam, q, c->stream); });
+    if (e != hipSuccess) return hip_fail(c, e, "surface kernel launch");
+    e = timed(c, ZM_KERNEL_PAIRS,
+              [&] { return zm::launch_pairs_f64(m, c->shape, z, gam, part, c->stream); });
+    if (e != hipSuccess) return hip_fail(c, e, "pair kernel launch");
+    if ((m.n1 % 2) == 0 || (m.n2 % 2) == 0) {
+        e = timed(c, ZM_KERNEL_TIES, [&] { return zm::launch_ties(m, z, gam, tie, c->stream); });
+        if (e != hipSuccess) return hip_fail(c, e, "tie kernel launch");
+    }
+    e = timed(c, ZM_KERNEL_REDUCE, [&] {
+        return zm::launch_reduce(m, c->shape.splits, part, tie, q, z, u, V, c->stream);
+    });
+    if (e != hipSuccess) return hip_fail(c, e, "reduce kernel launch");
+    return ZM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t zm_workspace_bytes(const zm_params* params)
+{
+    if (validate(params)) return 0;
+    const zm::PairShape sh = zm::choose_pair_shape(params->n1, params->n2, params->precision);
+    return make_layout(*params, sh).total;
+}
+
+zm_status zm_create(zm_ctx** out, const zm_params* params, void* d_workspace,
+                    size_t workspace_bytes, void* hip_stream)
+{
+    g_create_error.clear();
+    if (!out) { g_create_error = "out is NULL"; return ZM_ERR_INVALID_ARG; }
+    *out = nullptr;
+    if (const char* why = validate(params)) { g_create_error = why; return ZM_ERR_INVALID_ARG; }
+    if (params->precision == ZM_FP32_PAIRS) {
+        g_create_error = "ZM_FP32_PAIRS is not provided by this build";
+        return ZM_ERR_UNSUPPORTED;
+    }
+    const zm::PairShape sh = zm::choose_pair_shape(params->n1, params->n2, params->precision);
+    const Layout L = make_layout(*params, sh);
+    if (!d_workspace || !aligned(d_workspace)) {
+        g_create_error = "workspace is NULL or not 256-byte aligned";
+        return ZM_ERR_WORKSPACE;
+    }
+    if (workspace_bytes < L.total) {
+        g_create_error = "workspace smaller than zm_workspace_bytes()";
+        return ZM_ERR_WORKSPACE;
+    }
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) {
+        g_create_error = std::string("hipGetDevice: ") + hipGetErrorString(e);
+        return ZM_ERR_HIP;
+    }
+    zm_ctx* c = new (std::nothrow) zm_ctx();
+    if (!c) { g_create_error = "host allocation failed"; return ZM_ERR_CAPACITY; }
+    c->prm = *params;
+    c->shape = sh;
+    c->layout = L;
+    c->stream = reinterpret_cast<hipStream_t>(hip_stream);
+    c->device = dev;
+    c->ws = reinterpret_cast<char*>(d_workspace);
+    std::memset(c->stats, 0, sizeof(c->stats));
+    zm::Mesh& m = c->mesh;
+    m.n1 = params->n1;
+    m.n2 = params->n2;
+    m.N = params->n1 * params->n2;
+    m.K = params->image_layers;
+    m.L1 = params->period1;
+    m.L2 = params->period2;
+    m.h1 = params->period1 / params->n1;
+    m.h2 = params->period2 / params->n2;
+    m.eps2 = params->eps * params->eps;
+    m.coef = -(m.h1 * m.h2) / (4.0 * M_PI);
+    m.atwood = params->atwood;
+    m.gravity = params->gravity;
+    m.nu = params->nu;
+    m.dt = params->dt;
+    *out = c;
+    return ZM_OK;
+}
+
+zm_status zm_init_state(zm_ctx* c, const double* d_z, const double* d_w)
+{
+    if (!c) return ZM_ERR_INVALID_ARG;
+    if (!aligned(d_z) || !aligned(d_w))
+        return fail(c, ZM_ERR_INVALID_ARG, "state pointers must be non-NULL and 256-byte aligned");
+    DeviceGuard g(c->device);
+    if (!g.ok) return fail(c, ZM_ERR_HIP, "cannot select the context device");
+    const size_t N = c->N();
+    double* y0 = c->at(c->layout.y0);
+    hipError_t e = hipMemcpyAsync(y0, d_z, 3 * N * sizeof(double), hipMemcpyDeviceToDevice, c->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(y0 + 3 * N, d_w, 2 * N * sizeof(double), hipMemcpyDeviceToDevice,
+                           c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "state copy");
+    return ZM_OK;
+}
+
+zm_status zm_get_state(zm_ctx* c, double* d_z, double* d_w)
+{
+    if (!c) return ZM_ERR_INVALID_ARG;
+    if (!aligned(d_z) || !aligned(d_w))
+        return fail(c, ZM_ERR_INVALID_ARG, "state pointers must be non-NULL and 256-byte aligned");
+    DeviceGuard g(c->device);
+    if (!g.ok) return fail(c, ZM_ERR_HIP, "cannot select the context device");
+    const size_t N = c->N();
+    const double* y0 = c->at(c->layout.y0);
+    hipError_t e = hipMemcpyAsync(d_z, y0, 3 * N * sizeof(double), hipMemcpyDeviceToDevice, c->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(d_w, y0 + 3 * N, 2 * N * sizeof(double), hipMemcpyDeviceToDevice,
+                           c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "state copy");
+    return ZM_OK;
+}
+
+zm_status zm_br_velocity(zm_ctx* c, const double* d_z, const double* d_w, double* d_u)
+{
+    if (!c) return ZM_ERR_INVALID_ARG;
+    if (!aligned(d_z) || !aligned(d_w) || !aligned(d_u))
+        return fail(c, ZM_ERR_INVALID_ARG, "pointers must be non-NULL and 256-byte aligned");
+    const size_t N = c->N(), d = sizeof(double);
+    if (overlaps(d_u, 3 * N * d, d_z, 3 * N * d) || overlaps(d_u, 3 * N * d, d_w, 2 * N * d))
+        return fail(c, ZM_ERR_INVALID_ARG, "d_u overlaps an input");
+    DeviceGuard g(c->device);
+    if (!g.ok) return fail(c, ZM_ERR_HIP, "cannot select the context device");
+    return eval_velocity(c, d_z, d_w, d_u, nullptr);
+}
+
+zm_status zm_rhs(zm_ctx* c, const double* d_z, const double* d_w, double* d_zt, double* d_wt)
+{
+    if (!c) return ZM_ERR_INVALID_ARG;
+    if (!aligned(d_z) || !aligned(d_w) || !aligned(d_zt) || !aligned(d_wt))
+        return fail(c, ZM_ERR_INVALID_ARG, "pointers must be non-NULL and 256-byte aligned");
+    const size_t N = c->N(), d = sizeof(double);
+    const void* in[2] = {d_z, d_w};
+    const size_t nin[2] = {3 * N * d, 2 * N * d};
+    for (int i = 0; i < 2; ++i)
+        if (overlaps(d_zt, 3 * N * d, in[i], nin[i]) || overlaps(d_wt, 2 * N * d, in[i], nin[i]))
+            return fail(c, ZM_ERR_INVALID_ARG, "an output overlaps an input");
+    if (overlaps(d_zt, 3 * N * d, d_wt, 2 * N * d))
+        return fail(c, ZM_ERR_INVALID_ARG, "d_zt overlaps d_wt");
+    DeviceGuard g(c->device);
+    if (!g.ok) return fail(c, ZM_ERR_HIP, "cannot select the context device");
+    double* u = c->at(c->layout.u);
+    double* V = c->at(c->layout.V);
+    zm_status st = eval_velocity(c, d_z, d_w, u, V);
+    if (st != ZM_OK) return st;
+    hipError_t e = timed(c, ZM_KERNEL_UPDATE, [&] {
+        return zm::launch_update(c->mesh, 3, nullptr, nullptr, d_z, d_w, u, V, d_zt, d_wt, nullptr,
+                                 c->stream);
+    });
+    if (e != hipSuccess) return hip_fail(c, e, "update kernel launch");
+    return ZM_OK;
+}
+
+zm_status zm_step(zm_ctx* c, int32_t nsteps)
+{
+    if (!c) return ZM_ERR_INVALID_ARG;
+    if (nsteps < 0) return fail(c, ZM_ERR_INVALID_ARG, "nsteps must be >= 0");
+    DeviceGuard g(c->device);
+    if (!g.ok) return fail(c, ZM_ERR_HIP, "cannot select the context device");
+    const size_t N = c->N();
+    double* Y[3] = {c->at(c->layout.y0), c->at(c->layout.y1), c->at(c->layout.y2)};
+    double* u = c->at(c->layout.u);
+    double* V = c->at(c->layout.V);
+    int* flag = reinterpret_cast<int*>(c->ws + c->layout.flag);
+    const bool check = (c->prm.flags & ZM_FLAG_CHECK_FINITE) != 0;
+    hipError_t e;
+    if (check) {
+        e = hipMemsetAsync(flag, 0, sizeof(int), c->stream);
+        if (e != hipSuccess) return hip_fail(c, e, "flag clear");
+    }
+    for (int step = 0; step < nsteps; ++step) {
+        for (int stage = 0; stage < 3; ++stage) {
+            double* ys = Y[stage];                       // state F is evaluated at
+            double* out = Y[(stage + 1) % 3];            // Y1, Y2, then Y0 in place
+            zm_status st = eval_velocity(c, ys, ys + 3 * N, u, V);
+            if (st != ZM_OK) return st;
+            e = timed(c, ZM_KERNEL_UPDATE, [&] {
+                return zm::launch_update(c->mesh, stage, Y[0], Y[0] + 3 * N, ys, ys + 3 * N, u, V,
+                                         out, out + 3 * N, check ? flag : nullptr, c->stream);
+            });
+            if (e != hipSuccess) return hip_fail(c, e, "update kernel launch");
+        }
+    }
+    if (check) {
+        int host_flag = 0;
+        e = hipMemcpyAsync(&host_flag, flag, sizeof(int), hipMemcpyDeviceToHost, c->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+        if (e != hipSuccess) return hip_fail(c, e, "flag read");
+        if (host_flag) return fail(c, ZM_ERR_NONFINITE, "state became non-finite");
+    }
+    return ZM_OK;
+}
+
+zm_status zm_destroy(zm_ctx* c)
+{
+    if (!c) return ZM_OK;
+    zm_status st = ZM_OK;
+    {
+        DeviceGuard g(c->device);
+        if (g.ok && hipStreamSynchronize(c->stream) != hipSuccess) st = ZM_ERR_HIP;
+        for (auto& t : c->pending) {
+            (void)hipEventDestroy(t.start);
+            (void)hipEventDestroy(t.stop);
+        }
+        for (auto e : c->spare) (void)hipEventDestroy(e);
+    }
+    delete c;
+    return st;
+}
+
+const char* zm_status_string(zm_status s)
+{
+    switch (s) {
+    case ZM_OK: return "ok";
+    case ZM_ERR_INVALID_ARG: return "invalid argument";
+    case ZM_ERR_UNSUPPORTED: return "unsupported";
+    case ZM_ERR_WORKSPACE: return "workspace missing, too small or misaligned";
+    case ZM_ERR_HIP: return "HIP runtime error";
+    case ZM_ERR_NONFINITE: return "non-finite state";
+    case ZM_ERR_CAPACITY: return "capacity exceeded";
+    default: return "unknown status";
+    }
+}
+
+const char* zm_last_error(const zm_ctx* c)
+{
+    if (!c) return g_create_error.c_str();
+    return c->err.c_str();
+}
+
+zm_status zm_get_launch_info(const zm_ctx* c, zm_launch_info* out)
+{
+    if (!c || !out) return ZM_ERR_INVALID_ARG;
+    const zm::PairShape& sh = c->shape;
+    out->targets_per_lane = sh.R;
+    out->patch_cols = sh.cx;
+    out->patch_rows = sh.prow;
+    out->source_splits = sh.splits;
+    out->workgroups = sh.px * sh.py * sh.splits;
+    out->threads_per_group = 256;
+    const int64_t side = 2 * (int64_t)c->mesh.K + 1;
+    out->pairs_per_eval = (int64_t)c->mesh.N * (int64_t)c->mesh.N * side * side;
+    return ZM_OK;
+}
+
+zm_status zm_profile_enable(zm_ctx* c, int32_t on)
+{
+    if (!c) return ZM_ERR_INVALID_ARG;
+    c->profiling = (on != 0);
+    return ZM_OK;
+}
+
+zm_status zm_profile_read(zm_ctx* c, zm_kernel_stats* out)
+{
+    if (!c || !out) return ZM_ERR_INVALID_ARG;
+    DeviceGuard g(c->device);
+    if (!g.ok) return fail(c, ZM_ERR_HIP, "cannot select the context device");
+    zm_status st = ZM_OK;
+    for (auto& t : c->pending) {
+        float ms = 0.0f;
+        hipError_t e = hipEventSynchronize(t.stop);
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, t.start, t.stop);
+        if (e != hipSuccess) {
+            st = hip_fail(c, e, "event timing");
+        } else {
+            c->stats[t.kernel].launches += 1;
+            c->stats[t.kernel].total_ms += (double)ms;
+        }
+        c->spare.push_back(t.start);
+        c->spare.push_back(t.stop);
+    }
+    c->pending.clear();
+    std::memcpy(out, c->stats, sizeof(c->stats));
+    std::memset(c->stats, 0, sizeof(c->stats));
+    return st;
+}
+
+int32_t zm_abi_version(void) { return 1; }
+
+}  // extern "C"

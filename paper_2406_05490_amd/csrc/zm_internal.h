@@ -1,0 +1,66 @@
+// Internal interface between the host runtime (zm_api.hip) and the device
+// kernels (zm_kernels.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace zm {
+
+// Mesh geometry and model constants, passed by value to every kernel.
+struct Mesh {
+    int n1, n2;          // points per axis
+    int N;               // n1 * n2
+    int K;               // extra image layers
+    double L1, L2;       // periods
+    double h1, h2;       // spacings L_a / n_a
+    double eps2;         // eps^2
+    double coef;         // -(h1 h2) / (4 pi)
+    double atwood, gravity, nu, dt;
+};
+
+// Launch shape of the all-pairs kernel.
+struct PairShape {
+    int R;               // targets per lane (register blocking)
+    int cx;              // patch columns; 256 / cx thread rows
+    int prow;            // patch rows = (256 / cx) * R
+    int px, py;          // patches along axis 1 / axis 2
+    int splits;          // source row ranges
+    int rows_per_split;
+};
+
+PairShape choose_pair_shape(int n1, int n2, int precision);
+
+// Each launcher enqueues one kernel on `s` and returns the launch status.
+hipError_t launch_surface(const Mesh& m, const double* z, const double* w,
+                          double* gam, double* q, hipStream_t s);
+
+// part[split][3][N] = unscaled sums over the split's sources of
+// (r x gamma) / (|r|^2 + eps^2)^(3/2), images handled as described in zm.h
+// with ties counted once at the image of offset -n_a/2.
+hipError_t launch_pairs_f64(const Mesh& m, const PairShape& sh, const double* z,
+                            const double* gam, double* part, hipStream_t s);
+
+// tie[pass][3][N]: pass 0 (n1 even) corrects the tie column, pass 1 (n2 even)
+// the tie row, so that tied sources end with weight 1/2 per end image.
+hipError_t launch_ties(const Mesh& m, const double* z, const double* gam, double* tie,
+                       hipStream_t s);
+
+// u = coef * (sum_s part[s] + ties); optionally V = A (|u|^2 - q/4 - 2 g z3).
+hipError_t launch_reduce(const Mesh& m, int splits, const double* part, const double* tie,
+                         const double* q, const double* z, double* u, double* V,
+                         hipStream_t s);
+
+// F = (u, D V + nu Lap w) at state ys, then
+//   stage 0: out = ys + dt F
+//   stage 1: out = 3/4 y0 + 1/4 (ys + dt F)
+//   stage 2: out = 1/3 y0 + 2/3 (ys + dt F)
+//   stage 3: out = F (plain right-hand side; out_z / out_w are zt / wt)
+// y0_z / ys_z / out_z: 3 planes, *_w: 2 planes.  out may alias y0 (read and
+// written by the same thread), never ys.  nonfinite != NULL receives 1 if any
+// output is not finite.
+hipError_t launch_update(const Mesh& m, int stage, const double* y0_z, const double* y0_w,
+                         const double* ys_z, const double* ys_w, const double* u, const double* V,
+                         double* out_z, double* out_w, int* nonfinite, hipStream_t s);
+
+}  // namespace zm

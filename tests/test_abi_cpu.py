@@ -1,0 +1,103 @@
+"""The C ABI library loads, exports what include/zm.h declares, and rejects
+bad arguments on the host (no GPU needed: these checks run before any HIP
+call)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_2406_05490_amd as zm
+from paper_2406_05490_amd import _zm
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "zm.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return re.findall(r"\b(zm_[a-z0-9_]+)\s*\(", src)
+
+
+def test_header_declares_binding_exports():
+    assert tuple(declared_functions()) == _zm.EXPORTS
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(zm.LIB_PATH)
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+
+
+def test_abi_version_and_status_strings():
+    lib = zm.load()
+    assert lib.zm_abi_version() == 1
+    assert zm.status_string(zm.ZM_OK) == "ok"
+    for st in (zm.ZM_ERR_INVALID_ARG, zm.ZM_ERR_UNSUPPORTED, zm.ZM_ERR_WORKSPACE,
+               zm.ZM_ERR_HIP, zm.ZM_ERR_NONFINITE, zm.ZM_ERR_CAPACITY):
+        assert zm.status_string(st) not in ("ok", "unknown status")
+    assert zm.status_string(12345) == "unknown status"
+
+
+def test_struct_layout_matches_header():
+    # n1 n2 (8) + 7 doubles (56) + 4 int32 (16) = 80 bytes
+    assert ctypes.sizeof(_zm.zm_params) == 80
+    assert ctypes.sizeof(_zm.zm_launch_info) == 32
+    assert ctypes.sizeof(_zm.zm_kernel_stats) == 16
+
+
+@pytest.mark.parametrize("bad", [
+    dict(n1=7), dict(n2=4), dict(n1=20000), dict(eps=0.0), dict(eps=-1.0),
+    dict(eps=float("nan")), dict(dt=0.0), dict(nu=-1.0), dict(period1=0.0),
+    dict(atwood=float("inf")), dict(precision=7), dict(image_layers=-1),
+    dict(image_layers=17), dict(flags=0x80),
+])
+def test_workspace_bytes_rejects_invalid(bad):
+    kw = dict(n1=16, n2=16, eps=1 / 16)
+    kw.update(bad)
+    assert zm.workspace_bytes(zm.Params(**kw)) == 0
+
+
+def test_workspace_bytes_grows_with_mesh():
+    a = zm.workspace_bytes(zm.Params(16, 16, eps=1 / 16))
+    b = zm.workspace_bytes(zm.Params(64, 64, eps=1 / 64))
+    assert 0 < a < b
+    assert a % 256 == 0 and b % 256 == 0
+
+
+def _create(p, ws, nbytes):
+    lib = zm.load()
+    h = ctypes.c_void_p(1234)
+    st = lib.zm_create(ctypes.byref(h), ctypes.byref(p.c()), ws, nbytes, None)
+    return st, h, lib.zm_last_error(None).decode()
+
+
+def test_create_rejects_bad_params_without_touching_device():
+    st, h, msg = _create(zm.Params(4, 16, eps=0.1), 256, 1 << 20)
+    assert st == zm.ZM_ERR_INVALID_ARG and h.value is None and "n1" in msg
+
+
+def test_create_rejects_missing_or_small_workspace():
+    p = zm.Params(16, 16, eps=1 / 16)
+    need = zm.workspace_bytes(p)
+    st, h, msg = _create(p, None, need)
+    assert st == zm.ZM_ERR_WORKSPACE and h.value is None
+    st, h, msg = _create(p, 256 * 3 + 8, need)          # misaligned
+    assert st == zm.ZM_ERR_WORKSPACE
+    st, h, msg = _create(p, 4096, need - 1)             # too small
+    assert st == zm.ZM_ERR_WORKSPACE and "smaller" in msg
+
+
+def test_create_reports_fp32_pairs_unsupported():
+    p = zm.Params(16, 16, eps=1 / 16, precision=zm.ZM_FP32_PAIRS)
+    st, h, msg = _create(p, 4096, zm.workspace_bytes(p))
+    assert st == zm.ZM_ERR_UNSUPPORTED
+
+
+def test_null_context_calls_are_rejected():
+    lib = zm.load()
+    assert lib.zm_step(None, 1) == zm.ZM_ERR_INVALID_ARG
+    assert lib.zm_init_state(None, None, None) == zm.ZM_ERR_INVALID_ARG
+    assert lib.zm_br_velocity(None, None, None, None) == zm.ZM_ERR_INVALID_ARG
+    assert lib.zm_destroy(None) == zm.ZM_OK
