@@ -27,28 +27,33 @@ FLAGS = [
 ]
 
 
-def build(verbose: bool = False, asm_dir: str | None = None) -> str:
+def build(verbose: bool = False, asm_dir: str | None = None, defines=(), out: str = LIB) -> str:
+    """Compile and link; `defines` are extra -D macros (tuning builds), `out`
+    the library path."""
     objs = []
+    extra = [f"-D{d}" for d in defines]
+    tag = "_".join(d.replace("=", "") for d in defines)
     for src in SOURCES:
-        obj = os.path.join(CSRC, os.path.basename(src) + ".o")
-        cmd = [HIPCC, *FLAGS, "-c", src, "-o", obj]
+        obj = os.path.join(CSRC, os.path.basename(src) + (f".{tag}" if tag else "") + ".o")
+        cmd = [HIPCC, *FLAGS, *extra, "-c", src, "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.run(cmd, check=True)
         objs.append(obj)
         if asm_dir:
-            acmd = [HIPCC, *FLAGS, "--cuda-device-only", "-S", src, "-o",
+            os.makedirs(asm_dir, exist_ok=True)
+            acmd = [HIPCC, *FLAGS, *extra, "--cuda-device-only", "-S", src, "-o",
                     os.path.join(asm_dir, os.path.basename(src) + ".s")]
             subprocess.run(acmd, check=True)
-    tmp = LIB + ".tmp"
+    tmp = out + ".tmp"
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
-    os.replace(tmp, LIB)
+    os.replace(tmp, out)
     for o in objs:
         os.remove(o)
-    return LIB
+    return out
 
 
 if __name__ == "__main__":

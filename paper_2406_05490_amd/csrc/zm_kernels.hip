@@ -27,6 +27,14 @@ namespace {
 
 constexpr int kThreads = 256;
 
+// Source-loop unroll depth and targets per lane of the pair kernel.
+#ifndef ZM_PAIR_UNROLL
+#define ZM_PAIR_UNROLL 2
+#endif
+#ifndef ZM_PAIR_R
+#define ZM_PAIR_R 4
+#endif
+
 // Periodic neighbour index along one axis; sets wrap to -1/0/+1.
 __device__ __forceinline__ int nbr(int i, int d, int n, int& wrap)
 {
@@ -48,17 +56,17 @@ __device__ __forceinline__ double d2_5pt(double fm2, double fm1, double f0, doub
     return (-fp2 + 16.0 * fp1 - 30.0 * f0 + 16.0 * fm1 - fm2) / (12.0 * h * h);
 }
 
-// w = (|r|^2 + eps^2)^(-3/2) from s = |r|^2 + eps^2: hardware reciprocal
-// square root y0, then one third-order correction in e = 1 - s y0^2:
-// w = y0^3 (1 + 3e/2 + 15e^2/8), exact to O(e^3).
+// w = (|r|^2 + eps^2)^(-3/2) from s = |r|^2 + eps^2.  The hardware reciprocal
+// square root y0 has relative error below 2^-24 on gfx950; with
+// e = 1 - s y0^2 the exact value is y0^3 (1 - e)^(-3/2) and the first-order
+// correction w = y0^3 (1 + 3e/2) leaves 15 e^2 / 8 < 2e-14 (always low).
 __device__ __forceinline__ double inv_cube_sqrt(double s)
 {
     const double y0 = __builtin_amdgcn_rsq(s);
     const double y2 = y0 * y0;
     const double e = fma(-s, y2, 1.0);
     const double w0 = y2 * y0;
-    const double c = e * fma(e, 1.875, 1.5);
-    return fma(w0, c, w0);
+    return fma(w0 * e, 1.5, w0);
 }
 
 // ---------------------------------------------------------------------------
@@ -135,6 +143,50 @@ __device__ __forceinline__ AxisImg axis_img(int i, int n)
     return a;
 }
 
+// Unscaled contributions of sources [k0, k0 + cnt) of the current LDS tile,
+// all in one source row and one column segment, to the lane's R targets.
+// CORE: every target of the lane has a fixed image shift over the segment,
+// already folded into xt.  Otherwise (seam band) the axis-1 shift is chosen
+// per source: sources with column < b1 sit at shift Sx_lo, the others at
+// Sx_hi.
+template <int R, bool CORE>
+__device__ __forceinline__ void pair_segment(const double2 (*__restrict__ buf)[kThreads], int k0,
+                                             int cnt, int j1s, int b1, double Sx_lo, double Sx_hi,
+                                             const double* xt, const double* yt, const double* zi,
+                                             double eps2, double (*sa)[3])
+{
+#pragma unroll ZM_PAIR_UNROLL
+    for (int c = 0; c < cnt; ++c) {
+        const double2 v0 = buf[0][k0 + c];
+        const double2 v1 = buf[1][k0 + c];
+        const double2 v2 = buf[2][k0 + c];
+        double xs = v0.x;
+        if (!CORE) xs = xs + ((j1s + c < b1) ? Sx_lo : Sx_hi);
+        const double ys = v0.y, zs = v1.x;
+        const double g1 = v1.y, g2 = v2.x, g3 = v2.y;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const double r1 = xt[r] - xs;
+            const double r2 = yt[r] - ys;
+            const double r3 = zi[r] - zs;
+            const double s = fma(r1, r1, fma(r2, r2, fma(r3, r3, eps2)));
+            const double wgt = inv_cube_sqrt(s);
+            const double a1 = wgt * g1, a2 = wgt * g2, a3 = wgt * g3;
+            sa[r][0] = fma(r2, a3, sa[r][0]);
+            sa[r][0] = fma(-r3, a2, sa[r][0]);
+            sa[r][1] = fma(r3, a1, sa[r][1]);
+            sa[r][1] = fma(-r1, a3, sa[r][1]);
+            sa[r][2] = fma(r1, a2, sa[r][2]);
+            sa[r][2] = fma(-r2, a1, sa[r][2]);
+        }
+    }
+}
+
+// All-pairs sweep.  Workgroup = target patch (CX columns x prow rows; lane =
+// one column, R rows spaced 256/CX apart) x one range of source rows.  The
+// axis-1 image breakpoints b1 of the patch's columns form a band of CX
+// consecutive source columns (mod n1); outside it every lane's shift is
+// constant per row segment, inside it the shift is selected per source.
 template <int R, int CX>
 __global__ __launch_bounds__(kThreads) void k_pairs_f64(Mesh m, PairShape sh,
                                                         const double* __restrict__ z,
@@ -158,13 +210,18 @@ __global__ __launch_bounds__(kThreads) void k_pairs_f64(Mesh m, PairShape sh,
     if (row_begin >= row_end) return;  // uniform over the workgroup
 
     // ---- targets of this lane: one column, R rows -------------------------
-    const int col = ptx * CX + (tid % CX);
+    const int c0 = ptx * CX;
+    const int col = c0 + (tid % CX);
     const int rowg = tid / CX;
     const bool col_ok = col < n1;
     const int i1 = col_ok ? col : 0;
     const AxisImg ax1 = axis_img(i1, n1);
+    // seam band of source columns: b1 of columns c0 .. c0+CX-1, mod n1
+    const int band_lo = axis_img(c0, n1).b;
+    const bool band_all = CX >= n1;
+    const bool band_wraps = band_lo + CX > n1;
 
-    double xi[R], yi[R], zi[R], yt[R];
+    double xi[R], yi[R], zi[R], xt[R], yt[R];
     int b2[R], s2lo[R], pidx[R];
     bool valid[R];
 #pragma unroll
@@ -179,6 +236,7 @@ __global__ __launch_bounds__(kThreads) void k_pairs_f64(Mesh m, PairShape sh,
         const AxisImg ax2 = axis_img(i2, n2);
         b2[k] = ax2.b;
         s2lo[k] = ax2.s_lo;
+        xt[k] = xi[k];
         yt[k] = yi[k];
     }
 
@@ -223,8 +281,8 @@ __global__ __launch_bounds__(kThreads) void k_pairs_f64(Mesh m, PairShape sh,
         const int tile = t - img * ntiles;
         const int m1 = img % side - m.K;
         const int m2 = img / side - m.K;
-        const double xoff_lo = (double)(ax1.s_lo + m1) * m.L1;
-        const double xoff_hi = (double)(ax1.s_lo - 1 + m1) * m.L1;
+        const double Sx_lo = (double)(ax1.s_lo + m1) * m.L1;
+        const double Sx_hi = (double)(ax1.s_lo - 1 + m1) * m.L1;
 
         const int j0 = src_begin + tile * kThreads;
         const int cnt = min(kThreads, src_end - j0);
@@ -232,8 +290,7 @@ __global__ __launch_bounds__(kThreads) void k_pairs_f64(Mesh m, PairShape sh,
         int j1 = j0 - j2 * n1;
         int k = 0;
         while (k < cnt) {
-            const int seg = min(cnt - k, n1 - j1);
-            // axis-2 image of this source row, per target
+            const int seg = min(cnt - k, n1 - j1);   // this row's columns [j1, j1 + seg)
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 const int s2 = (j2 < b2[r]) ? s2lo[r] : s2lo[r] - 1;
@@ -243,29 +300,36 @@ __global__ __launch_bounds__(kThreads) void k_pairs_f64(Mesh m, PairShape sh,
 #pragma unroll
             for (int r = 0; r < R; ++r) sa[r][0] = sa[r][1] = sa[r][2] = 0.0;
 
-            for (int c = 0; c < seg; ++c) {
-                const double2 v0 = lds[buf][0][k + c];
-                const double2 v1 = lds[buf][1][k + c];
-                const double2 v2 = lds[buf][2][k + c];
-                const double off = (j1 + c < ax1.b) ? xoff_lo : xoff_hi;
-                const double xs = v0.x + off;
-                const double ys = v0.y, zs = v1.x;
-                const double g1 = v1.y, g2 = v2.x, g3 = v2.y;
-#pragma unroll
-                for (int r = 0; r < R; ++r) {
-                    const double r1 = xi[r] - xs;
-                    const double r2 = yt[r] - ys;
-                    const double r3 = zi[r] - zs;
-                    const double s = fma(r1, r1, fma(r2, r2, fma(r3, r3, m.eps2)));
-                    const double wgt = inv_cube_sqrt(s);
-                    const double a1 = wgt * g1, a2 = wgt * g2, a3 = wgt * g3;
-                    sa[r][0] = fma(r2, a3, sa[r][0]);
-                    sa[r][0] = fma(-r3, a2, sa[r][0]);
-                    sa[r][1] = fma(r3, a1, sa[r][1]);
-                    sa[r][1] = fma(-r1, a3, sa[r][1]);
-                    sa[r][2] = fma(r1, a2, sa[r][2]);
-                    sa[r][2] = fma(-r2, a1, sa[r][2]);
+            // split [j1, j1 + seg) at the band edges: core pieces and band pieces
+            int a = j1;
+            const int e = j1 + seg;
+            while (a < e) {
+                bool in_band;
+                int stop;
+                if (band_all) {
+                    in_band = true; stop = e;
+                } else if (!band_wraps) {
+                    if (a < band_lo) { in_band = false; stop = min(e, band_lo); }
+                    else if (a < band_lo + CX) { in_band = true; stop = min(e, band_lo + CX); }
+                    else { in_band = false; stop = e; }
+                } else {
+                    const int hi_end = band_lo + CX - n1;   // band = [band_lo, n1) + [0, hi_end)
+                    if (a < hi_end) { in_band = true; stop = min(e, hi_end); }
+                    else if (a < band_lo) { in_band = false; stop = min(e, band_lo); }
+                    else { in_band = true; stop = e; }
                 }
+                const int kk = k + (a - j1);
+                if (in_band) {
+                    pair_segment<R, false>(lds[buf], kk, stop - a, a, ax1.b, Sx_lo, Sx_hi, xi, yt,
+                                           zi, m.eps2, sa);
+                } else {
+                    const double Sx = (a < ax1.b) ? Sx_lo : Sx_hi;
+#pragma unroll
+                    for (int r = 0; r < R; ++r) xt[r] = xi[r] - Sx;
+                    pair_segment<R, true>(lds[buf], kk, stop - a, a, ax1.b, Sx_lo, Sx_hi, xt, yt,
+                                          zi, m.eps2, sa);
+                }
+                a = stop;
             }
 #pragma unroll
             for (int r = 0; r < R; ++r) {
@@ -489,7 +553,7 @@ PairShape choose_pair_shape(int n1, int n2, int precision)
 {
     (void)precision;
     PairShape sh;
-    sh.R = 4;
+    sh.R = ZM_PAIR_R;
     sh.cx = (n1 >= 16) ? 16 : 8;
     sh.prow = (kThreads / sh.cx) * sh.R;
     sh.px = (n1 + sh.cx - 1) / sh.cx;
@@ -516,10 +580,11 @@ hipError_t launch_pairs_f64(const Mesh& m, const PairShape& sh, const double* z,
                             const double* gam, double* part, hipStream_t s)
 {
     const dim3 grid((unsigned)(sh.px * sh.py), (unsigned)sh.splits);
-    if (sh.R == 4 && sh.cx == 16)
-        hipLaunchKernelGGL((k_pairs_f64<4, 16>), grid, dim3(kThreads), 0, s, m, sh, z, gam, part);
-    else if (sh.R == 4 && sh.cx == 8)
-        hipLaunchKernelGGL((k_pairs_f64<4, 8>), grid, dim3(kThreads), 0, s, m, sh, z, gam, part);
+    constexpr int R = ZM_PAIR_R;
+    if (sh.R == R && sh.cx == 16)
+        hipLaunchKernelGGL((k_pairs_f64<R, 16>), grid, dim3(kThreads), 0, s, m, sh, z, gam, part);
+    else if (sh.R == R && sh.cx == 8)
+        hipLaunchKernelGGL((k_pairs_f64<R, 8>), grid, dim3(kThreads), 0, s, m, sh, z, gam, part);
     else
         return hipErrorInvalidConfiguration;
     return hipGetLastError();
