@@ -41,6 +41,8 @@ def parse():
     ap.add_argument("--workload", default=DEFAULT_WORKLOAD, choices=sorted(rr.WORKLOADS))
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target CPU time of the oracle sample (0 = skip)")
+    ap.add_argument("--no-sweep", action="store_true",
+                    help="skip the 1M-point BR sweep (FP64 and FP32 forms)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of this many MiB (counter calibration)")
     return ap.parse_args()
@@ -55,6 +57,45 @@ def copy_calibration(mib: int):
         b.copy_(a)
     torch.cuda.synchronize()
     print(json.dumps({"copy_calibration_bytes_read": n * 8, "bytes_written": n * 8, "launches": 3}))
+
+
+def br_sweep_1m(zm, torch, reps: int = 2):
+    """One BR evaluation on the 1024 x 1024 precision workload (synthetic
+    vorticity) in the FP64 and FP32 forms: pair-kernel time from HIP events,
+    roofline fraction against each form's vector peak, speedup and error."""
+    wl = rr.WORKLOADS["periodic1024_multimode16_fp32"]
+    z, _ = wl.state()
+    w = rr.synthetic_vorticity(wl.n1, wl.n2, seed=wl.seed)
+    dev = torch.device("cuda:0")
+    zd = torch.from_numpy(z.ravel()).to(dev)
+    wd = torch.from_numpy(w.ravel()).to(dev)
+    res, us = {}, {}
+    for name, prec in (("fp64", zm.ZM_FP64), ("fp32_pairs", zm.ZM_FP32_PAIRS)):
+        p = zm.Params(wl.n1, wl.n2, eps=wl.eps, atwood=wl.atwood, gravity=wl.gravity,
+                      dt=wl.dt, precision=prec)
+        ctx = zm.Context(p)
+        ud = torch.empty_like(zd)
+        ctx.br_velocity(zd, wd, ud)          # warm-up
+        torch.cuda.synchronize()
+        ctx.profile_read()
+        ctx.profile_enable(True)
+        for _ in range(reps):
+            ctx.br_velocity(zd, wd, ud)
+        st = ctx.profile_read()
+        torch.cuda.synchronize()
+        n, ms = st["pairs"]
+        pairs = ctx.launch_info().pairs_per_eval
+        sec = ms / 1e3 / n
+        tf = FLOPS_PER_PAIR * pairs / sec / 1e12
+        res[name] = {"pair_kernel_ms": sec * 1e3, "pairs_per_s": pairs / sec, "tflops": tf,
+                     "peak_tflops": PEAK_TFLOPS[name], "frac": tf / PEAK_TFLOPS[name]}
+        us[name] = ud.cpu().numpy()
+        del ctx
+    err = float(np.max(np.abs(us["fp32_pairs"] - us["fp64"])) / np.max(np.abs(us["fp64"])))
+    res["fp32_over_fp64_speedup"] = res["fp32_pairs"]["pairs_per_s"] / res["fp64"]["pairs_per_s"]
+    res["fp32_vs_fp64_max_rel_err"] = err
+    res["workload"] = f"{wl.name}: one BR evaluation, synthetic vorticity, {wl.n} points"
+    return res
 
 
 def oracle_threads() -> int:
@@ -142,12 +183,12 @@ def main():
     import paper_2406_05490_amd as zm
 
     wl = rr.WORKLOADS[args.workload]
-    if wl.precision != "fp64":
-        raise SystemExit(f"{wl.name}: precision {wl.precision} is not provided by this build")
+    prec = zm.ZM_FP32_PAIRS if wl.precision == "fp32_pairs" else zm.ZM_FP64
     steps = wl.steps if args.steps is None else args.steps
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    p = zm.Params(wl.n1, wl.n2, eps=wl.eps, atwood=wl.atwood, gravity=wl.gravity, dt=wl.dt)
+    p = zm.Params(wl.n1, wl.n2, eps=wl.eps, atwood=wl.atwood, gravity=wl.gravity, dt=wl.dt,
+                  precision=prec)
     z0, w0 = wl.state()
     zd = torch.from_numpy(z0.ravel()).to(dev)
     wd = torch.from_numpy(w0.ravel()).to(dev)
@@ -193,7 +234,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if prec == zm.ZM_FP64 else "f32",
         "data": "synthetic",
         "config": {
             "workload": wl.name, "mesh": f"{wl.n1}x{wl.n2}", "points": wl.n,
@@ -203,7 +244,7 @@ def main():
             "source_splits": info.source_splits, "targets_per_lane": info.targets_per_lane,
         },
         "roofline": {
-            "kernel": "k_pairs_f64", "bound": "alu", "achieved": achieved, "peak": peak,
+            "kernel": "k_pairs_f64" if prec == zm.ZM_FP64 else "k_pairs_f32", "bound": "alu", "achieved": achieved, "peak": peak,
             "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,
             "flops_per_pair": FLOPS_PER_PAIR, "pairs_per_launch": info.pairs_per_eval,
             "avg_launch_ms": avg_pair_s * 1e3, "launches": launches,
@@ -212,6 +253,8 @@ def main():
         "pair_kernel_share": pair_ms / 1e3 / elapsed,
     }
 
+    if not args.no_sweep:
+        out["br_sweep_1m"] = br_sweep_1m(zm, torch)
     if args.cpu_seconds > 0:
         out["cpu_baseline"] = cpu_baseline(wl, lambda: zm.Context(p), z0, w0, args.cpu_seconds)
     print(json.dumps(out), flush=True)

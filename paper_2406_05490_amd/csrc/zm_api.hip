@@ -180,8 +180,11 @@ zm_status eval_velocity(zm_ctx* c, const double* z, const double* w, double* u, 
     hipError_t e;
     e = timed(c, ZM_KERNEL_SURFACE, [&] { return zm::launch_surface(m, z, w, gam, q, c->stream); });
     if (e != hipSuccess) return hip_fail(c, e, "surface kernel launch");
-    e = timed(c, ZM_KERNEL_PAIRS,
-              [&] { return zm::launch_pairs_f64(m, c->shape, z, gam, part, c->stream); });
+    e = timed(c, ZM_KERNEL_PAIRS, [&] {
+        return c->prm.precision == ZM_FP32_PAIRS
+                   ? zm::launch_pairs_f32(m, c->shape, z, gam, part, c->stream)
+                   : zm::launch_pairs_f64(m, c->shape, z, gam, part, c->stream);
+    });
     if (e != hipSuccess) return hip_fail(c, e, "pair kernel launch");
     if ((m.n1 % 2) == 0 || (m.n2 % 2) == 0) {
         e = timed(c, ZM_KERNEL_TIES, [&] { return zm::launch_ties(m, z, gam, tie, c->stream); });
@@ -212,10 +215,6 @@ zm_status zm_create(zm_ctx** out, const zm_params* params, void* d_workspace,
     if (!out) { g_create_error = "out is NULL"; return ZM_ERR_INVALID_ARG; }
     *out = nullptr;
     if (const char* why = validate(params)) { g_create_error = why; return ZM_ERR_INVALID_ARG; }
-    if (params->precision == ZM_FP32_PAIRS) {
-        g_create_error = "ZM_FP32_PAIRS is not provided by this build";
-        return ZM_ERR_UNSUPPORTED;
-    }
     const zm::PairShape sh = zm::choose_pair_shape(params->n1, params->n2, params->precision);
     const Layout L = make_layout(*params, sh);
     if (!d_workspace || !aligned(d_workspace)) {

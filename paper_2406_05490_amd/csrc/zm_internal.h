@@ -41,6 +41,11 @@ hipError_t launch_surface(const Mesh& m, const double* z, const double* w,
 hipError_t launch_pairs_f64(const Mesh& m, const PairShape& sh, const double* z,
                             const double* gam, double* part, hipStream_t s);
 
+// Same contract, pair terms in FP32 with tile-relative coordinates and FP64
+// per-target sums.
+hipError_t launch_pairs_f32(const Mesh& m, const PairShape& sh, const double* z,
+                            const double* gam, double* part, hipStream_t s);
+
 // tie[pass][3][N]: pass 0 (n1 even) corrects the tie column, pass 1 (n2 even)
 // the tie row, so that tied sources end with weight 1/2 per end image.
 hipError_t launch_ties(const Mesh& m, const double* z, const double* gam, double* tie,

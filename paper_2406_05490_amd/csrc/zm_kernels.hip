@@ -34,6 +34,9 @@ constexpr int kThreads = 256;
 #ifndef ZM_PAIR_R
 #define ZM_PAIR_R 4
 #endif
+#ifndef ZM_PAIR32_R
+#define ZM_PAIR32_R 4
+#endif
 
 // Periodic neighbour index along one axis; sets wrap to -1/0/+1.
 __device__ __forceinline__ int nbr(int i, int d, int n, int& wrap)
@@ -358,6 +361,245 @@ __global__ __launch_bounds__(kThreads) void k_pairs_f64(Mesh m, PairShape sh,
 }
 
 // ---------------------------------------------------------------------------
+// all-pairs BR sweep, FP32 pair arithmetic, FP64 per-target sums
+// ---------------------------------------------------------------------------
+//
+// Coordinates are tile-relative: the workgroup takes the FP64 position c of
+// a target near the middle of its patch, and every staged source is stored
+// as the FP32 rounding of (z_j + S_c(j) L - c), where S_c(j) is the source's
+// periodic image seen from that centre target.  Near pairs therefore
+// subtract small numbers (error ~ ulp of the patch extent, not of the
+// domain).  A lane's own image differs from the centre's only for sources in
+// the antipodal band (columns / rows where some patch target's image
+// breakpoint lies); there the difference (a whole period) is added per
+// source.  Pair terms and per-row partial sums are FP32; every row's partial
+// is added into FP64 per-target accumulators.
+
+#ifndef ZM_PAIR32_UNROLL
+#define ZM_PAIR32_UNROLL 2
+#endif
+
+template <int R, bool BAND>
+__device__ __forceinline__ void pair_segment_f32(const float4* __restrict__ p0,
+                                                 const float2* __restrict__ p1, int k0, int cnt,
+                                                 int j1s, int b1, int s1lo, int bc1, int sc1lo,
+                                                 float L1, float dm1, const float* ax,
+                                                 const float* ay, const float* az, float eps2,
+                                                 float (*sa)[3])
+{
+#pragma unroll ZM_PAIR32_UNROLL
+    for (int c = 0; c < cnt; ++c) {
+        const float4 v0 = p0[k0 + c];
+        const float2 v1 = p1[k0 + c];
+        float bx = v0.x;
+        if (BAND) {
+            const int jj = j1s + c;
+            const int si = (jj < b1) ? s1lo : s1lo - 1;
+            const int sc = (jj < bc1) ? sc1lo : sc1lo - 1;
+            bx = fmaf((float)(si - sc), L1, bx) + dm1;
+        }
+        const float by = v0.y, bz = v0.z;
+        const float g1 = v0.w, g2 = v1.x, g3 = v1.y;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const float r1 = ax[r] - bx;
+            const float r2 = ay[r] - by;
+            const float r3 = az[r] - bz;
+            const float s = fmaf(r1, r1, fmaf(r2, r2, fmaf(r3, r3, eps2)));
+            const float y = __builtin_amdgcn_rsqf(s);
+            const float wgt = y * y * y;
+            const float a1 = wgt * g1, a2 = wgt * g2, a3 = wgt * g3;
+            sa[r][0] = fmaf(r2, a3, sa[r][0]);
+            sa[r][0] = fmaf(-r3, a2, sa[r][0]);
+            sa[r][1] = fmaf(r3, a1, sa[r][1]);
+            sa[r][1] = fmaf(-r1, a3, sa[r][1]);
+            sa[r][2] = fmaf(r1, a2, sa[r][2]);
+            sa[r][2] = fmaf(-r2, a1, sa[r][2]);
+        }
+    }
+}
+
+// Workgroup = target patch of PX columns x (256/PX)*R rows (lane = one
+// column, R rows 256/PX apart) x one range of source rows.
+template <int R, int PX>
+__global__ __launch_bounds__(kThreads) void k_pairs_f32(Mesh m, PairShape sh,
+                                                        const double* __restrict__ z,
+                                                        const double* __restrict__ gam,
+                                                        double* __restrict__ part)
+{
+    constexpr int RY = kThreads / PX;
+    constexpr int PY = RY * R;
+    __shared__ float4 lds0[2][kThreads];   // (x, y, z, g1) relative to the patch centre
+    __shared__ float2 lds1[2][kThreads];   // (g2, g3)
+
+    const int N = m.N, n1 = m.n1, n2 = m.n2;
+    const int tid = threadIdx.x;
+    const int patch = blockIdx.x;
+    const int split = blockIdx.y;
+    const int ptx = patch % sh.px;
+    const int pty = patch / sh.px;
+    const int row_begin = split * sh.rows_per_split;
+    const int row_end = min(n2, row_begin + sh.rows_per_split);
+    if (row_begin >= row_end) return;  // uniform over the workgroup
+
+    // ---- patch centre ----------------------------------------------------
+    const int c0 = ptx * PX, r0 = pty * PY;
+    const int ci1 = min(c0 + PX / 2, n1 - 1), ci2 = min(r0 + PY / 2, n2 - 1);
+    const int pc = ci2 * n1 + ci1;
+    const double cx = z[pc], cy = z[N + pc], cz = z[2 * N + pc];
+    const AxisImg cimg1 = axis_img(ci1, n1), cimg2 = axis_img(ci2, n2);
+    // antipodal band along axis 1: breakpoints of columns c0 .. c0+PX-1
+    const int band_lo = axis_img(c0, n1).b;
+    const bool band_all = PX >= n1;
+    const bool band_wraps = band_lo + PX > n1;
+
+    // ---- targets of this lane --------------------------------------------
+    const int col = c0 + (tid % PX);
+    const int rowg = tid / PX;
+    const bool col_ok = col < n1;
+    const int i1 = col_ok ? col : ci1;
+    const AxisImg ax1 = axis_img(i1, n1);
+    float ax[R], az[R], ay[R];
+    double ayd[R];
+    int b2[R], s2lo[R], pidx[R];
+    bool valid[R];
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        const int r = r0 + rowg + RY * k;
+        valid[k] = col_ok && (r < n2);
+        const int i2 = (r < n2) ? r : ci2;
+        pidx[k] = i2 * n1 + i1;
+        ax[k] = (float)(z[pidx[k]] - cx);
+        ayd[k] = z[N + pidx[k]] - cy;
+        az[k] = (float)(z[2 * N + pidx[k]] - cz);
+        ay[k] = (float)ayd[k];
+        const AxisImg a2 = axis_img(i2, n2);
+        b2[k] = a2.b;
+        s2lo[k] = a2.s_lo;
+    }
+    double acc[R][3];
+#pragma unroll
+    for (int k = 0; k < R; ++k) acc[k][0] = acc[k][1] = acc[k][2] = 0.0;
+
+    const int src_begin = row_begin * n1;
+    const int src_end = row_end * n1;
+    const int ntiles = (src_end - src_begin + kThreads - 1) / kThreads;
+    const int side = 2 * m.K + 1;
+    const int total = ntiles * side * side;
+    const float L1f = (float)m.L1;
+    const float eps2f = (float)m.eps2;
+
+    // ---- staging: source j relative to the centre, centre's image --------
+    float4 st0;
+    float2 st1;
+    auto load_tile = [&](int t) {
+        const int tile = t % ntiles;
+        const int j = src_begin + tile * kThreads + tid;
+        if (j < src_end) {
+            const int j2 = j / n1, j1 = j - j2 * n1;
+            const int sc1 = (j1 < cimg1.b) ? cimg1.s_lo : cimg1.s_lo - 1;
+            const int sc2 = (j2 < cimg2.b) ? cimg2.s_lo : cimg2.s_lo - 1;
+            st0 = make_float4((float)((z[j] + (double)sc1 * m.L1) - cx),
+                              (float)((z[N + j] + (double)sc2 * m.L2) - cy),
+                              (float)(z[2 * N + j] - cz), (float)gam[j]);
+            st1 = make_float2((float)gam[N + j], (float)gam[2 * N + j]);
+        } else {
+            st0 = make_float4(0.f, 0.f, 0.f, 0.f);
+            st1 = make_float2(0.f, 0.f);
+        }
+    };
+    auto store_tile = [&](int buf) {
+        lds0[buf][tid] = st0;
+        lds1[buf][tid] = st1;
+    };
+
+    load_tile(0);
+    store_tile(0);
+    __syncthreads();
+
+    for (int t = 0; t < total; ++t) {
+        const int buf = t & 1;
+        if (t + 1 < total) load_tile(t + 1);
+        const int img = t / ntiles;
+        const int tile = t - img * ntiles;
+        const int m1 = img % side - m.K;
+        const int m2 = img / side - m.K;
+        // extra image layers shift every source by (m1 L1, m2 L2)
+        const float dm1 = (float)((double)m1 * m.L1);
+
+        const int j0 = src_begin + tile * kThreads;
+        const int cnt = min(kThreads, src_end - j0);
+        int j2 = j0 / n1;
+        int j1 = j0 - j2 * n1;
+        int k = 0;
+        while (k < cnt) {
+            const int seg = min(cnt - k, n1 - j1);
+            const int sc2 = (j2 < cimg2.b) ? cimg2.s_lo : cimg2.s_lo - 1;
+            float ayr[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const int s2 = (j2 < b2[r]) ? s2lo[r] : s2lo[r] - 1;
+                ayr[r] = (float)(ayd[r] - (double)(s2 - sc2 + m2) * m.L2);
+            }
+            float sa[R][3];
+#pragma unroll
+            for (int r = 0; r < R; ++r) sa[r][0] = sa[r][1] = sa[r][2] = 0.f;
+
+            int a = j1;
+            const int e = j1 + seg;
+            while (a < e) {
+                bool in_band;
+                int stop;
+                if (band_all) {
+                    in_band = true; stop = e;
+                } else if (!band_wraps) {
+                    if (a < band_lo) { in_band = false; stop = min(e, band_lo); }
+                    else if (a < band_lo + PX) { in_band = true; stop = min(e, band_lo + PX); }
+                    else { in_band = false; stop = e; }
+                } else {
+                    const int hi_end = band_lo + PX - n1;
+                    if (a < hi_end) { in_band = true; stop = min(e, hi_end); }
+                    else if (a < band_lo) { in_band = false; stop = min(e, band_lo); }
+                    else { in_band = true; stop = e; }
+                }
+                const int kk = k + (a - j1);
+                if (in_band || m1 != 0) {
+                    pair_segment_f32<R, true>(lds0[buf], lds1[buf], kk, stop - a, a, ax1.b,
+                                              ax1.s_lo, cimg1.b, cimg1.s_lo, L1f, dm1, ax, ayr, az,
+                                              eps2f, sa);
+                } else {
+                    pair_segment_f32<R, false>(lds0[buf], lds1[buf], kk, stop - a, a, ax1.b,
+                                               ax1.s_lo, cimg1.b, cimg1.s_lo, L1f, dm1, ax, ayr,
+                                               az, eps2f, sa);
+                }
+                a = stop;
+            }
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                acc[r][0] += (double)sa[r][0];
+                acc[r][1] += (double)sa[r][1];
+                acc[r][2] += (double)sa[r][2];
+            }
+            k += seg;
+            j1 += seg;
+            if (j1 == n1) { j1 = 0; ++j2; }
+        }
+        if (t + 1 < total) store_tile(buf ^ 1);
+        __syncthreads();
+    }
+
+    double* out = part + (size_t)split * 3 * N;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        if (valid[r]) {
+            out[pidx[r]] = acc[r][0];
+            out[N + pidx[r]] = acc[r][1];
+            out[2 * N + pidx[r]] = acc[r][2];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // split-tie correction
 // ---------------------------------------------------------------------------
 
@@ -551,10 +793,15 @@ inline unsigned blocks_for(int n) { return (unsigned)((n + kThreads - 1) / kThre
 
 PairShape choose_pair_shape(int n1, int n2, int precision)
 {
-    (void)precision;
     PairShape sh;
-    sh.R = ZM_PAIR_R;
-    sh.cx = (n1 >= 16) ? 16 : 8;
+    if (precision == 1) {
+        // FP32 pairs: compact patches keep tile-relative coordinates small
+        sh.R = ZM_PAIR32_R;
+        sh.cx = (n1 >= 32) ? 32 : (n1 >= 16 ? 16 : 8);
+    } else {
+        sh.R = ZM_PAIR_R;
+        sh.cx = (n1 >= 16) ? 16 : 8;
+    }
     sh.prow = (kThreads / sh.cx) * sh.R;
     sh.px = (n1 + sh.cx - 1) / sh.cx;
     sh.py = (n2 + sh.prow - 1) / sh.prow;
@@ -585,6 +832,22 @@ hipError_t launch_pairs_f64(const Mesh& m, const PairShape& sh, const double* z,
         hipLaunchKernelGGL((k_pairs_f64<R, 16>), grid, dim3(kThreads), 0, s, m, sh, z, gam, part);
     else if (sh.R == R && sh.cx == 8)
         hipLaunchKernelGGL((k_pairs_f64<R, 8>), grid, dim3(kThreads), 0, s, m, sh, z, gam, part);
+    else
+        return hipErrorInvalidConfiguration;
+    return hipGetLastError();
+}
+
+hipError_t launch_pairs_f32(const Mesh& m, const PairShape& sh, const double* z,
+                            const double* gam, double* part, hipStream_t s)
+{
+    const dim3 grid((unsigned)(sh.px * sh.py), (unsigned)sh.splits);
+    constexpr int R = ZM_PAIR32_R;
+    if (sh.R == R && sh.cx == 32)
+        hipLaunchKernelGGL((k_pairs_f32<R, 32>), grid, dim3(kThreads), 0, s, m, sh, z, gam, part);
+    else if (sh.R == R && sh.cx == 16)
+        hipLaunchKernelGGL((k_pairs_f32<R, 16>), grid, dim3(kThreads), 0, s, m, sh, z, gam, part);
+    else if (sh.R == R && sh.cx == 8)
+        hipLaunchKernelGGL((k_pairs_f32<R, 8>), grid, dim3(kThreads), 0, s, m, sh, z, gam, part);
     else
         return hipErrorInvalidConfiguration;
     return hipGetLastError();

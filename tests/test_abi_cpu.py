@@ -89,12 +89,6 @@ def test_create_rejects_missing_or_small_workspace():
     assert st == zm.ZM_ERR_WORKSPACE and "smaller" in msg
 
 
-def test_create_reports_fp32_pairs_unsupported():
-    p = zm.Params(16, 16, eps=1 / 16, precision=zm.ZM_FP32_PAIRS)
-    st, h, msg = _create(p, 4096, zm.workspace_bytes(p))
-    assert st == zm.ZM_ERR_UNSUPPORTED
-
-
 def test_null_context_calls_are_rejected():
     lib = zm.load()
     assert lib.zm_step(None, 1) == zm.ZM_ERR_INVALID_ARG
