@@ -98,6 +98,56 @@ def br_sweep_1m(zm, torch, reps: int = 2):
     return res
 
 
+def ensemble64(zm, torch, steps: int = 20):
+    """The 64-member uneven ensemble (sides 32..256, FP32 form) advanced by
+    one batch with graph-captured RK3 steps: aggregate pair-interactions/s."""
+    ms = rr.ensemble(64, seed=3)
+    ps = [zm.Params(m.n, m.n, eps=m.eps, atwood=m.atwood, gravity=1.0, dt=1e-3,
+                    precision=zm.ZM_FP32_PAIRS) for m in ms]
+    b = zm.Batch(ps, flags=zm.ZM_FLAG_GRAPH)
+    dev = torch.device("cuda:0")
+    for i, m in enumerate(ms):
+        z, w = m.state()
+        b.init_state(i, torch.from_numpy(z.ravel()).to(dev), torch.from_numpy(w.ravel()).to(dev))
+    b.step(1)                                   # capture + warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.step(steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    info = b.info()
+    b.destroy()
+    return {"members": 64, "sides": sorted({m.n for m in ms}), "steps": steps,
+            "pairs_per_step": info.pairs_per_step, "work_items": info.work_items[1],
+            "persistent_groups": info.persistent_groups, "seconds": dt,
+            "pairs_per_s": info.pairs_per_step * steps / dt,
+            "tflops": FLOPS_PER_PAIR * info.pairs_per_step * steps / dt / 1e12,
+            "frac_of_fp32_peak": FLOPS_PER_PAIR * info.pairs_per_step * steps / dt / 1e12 / 157.3}
+
+
+def small_mesh_latency(zm, torch, steps: int = 50):
+    """64 x 64 FP64 (launch-latency bound): ms per RK3 step with direct
+    launches and with the captured graph."""
+    wl = rr.WORKLOADS["periodic64_single_fp64"]
+    z, w = wl.state()
+    dev = torch.device("cuda:0")
+    out = {}
+    for name, flags in (("direct", 0), ("graph", zm.ZM_FLAG_GRAPH)):
+        p = zm.Params(wl.n1, wl.n2, eps=wl.eps, atwood=wl.atwood, gravity=wl.gravity, dt=wl.dt,
+                      flags=flags)
+        ctx = zm.Context(p)
+        ctx.init_state(torch.from_numpy(z.ravel()).to(dev), torch.from_numpy(w.ravel()).to(dev))
+        ctx.step(2)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.step(steps)
+        torch.cuda.synchronize()
+        out[name + "_ms_per_step"] = (time.perf_counter() - t0) / steps * 1e3
+        del ctx
+    out["pairs_per_s_graph"] = 3 * wl.n * wl.n / (out["graph_ms_per_step"] / 1e3)
+    return out
+
+
 def oracle_threads() -> int:
     return int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or os.cpu_count()
 
@@ -255,6 +305,8 @@ def main():
 
     if not args.no_sweep:
         out["br_sweep_1m"] = br_sweep_1m(zm, torch)
+        out["ensemble64_fp32_graph"] = ensemble64(zm, torch)
+        out["periodic64_latency"] = small_mesh_latency(zm, torch)
     if args.cpu_seconds > 0:
         out["cpu_baseline"] = cpu_baseline(wl, lambda: zm.Context(p), z0, w0, args.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -74,13 +74,17 @@ typedef int32_t zm_status;
 
 /* ---- precision of the pair interactions ---------------------------------- */
 #define ZM_FP64        0  /* all arithmetic in float64                          */
-#define ZM_FP32_PAIRS  1  /* pair terms in float32, per-target sums, state and
-                             RK3 in float64 (reserved: not yet provided)        */
+#define ZM_FP32_PAIRS  1  /* pair terms in float32 on tile-relative coordinates;
+                             per-target sums, state, ties and RK3 in float64   */
 
 /* ---- flags ---------------------------------------------------------------- */
 #define ZM_FLAG_CHECK_FINITE 0x1u /* zm_step checks the state after each call
                                      and returns ZM_ERR_NONFINITE (this makes
                                      zm_step wait for its own work)            */
+#define ZM_FLAG_GRAPH        0x2u /* zm_step captures one RK3 step into a HIP
+                                     graph on first use and replays it (per-
+                                     kernel timing, when enabled, uses the
+                                     direct launches instead)                  */
 
 /* ---- parameters ------------------------------------------------------------ */
 typedef struct zm_params {
@@ -177,6 +181,58 @@ zm_status zm_profile_enable(zm_ctx *ctx, int32_t on);
 /* Wait for the timed launches, write ZM_KERNEL_COUNT entries to out (indexed
  * by ZM_KERNEL_*) and reset the counters. */
 zm_status zm_profile_read(zm_ctx *ctx, zm_kernel_stats *out);
+
+/* ---- batched ensemble ---------------------------------------------------- */
+/*
+ * A batch advances `count` independent instances (each with its own mesh
+ * size and parameters, one entry of `params`) with one set of launches per
+ * RK3 stage: point kernels over all instances' points, and one persistent
+ * pair launch per precision whose workgroups take (instance, target patch,
+ * source split) items from a device work list ordered longest first.  Each
+ * item runs exactly the arithmetic of the single-instance context with the
+ * same parameters, so every instance's result is bitwise identical to a solo
+ * zm_step.  Same ownership rules as the single-instance API: the caller
+ * provides the workspace, the library never allocates device memory.
+ */
+typedef struct zm_batch zm_batch;  /* opaque */
+
+typedef struct zm_batch_info {
+    int32_t count;              /* instances                                   */
+    int32_t work_items[2];      /* pair work items: [0] FP64, [1] FP32 pairs   */
+    int32_t persistent_groups;  /* workgroups of one persistent pair launch    */
+    int64_t pairs_per_step;     /* sum over instances of 3 N^2 (2K+1)^2        */
+} zm_batch_info;
+
+/* Workspace bytes for a batch of `count` instances (0 if any entry of params
+ * is invalid or count < 1). */
+size_t zm_batch_workspace_bytes(const zm_params *params, int32_t count);
+
+/* Create a batch on the current device.  params: `count` parameter sets
+ * (copied).  batch_flags: ZM_FLAG_GRAPH and/or ZM_FLAG_CHECK_FINITE (the
+ * per-instance params.flags must be 0).  Workspace and stream as for
+ * zm_create.  Uploads the descriptor table and work list (waits for the
+ * stream once).  On failure *out is NULL and zm_batch_last_error(NULL) says
+ * why. */
+zm_status zm_batch_create(zm_batch **out, const zm_params *params, int32_t count,
+                          uint32_t batch_flags, void *d_workspace, size_t workspace_bytes,
+                          void *hip_stream);
+
+/* Copy a state into / out of instance `index` (0 <= index < count); planes
+ * of that instance's N points, as for zm_init_state / zm_get_state. */
+zm_status zm_batch_init_state(zm_batch *b, int32_t index, const double *d_z, const double *d_w);
+zm_status zm_batch_get_state(zm_batch *b, int32_t index, double *d_z, double *d_w);
+
+/* Advance every instance by nsteps >= 0 RK3 steps. */
+zm_status zm_batch_step(zm_batch *b, int32_t nsteps);
+
+zm_status zm_batch_get_info(const zm_batch *b, zm_batch_info *out);
+
+/* Wait for outstanding work and release host resources (NULL accepted). */
+zm_status zm_batch_destroy(zm_batch *b);
+
+/* Last error of this batch ("" if none; NULL: last failed zm_batch_create
+ * on this thread). */
+const char *zm_batch_last_error(const zm_batch *b);
 
 /* Interface version (incremented on any ABI change). */
 int32_t zm_abi_version(void);

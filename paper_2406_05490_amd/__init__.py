@@ -6,7 +6,8 @@ binding.  Importing it loads the library and fails loudly if it has not been
 built -- there is no CPU fallback.
 """
 from ._zm import (  # noqa: F401
-    EXPORTS, KERNELS, LIB_PATH, Context, Params, ZMError,
+    EXPORTS, KERNELS, LIB_PATH, Batch, Context, Params, ZMError, batch_workspace_bytes,
+    ZM_FLAG_GRAPH,
     ZM_ERR_CAPACITY, ZM_ERR_HIP, ZM_ERR_INVALID_ARG, ZM_ERR_NONFINITE,
     ZM_ERR_UNSUPPORTED, ZM_ERR_WORKSPACE, ZM_FLAG_CHECK_FINITE, ZM_FP32_PAIRS,
     ZM_FP64, ZM_OK, load, status_string, workspace_bytes,

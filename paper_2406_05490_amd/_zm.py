@@ -24,6 +24,7 @@ ZM_ERR_CAPACITY = -6
 ZM_FP64 = 0
 ZM_FP32_PAIRS = 1
 ZM_FLAG_CHECK_FINITE = 0x1
+ZM_FLAG_GRAPH = 0x2
 
 KERNELS = ("surface", "pairs", "ties", "reduce", "update")
 
@@ -58,11 +59,19 @@ class zm_kernel_stats(ctypes.Structure):
     _fields_ = [("launches", ctypes.c_int64), ("total_ms", ctypes.c_double)]
 
 
+class zm_batch_info(ctypes.Structure):
+    _fields_ = [("count", ctypes.c_int32), ("work_items", ctypes.c_int32 * 2),
+                ("persistent_groups", ctypes.c_int32), ("pairs_per_step", ctypes.c_int64)]
+
+
 # names declared in include/zm.h, in order
 EXPORTS = (
     "zm_workspace_bytes", "zm_create", "zm_init_state", "zm_br_velocity", "zm_rhs",
     "zm_step", "zm_get_state", "zm_destroy", "zm_status_string", "zm_last_error",
-    "zm_get_launch_info", "zm_profile_enable", "zm_profile_read", "zm_abi_version",
+    "zm_get_launch_info", "zm_profile_enable", "zm_profile_read",
+    "zm_batch_workspace_bytes", "zm_batch_create", "zm_batch_init_state", "zm_batch_get_state",
+    "zm_batch_step", "zm_batch_get_info", "zm_batch_destroy", "zm_batch_last_error",
+    "zm_abi_version",
 )
 
 _lib = None
@@ -110,6 +119,23 @@ def load(path: str = LIB_PATH):
     lib.zm_profile_enable.restype = ctypes.c_int32
     lib.zm_profile_read.argtypes = [vp, ctypes.POINTER(zm_kernel_stats)]
     lib.zm_profile_read.restype = ctypes.c_int32
+    lib.zm_batch_workspace_bytes.argtypes = [P, ctypes.c_int32]
+    lib.zm_batch_workspace_bytes.restype = ctypes.c_size_t
+    lib.zm_batch_create.argtypes = [ctypes.POINTER(vp), P, ctypes.c_int32, ctypes.c_uint32, vp,
+                                    ctypes.c_size_t, vp]
+    lib.zm_batch_create.restype = ctypes.c_int32
+    lib.zm_batch_init_state.argtypes = [vp, ctypes.c_int32, vp, vp]
+    lib.zm_batch_init_state.restype = ctypes.c_int32
+    lib.zm_batch_get_state.argtypes = [vp, ctypes.c_int32, vp, vp]
+    lib.zm_batch_get_state.restype = ctypes.c_int32
+    lib.zm_batch_step.argtypes = [vp, ctypes.c_int32]
+    lib.zm_batch_step.restype = ctypes.c_int32
+    lib.zm_batch_get_info.argtypes = [vp, ctypes.POINTER(zm_batch_info)]
+    lib.zm_batch_get_info.restype = ctypes.c_int32
+    lib.zm_batch_destroy.argtypes = [vp]
+    lib.zm_batch_destroy.restype = ctypes.c_int32
+    lib.zm_batch_last_error.argtypes = [vp]
+    lib.zm_batch_last_error.restype = ctypes.c_char_p
     lib.zm_abi_version.argtypes = []
     lib.zm_abi_version.restype = ctypes.c_int32
     _lib = lib
@@ -225,6 +251,76 @@ class Context:
             self.handle = None
             if st != ZM_OK:
                 raise ZMError(st, "destroy")
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+def _params_array(ps):
+    arr = (zm_params * len(ps))()
+    for i, p in enumerate(ps):
+        arr[i] = p.c()
+    return arr
+
+
+def batch_workspace_bytes(ps) -> int:
+    return int(load().zm_batch_workspace_bytes(_params_array(ps), len(ps)))
+
+
+class Batch:
+    """One zm_batch: many independent instances advanced together."""
+
+    def __init__(self, ps, flags: int = 0, stream=None, device=None):
+        import torch
+        self.lib = load()
+        self.params = list(ps)
+        dev = torch.device("cuda", torch.cuda.current_device()) if device is None else device
+        arr = _params_array(self.params)
+        nbytes = int(self.lib.zm_batch_workspace_bytes(arr, len(self.params)))
+        if nbytes == 0:
+            raise ZMError(ZM_ERR_INVALID_ARG, "invalid batch parameters")
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+        self.stream = torch.cuda.current_stream(dev) if stream is None else stream
+        h = ctypes.c_void_p()
+        with torch.cuda.device(dev):
+            st = self.lib.zm_batch_create(ctypes.byref(h), arr, len(self.params), int(flags),
+                                          self.workspace.data_ptr(), nbytes,
+                                          self.stream.cuda_stream)
+        if st != ZM_OK:
+            raise ZMError(st, self.lib.zm_batch_last_error(None).decode())
+        self.handle = h
+
+    def _raise(self, st):
+        if st != ZM_OK:
+            raise ZMError(st, self.lib.zm_batch_last_error(self.handle).decode())
+
+    def init_state(self, i: int, z, w):
+        n = self.params[i].n
+        _check_f64_planes(z, 3, n, "z"); _check_f64_planes(w, 2, n, "w")
+        self._raise(self.lib.zm_batch_init_state(self.handle, int(i), _ptr(z), _ptr(w)))
+
+    def get_state(self, i: int, z, w):
+        n = self.params[i].n
+        _check_f64_planes(z, 3, n, "z"); _check_f64_planes(w, 2, n, "w")
+        self._raise(self.lib.zm_batch_get_state(self.handle, int(i), _ptr(z), _ptr(w)))
+
+    def step(self, nsteps: int):
+        self._raise(self.lib.zm_batch_step(self.handle, int(nsteps)))
+
+    def info(self) -> zm_batch_info:
+        out = zm_batch_info()
+        self._raise(self.lib.zm_batch_get_info(self.handle, ctypes.byref(out)))
+        return out
+
+    def destroy(self):
+        if getattr(self, "handle", None) is not None:
+            st = self.lib.zm_batch_destroy(self.handle)
+            self.handle = None
+            if st != ZM_OK:
+                raise ZMError(st, "batch destroy")
 
     def __del__(self):
         try:

@@ -15,7 +15,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libzm.so")
-SOURCES = [os.path.join(CSRC, "zm_kernels.hip"), os.path.join(CSRC, "zm_api.hip")]
+SOURCES = [os.path.join(CSRC, f) for f in
+           ("zm_kernels.hip", "zm_batch.hip", "zm_api.hip", "zm_batch_api.hip")]
 ARCH = "gfx950"
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

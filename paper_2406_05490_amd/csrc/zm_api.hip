@@ -5,6 +5,7 @@
 // kernel sequence on the caller's stream.  Per derivative evaluation:
 //   k_surface -> k_pairs -> [k_ties] -> k_reduce -> k_update
 #include "zm.h"
+#include "zm_host.h"
 #include "zm_internal.h"
 
 #include <hip/hip_runtime.h>
@@ -17,64 +18,14 @@
 #include <string>
 #include <vector>
 
+using zm::Layout;
+using zm::aligned;
+using zm::DeviceGuard;
+using zm::make_layout;
+using zm::overlaps;
+using zm::validate;
+
 namespace {
-
-constexpr size_t kAlign = 256;
-constexpr int kMaxSide = 16384;
-constexpr int kMaxImages = 16;
-
-size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
-
-// Workspace regions, all 256-byte aligned, in bytes from the base.
-struct Layout {
-    size_t y0, y1, y2;   // 5N doubles each (z1 z2 z3 w1 w2)
-    size_t gam, q;       // 3N, N
-    size_t part;         // splits * 3N
-    size_t tie;          // 6N
-    size_t u, V;         // 3N, N
-    size_t flag;         // one int
-    size_t total;
-};
-
-Layout make_layout(const zm_params& p, const zm::PairShape& sh)
-{
-    const size_t N = (size_t)p.n1 * (size_t)p.n2;
-    const size_t d = sizeof(double);
-    Layout L;
-    size_t o = 0;
-    auto take = [&](size_t bytes) { size_t at = o; o = align_up(o + bytes); return at; };
-    L.y0 = take(5 * N * d);
-    L.y1 = take(5 * N * d);
-    L.y2 = take(5 * N * d);
-    L.gam = take(3 * N * d);
-    L.q = take(N * d);
-    L.part = take((size_t)sh.splits * 3 * N * d);
-    L.tie = take(6 * N * d);
-    L.u = take(3 * N * d);
-    L.V = take(N * d);
-    L.flag = take(sizeof(int));
-    L.total = o;
-    return L;
-}
-
-const char* validate(const zm_params* p)
-{
-    if (!p) return "params is NULL";
-    if (p->n1 < 8 || p->n2 < 8) return "n1 and n2 must be >= 8";
-    if (p->n1 > kMaxSide || p->n2 > kMaxSide) return "n1 and n2 must be <= 16384";
-    if (!(std::isfinite(p->period1) && p->period1 > 0.0)) return "period1 must be finite and > 0";
-    if (!(std::isfinite(p->period2) && p->period2 > 0.0)) return "period2 must be finite and > 0";
-    if (!(std::isfinite(p->eps) && p->eps > 0.0)) return "eps must be finite and > 0";
-    if (!(std::isfinite(p->dt) && p->dt > 0.0)) return "dt must be finite and > 0";
-    if (!(std::isfinite(p->nu) && p->nu >= 0.0)) return "nu must be finite and >= 0";
-    if (!std::isfinite(p->atwood)) return "atwood must be finite";
-    if (!std::isfinite(p->gravity)) return "gravity must be finite";
-    if (p->precision != ZM_FP64 && p->precision != ZM_FP32_PAIRS) return "unknown precision";
-    if (p->image_layers < 0 || p->image_layers > kMaxImages) return "image_layers must be in [0, 16]";
-    if (p->flags & ~ZM_FLAG_CHECK_FINITE) return "unknown flag bits";
-    if (p->reserved != 0) return "reserved must be 0";
-    return nullptr;
-}
 
 thread_local std::string g_create_error;
 
@@ -98,6 +49,8 @@ struct zm_ctx {
     std::vector<Timed> pending;
     std::vector<hipEvent_t> spare;
     zm_kernel_stats stats[ZM_KERNEL_COUNT];
+    hipStream_t capture_stream = nullptr;   // graph capture (non-blocking, default priority)
+    hipGraphExec_t graph = nullptr;         // one captured RK3 step
 
     double* at(size_t off) { return reinterpret_cast<double*>(ws + off); }
     size_t N() const { return (size_t)mesh.N; }
@@ -115,30 +68,6 @@ zm_status hip_fail(zm_ctx* c, hipError_t e, const char* where)
 {
     return fail(c, ZM_ERR_HIP, std::string(where) + ": " + hipGetErrorString(e));
 }
-
-bool aligned(const void* p) { return p && ((uintptr_t)p % kAlign) == 0; }
-
-bool overlaps(const void* a, size_t na, const void* b, size_t nb)
-{
-    const uintptr_t x = (uintptr_t)a, y = (uintptr_t)b;
-    return x < y + nb && y < x + na;
-}
-
-// Makes the context's device current for the duration of a call.
-struct DeviceGuard {
-    int prev = -1;
-    bool ok = true;
-    explicit DeviceGuard(int dev)
-    {
-        if (hipGetDevice(&prev) != hipSuccess) { ok = false; return; }
-        if (prev != dev && hipSetDevice(dev) != hipSuccess) ok = false;
-    }
-    ~DeviceGuard()
-    {
-        int cur;
-        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
-    }
-};
 
 hipEvent_t get_event(zm_ctx* c)
 {
@@ -170,7 +99,8 @@ hipError_t timed(zm_ctx* c, int kernel, F&& launch)
 }
 
 // u (3 planes) = BR velocity of (z, w); optionally V as well.
-zm_status eval_velocity(zm_ctx* c, const double* z, const double* w, double* u, double* V)
+zm_status eval_velocity(zm_ctx* c, const double* z, const double* w, double* u, double* V,
+                        hipStream_t stream)
 {
     const zm::Mesh& m = c->mesh;
     double* gam = c->at(c->layout.gam);
@@ -178,20 +108,20 @@ zm_status eval_velocity(zm_ctx* c, const double* z, const double* w, double* u, 
     double* part = c->at(c->layout.part);
     double* tie = c->at(c->layout.tie);
     hipError_t e;
-    e = timed(c, ZM_KERNEL_SURFACE, [&] { return zm::launch_surface(m, z, w, gam, q, c->stream); });
+    e = timed(c, ZM_KERNEL_SURFACE, [&] { return zm::launch_surface(m, z, w, gam, q, stream); });
     if (e != hipSuccess) return hip_fail(c, e, "surface kernel launch");
     e = timed(c, ZM_KERNEL_PAIRS, [&] {
         return c->prm.precision == ZM_FP32_PAIRS
-                   ? zm::launch_pairs_f32(m, c->shape, z, gam, part, c->stream)
-                   : zm::launch_pairs_f64(m, c->shape, z, gam, part, c->stream);
+                   ? zm::launch_pairs_f32(m, c->shape, z, gam, part, stream)
+                   : zm::launch_pairs_f64(m, c->shape, z, gam, part, stream);
     });
     if (e != hipSuccess) return hip_fail(c, e, "pair kernel launch");
     if ((m.n1 % 2) == 0 || (m.n2 % 2) == 0) {
-        e = timed(c, ZM_KERNEL_TIES, [&] { return zm::launch_ties(m, z, gam, tie, c->stream); });
+        e = timed(c, ZM_KERNEL_TIES, [&] { return zm::launch_ties(m, z, gam, tie, stream); });
         if (e != hipSuccess) return hip_fail(c, e, "tie kernel launch");
     }
     e = timed(c, ZM_KERNEL_REDUCE, [&] {
-        return zm::launch_reduce(m, c->shape.splits, part, tie, q, z, u, V, c->stream);
+        return zm::launch_reduce(m, c->shape.splits, part, tie, q, z, u, V, stream);
     });
     if (e != hipSuccess) return hip_fail(c, e, "reduce kernel launch");
     return ZM_OK;
@@ -240,21 +170,7 @@ zm_status zm_create(zm_ctx** out, const zm_params* params, void* d_workspace,
     c->device = dev;
     c->ws = reinterpret_cast<char*>(d_workspace);
     std::memset(c->stats, 0, sizeof(c->stats));
-    zm::Mesh& m = c->mesh;
-    m.n1 = params->n1;
-    m.n2 = params->n2;
-    m.N = params->n1 * params->n2;
-    m.K = params->image_layers;
-    m.L1 = params->period1;
-    m.L2 = params->period2;
-    m.h1 = params->period1 / params->n1;
-    m.h2 = params->period2 / params->n2;
-    m.eps2 = params->eps * params->eps;
-    m.coef = -(m.h1 * m.h2) / (4.0 * M_PI);
-    m.atwood = params->atwood;
-    m.gravity = params->gravity;
-    m.nu = params->nu;
-    m.dt = params->dt;
+    c->mesh = zm::make_mesh(*params);
     *out = c;
     return ZM_OK;
 }
@@ -303,7 +219,7 @@ zm_status zm_br_velocity(zm_ctx* c, const double* d_z, const double* d_w, double
         return fail(c, ZM_ERR_INVALID_ARG, "d_u overlaps an input");
     DeviceGuard g(c->device);
     if (!g.ok) return fail(c, ZM_ERR_HIP, "cannot select the context device");
-    return eval_velocity(c, d_z, d_w, d_u, nullptr);
+    return eval_velocity(c, d_z, d_w, d_u, nullptr, c->stream);
 }
 
 zm_status zm_rhs(zm_ctx* c, const double* d_z, const double* d_w, double* d_zt, double* d_wt)
@@ -323,7 +239,7 @@ zm_status zm_rhs(zm_ctx* c, const double* d_z, const double* d_w, double* d_zt, 
     if (!g.ok) return fail(c, ZM_ERR_HIP, "cannot select the context device");
     double* u = c->at(c->layout.u);
     double* V = c->at(c->layout.V);
-    zm_status st = eval_velocity(c, d_z, d_w, u, V);
+    zm_status st = eval_velocity(c, d_z, d_w, u, V, c->stream);
     if (st != ZM_OK) return st;
     hipError_t e = timed(c, ZM_KERNEL_UPDATE, [&] {
         return zm::launch_update(c->mesh, 3, nullptr, nullptr, d_z, d_w, u, V, d_zt, d_wt, nullptr,
@@ -333,16 +249,67 @@ zm_status zm_rhs(zm_ctx* c, const double* d_z, const double* d_w, double* d_zt, 
     return ZM_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// Enqueue one RK3 step (three derivative evaluations and stage updates).
+zm_status enqueue_step(zm_ctx* c, hipStream_t stream)
+{
+    const size_t N = c->N();
+    double* Y[3] = {c->at(c->layout.y0), c->at(c->layout.y1), c->at(c->layout.y2)};
+    double* u = c->at(c->layout.u);
+    double* V = c->at(c->layout.V);
+    int* flag = (c->prm.flags & ZM_FLAG_CHECK_FINITE)
+                    ? reinterpret_cast<int*>(c->ws + c->layout.flag) : nullptr;
+    for (int stage = 0; stage < 3; ++stage) {
+        double* ys = Y[stage];                       // state F is evaluated at
+        double* out = Y[(stage + 1) % 3];            // Y1, Y2, then Y0 in place
+        zm_status st = eval_velocity(c, ys, ys + 3 * N, u, V, stream);
+        if (st != ZM_OK) return st;
+        hipError_t e = timed(c, ZM_KERNEL_UPDATE, [&] {
+            return zm::launch_update(c->mesh, stage, Y[0], Y[0] + 3 * N, ys, ys + 3 * N, u, V, out,
+                                     out + 3 * N, flag, stream);
+        });
+        if (e != hipSuccess) return hip_fail(c, e, "update kernel launch");
+    }
+    return ZM_OK;
+}
+
+// Capture one step into a graph on a private non-blocking stream (the
+// caller's stream may be the null stream, which cannot be captured).  The
+// graph holds kernel nodes only.
+zm_status ensure_graph(zm_ctx* c)
+{
+    if (c->graph) return ZM_OK;
+    hipError_t e = hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking);
+    if (e != hipSuccess) return hip_fail(c, e, "capture stream");
+    e = hipStreamBeginCapture(c->capture_stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return hip_fail(c, e, "begin capture");
+    const bool prof = c->profiling;
+    c->profiling = false;
+    zm_status st = enqueue_step(c, c->capture_stream);
+    c->profiling = prof;
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(c->capture_stream, &g);
+    if (st != ZM_OK) { if (g) (void)hipGraphDestroy(g); return st; }
+    if (e != hipSuccess) return hip_fail(c, e, "end capture");
+    e = hipGraphInstantiate(&c->graph, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) { c->graph = nullptr; return hip_fail(c, e, "graph instantiate"); }
+    return ZM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 zm_status zm_step(zm_ctx* c, int32_t nsteps)
 {
     if (!c) return ZM_ERR_INVALID_ARG;
     if (nsteps < 0) return fail(c, ZM_ERR_INVALID_ARG, "nsteps must be >= 0");
     DeviceGuard g(c->device);
     if (!g.ok) return fail(c, ZM_ERR_HIP, "cannot select the context device");
-    const size_t N = c->N();
-    double* Y[3] = {c->at(c->layout.y0), c->at(c->layout.y1), c->at(c->layout.y2)};
-    double* u = c->at(c->layout.u);
-    double* V = c->at(c->layout.V);
     int* flag = reinterpret_cast<int*>(c->ws + c->layout.flag);
     const bool check = (c->prm.flags & ZM_FLAG_CHECK_FINITE) != 0;
     hipError_t e;
@@ -350,17 +317,18 @@ zm_status zm_step(zm_ctx* c, int32_t nsteps)
         e = hipMemsetAsync(flag, 0, sizeof(int), c->stream);
         if (e != hipSuccess) return hip_fail(c, e, "flag clear");
     }
+    const bool graph = (c->prm.flags & ZM_FLAG_GRAPH) && !c->profiling;
+    if (graph && nsteps > 0) {
+        zm_status st = ensure_graph(c);
+        if (st != ZM_OK) return st;
+    }
     for (int step = 0; step < nsteps; ++step) {
-        for (int stage = 0; stage < 3; ++stage) {
-            double* ys = Y[stage];                       // state F is evaluated at
-            double* out = Y[(stage + 1) % 3];            // Y1, Y2, then Y0 in place
-            zm_status st = eval_velocity(c, ys, ys + 3 * N, u, V);
+        if (graph) {
+            e = hipGraphLaunch(c->graph, c->stream);
+            if (e != hipSuccess) return hip_fail(c, e, "graph launch");
+        } else {
+            zm_status st = enqueue_step(c, c->stream);
             if (st != ZM_OK) return st;
-            e = timed(c, ZM_KERNEL_UPDATE, [&] {
-                return zm::launch_update(c->mesh, stage, Y[0], Y[0] + 3 * N, ys, ys + 3 * N, u, V,
-                                         out, out + 3 * N, check ? flag : nullptr, c->stream);
-            });
-            if (e != hipSuccess) return hip_fail(c, e, "update kernel launch");
         }
     }
     if (check) {
@@ -385,6 +353,8 @@ zm_status zm_destroy(zm_ctx* c)
             (void)hipEventDestroy(t.stop);
         }
         for (auto e : c->spare) (void)hipEventDestroy(e);
+        if (c->graph) (void)hipGraphExecDestroy(c->graph);
+        if (c->capture_stream) (void)hipStreamDestroy(c->capture_stream);
     }
     delete c;
     return st;

@@ -1,0 +1,164 @@
+// Batched kernels: many independent Z-Model instances advanced by one set of
+// launches per RK3 stage.
+//
+// Every instance has a device descriptor (mesh, pair-kernel shape, buffer
+// pointers).  Point-wise kernels run over the concatenated block ranges of
+// all instances; a block finds its instance by binary search over the block
+// offsets.  The pair sweep is one persistent launch per precision: each
+// workgroup repeatedly takes the next (instance, target patch, source split)
+// item from a device work list sorted longest first and runs the same body
+// as the single-instance kernel, so every instance's arithmetic is identical
+// alone and in a batch.
+#include "zm_batch_internal.h"
+#include "zm_device.h"
+
+#include <hip/hip_runtime.h>
+
+namespace zm {
+namespace {
+
+using dev::kThreads;
+
+// Instance owning global block b: largest i with block_begin <= b.
+__device__ __forceinline__ int find_instance(const InstDesc* __restrict__ T, int count, int b)
+{
+    int lo = 0, hi = count - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (T[mid].block_begin <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+__global__ __launch_bounds__(kThreads) void kb_surface(const InstDesc* __restrict__ T, int count,
+                                                       int stage)
+{
+    const int i = find_instance(T, count, blockIdx.x);
+    const InstDesc& d = T[i];
+    const int p = (blockIdx.x - d.block_begin) * kThreads + threadIdx.x;
+    const double* ys = d.Y[stage];
+    dev::surface_point(d.m, p, ys, ys + 3 * (size_t)d.m.N, d.gam, d.q);
+}
+
+__global__ __launch_bounds__(kThreads) void kb_ties(const InstDesc* __restrict__ T, int count,
+                                                    int stage)
+{
+    const int i = find_instance(T, count, blockIdx.x);
+    const InstDesc& d = T[i];
+    const int p = (blockIdx.x - d.block_begin) * kThreads + threadIdx.x;
+    dev::ties_point(d.m, p, blockIdx.y, d.Y[stage], d.gam, d.tie);
+}
+
+__global__ __launch_bounds__(kThreads) void kb_reduce(const InstDesc* __restrict__ T, int count,
+                                                      int stage)
+{
+    const int i = find_instance(T, count, blockIdx.x);
+    const InstDesc& d = T[i];
+    const int p = (blockIdx.x - d.block_begin) * kThreads + threadIdx.x;
+    dev::reduce_point(d.m, p, d.sh.splits, d.part, d.tie, d.q, d.Y[stage], d.u, d.V);
+}
+
+__global__ __launch_bounds__(kThreads) void kb_update(const InstDesc* __restrict__ T, int count,
+                                                      int stage, int* __restrict__ nonfinite)
+{
+    const int i = find_instance(T, count, blockIdx.x);
+    const InstDesc& d = T[i];
+    const int p = (blockIdx.x - d.block_begin) * kThreads + threadIdx.x;
+    const size_t N = d.m.N;
+    const double* ys = d.Y[stage];
+    double* out = d.Y[(stage + 1) % 3];
+    const double* y0 = d.Y[0];
+    dev::update_point(d.m, p, stage, y0, y0 + 3 * N, ys, ys + 3 * N, d.u, d.V, out, out + 3 * N,
+                      nonfinite);
+}
+
+// Resets the work counter of a persistent launch (a kernel, not a memset, so
+// it can sit inside a captured graph).
+__global__ void kb_reset(int* __restrict__ counter)
+{
+    if (threadIdx.x == 0) counter[0] = 0;
+}
+
+// Persistent pair sweep over the FP64 items.  Exit: a workgroup leaves once
+// the counter passes nitems, which every workgroup reaches.
+template <int R>
+__global__ __launch_bounds__(kThreads) void kb_pairs_f64(const InstDesc* __restrict__ T,
+                                                         const WorkItem* __restrict__ items,
+                                                         int nitems, int* __restrict__ counter,
+                                                         int stage)
+{
+    __shared__ double2 lds[2][3][kThreads];
+    __shared__ int next;
+    for (;;) {
+        if (threadIdx.x == 0) next = atomicAdd(counter, 1);
+        __syncthreads();
+        const int it = next;
+        __syncthreads();
+        if (it >= nitems) break;
+        const WorkItem w = items[it];
+        const InstDesc& d = T[w.inst];
+        if (d.sh.cx == 16)
+            dev::pairs_f64_block<R, 16>(d.m, d.sh, d.Y[stage], d.gam, d.part, w.patch, w.split, lds);
+        else
+            dev::pairs_f64_block<R, 8>(d.m, d.sh, d.Y[stage], d.gam, d.part, w.patch, w.split, lds);
+    }
+}
+
+template <int R>
+__global__ __launch_bounds__(kThreads) void kb_pairs_f32(const InstDesc* __restrict__ T,
+                                                         const WorkItem* __restrict__ items,
+                                                         int nitems, int* __restrict__ counter,
+                                                         int stage)
+{
+    __shared__ float4 lds0[2][kThreads];
+    __shared__ float2 lds1[2][kThreads];
+    __shared__ int next;
+    for (;;) {
+        if (threadIdx.x == 0) next = atomicAdd(counter, 1);
+        __syncthreads();
+        const int it = next;
+        __syncthreads();
+        if (it >= nitems) break;
+        const WorkItem w = items[it];
+        const InstDesc& d = T[w.inst];
+        if (d.sh.cx == 32)
+            dev::pairs_f32_block<R, 32>(d.m, d.sh, d.Y[stage], d.gam, d.part, w.patch, w.split,
+                                        lds0, lds1);
+        else if (d.sh.cx == 16)
+            dev::pairs_f32_block<R, 16>(d.m, d.sh, d.Y[stage], d.gam, d.part, w.patch, w.split,
+                                        lds0, lds1);
+        else
+            dev::pairs_f32_block<R, 8>(d.m, d.sh, d.Y[stage], d.gam, d.part, w.patch, w.split,
+                                       lds0, lds1);
+    }
+}
+
+}  // namespace
+
+hipError_t launch_batch_stage(const BatchLaunch& b, int stage, int* nonfinite, hipStream_t s)
+{
+    if (b.count <= 0) return hipSuccess;
+    const dim3 blk(kThreads);
+    hipLaunchKernelGGL(kb_surface, dim3(b.total_blocks), blk, 0, s, b.table, b.count, stage);
+    for (int prec = 0; prec < 2; ++prec) {
+        const int n = b.nitems[prec];
+        if (n == 0) continue;
+        hipLaunchKernelGGL(kb_reset, dim3(1), dim3(64), 0, s, b.counters + prec);
+        const unsigned grid = (unsigned)(n < b.persistent_groups ? n : b.persistent_groups);
+        const WorkItem* items = b.items + b.item_begin[prec];
+        if (prec == 0)
+            hipLaunchKernelGGL((kb_pairs_f64<ZM_PAIR_R>), dim3(grid), blk, 0, s, b.table, items, n,
+                               b.counters + prec, stage);
+        else
+            hipLaunchKernelGGL((kb_pairs_f32<ZM_PAIR32_R>), dim3(grid), blk, 0, s, b.table, items,
+                               n, b.counters + prec, stage);
+    }
+    if (b.any_even) hipLaunchKernelGGL(kb_ties, dim3(b.total_blocks, 2), blk, 0, s, b.table, b.count, stage);
+    hipLaunchKernelGGL(kb_reduce, dim3(b.total_blocks), blk, 0, s, b.table, b.count, stage);
+    hipLaunchKernelGGL(kb_update, dim3(b.total_blocks), blk, 0, s, b.table, b.count, stage,
+                       nonfinite);
+    return hipGetLastError();
+}
+
+}  // namespace zm

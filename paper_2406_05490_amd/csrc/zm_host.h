@@ -1,0 +1,116 @@
+// Host-side helpers shared by the single-instance and batched runtimes.
+#pragma once
+
+#include "zm.h"
+#include "zm_internal.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstddef>
+#include <cstdint>
+
+namespace zm {
+
+constexpr size_t kAlign = 256;
+constexpr int kMaxSide = 16384;
+constexpr int kMaxImages = 16;
+
+inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+// Workspace regions, all 256-byte aligned, in bytes from the base.
+struct Layout {
+    size_t y0, y1, y2;   // 5N doubles each (z1 z2 z3 w1 w2)
+    size_t gam, q;       // 3N, N
+    size_t part;         // splits * 3N
+    size_t tie;          // 6N
+    size_t u, V;         // 3N, N
+    size_t flag;         // one int
+    size_t total;
+};
+
+inline Layout make_layout(const zm_params& p, const zm::PairShape& sh)
+{
+    const size_t N = (size_t)p.n1 * (size_t)p.n2;
+    const size_t d = sizeof(double);
+    Layout L;
+    size_t o = 0;
+    auto take = [&](size_t bytes) { size_t at = o; o = align_up(o + bytes); return at; };
+    L.y0 = take(5 * N * d);
+    L.y1 = take(5 * N * d);
+    L.y2 = take(5 * N * d);
+    L.gam = take(3 * N * d);
+    L.q = take(N * d);
+    L.part = take((size_t)sh.splits * 3 * N * d);
+    L.tie = take(6 * N * d);
+    L.u = take(3 * N * d);
+    L.V = take(N * d);
+    L.flag = take(sizeof(int));
+    L.total = o;
+    return L;
+}
+
+inline const char* validate(const zm_params* p)
+{
+    if (!p) return "params is NULL";
+    if (p->n1 < 8 || p->n2 < 8) return "n1 and n2 must be >= 8";
+    if (p->n1 > kMaxSide || p->n2 > kMaxSide) return "n1 and n2 must be <= 16384";
+    if (!(std::isfinite(p->period1) && p->period1 > 0.0)) return "period1 must be finite and > 0";
+    if (!(std::isfinite(p->period2) && p->period2 > 0.0)) return "period2 must be finite and > 0";
+    if (!(std::isfinite(p->eps) && p->eps > 0.0)) return "eps must be finite and > 0";
+    if (!(std::isfinite(p->dt) && p->dt > 0.0)) return "dt must be finite and > 0";
+    if (!(std::isfinite(p->nu) && p->nu >= 0.0)) return "nu must be finite and >= 0";
+    if (!std::isfinite(p->atwood)) return "atwood must be finite";
+    if (!std::isfinite(p->gravity)) return "gravity must be finite";
+    if (p->precision != ZM_FP64 && p->precision != ZM_FP32_PAIRS) return "unknown precision";
+    if (p->image_layers < 0 || p->image_layers > kMaxImages) return "image_layers must be in [0, 16]";
+    if (p->flags & ~(ZM_FLAG_CHECK_FINITE | ZM_FLAG_GRAPH)) return "unknown flag bits";
+    if (p->reserved != 0) return "reserved must be 0";
+    return nullptr;
+}
+
+inline bool aligned(const void* p) { return p && ((uintptr_t)p % kAlign) == 0; }
+
+inline bool overlaps(const void* a, size_t na, const void* b, size_t nb)
+{
+    const uintptr_t x = (uintptr_t)a, y = (uintptr_t)b;
+    return x < y + nb && y < x + na;
+}
+
+// Makes the context's device current for the duration of a call.
+struct DeviceGuard {
+    int prev = -1;
+    bool ok = true;
+    explicit DeviceGuard(int dev)
+    {
+        if (hipGetDevice(&prev) != hipSuccess) { ok = false; return; }
+        if (prev != dev && hipSetDevice(dev) != hipSuccess) ok = false;
+    }
+    ~DeviceGuard()
+    {
+        int cur;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+inline Mesh make_mesh(const zm_params& p)
+{
+    Mesh m;
+    m.n1 = p.n1;
+    m.n2 = p.n2;
+    m.N = p.n1 * p.n2;
+    m.K = p.image_layers;
+    m.L1 = p.period1;
+    m.L2 = p.period2;
+    m.h1 = p.period1 / p.n1;
+    m.h2 = p.period2 / p.n2;
+    m.eps2 = p.eps * p.eps;
+    m.coef = -(m.h1 * m.h2) / (4.0 * M_PI);
+    m.atwood = p.atwood;
+    m.gravity = p.gravity;
+    m.nu = p.nu;
+    m.dt = p.dt;
+    return m;
+}
+
+}  // namespace zm

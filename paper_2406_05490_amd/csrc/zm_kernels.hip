@@ -1,23 +1,6 @@
-// Device kernels of the Z-Model high-order step for gfx950 (MI355X).
-//
-// Data layout: structure-of-arrays float64 planes in HBM, point index
-// p = i2 * n1 + i1.  All kernels are launched with 256-thread workgroups
-// (four 64-wide waves).
-//
-//   k_surface  tangents T_a (5-point, periodic, seam-corrected), source
-//              strength gamma = w1 T2 - w2 T1, q = |gamma|^2/|T1 x T2|^2.
-//              One thread per point, HBM-bound.
-//   k_pairs    the all-pairs Birkhoff-Rott sweep.  A workgroup owns a patch
-//              of targets (cx columns x prow rows, R targets per lane in
-//              one column) and one range of source rows.  Sources are
-//              staged 256 at a time through LDS (coalesced plane loads,
-//              double-buffered) and read back as wave-wide broadcasts; the
-//              pair arithmetic is VALU-only.  Per-target sums are blocked
-//              per source row.  Bound by VALU issue.
-//   k_ties     split-tie correction for even n_a, one thread per target.
-//   k_reduce   fixed-order sum over source splits and tie passes, scale,
-//              Bernoulli potential V.
-//   k_update   D V (+ nu Lap w) and the SSP-RK3 stage combination.
+// Single-instance kernels: thin wrappers that map the launch grid onto the
+// device bodies in zm_device.h, plus the launch-shape choice and launchers.
+#include "zm_device.h"
 #include "zm_internal.h"
 
 #include <hip/hip_runtime.h>
@@ -25,662 +8,44 @@
 namespace zm {
 namespace {
 
-constexpr int kThreads = 256;
-
-// Source-loop unroll depth and targets per lane of the pair kernel.
-#ifndef ZM_PAIR_UNROLL
-#define ZM_PAIR_UNROLL 2
-#endif
-#ifndef ZM_PAIR_R
-#define ZM_PAIR_R 4
-#endif
-#ifndef ZM_PAIR32_R
-#define ZM_PAIR32_R 4
-#endif
-
-// Periodic neighbour index along one axis; sets wrap to -1/0/+1.
-__device__ __forceinline__ int nbr(int i, int d, int n, int& wrap)
-{
-    int j = i + d;
-    wrap = 0;
-    if (j < 0) { j += n; wrap = -1; }
-    else if (j >= n) { j -= n; wrap = 1; }
-    return j;
-}
-
-__device__ __forceinline__ double d1_5pt(double fm2, double fm1, double fp1, double fp2, double h)
-{
-    return (8.0 * (fp1 - fm1) - (fp2 - fm2)) / (12.0 * h);
-}
-
-__device__ __forceinline__ double d2_5pt(double fm2, double fm1, double f0, double fp1, double fp2,
-                                         double h)
-{
-    return (-fp2 + 16.0 * fp1 - 30.0 * f0 + 16.0 * fm1 - fm2) / (12.0 * h * h);
-}
-
-// w = (|r|^2 + eps^2)^(-3/2) from s = |r|^2 + eps^2.  The hardware reciprocal
-// square root y0 has relative error below 2^-24 on gfx950; with
-// e = 1 - s y0^2 the exact value is y0^3 (1 - e)^(-3/2) and the first-order
-// correction w = y0^3 (1 + 3e/2) leaves 15 e^2 / 8 < 2e-14 (always low).
-__device__ __forceinline__ double inv_cube_sqrt(double s)
-{
-    const double y0 = __builtin_amdgcn_rsq(s);
-    const double y2 = y0 * y0;
-    const double e = fma(-s, y2, 1.0);
-    const double w0 = y2 * y0;
-    return fma(w0 * e, 1.5, w0);
-}
-
-// ---------------------------------------------------------------------------
-// surface derivatives
-// ---------------------------------------------------------------------------
+using dev::kThreads;
 
 __global__ __launch_bounds__(kThreads) void k_surface(Mesh m, const double* __restrict__ z,
                                                       const double* __restrict__ w,
                                                       double* __restrict__ gam,
                                                       double* __restrict__ q)
 {
-    const int p = blockIdx.x * kThreads + threadIdx.x;
-    if (p >= m.N) return;
-    const int N = m.N;
-    const int i2 = p / m.n1;
-    const int i1 = p - i2 * m.n1;
-
-    int wa[4], wb[4];
-    int pa[4], pb[4];
-    const int offs[4] = {-2, -1, 1, 2};
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const int j1 = nbr(i1, offs[k], m.n1, wa[k]);
-        const int j2 = nbr(i2, offs[k], m.n2, wb[k]);
-        pa[k] = i2 * m.n1 + j1;
-        pb[k] = j2 * m.n1 + i1;
-    }
-    double T1[3], T2[3];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        const double* f = z + (size_t)c * N;
-        double a[4], b[4];
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            a[k] = f[pa[k]];
-            b[k] = f[pb[k]];
-            if (c == 0 && wa[k] != 0) a[k] = a[k] + (double)wa[k] * m.L1;
-            if (c == 1 && wb[k] != 0) b[k] = b[k] + (double)wb[k] * m.L2;
-        }
-        T1[c] = d1_5pt(a[0], a[1], a[2], a[3], m.h1);
-        T2[c] = d1_5pt(b[0], b[1], b[2], b[3], m.h2);
-    }
-    const double w1 = w[p], w2 = w[N + p];
-    const double g1 = w1 * T2[0] - w2 * T1[0];
-    const double g2 = w1 * T2[1] - w2 * T1[1];
-    const double g3 = w1 * T2[2] - w2 * T1[2];
-    gam[p] = g1;
-    gam[N + p] = g2;
-    gam[2 * N + p] = g3;
-    const double c1 = T1[1] * T2[2] - T1[2] * T2[1];
-    const double c2 = T1[2] * T2[0] - T1[0] * T2[2];
-    const double c3 = T1[0] * T2[1] - T1[1] * T2[0];
-    q[p] = (g1 * g1 + g2 * g2 + g3 * g3) / (c1 * c1 + c2 * c2 + c3 * c3);
+    dev::surface_point(m, blockIdx.x * kThreads + threadIdx.x, z, w, gam, q);
 }
 
-// ---------------------------------------------------------------------------
-// all-pairs BR sweep, float64
-// ---------------------------------------------------------------------------
-
-// Image bookkeeping along one axis for target index i on n points:
-// sources j < b sit at shift s_lo, sources j >= b at s_hi = s_lo - 1.  The
-// source at j == b has offset exactly -n/2 when n is even (a tie).
-struct AxisImg {
-    int b;
-    int s_lo;
-};
-
-__device__ __forceinline__ AxisImg axis_img(int i, int n)
-{
-    const int H = n >> 1;
-    AxisImg a;
-    a.b = (i >= H) ? i - H : i + n - H;
-    a.s_lo = (i >= H) ? 1 : 0;
-    return a;
-}
-
-// Unscaled contributions of sources [k0, k0 + cnt) of the current LDS tile,
-// all in one source row and one column segment, to the lane's R targets.
-// CORE: every target of the lane has a fixed image shift over the segment,
-// already folded into xt.  Otherwise (seam band) the axis-1 shift is chosen
-// per source: sources with column < b1 sit at shift Sx_lo, the others at
-// Sx_hi.
-template <int R, bool CORE>
-__device__ __forceinline__ void pair_segment(const double2 (*__restrict__ buf)[kThreads], int k0,
-                                             int cnt, int j1s, int b1, double Sx_lo, double Sx_hi,
-                                             const double* xt, const double* yt, const double* zi,
-                                             double eps2, double (*sa)[3])
-{
-#pragma unroll ZM_PAIR_UNROLL
-    for (int c = 0; c < cnt; ++c) {
-        const double2 v0 = buf[0][k0 + c];
-        const double2 v1 = buf[1][k0 + c];
-        const double2 v2 = buf[2][k0 + c];
-        double xs = v0.x;
-        if (!CORE) xs = xs + ((j1s + c < b1) ? Sx_lo : Sx_hi);
-        const double ys = v0.y, zs = v1.x;
-        const double g1 = v1.y, g2 = v2.x, g3 = v2.y;
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const double r1 = xt[r] - xs;
-            const double r2 = yt[r] - ys;
-            const double r3 = zi[r] - zs;
-            const double s = fma(r1, r1, fma(r2, r2, fma(r3, r3, eps2)));
-            const double wgt = inv_cube_sqrt(s);
-            const double a1 = wgt * g1, a2 = wgt * g2, a3 = wgt * g3;
-            sa[r][0] = fma(r2, a3, sa[r][0]);
-            sa[r][0] = fma(-r3, a2, sa[r][0]);
-            sa[r][1] = fma(r3, a1, sa[r][1]);
-            sa[r][1] = fma(-r1, a3, sa[r][1]);
-            sa[r][2] = fma(r1, a2, sa[r][2]);
-            sa[r][2] = fma(-r2, a1, sa[r][2]);
-        }
-    }
-}
-
-// All-pairs sweep.  Workgroup = target patch (CX columns x prow rows; lane =
-// one column, R rows spaced 256/CX apart) x one range of source rows.  The
-// axis-1 image breakpoints b1 of the patch's columns form a band of CX
-// consecutive source columns (mod n1); outside it every lane's shift is
-// constant per row segment, inside it the shift is selected per source.
 template <int R, int CX>
 __global__ __launch_bounds__(kThreads) void k_pairs_f64(Mesh m, PairShape sh,
                                                         const double* __restrict__ z,
                                                         const double* __restrict__ gam,
                                                         double* __restrict__ part)
 {
-    constexpr int RY = kThreads / CX;
-    constexpr int PR = RY * R;
-    // [buffer][(x,y) (z,g1) (g2,g3)][source]
     __shared__ double2 lds[2][3][kThreads];
-
-    const int N = m.N, n1 = m.n1, n2 = m.n2;
-    const int tid = threadIdx.x;
-    const int patch = blockIdx.x;
-    const int split = blockIdx.y;
-    const int ptx = patch % sh.px;
-    const int pty = patch / sh.px;
-
-    const int row_begin = split * sh.rows_per_split;
-    const int row_end = min(n2, row_begin + sh.rows_per_split);
-    if (row_begin >= row_end) return;  // uniform over the workgroup
-
-    // ---- targets of this lane: one column, R rows -------------------------
-    const int c0 = ptx * CX;
-    const int col = c0 + (tid % CX);
-    const int rowg = tid / CX;
-    const bool col_ok = col < n1;
-    const int i1 = col_ok ? col : 0;
-    const AxisImg ax1 = axis_img(i1, n1);
-    // seam band of source columns: b1 of columns c0 .. c0+CX-1, mod n1
-    const int band_lo = axis_img(c0, n1).b;
-    const bool band_all = CX >= n1;
-    const bool band_wraps = band_lo + CX > n1;
-
-    double xi[R], yi[R], zi[R], xt[R], yt[R];
-    int b2[R], s2lo[R], pidx[R];
-    bool valid[R];
-#pragma unroll
-    for (int k = 0; k < R; ++k) {
-        const int r = pty * PR + rowg + RY * k;
-        valid[k] = col_ok && (r < n2);
-        const int i2 = (r < n2) ? r : 0;
-        pidx[k] = i2 * n1 + i1;
-        xi[k] = z[pidx[k]];
-        yi[k] = z[N + pidx[k]];
-        zi[k] = z[2 * N + pidx[k]];
-        const AxisImg ax2 = axis_img(i2, n2);
-        b2[k] = ax2.b;
-        s2lo[k] = ax2.s_lo;
-        xt[k] = xi[k];
-        yt[k] = yi[k];
-    }
-
-    double acc[R][3];
-#pragma unroll
-    for (int k = 0; k < R; ++k) acc[k][0] = acc[k][1] = acc[k][2] = 0.0;
-
-    const int src_begin = row_begin * n1;
-    const int src_end = row_end * n1;
-    const int ntiles = (src_end - src_begin + kThreads - 1) / kThreads;
-    const int side = 2 * m.K + 1;
-    const int total = ntiles * side * side;
-
-    // ---- staging: one source per thread per tile ---------------------------
-    double2 st0, st1, st2;
-    auto load_tile = [&](int t) {
-        const int tile = t % ntiles;
-        const int j = src_begin + tile * kThreads + tid;
-        if (j < src_end) {
-            st0 = make_double2(z[j], z[N + j]);
-            st1 = make_double2(z[2 * N + j], gam[j]);
-            st2 = make_double2(gam[N + j], gam[2 * N + j]);
-        } else {
-            st0 = st1 = st2 = make_double2(0.0, 0.0);
-        }
-    };
-    auto store_tile = [&](int buf) {
-        lds[buf][0][tid] = st0;
-        lds[buf][1][tid] = st1;
-        lds[buf][2][tid] = st2;
-    };
-
-    load_tile(0);
-    store_tile(0);
-    __syncthreads();
-
-    for (int t = 0; t < total; ++t) {
-        const int buf = t & 1;
-        if (t + 1 < total) load_tile(t + 1);
-
-        const int img = t / ntiles;
-        const int tile = t - img * ntiles;
-        const int m1 = img % side - m.K;
-        const int m2 = img / side - m.K;
-        const double Sx_lo = (double)(ax1.s_lo + m1) * m.L1;
-        const double Sx_hi = (double)(ax1.s_lo - 1 + m1) * m.L1;
-
-        const int j0 = src_begin + tile * kThreads;
-        const int cnt = min(kThreads, src_end - j0);
-        int j2 = j0 / n1;
-        int j1 = j0 - j2 * n1;
-        int k = 0;
-        while (k < cnt) {
-            const int seg = min(cnt - k, n1 - j1);   // this row's columns [j1, j1 + seg)
-#pragma unroll
-            for (int r = 0; r < R; ++r) {
-                const int s2 = (j2 < b2[r]) ? s2lo[r] : s2lo[r] - 1;
-                yt[r] = yi[r] - (double)(s2 + m2) * m.L2;
-            }
-            double sa[R][3];
-#pragma unroll
-            for (int r = 0; r < R; ++r) sa[r][0] = sa[r][1] = sa[r][2] = 0.0;
-
-            // split [j1, j1 + seg) at the band edges: core pieces and band pieces
-            int a = j1;
-            const int e = j1 + seg;
-            while (a < e) {
-                bool in_band;
-                int stop;
-                if (band_all) {
-                    in_band = true; stop = e;
-                } else if (!band_wraps) {
-                    if (a < band_lo) { in_band = false; stop = min(e, band_lo); }
-                    else if (a < band_lo + CX) { in_band = true; stop = min(e, band_lo + CX); }
-                    else { in_band = false; stop = e; }
-                } else {
-                    const int hi_end = band_lo + CX - n1;   // band = [band_lo, n1) + [0, hi_end)
-                    if (a < hi_end) { in_band = true; stop = min(e, hi_end); }
-                    else if (a < band_lo) { in_band = false; stop = min(e, band_lo); }
-                    else { in_band = true; stop = e; }
-                }
-                const int kk = k + (a - j1);
-                if (in_band) {
-                    pair_segment<R, false>(lds[buf], kk, stop - a, a, ax1.b, Sx_lo, Sx_hi, xi, yt,
-                                           zi, m.eps2, sa);
-                } else {
-                    const double Sx = (a < ax1.b) ? Sx_lo : Sx_hi;
-#pragma unroll
-                    for (int r = 0; r < R; ++r) xt[r] = xi[r] - Sx;
-                    pair_segment<R, true>(lds[buf], kk, stop - a, a, ax1.b, Sx_lo, Sx_hi, xt, yt,
-                                          zi, m.eps2, sa);
-                }
-                a = stop;
-            }
-#pragma unroll
-            for (int r = 0; r < R; ++r) {
-                acc[r][0] += sa[r][0];
-                acc[r][1] += sa[r][1];
-                acc[r][2] += sa[r][2];
-            }
-            k += seg;
-            j1 += seg;
-            if (j1 == n1) { j1 = 0; ++j2; }
-        }
-
-        if (t + 1 < total) store_tile(buf ^ 1);
-        __syncthreads();
-    }
-
-    double* out = part + (size_t)split * 3 * N;
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-        if (valid[r]) {
-            out[pidx[r]] = acc[r][0];
-            out[N + pidx[r]] = acc[r][1];
-            out[2 * N + pidx[r]] = acc[r][2];
-        }
-    }
+    dev::pairs_f64_block<R, CX>(m, sh, z, gam, part, blockIdx.x, blockIdx.y, lds);
 }
 
-// ---------------------------------------------------------------------------
-// all-pairs BR sweep, FP32 pair arithmetic, FP64 per-target sums
-// ---------------------------------------------------------------------------
-//
-// Coordinates are tile-relative: the workgroup takes the FP64 position c of
-// a target near the middle of its patch, and every staged source is stored
-// as the FP32 rounding of (z_j + S_c(j) L - c), where S_c(j) is the source's
-// periodic image seen from that centre target.  Near pairs therefore
-// subtract small numbers (error ~ ulp of the patch extent, not of the
-// domain).  A lane's own image differs from the centre's only for sources in
-// the antipodal band (columns / rows where some patch target's image
-// breakpoint lies); there the difference (a whole period) is added per
-// source.  Pair terms and per-row partial sums are FP32; every row's partial
-// is added into FP64 per-target accumulators.
-
-#ifndef ZM_PAIR32_UNROLL
-#define ZM_PAIR32_UNROLL 2
-#endif
-
-template <int R, bool BAND>
-__device__ __forceinline__ void pair_segment_f32(const float4* __restrict__ p0,
-                                                 const float2* __restrict__ p1, int k0, int cnt,
-                                                 int j1s, int b1, int s1lo, int bc1, int sc1lo,
-                                                 float L1, float dm1, const float* ax,
-                                                 const float* ay, const float* az, float eps2,
-                                                 float (*sa)[3])
-{
-#pragma unroll ZM_PAIR32_UNROLL
-    for (int c = 0; c < cnt; ++c) {
-        const float4 v0 = p0[k0 + c];
-        const float2 v1 = p1[k0 + c];
-        float bx = v0.x;
-        if (BAND) {
-            const int jj = j1s + c;
-            const int si = (jj < b1) ? s1lo : s1lo - 1;
-            const int sc = (jj < bc1) ? sc1lo : sc1lo - 1;
-            bx = fmaf((float)(si - sc), L1, bx) + dm1;
-        }
-        const float by = v0.y, bz = v0.z;
-        const float g1 = v0.w, g2 = v1.x, g3 = v1.y;
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const float r1 = ax[r] - bx;
-            const float r2 = ay[r] - by;
-            const float r3 = az[r] - bz;
-            const float s = fmaf(r1, r1, fmaf(r2, r2, fmaf(r3, r3, eps2)));
-            const float y = __builtin_amdgcn_rsqf(s);
-            const float wgt = y * y * y;
-            const float a1 = wgt * g1, a2 = wgt * g2, a3 = wgt * g3;
-            sa[r][0] = fmaf(r2, a3, sa[r][0]);
-            sa[r][0] = fmaf(-r3, a2, sa[r][0]);
-            sa[r][1] = fmaf(r3, a1, sa[r][1]);
-            sa[r][1] = fmaf(-r1, a3, sa[r][1]);
-            sa[r][2] = fmaf(r1, a2, sa[r][2]);
-            sa[r][2] = fmaf(-r2, a1, sa[r][2]);
-        }
-    }
-}
-
-// Workgroup = target patch of PX columns x (256/PX)*R rows (lane = one
-// column, R rows 256/PX apart) x one range of source rows.
 template <int R, int PX>
 __global__ __launch_bounds__(kThreads) void k_pairs_f32(Mesh m, PairShape sh,
                                                         const double* __restrict__ z,
                                                         const double* __restrict__ gam,
                                                         double* __restrict__ part)
 {
-    constexpr int RY = kThreads / PX;
-    constexpr int PY = RY * R;
-    __shared__ float4 lds0[2][kThreads];   // (x, y, z, g1) relative to the patch centre
-    __shared__ float2 lds1[2][kThreads];   // (g2, g3)
-
-    const int N = m.N, n1 = m.n1, n2 = m.n2;
-    const int tid = threadIdx.x;
-    const int patch = blockIdx.x;
-    const int split = blockIdx.y;
-    const int ptx = patch % sh.px;
-    const int pty = patch / sh.px;
-    const int row_begin = split * sh.rows_per_split;
-    const int row_end = min(n2, row_begin + sh.rows_per_split);
-    if (row_begin >= row_end) return;  // uniform over the workgroup
-
-    // ---- patch centre ----------------------------------------------------
-    const int c0 = ptx * PX, r0 = pty * PY;
-    const int ci1 = min(c0 + PX / 2, n1 - 1), ci2 = min(r0 + PY / 2, n2 - 1);
-    const int pc = ci2 * n1 + ci1;
-    const double cx = z[pc], cy = z[N + pc], cz = z[2 * N + pc];
-    const AxisImg cimg1 = axis_img(ci1, n1), cimg2 = axis_img(ci2, n2);
-    // antipodal band along axis 1: breakpoints of columns c0 .. c0+PX-1
-    const int band_lo = axis_img(c0, n1).b;
-    const bool band_all = PX >= n1;
-    const bool band_wraps = band_lo + PX > n1;
-
-    // ---- targets of this lane --------------------------------------------
-    const int col = c0 + (tid % PX);
-    const int rowg = tid / PX;
-    const bool col_ok = col < n1;
-    const int i1 = col_ok ? col : ci1;
-    const AxisImg ax1 = axis_img(i1, n1);
-    float ax[R], az[R], ay[R];
-    double ayd[R];
-    int b2[R], s2lo[R], pidx[R];
-    bool valid[R];
-#pragma unroll
-    for (int k = 0; k < R; ++k) {
-        const int r = r0 + rowg + RY * k;
-        valid[k] = col_ok && (r < n2);
-        const int i2 = (r < n2) ? r : ci2;
-        pidx[k] = i2 * n1 + i1;
-        ax[k] = (float)(z[pidx[k]] - cx);
-        ayd[k] = z[N + pidx[k]] - cy;
-        az[k] = (float)(z[2 * N + pidx[k]] - cz);
-        ay[k] = (float)ayd[k];
-        const AxisImg a2 = axis_img(i2, n2);
-        b2[k] = a2.b;
-        s2lo[k] = a2.s_lo;
-    }
-    double acc[R][3];
-#pragma unroll
-    for (int k = 0; k < R; ++k) acc[k][0] = acc[k][1] = acc[k][2] = 0.0;
-
-    const int src_begin = row_begin * n1;
-    const int src_end = row_end * n1;
-    const int ntiles = (src_end - src_begin + kThreads - 1) / kThreads;
-    const int side = 2 * m.K + 1;
-    const int total = ntiles * side * side;
-    const float L1f = (float)m.L1;
-    const float eps2f = (float)m.eps2;
-
-    // ---- staging: source j relative to the centre, centre's image --------
-    float4 st0;
-    float2 st1;
-    auto load_tile = [&](int t) {
-        const int tile = t % ntiles;
-        const int j = src_begin + tile * kThreads + tid;
-        if (j < src_end) {
-            const int j2 = j / n1, j1 = j - j2 * n1;
-            const int sc1 = (j1 < cimg1.b) ? cimg1.s_lo : cimg1.s_lo - 1;
-            const int sc2 = (j2 < cimg2.b) ? cimg2.s_lo : cimg2.s_lo - 1;
-            st0 = make_float4((float)((z[j] + (double)sc1 * m.L1) - cx),
-                              (float)((z[N + j] + (double)sc2 * m.L2) - cy),
-                              (float)(z[2 * N + j] - cz), (float)gam[j]);
-            st1 = make_float2((float)gam[N + j], (float)gam[2 * N + j]);
-        } else {
-            st0 = make_float4(0.f, 0.f, 0.f, 0.f);
-            st1 = make_float2(0.f, 0.f);
-        }
-    };
-    auto store_tile = [&](int buf) {
-        lds0[buf][tid] = st0;
-        lds1[buf][tid] = st1;
-    };
-
-    load_tile(0);
-    store_tile(0);
-    __syncthreads();
-
-    for (int t = 0; t < total; ++t) {
-        const int buf = t & 1;
-        if (t + 1 < total) load_tile(t + 1);
-        const int img = t / ntiles;
-        const int tile = t - img * ntiles;
-        const int m1 = img % side - m.K;
-        const int m2 = img / side - m.K;
-        // extra image layers shift every source by (m1 L1, m2 L2)
-        const float dm1 = (float)((double)m1 * m.L1);
-
-        const int j0 = src_begin + tile * kThreads;
-        const int cnt = min(kThreads, src_end - j0);
-        int j2 = j0 / n1;
-        int j1 = j0 - j2 * n1;
-        int k = 0;
-        while (k < cnt) {
-            const int seg = min(cnt - k, n1 - j1);
-            const int sc2 = (j2 < cimg2.b) ? cimg2.s_lo : cimg2.s_lo - 1;
-            float ayr[R];
-#pragma unroll
-            for (int r = 0; r < R; ++r) {
-                const int s2 = (j2 < b2[r]) ? s2lo[r] : s2lo[r] - 1;
-                ayr[r] = (float)(ayd[r] - (double)(s2 - sc2 + m2) * m.L2);
-            }
-            float sa[R][3];
-#pragma unroll
-            for (int r = 0; r < R; ++r) sa[r][0] = sa[r][1] = sa[r][2] = 0.f;
-
-            int a = j1;
-            const int e = j1 + seg;
-            while (a < e) {
-                bool in_band;
-                int stop;
-                if (band_all) {
-                    in_band = true; stop = e;
-                } else if (!band_wraps) {
-                    if (a < band_lo) { in_band = false; stop = min(e, band_lo); }
-                    else if (a < band_lo + PX) { in_band = true; stop = min(e, band_lo + PX); }
-                    else { in_band = false; stop = e; }
-                } else {
-                    const int hi_end = band_lo + PX - n1;
-                    if (a < hi_end) { in_band = true; stop = min(e, hi_end); }
-                    else if (a < band_lo) { in_band = false; stop = min(e, band_lo); }
-                    else { in_band = true; stop = e; }
-                }
-                const int kk = k + (a - j1);
-                if (in_band || m1 != 0) {
-                    pair_segment_f32<R, true>(lds0[buf], lds1[buf], kk, stop - a, a, ax1.b,
-                                              ax1.s_lo, cimg1.b, cimg1.s_lo, L1f, dm1, ax, ayr, az,
-                                              eps2f, sa);
-                } else {
-                    pair_segment_f32<R, false>(lds0[buf], lds1[buf], kk, stop - a, a, ax1.b,
-                                               ax1.s_lo, cimg1.b, cimg1.s_lo, L1f, dm1, ax, ayr,
-                                               az, eps2f, sa);
-                }
-                a = stop;
-            }
-#pragma unroll
-            for (int r = 0; r < R; ++r) {
-                acc[r][0] += (double)sa[r][0];
-                acc[r][1] += (double)sa[r][1];
-                acc[r][2] += (double)sa[r][2];
-            }
-            k += seg;
-            j1 += seg;
-            if (j1 == n1) { j1 = 0; ++j2; }
-        }
-        if (t + 1 < total) store_tile(buf ^ 1);
-        __syncthreads();
-    }
-
-    double* out = part + (size_t)split * 3 * N;
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-        if (valid[r]) {
-            out[pidx[r]] = acc[r][0];
-            out[N + pidx[r]] = acc[r][1];
-            out[2 * N + pidx[r]] = acc[r][2];
-        }
-    }
+    __shared__ float4 lds0[2][kThreads];
+    __shared__ float2 lds1[2][kThreads];
+    dev::pairs_f32_block<R, PX>(m, sh, z, gam, part, blockIdx.x, blockIdx.y, lds0, lds1);
 }
 
-// ---------------------------------------------------------------------------
-// split-tie correction
-// ---------------------------------------------------------------------------
-
-// Unscaled pair term f = (r x g) / (|r|^2 + eps^2)^(3/2) added with weight c.
-__device__ __forceinline__ void tie_term(const Mesh& m, double xi, double yi, double zi,
-                                         const double* __restrict__ z,
-                                         const double* __restrict__ gam, int pj, double S1,
-                                         double S2, double c, double acc[3])
-{
-    const int N = m.N;
-    const double r1 = xi - z[pj] - S1 * m.L1;
-    const double r2 = yi - z[N + pj] - S2 * m.L2;
-    const double r3 = zi - z[2 * N + pj];
-    const double g1 = gam[pj], g2 = gam[N + pj], g3 = gam[2 * N + pj];
-    const double s = r1 * r1 + r2 * r2 + r3 * r3 + m.eps2;
-    const double wgt = c * inv_cube_sqrt(s);
-    acc[0] += wgt * (r2 * g3 - r3 * g2);
-    acc[1] += wgt * (r3 * g1 - r1 * g3);
-    acc[2] += wgt * (r1 * g2 - r2 * g1);
-}
-
-// blockIdx.y = pass: 0 corrects the tie column (needs n1 even), 1 the tie
-// row (needs n2 even).  The pair kernel counted each tied source once at
-// the image s_hi; the correct weight is 1/2 at s_hi and 1/2 at s_lo on each
-// tied axis.  The corner (tied on both axes) is handled by pass 0.
+// blockIdx.y = pass (0: tie column, 1: tie row)
 __global__ __launch_bounds__(kThreads) void k_ties(Mesh m, const double* __restrict__ z,
                                                    const double* __restrict__ gam,
                                                    double* __restrict__ tie)
 {
-    const int p = blockIdx.x * kThreads + threadIdx.x;
-    const int pass = blockIdx.y;
-    if (p >= m.N) return;
-    const int N = m.N, n1 = m.n1, n2 = m.n2;
-    const int i2 = p / n1;
-    const int i1 = p - i2 * n1;
-    const AxisImg a1 = axis_img(i1, n1);
-    const AxisImg a2 = axis_img(i2, n2);
-    const bool even1 = (n1 & 1) == 0, even2 = (n2 & 1) == 0;
-    const double xi = z[p], yi = z[N + p], zi = z[2 * N + p];
-    double acc[3] = {0.0, 0.0, 0.0};
-
-    for (int m2 = -m.K; m2 <= m.K; ++m2) {
-        for (int m1 = -m.K; m1 <= m.K; ++m1) {
-            const double lo1 = a1.s_lo + m1, hi1 = a1.s_lo - 1 + m1;
-            const double lo2 = a2.s_lo + m2, hi2 = a2.s_lo - 1 + m2;
-            if (pass == 0 && even1) {
-                const int j1 = a1.b;
-                for (int j2 = 0; j2 < n2; ++j2) {
-                    const int pj = j2 * n1 + j1;
-                    if (even2 && j2 == a2.b) {
-                        tie_term(m, xi, yi, zi, z, gam, pj, lo1, lo2, 0.25, acc);
-                        tie_term(m, xi, yi, zi, z, gam, pj, lo1, hi2, 0.25, acc);
-                        tie_term(m, xi, yi, zi, z, gam, pj, hi1, lo2, 0.25, acc);
-                        tie_term(m, xi, yi, zi, z, gam, pj, hi1, hi2, -0.75, acc);
-                    } else {
-                        const double S2 = (j2 < a2.b) ? lo2 : hi2;
-                        tie_term(m, xi, yi, zi, z, gam, pj, lo1, S2, 0.5, acc);
-                        tie_term(m, xi, yi, zi, z, gam, pj, hi1, S2, -0.5, acc);
-                    }
-                }
-            } else if (pass == 1 && even2) {
-                const int j2 = a2.b;
-                for (int j1 = 0; j1 < n1; ++j1) {
-                    if (even1 && j1 == a1.b) continue;
-                    const int pj = j2 * n1 + j1;
-                    const double S1 = (j1 < a1.b) ? lo1 : hi1;
-                    tie_term(m, xi, yi, zi, z, gam, pj, S1, lo2, 0.5, acc);
-                    tie_term(m, xi, yi, zi, z, gam, pj, S1, hi2, -0.5, acc);
-                }
-            }
-        }
-    }
-    double* out = tie + (size_t)pass * 3 * N;
-    out[p] = acc[0];
-    out[N + p] = acc[1];
-    out[2 * N + p] = acc[2];
+    dev::ties_point(m, blockIdx.x * kThreads + threadIdx.x, blockIdx.y, z, gam, tie);
 }
-
-// ---------------------------------------------------------------------------
-// reduction over source splits, Bernoulli potential
-// ---------------------------------------------------------------------------
 
 __global__ __launch_bounds__(kThreads) void k_reduce(Mesh m, int splits,
                                                      const double* __restrict__ part,
@@ -690,32 +55,10 @@ __global__ __launch_bounds__(kThreads) void k_reduce(Mesh m, int splits,
                                                      double* __restrict__ u,
                                                      double* __restrict__ V)
 {
-    const int p = blockIdx.x * kThreads + threadIdx.x;
-    if (p >= m.N) return;
-    const size_t N = m.N;
-    double a[3];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        double s = 0.0;
-        for (int k = 0; k < splits; ++k) s += part[(k * 3 + c) * N + p];
-        if ((m.n1 & 1) == 0) s += tie[c * N + p];
-        if ((m.n2 & 1) == 0) s += tie[(3 + c) * N + p];
-        a[c] = m.coef * s;
-        u[c * N + p] = a[c];
-    }
-    if (V) {
-        const double uu = a[0] * a[0] + a[1] * a[1] + a[2] * a[2];
-        V[p] = m.atwood * ((uu - 0.25 * q[p]) - (2.0 * m.gravity) * z[2 * N + p]);
-    }
+    dev::reduce_point(m, blockIdx.x * kThreads + threadIdx.x, splits, part, tie, q, z, u, V);
 }
 
-// ---------------------------------------------------------------------------
-// vorticity right-hand side and RK3 stage combination
-// ---------------------------------------------------------------------------
-
-// y0 may alias out (the last stage writes the new state over y0 in place,
-// each thread reading its own point before writing it), so neither carries
-// __restrict__.
+// y0 may alias out (see update_point), so neither carries __restrict__.
 __global__ __launch_bounds__(kThreads) void k_update(Mesh m, int stage, const double* y0_z,
                                                      const double* y0_w,
                                                      const double* __restrict__ ys_z,
@@ -725,67 +68,14 @@ __global__ __launch_bounds__(kThreads) void k_update(Mesh m, int stage, const do
                                                      double* out_z, double* out_w,
                                                      int* __restrict__ nonfinite)
 {
-    const int p = blockIdx.x * kThreads + threadIdx.x;
-    if (p >= m.N) return;
-    const int N = m.N, n1 = m.n1, n2 = m.n2;
-    const int i2 = p / n1;
-    const int i1 = p - i2 * n1;
-    int wr;
-    const int a_m2 = i2 * n1 + nbr(i1, -2, n1, wr), a_m1 = i2 * n1 + nbr(i1, -1, n1, wr);
-    const int a_p1 = i2 * n1 + nbr(i1, 1, n1, wr), a_p2 = i2 * n1 + nbr(i1, 2, n1, wr);
-    const int b_m2 = nbr(i2, -2, n2, wr) * n1 + i1, b_m1 = nbr(i2, -1, n2, wr) * n1 + i1;
-    const int b_p1 = nbr(i2, 1, n2, wr) * n1 + i1, b_p2 = nbr(i2, 2, n2, wr) * n1 + i1;
-
-    double F[5];
-    F[0] = u[p];
-    F[1] = u[N + p];
-    F[2] = u[2 * N + p];
-    F[3] = d1_5pt(V[a_m2], V[a_m1], V[a_p1], V[a_p2], m.h1);
-    F[4] = d1_5pt(V[b_m2], V[b_m1], V[b_p1], V[b_p2], m.h2);
-    if (m.nu != 0.0) {
-#pragma unroll
-        for (int c = 0; c < 2; ++c) {
-            const double* f = ys_w + (size_t)c * N;
-            const double lap = d2_5pt(f[a_m2], f[a_m1], f[p], f[a_p1], f[a_p2], m.h1) +
-                               d2_5pt(f[b_m2], f[b_m1], f[p], f[b_p1], f[b_p2], m.h2);
-            F[3 + c] = F[3 + c] + m.nu * lap;
-        }
-    }
-
-    double o[5];
-    if (stage == 3) {
-#pragma unroll
-        for (int c = 0; c < 5; ++c) o[c] = F[c];
-    } else {
-#pragma unroll
-        for (int c = 0; c < 5; ++c) {
-            const size_t off = (c < 3) ? (size_t)c * N + p : (size_t)(c - 3) * N + p;
-            const double yv = (c < 3) ? ys_z[off] : ys_w[off];
-            const double a = yv + m.dt * F[c];
-            if (stage == 0) {
-                o[c] = a;
-            } else {
-                const double y0v = (c < 3) ? y0_z[off] : y0_w[off];
-                if (stage == 1) o[c] = 0.75 * y0v + 0.25 * a;
-                else o[c] = (1.0 / 3.0) * y0v + (2.0 / 3.0) * a;
-            }
-        }
-    }
-#pragma unroll
-    for (int c = 0; c < 3; ++c) out_z[(size_t)c * N + p] = o[c];
-    out_w[p] = o[3];
-    out_w[N + p] = o[4];
-    if (nonfinite) {
-        bool bad = false;
-#pragma unroll
-        for (int c = 0; c < 5; ++c) bad |= !isfinite(o[c]);
-        if (bad) *nonfinite = 1;
-    }
+    dev::update_point(m, blockIdx.x * kThreads + threadIdx.x, stage, y0_z, y0_w, ys_z, ys_w, u,
+                      V, out_z, out_w, nonfinite);
 }
 
 inline unsigned blocks_for(int n) { return (unsigned)((n + kThreads - 1) / kThreads); }
 
 }  // namespace
+
 
 // ---------------------------------------------------------------------------
 // launch shapes and launchers

@@ -167,3 +167,61 @@ WORKLOADS = {
         "periodic1024_multimode16_fp32", 1024, 1024, atwood=0.9, gravity=1.0, dt=1e-3, steps=5,
         eps_over_h=0.5, seed=2, precision="fp32_pairs", kind="multi_mode", modes=16, noise=1e-4),
 }
+
+
+# --------------------------------------------------------------------------
+# Ensembles and request streams (sizes and draws only)
+# --------------------------------------------------------------------------
+
+ENSEMBLE_SIDES = (32, 48, 64, 96, 128, 192, 256)
+
+
+@dataclass
+class Member:
+    """One simulation of an ensemble or a request stream."""
+    n: int                    # mesh side (n x n)
+    atwood: float
+    amplitude: float          # single-mode amplitude a cos(pi x) cos(pi y)
+    steps: int = 0
+    arrival: float = 0.0      # seconds after the stream starts (requests only)
+
+    @property
+    def eps(self) -> float:
+        return 0.5 * PERIOD / self.n
+
+    def state(self):
+        return single_mode(self.n, self.n, self.amplitude)
+
+
+def ensemble(count: int = 64, seed: int = 3):
+    """Uneven ensemble: per member, in this order, side ~ U{32,...,256},
+    A ~ U[0.1, 0.9], amplitude ~ U[0.01, 0.1]; single mode, no noise."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(count):
+        n = int(rng.choice(ENSEMBLE_SIDES))
+        a = float(rng.uniform(0.1, 0.9))
+        amp = float(rng.uniform(0.01, 0.1))
+        out.append(Member(n, a, amp))
+    return out
+
+
+def request_stream(count: int = 200, rate: float = 1.0, seed: int = 4,
+                   side_min: int = 64, side_max: int = 512, steps_min: int = 100,
+                   steps_max: int = 1000):
+    """Poisson arrivals at `rate` per second.  Per request, in this order:
+    inter-arrival ~ Exp(rate), side = exp(U(ln side_min, ln side_max)) rounded
+    to a multiple of 8, A ~ U[0.1, 0.9], steps ~ U{steps_min..steps_max},
+    amplitude ~ U[0.01, 0.1]."""
+    rng = np.random.default_rng(seed)
+    t = 0.0
+    out = []
+    for _ in range(count):
+        t += float(rng.exponential(1.0 / rate))
+        side = float(np.exp(rng.uniform(math.log(side_min), math.log(side_max))))
+        n = int(max(8, 8 * round(side / 8)))
+        a = float(rng.uniform(0.1, 0.9))
+        steps = int(rng.integers(steps_min, steps_max + 1))
+        amp = float(rng.uniform(0.01, 0.1))
+        out.append(Member(n, a, amp, steps=steps, arrival=t))
+    return out

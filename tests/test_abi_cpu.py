@@ -95,3 +95,12 @@ def test_null_context_calls_are_rejected():
     assert lib.zm_init_state(None, None, None) == zm.ZM_ERR_INVALID_ARG
     assert lib.zm_br_velocity(None, None, None, None) == zm.ZM_ERR_INVALID_ARG
     assert lib.zm_destroy(None) == zm.ZM_OK
+
+
+def test_batch_workspace_validation():
+    ok = [zm.Params(16, 16, eps=1 / 16), zm.Params(32, 24, eps=1 / 32, precision=zm.ZM_FP32_PAIRS)]
+    assert zm.batch_workspace_bytes(ok) > zm.workspace_bytes(ok[0]) + zm.workspace_bytes(ok[1])
+    assert zm.batch_workspace_bytes(ok + [zm.Params(4, 16, eps=1.0)]) == 0
+    assert zm.batch_workspace_bytes([zm.Params(16, 16, eps=1 / 16, flags=1)]) == 0
+    lib = zm.load()
+    assert lib.zm_batch_workspace_bytes(None, 1) == 0
