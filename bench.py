@@ -43,6 +43,11 @@ def parse():
                     help="target CPU time of the oracle sample (0 = skip)")
     ap.add_argument("--no-sweep", action="store_true",
                     help="skip the 1M-point BR sweep (FP64 and FP32 forms)")
+    ap.add_argument("--serve-seconds", type=float, default=30.0,
+                    help="length of the real-time serving window (0 = skip)")
+    ap.add_argument("--tune-report", action="store_true",
+                    help="only autotune the pair kernel for a range of mesh sides and print "
+                         "the choice table (default shape vs tuned)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of this many MiB (counter calibration)")
     return ap.parse_args()
@@ -148,6 +153,138 @@ def small_mesh_latency(zm, torch, steps: int = 50):
     return out
 
 
+def pair_kernel_ms(zm, torch, n: int, prec: int, reps: int = 3) -> float:
+    """Average pair-kernel time (HIP events) of one BR evaluation on an n x n
+    seeded interface with the shape a new context gets."""
+    z, w = rr.random_state(n, n, seed=5, height=0.05)
+    dev = torch.device("cuda:0")
+    ctx = zm.Context(zm.Params(n, n, eps=1.0 / n, precision=prec))
+    zd = torch.from_numpy(z.ravel()).to(dev); wd = torch.from_numpy(w.ravel()).to(dev)
+    ud = torch.empty_like(zd)
+    ctx.br_velocity(zd, wd, ud)
+    torch.cuda.synchronize()
+    ctx.profile_read()
+    ctx.profile_enable(True)
+    for _ in range(reps):
+        ctx.br_velocity(zd, wd, ud)
+    n_, ms = ctx.profile_read()["pairs"]
+    return ms / n_
+
+
+def tune_report(zm, torch, sides=(32, 48, 64, 96, 128, 192, 256, 512, 1024)):
+    """Autotune the pair kernel per (side, precision); report the default and
+    tuned shapes with their measured pair-kernel times."""
+    rows = []
+    for prec, name in ((zm.ZM_FP64, "fp64"), (zm.ZM_FP32_PAIRS, "fp32_pairs")):
+        for n in sides:
+            zm.tuning_set(n, n, prec)
+            d = zm.tuning_get(n, n, prec)
+            ms_d = pair_kernel_ms(zm, torch, n, prec)
+            R, S, _ = zm.autotune(zm.Params(n, n, eps=1.0 / n, precision=prec))
+            ms_t = pair_kernel_ms(zm, torch, n, prec)
+            zm.tuning_set(n, n, prec)
+            rows.append({"side": n, "precision": name,
+                         "default": {"R": d[0], "splits": d[1], "pair_ms": ms_d},
+                         "tuned": {"R": R, "splits": S, "pair_ms": ms_t},
+                         "tuned_pairs_per_s": float(n) ** 4 / (ms_t / 1e3),
+                         "tuned_tflops": FLOPS_PER_PAIR * float(n) ** 4 / (ms_t / 1e3) / 1e12})
+            print(json.dumps(rows[-1]), file=sys.stderr, flush=True)
+    return rows
+
+
+def serving(zm, torch, window_s: float = 30.0, budget: int = 1 << 30, count: int = 200,
+            step_scale: int = 10):
+    """Poisson request stream (sides log-uniform 64..512, A ~ U[0.1, 0.9],
+    100..1000 RK3 steps, FP32 form) served by one pool with a 1 GiB budget.
+    Capacity is measured first on a saturated pool; the arrival rate is then
+    0.8 x capacity and the stream is replayed in real time for window_s.
+
+    Time compression: every request's step count is divided by step_scale
+    (10..100 steps) and the rate multiplied by it.  The mean number of live
+    requests (rate x residence time) and hence the per-step latency
+    distribution of the steady state are unchanged, while a bounded window
+    sees step_scale times more arrivals and completions."""
+    import numpy as np
+    dev = torch.device("cuda:0")
+
+    def params(m):
+        return zm.Params(m.n, m.n, eps=m.eps, atwood=m.atwood, gravity=1.0, dt=1e-3,
+                         precision=zm.ZM_FP32_PAIRS)
+
+    probe = rr.request_stream(count, rate=1.0, seed=4, steps_min=100 // step_scale,
+                              steps_max=1000 // step_scale)
+    mean_pairs = float(np.mean([3.0 * m.n ** 4 * m.steps for m in probe]))
+    # capacity: a saturated pool (requests waiting), pairs/s over 40 iterations
+    pool = zm.Pool(budget)
+    keep = []
+    for m in probe[:40]:
+        z, w = m.state()
+        zt = torch.from_numpy(z.ravel()).to(dev); wt = torch.from_numpy(w.ravel()).to(dev)
+        keep.append((zt, wt))
+        pool.submit(params(m), zt, wt, m.steps)
+    pool.iterate()
+    s0 = pool.stats().pairs_done
+    t0 = time.perf_counter()
+    for _ in range(40):
+        pool.iterate()
+    dt = time.perf_counter() - t0
+    cap_pairs = (pool.stats().pairs_done - s0) / dt
+    pool.destroy(); del keep
+    rate = 0.8 * cap_pairs / mean_pairs
+    stream = rr.request_stream(count, rate=rate, seed=4, steps_min=100 // step_scale,
+                               steps_max=1000 // step_scale)
+    pool = zm.Pool(budget)
+    lat, queue_delay, admitted_at = [], [], {}
+    ids = {}
+    nxt = 0
+    start = time.perf_counter()
+    p0 = pool.stats().pairs_done
+    while True:
+        now = time.perf_counter() - start
+        if now >= window_s:
+            break
+        while nxt < len(stream) and stream[nxt].arrival <= now:
+            m = stream[nxt]
+            z, w = m.state()
+            rid = pool.submit(params(m), torch.from_numpy(z.ravel()).to(dev),
+                              torch.from_numpy(w.ravel()).to(dev), m.steps)
+            ids[rid] = nxt
+            nxt += 1
+        recs = pool.iterate()
+        t_now = time.perf_counter() - start
+        for rid, done, state, ms in recs:
+            lat.append(ms)
+            if rid not in admitted_at:
+                admitted_at[rid] = t_now
+                queue_delay.append(t_now - stream[ids[rid]].arrival)
+            if state == zm.ZM_REQ_FINISHED:
+                pool.release(rid)
+        if not recs:
+            if nxt >= len(stream):
+                break
+            time.sleep(min(0.01, max(0.0, stream[nxt].arrival - t_now)))
+    wall = time.perf_counter() - start
+    st = pool.stats()
+    out = {
+        "requests_total": count, "steps_per_request": [100 // step_scale, 1000 // step_scale],
+        "time_compression": step_scale, "arrived": nxt, "admitted": len(admitted_at),
+        "finished_in_window": sum(1 for r in ids if pool.query(r)[0] == zm.ZM_REQ_UNKNOWN),
+        "window_s": wall, "budget_bytes": budget,
+        "capacity_requests_per_s": cap_pairs / mean_pairs, "rate_requests_per_s": rate,
+        "step_samples": len(lat), "iterations": st.iterations,
+        "p50_step_ms": float(np.percentile(lat, 50)) if lat else None,
+        "p99_step_ms": float(np.percentile(lat, 99)) if lat else None,
+        "mean_step_ms": float(np.mean(lat)) if lat else None,
+        "queue_delay_p50_s": float(np.percentile(queue_delay, 50)) if queue_delay else None,
+        "queue_delay_p99_s": float(np.percentile(queue_delay, 99)) if queue_delay else None,
+        "pairs_per_s": (st.pairs_done - p0) / wall,
+        "saturated_pairs_per_s": cap_pairs,
+        "live_at_end": st.live, "queued_at_end": st.queued,
+    }
+    pool.destroy()
+    return out
+
+
 def oracle_threads() -> int:
     return int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or os.cpu_count()
 
@@ -232,6 +369,10 @@ def main():
     import torch
     import paper_2406_05490_amd as zm
 
+    if args.tune_report:
+        print(json.dumps({"tune_report": tune_report(zm, torch)}), flush=True)
+        return
+
     wl = rr.WORKLOADS[args.workload]
     prec = zm.ZM_FP32_PAIRS if wl.precision == "fp32_pairs" else zm.ZM_FP64
     steps = wl.steps if args.steps is None else args.steps
@@ -307,6 +448,8 @@ def main():
         out["br_sweep_1m"] = br_sweep_1m(zm, torch)
         out["ensemble64_fp32_graph"] = ensemble64(zm, torch)
         out["periodic64_latency"] = small_mesh_latency(zm, torch)
+    if args.serve_seconds > 0:
+        out["serving"] = serving(zm, torch, window_s=args.serve_seconds)
     if args.cpu_seconds > 0:
         out["cpu_baseline"] = cpu_baseline(wl, lambda: zm.Context(p), z0, w0, args.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -88,7 +88,7 @@ typedef int32_t zm_status;
 
 /* ---- parameters ------------------------------------------------------------ */
 typedef struct zm_params {
-    int32_t  n1, n2;           /* mesh points per axis, each >= 8               */
+    int32_t  n1, n2;           /* mesh points per axis, 8 <= n_a <= 8192        */
     double   period1, period2; /* L1, L2 > 0 (parameter and x / y period)       */
     double   atwood;           /* A = (rho+ - rho-) / (rho+ + rho-)             */
     double   gravity;          /* g (acceleration -g e3)                        */
@@ -182,6 +182,37 @@ zm_status zm_profile_enable(zm_ctx *ctx, int32_t on);
  * by ZM_KERNEL_*) and reset the counters. */
 zm_status zm_profile_read(zm_ctx *ctx, zm_kernel_stats *out);
 
+/* ---- launch-shape tuning --------------------------------------------------- */
+/*
+ * The pair kernel's launch shape (targets per lane, number of source ranges
+ * summed separately) is looked up per (n1, n2, precision) in a process-wide
+ * table when a context or batch is created; sizes without an entry use a
+ * built-in default.  The number of source ranges changes the order of the
+ * per-target sums, so contexts and batch members of one size created after
+ * the same tuning give bitwise-identical results.  The table is thread-safe.
+ */
+typedef struct zm_pair_tuning {
+    int32_t targets_per_lane;   /* 1, 2 or 4                                  */
+    int32_t source_splits;      /* >= 1 (clamped to n2)                       */
+} zm_pair_tuning;
+
+/* Set (t != NULL) or remove (t == NULL) the entry for (n1, n2, precision). */
+zm_status zm_tuning_set(int32_t n1, int32_t n2, int32_t precision, const zm_pair_tuning *t);
+
+/* The shape a new context of this size would use (entry or default). */
+zm_status zm_tuning_get(int32_t n1, int32_t n2, int32_t precision, zm_pair_tuning *out);
+
+/* Workspace bytes zm_autotune needs for these parameters (0 if invalid). */
+size_t zm_autotune_workspace_bytes(const zm_params *params);
+
+/* Time the pair kernel on synthetic data of this mesh size for every
+ * candidate shape (targets per lane 1, 2, 4 x source splits around the
+ * default), store the fastest in the table and return it (best, and its
+ * time per launch in best_ms; either may be NULL).  Synchronous: waits for
+ * its own work on hip_stream.  Uses only the caller's workspace. */
+zm_status zm_autotune(const zm_params *params, void *d_workspace, size_t workspace_bytes,
+                      void *hip_stream, zm_pair_tuning *best, double *best_ms);
+
 /* ---- batched ensemble ---------------------------------------------------- */
 /*
  * A batch advances `count` independent instances (each with its own mesh
@@ -233,6 +264,89 @@ zm_status zm_batch_destroy(zm_batch *b);
 /* Last error of this batch ("" if none; NULL: last failed zm_batch_create
  * on this thread). */
 const char *zm_batch_last_error(const zm_batch *b);
+
+/* ---- serving pool ----------------------------------------------------------- */
+/*
+ * Continuous batching of simulation requests of different mesh sizes.  The
+ * caller gives the pool a device budget; requests are admitted first-in
+ * first-out as soon as their footprint (zm_pool_request_bytes) fits in the
+ * free budget, keep their state resident in the pool, and every call of
+ * zm_pool_iterate advances all live requests by one RK3 step with one set
+ * of batched launches (the same arithmetic as a solo context: each request's
+ * trajectory is bitwise identical alone and in the mix).  Membership changes
+ * (admissions, completions, cancellations, failures) take effect between
+ * iterations.  The pool never allocates device memory.
+ */
+typedef struct zm_pool zm_pool;  /* opaque */
+
+#define ZM_REQ_UNKNOWN   (-1)
+#define ZM_REQ_QUEUED      0   /* waiting for budget                            */
+#define ZM_REQ_LIVE        1   /* resident, advanced by every iteration          */
+#define ZM_REQ_FINISHED    2   /* all steps done; state kept until released      */
+#define ZM_REQ_FAILED      3   /* state became non-finite (check-finite pools);
+                                  evicted alone, memory returned                 */
+
+typedef struct zm_step_record {
+    int64_t id;             /* request advanced by the iteration              */
+    int32_t steps_done;     /* its completed RK3 steps after the iteration    */
+    int32_t state;          /* ZM_REQ_* after the iteration                   */
+    double  iteration_ms;   /* device time of the whole batched iteration     */
+} zm_step_record;
+
+typedef struct zm_pool_stats {
+    int32_t queued, live, finished;
+    int32_t iterations;      /* iterations run so far                          */
+    int64_t used_bytes;      /* budget held by live and finished requests      */
+    int64_t budget_bytes;
+    int64_t pairs_done;      /* pair interactions evaluated so far             */
+} zm_pool_stats;
+
+/* Workspace bytes for a pool with this request budget (budget + tables). */
+size_t zm_pool_workspace_bytes(size_t budget_bytes);
+
+/* Budget bytes one request with these parameters occupies (0 if invalid). */
+size_t zm_pool_request_bytes(const zm_params *params);
+
+/* Create a pool on the current device.  flags: 0 or ZM_FLAG_CHECK_FINITE.
+ * Workspace: at least zm_pool_workspace_bytes(budget_bytes), 256-byte
+ * aligned, caller-owned. */
+zm_status zm_pool_create(zm_pool **out, size_t budget_bytes, uint32_t flags, void *d_workspace,
+                         size_t workspace_bytes, void *hip_stream);
+
+/* Queue a request: params (params.flags must be 0), initial state d_z (3
+ * planes) / d_w (2 planes), steps >= 1.  The state is copied when the request
+ * is admitted, so d_z / d_w must stay valid and unchanged until
+ * zm_pool_query reports it no longer queued.  A request larger than the whole
+ * budget is refused with ZM_ERR_CAPACITY. */
+zm_status zm_pool_submit(zm_pool *pool, const zm_params *params, const double *d_z,
+                         const double *d_w, int32_t steps, int64_t *id);
+
+/* One iteration: retire/admit, then one RK3 step of every live request.
+ * Writes up to `capacity` records (one per advanced request) and their
+ * number to *count.  Waits for its own work (the iteration time is measured
+ * with HIP events on the pool stream). */
+zm_status zm_pool_iterate(zm_pool *pool, zm_step_record *records, int32_t capacity,
+                          int32_t *count);
+
+/* State (ZM_REQ_*) and completed steps of a request (ZM_REQ_UNKNOWN for ids
+ * never issued or already released). */
+zm_status zm_pool_query(const zm_pool *pool, int64_t id, int32_t *state, int32_t *steps_done);
+
+/* Copy a live or finished request's current state out. */
+zm_status zm_pool_fetch(zm_pool *pool, int64_t id, double *d_z, double *d_w);
+
+/* Forget a finished or failed request and return its budget. */
+zm_status zm_pool_release(zm_pool *pool, int64_t id);
+
+/* Drop a queued or live request (its budget returns at once). */
+zm_status zm_pool_cancel(zm_pool *pool, int64_t id);
+
+zm_status zm_pool_get_stats(const zm_pool *pool, zm_pool_stats *out);
+
+/* Wait for outstanding work and release host resources (NULL accepted). */
+zm_status zm_pool_destroy(zm_pool *pool);
+
+const char *zm_pool_last_error(const zm_pool *pool);
 
 /* Interface version (incremented on any ABI change). */
 int32_t zm_abi_version(void);

@@ -59,6 +59,28 @@ class zm_kernel_stats(ctypes.Structure):
     _fields_ = [("launches", ctypes.c_int64), ("total_ms", ctypes.c_double)]
 
 
+ZM_REQ_UNKNOWN = -1
+ZM_REQ_QUEUED = 0
+ZM_REQ_LIVE = 1
+ZM_REQ_FINISHED = 2
+ZM_REQ_FAILED = 3
+
+
+class zm_step_record(ctypes.Structure):
+    _fields_ = [("id", ctypes.c_int64), ("steps_done", ctypes.c_int32), ("state", ctypes.c_int32),
+                ("iteration_ms", ctypes.c_double)]
+
+
+class zm_pool_stats(ctypes.Structure):
+    _fields_ = [("queued", ctypes.c_int32), ("live", ctypes.c_int32), ("finished", ctypes.c_int32),
+                ("iterations", ctypes.c_int32), ("used_bytes", ctypes.c_int64),
+                ("budget_bytes", ctypes.c_int64), ("pairs_done", ctypes.c_int64)]
+
+
+class zm_pair_tuning(ctypes.Structure):
+    _fields_ = [("targets_per_lane", ctypes.c_int32), ("source_splits", ctypes.c_int32)]
+
+
 class zm_batch_info(ctypes.Structure):
     _fields_ = [("count", ctypes.c_int32), ("work_items", ctypes.c_int32 * 2),
                 ("persistent_groups", ctypes.c_int32), ("pairs_per_step", ctypes.c_int64)]
@@ -69,8 +91,12 @@ EXPORTS = (
     "zm_workspace_bytes", "zm_create", "zm_init_state", "zm_br_velocity", "zm_rhs",
     "zm_step", "zm_get_state", "zm_destroy", "zm_status_string", "zm_last_error",
     "zm_get_launch_info", "zm_profile_enable", "zm_profile_read",
+    "zm_tuning_set", "zm_tuning_get", "zm_autotune_workspace_bytes", "zm_autotune",
     "zm_batch_workspace_bytes", "zm_batch_create", "zm_batch_init_state", "zm_batch_get_state",
     "zm_batch_step", "zm_batch_get_info", "zm_batch_destroy", "zm_batch_last_error",
+    "zm_pool_workspace_bytes", "zm_pool_request_bytes", "zm_pool_create", "zm_pool_submit",
+    "zm_pool_iterate", "zm_pool_query", "zm_pool_fetch", "zm_pool_release", "zm_pool_cancel",
+    "zm_pool_get_stats", "zm_pool_destroy", "zm_pool_last_error",
     "zm_abi_version",
 )
 
@@ -84,7 +110,7 @@ def load(path: str = LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise ImportError(f"{path} is missing: build it with "
-                          "`python -m paper_2406_05490_amd.build` (no fallback exists)")
+                          "`python paper_2406_05490_amd/build.py` (no fallback exists)")
     # PyTorch ships its own HIP runtime.  Loading torch first makes the
     # library's libamdhip64.so.7 dependency resolve to that same runtime, so
     # torch's streams and allocations are valid in the library (a second
@@ -119,6 +145,15 @@ def load(path: str = LIB_PATH):
     lib.zm_profile_enable.restype = ctypes.c_int32
     lib.zm_profile_read.argtypes = [vp, ctypes.POINTER(zm_kernel_stats)]
     lib.zm_profile_read.restype = ctypes.c_int32
+    T = ctypes.POINTER(zm_pair_tuning)
+    lib.zm_tuning_set.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, T]
+    lib.zm_tuning_set.restype = ctypes.c_int32
+    lib.zm_tuning_get.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, T]
+    lib.zm_tuning_get.restype = ctypes.c_int32
+    lib.zm_autotune_workspace_bytes.argtypes = [P]
+    lib.zm_autotune_workspace_bytes.restype = ctypes.c_size_t
+    lib.zm_autotune.argtypes = [P, vp, ctypes.c_size_t, vp, T, ctypes.POINTER(ctypes.c_double)]
+    lib.zm_autotune.restype = ctypes.c_int32
     lib.zm_batch_workspace_bytes.argtypes = [P, ctypes.c_int32]
     lib.zm_batch_workspace_bytes.restype = ctypes.c_size_t
     lib.zm_batch_create.argtypes = [ctypes.POINTER(vp), P, ctypes.c_int32, ctypes.c_uint32, vp,
@@ -136,6 +171,33 @@ def load(path: str = LIB_PATH):
     lib.zm_batch_destroy.restype = ctypes.c_int32
     lib.zm_batch_last_error.argtypes = [vp]
     lib.zm_batch_last_error.restype = ctypes.c_char_p
+    I64P = ctypes.POINTER(ctypes.c_int64)
+    I32P = ctypes.POINTER(ctypes.c_int32)
+    lib.zm_pool_workspace_bytes.argtypes = [ctypes.c_size_t]
+    lib.zm_pool_workspace_bytes.restype = ctypes.c_size_t
+    lib.zm_pool_request_bytes.argtypes = [P]
+    lib.zm_pool_request_bytes.restype = ctypes.c_size_t
+    lib.zm_pool_create.argtypes = [ctypes.POINTER(vp), ctypes.c_size_t, ctypes.c_uint32, vp,
+                                   ctypes.c_size_t, vp]
+    lib.zm_pool_create.restype = ctypes.c_int32
+    lib.zm_pool_submit.argtypes = [vp, P, vp, vp, ctypes.c_int32, I64P]
+    lib.zm_pool_submit.restype = ctypes.c_int32
+    lib.zm_pool_iterate.argtypes = [vp, ctypes.POINTER(zm_step_record), ctypes.c_int32, I32P]
+    lib.zm_pool_iterate.restype = ctypes.c_int32
+    lib.zm_pool_query.argtypes = [vp, ctypes.c_int64, I32P, I32P]
+    lib.zm_pool_query.restype = ctypes.c_int32
+    lib.zm_pool_fetch.argtypes = [vp, ctypes.c_int64, vp, vp]
+    lib.zm_pool_fetch.restype = ctypes.c_int32
+    lib.zm_pool_release.argtypes = [vp, ctypes.c_int64]
+    lib.zm_pool_release.restype = ctypes.c_int32
+    lib.zm_pool_cancel.argtypes = [vp, ctypes.c_int64]
+    lib.zm_pool_cancel.restype = ctypes.c_int32
+    lib.zm_pool_get_stats.argtypes = [vp, ctypes.POINTER(zm_pool_stats)]
+    lib.zm_pool_get_stats.restype = ctypes.c_int32
+    lib.zm_pool_destroy.argtypes = [vp]
+    lib.zm_pool_destroy.restype = ctypes.c_int32
+    lib.zm_pool_last_error.argtypes = [vp]
+    lib.zm_pool_last_error.restype = ctypes.c_char_p
     lib.zm_abi_version.argtypes = []
     lib.zm_abi_version.restype = ctypes.c_int32
     _lib = lib
@@ -259,6 +321,45 @@ class Context:
             pass
 
 
+def tuning_set(n1: int, n2: int, precision: int, targets_per_lane=None, source_splits=None):
+    """Set the launch shape for a mesh size (None, None: remove the entry)."""
+    lib = load()
+    if targets_per_lane is None:
+        st = lib.zm_tuning_set(n1, n2, precision, None)
+    else:
+        t = zm_pair_tuning(int(targets_per_lane), int(source_splits))
+        st = lib.zm_tuning_set(n1, n2, precision, ctypes.byref(t))
+    if st != ZM_OK:
+        raise ZMError(st, "tuning_set")
+
+
+def tuning_get(n1: int, n2: int, precision: int):
+    out = zm_pair_tuning()
+    st = load().zm_tuning_get(n1, n2, precision, ctypes.byref(out))
+    if st != ZM_OK:
+        raise ZMError(st, "tuning_get")
+    return int(out.targets_per_lane), int(out.source_splits)
+
+
+def autotune(p: "Params", stream=None):
+    """Time the candidate launch shapes for p's mesh size, store the fastest
+    in the process-wide table; returns (targets_per_lane, splits, ms)."""
+    import torch
+    lib = load()
+    nbytes = int(lib.zm_autotune_workspace_bytes(ctypes.byref(p.c())))
+    if nbytes == 0:
+        raise ZMError(ZM_ERR_INVALID_ARG, "invalid parameters")
+    ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    stream = torch.cuda.current_stream() if stream is None else stream
+    best = zm_pair_tuning()
+    ms = ctypes.c_double()
+    st = lib.zm_autotune(ctypes.byref(p.c()), ws.data_ptr(), nbytes, stream.cuda_stream,
+                         ctypes.byref(best), ctypes.byref(ms))
+    if st != ZM_OK:
+        raise ZMError(st, "autotune")
+    return int(best.targets_per_lane), int(best.source_splits), float(ms.value)
+
+
 def _params_array(ps):
     arr = (zm_params * len(ps))()
     for i, p in enumerate(ps):
@@ -321,6 +422,86 @@ class Batch:
             self.handle = None
             if st != ZM_OK:
                 raise ZMError(st, "batch destroy")
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+def pool_request_bytes(p: Params) -> int:
+    return int(load().zm_pool_request_bytes(ctypes.byref(p.c())))
+
+
+class Pool:
+    """One zm_pool: continuous batching of simulation requests."""
+
+    def __init__(self, budget_bytes: int, flags: int = 0, stream=None, device=None):
+        import torch
+        self.lib = load()
+        dev = torch.device("cuda", torch.cuda.current_device()) if device is None else device
+        nbytes = int(self.lib.zm_pool_workspace_bytes(int(budget_bytes)))
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+        self.stream = torch.cuda.current_stream(dev) if stream is None else stream
+        self._inputs = {}          # id -> (z, w) kept alive until admitted
+        h = ctypes.c_void_p()
+        with torch.cuda.device(dev):
+            st = self.lib.zm_pool_create(ctypes.byref(h), int(budget_bytes), int(flags),
+                                         self.workspace.data_ptr(), nbytes, self.stream.cuda_stream)
+        if st != ZM_OK:
+            raise ZMError(st, self.lib.zm_pool_last_error(None).decode())
+        self.handle = h
+        self._rec = (zm_step_record * 4096)()
+
+    def _raise(self, st):
+        if st != ZM_OK:
+            raise ZMError(st, self.lib.zm_pool_last_error(self.handle).decode())
+
+    def submit(self, p: Params, z, w, steps: int) -> int:
+        _check_f64_planes(z, 3, p.n, "z"); _check_f64_planes(w, 2, p.n, "w")
+        rid = ctypes.c_int64()
+        self._raise(self.lib.zm_pool_submit(self.handle, ctypes.byref(p.c()), _ptr(z), _ptr(w),
+                                            int(steps), ctypes.byref(rid)))
+        self._inputs[rid.value] = (z, w)
+        return rid.value
+
+    def iterate(self):
+        """One iteration; returns [(id, steps_done, state, iteration_ms)]."""
+        n = ctypes.c_int32()
+        self._raise(self.lib.zm_pool_iterate(self.handle, self._rec, len(self._rec), ctypes.byref(n)))
+        out = [(r.id, r.steps_done, r.state, r.iteration_ms) for r in self._rec[:n.value]]
+        for rid in list(self._inputs):
+            if self.query(rid)[0] != ZM_REQ_QUEUED:
+                del self._inputs[rid]
+        return out
+
+    def query(self, rid: int):
+        st, done = ctypes.c_int32(), ctypes.c_int32()
+        self._raise(self.lib.zm_pool_query(self.handle, int(rid), ctypes.byref(st), ctypes.byref(done)))
+        return st.value, done.value
+
+    def fetch(self, rid: int, z, w):
+        self._raise(self.lib.zm_pool_fetch(self.handle, int(rid), _ptr(z), _ptr(w)))
+
+    def release(self, rid: int):
+        self._raise(self.lib.zm_pool_release(self.handle, int(rid)))
+
+    def cancel(self, rid: int):
+        self._raise(self.lib.zm_pool_cancel(self.handle, int(rid)))
+        self._inputs.pop(rid, None)
+
+    def stats(self) -> zm_pool_stats:
+        out = zm_pool_stats()
+        self._raise(self.lib.zm_pool_get_stats(self.handle, ctypes.byref(out)))
+        return out
+
+    def destroy(self):
+        if getattr(self, "handle", None) is not None:
+            st = self.lib.zm_pool_destroy(self.handle)
+            self.handle = None
+            if st != ZM_OK:
+                raise ZMError(st, "pool destroy")
 
     def __del__(self):
         try:

@@ -1,6 +1,9 @@
 """Build libzm.so (HIP kernels + host runtime) in-tree for gfx950.
 
-    python -m paper_2406_05490_amd.build [-v] [--asm DIR]
+    python paper_2406_05490_amd/build.py [-v] [--asm DIR]
+
+Run it as a script (or load it by file path): importing the package itself
+loads libzm.so, which is what this builds.
 
 Packed-FP32 instruction selection is disabled for all device code.
 """
@@ -16,7 +19,8 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libzm.so")
 SOURCES = [os.path.join(CSRC, f) for f in
-           ("zm_kernels.hip", "zm_batch.hip", "zm_api.hip", "zm_batch_api.hip")]
+           ("zm_kernels.hip", "zm_batch.hip", "zm_api.hip", "zm_batch_api.hip", "zm_tune.hip",
+            "zm_pool_api.hip")]
 ARCH = "gfx950"
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

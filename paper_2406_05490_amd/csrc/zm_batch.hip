@@ -31,6 +31,18 @@ __device__ __forceinline__ int find_instance(const InstDesc* __restrict__ T, int
     return lo;
 }
 
+// The same search over the tie kernel's block offsets.
+__device__ __forceinline__ int find_tie_instance(const InstDesc* __restrict__ T, int count, int b)
+{
+    int lo = 0, hi = count - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (T[mid].tie_block_begin <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
 __global__ __launch_bounds__(kThreads) void kb_surface(const InstDesc* __restrict__ T, int count,
                                                        int stage)
 {
@@ -44,10 +56,13 @@ __global__ __launch_bounds__(kThreads) void kb_surface(const InstDesc* __restric
 __global__ __launch_bounds__(kThreads) void kb_ties(const InstDesc* __restrict__ T, int count,
                                                     int stage)
 {
-    const int i = find_instance(T, count, blockIdx.x);
+    const int i = find_tie_instance(T, count, blockIdx.x);
     const InstDesc& d = T[i];
-    const int p = (blockIdx.x - d.block_begin) * kThreads + threadIdx.x;
-    dev::ties_point(d.m, p, blockIdx.y, d.Y[stage], d.gam, d.tie);
+    const int t = (blockIdx.x - d.tie_block_begin) * kThreads + threadIdx.x;
+    const int L = dev::tie_lanes(d.m.N);   // uniform over the block (one instance)
+    if (L == 1) dev::ties_group<1>(d.m, t, 0, blockIdx.y, d.Y[stage], d.gam, d.tie);
+    else if (L == 4) dev::ties_group<4>(d.m, t / 4, t % 4, blockIdx.y, d.Y[stage], d.gam, d.tie);
+    else dev::ties_group<16>(d.m, t / 16, t % 16, blockIdx.y, d.Y[stage], d.gam, d.tie);
 }
 
 __global__ __launch_bounds__(kThreads) void kb_reduce(const InstDesc* __restrict__ T, int count,
@@ -60,7 +75,7 @@ __global__ __launch_bounds__(kThreads) void kb_reduce(const InstDesc* __restrict
 }
 
 __global__ __launch_bounds__(kThreads) void kb_update(const InstDesc* __restrict__ T, int count,
-                                                      int stage, int* __restrict__ nonfinite)
+                                                      int stage)
 {
     const int i = find_instance(T, count, blockIdx.x);
     const InstDesc& d = T[i];
@@ -70,7 +85,7 @@ __global__ __launch_bounds__(kThreads) void kb_update(const InstDesc* __restrict
     double* out = d.Y[(stage + 1) % 3];
     const double* y0 = d.Y[0];
     dev::update_point(d.m, p, stage, y0, y0 + 3 * N, ys, ys + 3 * N, d.u, d.V, out, out + 3 * N,
-                      nonfinite);
+                      d.flag);
 }
 
 // Resets the work counter of a persistent launch (a kernel, not a memset, so
@@ -102,6 +117,7 @@ __global__ __launch_bounds__(kThreads) void kb_pairs_f64(const InstDesc* __restr
             dev::pairs_f64_block<R, 16>(d.m, d.sh, d.Y[stage], d.gam, d.part, w.patch, w.split, lds);
         else
             dev::pairs_f64_block<R, 8>(d.m, d.sh, d.Y[stage], d.gam, d.part, w.patch, w.split, lds);
+        // the body ends with a barrier, so `next` and the LDS tiles are free
     }
 }
 
@@ -136,28 +152,36 @@ __global__ __launch_bounds__(kThreads) void kb_pairs_f32(const InstDesc* __restr
 
 }  // namespace
 
-hipError_t launch_batch_stage(const BatchLaunch& b, int stage, int* nonfinite, hipStream_t s)
+int dev_tie_lanes(int N) { return dev::tie_lanes(N); }
+
+hipError_t launch_batch_stage(const BatchLaunch& b, int stage, hipStream_t s)
 {
     if (b.count <= 0) return hipSuccess;
     const dim3 blk(kThreads);
     hipLaunchKernelGGL(kb_surface, dim3(b.total_blocks), blk, 0, s, b.table, b.count, stage);
-    for (int prec = 0; prec < 2; ++prec) {
-        const int n = b.nitems[prec];
-        if (n == 0) continue;
-        hipLaunchKernelGGL(kb_reset, dim3(1), dim3(64), 0, s, b.counters + prec);
-        const unsigned grid = (unsigned)(n < b.persistent_groups ? n : b.persistent_groups);
-        const WorkItem* items = b.items + b.item_begin[prec];
-        if (prec == 0)
-            hipLaunchKernelGGL((kb_pairs_f64<ZM_PAIR_R>), dim3(grid), blk, 0, s, b.table, items, n,
-                               b.counters + prec, stage);
-        else
-            hipLaunchKernelGGL((kb_pairs_f32<ZM_PAIR32_R>), dim3(grid), blk, 0, s, b.table, items,
-                               n, b.counters + prec, stage);
+    for (int g = 0; g < b.ngroups; ++g) {
+        const PairGroup& G = b.groups[g];
+        if (G.nitems == 0) continue;
+        hipLaunchKernelGGL(kb_reset, dim3(1), dim3(64), 0, s, b.counters + g);
+        const unsigned grid = (unsigned)(G.nitems < b.persistent_groups ? G.nitems
+                                                                         : b.persistent_groups);
+        const WorkItem* items = b.items + G.item_begin;
+        int* ctr = b.counters + g;
+        const int n = G.nitems;
+        if (G.precision == 0) {
+            if (G.R == 1) hipLaunchKernelGGL((kb_pairs_f64<1>), dim3(grid), blk, 0, s, b.table, items, n, ctr, stage);
+            else if (G.R == 2) hipLaunchKernelGGL((kb_pairs_f64<2>), dim3(grid), blk, 0, s, b.table, items, n, ctr, stage);
+            else hipLaunchKernelGGL((kb_pairs_f64<4>), dim3(grid), blk, 0, s, b.table, items, n, ctr, stage);
+        } else {
+            if (G.R == 1) hipLaunchKernelGGL((kb_pairs_f32<1>), dim3(grid), blk, 0, s, b.table, items, n, ctr, stage);
+            else if (G.R == 2) hipLaunchKernelGGL((kb_pairs_f32<2>), dim3(grid), blk, 0, s, b.table, items, n, ctr, stage);
+            else hipLaunchKernelGGL((kb_pairs_f32<4>), dim3(grid), blk, 0, s, b.table, items, n, ctr, stage);
+        }
     }
-    if (b.any_even) hipLaunchKernelGGL(kb_ties, dim3(b.total_blocks, 2), blk, 0, s, b.table, b.count, stage);
+    if (b.any_even)
+        hipLaunchKernelGGL(kb_ties, dim3(b.total_tie_blocks, 2), blk, 0, s, b.table, b.count, stage);
     hipLaunchKernelGGL(kb_reduce, dim3(b.total_blocks), blk, 0, s, b.table, b.count, stage);
-    hipLaunchKernelGGL(kb_update, dim3(b.total_blocks), blk, 0, s, b.table, b.count, stage,
-                       nonfinite);
+    hipLaunchKernelGGL(kb_update, dim3(b.total_blocks), blk, 0, s, b.table, b.count, stage);
     return hipGetLastError();
 }
 

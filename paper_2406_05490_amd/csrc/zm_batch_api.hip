@@ -25,12 +25,18 @@ struct BatchPlan {
     std::vector<zm::PairShape> shapes;
     std::vector<zm::Layout> layouts;
     std::vector<size_t> inst_off;
-    std::vector<zm::WorkItem> items;   // FP64 items then FP32 items
-    int nitems[2] = {0, 0};
+    size_t n_items = 0;
     size_t table_off = 0, items_off = 0, counters_off = 0, flag_off = 0, total = 0;
-    int total_blocks = 0;
-    bool any_even = false;
 };
+
+// Number of pair work items of one member.
+size_t count_items(const zm_params& p, const zm::PairShape& sh)
+{
+    size_t n = 0;
+    for (int sp = 0; sp < sh.splits; ++sp)
+        if (p.n2 - sp * sh.rows_per_split > 0) ++n;
+    return n * (size_t)(sh.px * sh.py);
+}
 
 const char* plan_batch(const zm_params* params, int32_t count, BatchPlan& P)
 {
@@ -38,7 +44,6 @@ const char* plan_batch(const zm_params* params, int32_t count, BatchPlan& P)
     if (count < 1) return "count must be >= 1";
     if (count > (1 << 20)) return "count too large";
     size_t off = 0;
-    std::vector<std::pair<double, zm::WorkItem>> keyed[2];
     for (int i = 0; i < count; ++i) {
         if (const char* why = zm::validate(&params[i])) return why;
         if (params[i].flags != 0) return "per-instance flags must be 0 in a batch";
@@ -49,32 +54,14 @@ const char* plan_batch(const zm_params* params, int32_t count, BatchPlan& P)
         P.layouts.push_back(L);
         P.inst_off.push_back(off);
         off = zm::align_up(off + L.total);
-        const int N = params[i].n1 * params[i].n2;
-        P.total_blocks += (N + 255) / 256;
-        if (params[i].n1 % 2 == 0 || params[i].n2 % 2 == 0) P.any_even = true;
-        const int prec = params[i].precision == ZM_FP32_PAIRS ? 1 : 0;
-        const int side = 2 * params[i].image_layers + 1;
-        for (int pt = 0; pt < sh.px * sh.py; ++pt) {
-            for (int sp = 0; sp < sh.splits; ++sp) {
-                const int rows = std::min(sh.rows_per_split, params[i].n2 - sp * sh.rows_per_split);
-                if (rows <= 0) continue;
-                const double cost = (double)rows * params[i].n1 * side * side;
-                keyed[prec].push_back({cost, zm::WorkItem{i, pt, sp, 0}});
-            }
-        }
-    }
-    for (int prec = 0; prec < 2; ++prec) {
-        std::stable_sort(keyed[prec].begin(), keyed[prec].end(),
-                         [](const auto& a, const auto& b) { return a.first > b.first; });
-        P.nitems[prec] = (int)keyed[prec].size();
-        for (auto& k : keyed[prec]) P.items.push_back(k.second);
+        P.n_items += count_items(params[i], sh);
     }
     P.table_off = off;
     off = zm::align_up(off + sizeof(zm::InstDesc) * count);
     P.items_off = off;
-    off = zm::align_up(off + sizeof(zm::WorkItem) * std::max<size_t>(1, P.items.size()));
+    off = zm::align_up(off + sizeof(zm::WorkItem) * std::max<size_t>(1, P.n_items));
     P.counters_off = off;
-    off = zm::align_up(off + 2 * sizeof(int));
+    off = zm::align_up(off + zm::kMaxPairGroups * sizeof(int));
     P.flag_off = off;
     off = zm::align_up(off + sizeof(int));
     P.total = off;
@@ -86,6 +73,7 @@ const char* plan_batch(const zm_params* params, int32_t count, BatchPlan& P)
 struct zm_batch {
     std::vector<zm_params> prm;
     BatchPlan plan;
+    std::vector<zm::PairGroup> groups;
     zm::BatchLaunch launch;
     hipStream_t stream = nullptr;
     int device = 0;
@@ -111,10 +99,8 @@ zm_status bhip(zm_batch* b, hipError_t e, const char* where)
 
 hipError_t enqueue_step(zm_batch* b, hipStream_t s)
 {
-    int* flag = (b->flags & ZM_FLAG_CHECK_FINITE)
-                    ? reinterpret_cast<int*>(b->ws + b->plan.flag_off) : nullptr;
     for (int stage = 0; stage < 3; ++stage) {
-        hipError_t e = zm::launch_batch_stage(b->launch, stage, flag, s);
+        hipError_t e = zm::launch_batch_stage(b->launch, stage, s);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
@@ -139,6 +125,66 @@ zm_status ensure_graph(zm_batch* b)
 }
 
 }  // namespace
+
+namespace zm {
+
+void build_tables(const zm_params* params, const PairShape* shapes, const Layout* layouts,
+                  char* const* bases, int* const* flags, int count, TableBuild& out)
+{
+    out = TableBuild();
+    out.table.resize(count);
+    std::vector<std::pair<double, WorkItem>> keyed[kMaxPairGroups];
+    int block = 0, tie_block = 0;
+    for (int i = 0; i < count; ++i) {
+        InstDesc& d = out.table[i];
+        std::memset(&d, 0, sizeof(d));
+        d.m = make_mesh(params[i]);
+        d.sh = shapes[i];
+        d.precision = params[i].precision;
+        d.block_begin = block;
+        d.blocks = (d.m.N + 255) / 256;
+        block += d.blocks;
+        d.tie_block_begin = tie_block;
+        tie_block += (d.m.N * dev_tie_lanes(d.m.N) + 255) / 256;
+        char* base = bases[i];
+        const Layout& L = layouts[i];
+        d.Y[0] = reinterpret_cast<double*>(base + L.y0);
+        d.Y[1] = reinterpret_cast<double*>(base + L.y1);
+        d.Y[2] = reinterpret_cast<double*>(base + L.y2);
+        d.gam = reinterpret_cast<double*>(base + L.gam);
+        d.q = reinterpret_cast<double*>(base + L.q);
+        d.part = reinterpret_cast<double*>(base + L.part);
+        d.tie = reinterpret_cast<double*>(base + L.tie);
+        d.u = reinterpret_cast<double*>(base + L.u);
+        d.V = reinterpret_cast<double*>(base + L.V);
+        d.flag = flags ? flags[i] : nullptr;
+        if (params[i].n1 % 2 == 0 || params[i].n2 % 2 == 0) out.any_even = true;
+        const PairShape& sh = shapes[i];
+        const int g = (params[i].precision == ZM_FP32_PAIRS ? 3 : 0) +
+                      (sh.R == 1 ? 0 : (sh.R == 2 ? 1 : 2));
+        const int side = 2 * params[i].image_layers + 1;
+        for (int pt = 0; pt < sh.px * sh.py; ++pt) {
+            for (int sp = 0; sp < sh.splits; ++sp) {
+                const int rows = std::min(sh.rows_per_split, params[i].n2 - sp * sh.rows_per_split);
+                if (rows <= 0) continue;
+                const double cost = (double)rows * params[i].n1 * side * side;
+                keyed[g].push_back({cost, WorkItem{i, pt, sp, 0}});
+            }
+        }
+    }
+    out.total_blocks = block;
+    out.total_tie_blocks = tie_block;
+    static const int kR[3] = {1, 2, 4};
+    for (int g = 0; g < kMaxPairGroups; ++g) {
+        if (keyed[g].empty()) continue;
+        std::stable_sort(keyed[g].begin(), keyed[g].end(),
+                         [](const auto& a, const auto& b) { return a.first > b.first; });
+        out.groups.push_back(PairGroup{g / 3, kR[g % 3], (int)out.items.size(), (int)keyed[g].size()});
+        for (auto& k : keyed[g]) out.items.push_back(k.second);
+    }
+}
+
+}  // namespace zm
 
 extern "C" {
 
@@ -186,35 +232,23 @@ zm_status zm_batch_create(zm_batch** out, const zm_params* params, int32_t count
     b->flags = batch_flags;
     const BatchPlan& P = b->plan;
 
-    std::vector<zm::InstDesc> table(count);
-    int block = 0;
+    std::vector<char*> bases(count);
+    std::vector<int*> flags(count);
     for (int i = 0; i < count; ++i) {
-        zm::InstDesc& d = table[i];
-        std::memset(&d, 0, sizeof(d));
-        d.m = zm::make_mesh(params[i]);
-        d.sh = P.shapes[i];
-        d.precision = params[i].precision;
-        d.block_begin = block;
-        d.blocks = (d.m.N + 255) / 256;
-        block += d.blocks;
-        char* base = b->ws + P.inst_off[i];
-        const zm::Layout& L = P.layouts[i];
-        d.Y[0] = reinterpret_cast<double*>(base + L.y0);
-        d.Y[1] = reinterpret_cast<double*>(base + L.y1);
-        d.Y[2] = reinterpret_cast<double*>(base + L.y2);
-        d.gam = reinterpret_cast<double*>(base + L.gam);
-        d.q = reinterpret_cast<double*>(base + L.q);
-        d.part = reinterpret_cast<double*>(base + L.part);
-        d.tie = reinterpret_cast<double*>(base + L.tie);
-        d.u = reinterpret_cast<double*>(base + L.u);
-        d.V = reinterpret_cast<double*>(base + L.V);
+        bases[i] = b->ws + P.inst_off[i];
+        flags[i] = (batch_flags & ZM_FLAG_CHECK_FINITE) ? reinterpret_cast<int*>(b->ws + P.flag_off)
+                                                        : nullptr;
     }
+    zm::TableBuild tb;
+    zm::build_tables(params, P.shapes.data(), P.layouts.data(), bases.data(), flags.data(), count,
+                     tb);
+    b->groups = tb.groups;
     zm::InstDesc* dtable = reinterpret_cast<zm::InstDesc*>(b->ws + P.table_off);
     zm::WorkItem* ditems = reinterpret_cast<zm::WorkItem*>(b->ws + P.items_off);
-    e = hipMemcpyAsync(dtable, table.data(), sizeof(zm::InstDesc) * count, hipMemcpyHostToDevice,
+    e = hipMemcpyAsync(dtable, tb.table.data(), sizeof(zm::InstDesc) * count, hipMemcpyHostToDevice,
                        b->stream);
-    if (e == hipSuccess && !P.items.empty())
-        e = hipMemcpyAsync(ditems, P.items.data(), sizeof(zm::WorkItem) * P.items.size(),
+    if (e == hipSuccess && !tb.items.empty())
+        e = hipMemcpyAsync(ditems, tb.items.data(), sizeof(zm::WorkItem) * tb.items.size(),
                            hipMemcpyHostToDevice, b->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
     if (e != hipSuccess) {
@@ -225,15 +259,14 @@ zm_status zm_batch_create(zm_batch** out, const zm_params* params, int32_t count
     zm::BatchLaunch& L = b->launch;
     L.table = dtable;
     L.count = count;
-    L.total_blocks = P.total_blocks;
+    L.total_blocks = tb.total_blocks;
+    L.total_tie_blocks = tb.total_tie_blocks;
     L.items = ditems;
-    L.nitems[0] = P.nitems[0];
-    L.nitems[1] = P.nitems[1];
-    L.item_begin[0] = 0;
-    L.item_begin[1] = P.nitems[0];
+    L.ngroups = (int)tb.groups.size();
+    for (int g = 0; g < L.ngroups; ++g) L.groups[g] = tb.groups[g];
     L.counters = reinterpret_cast<int*>(b->ws + P.counters_off);
     L.persistent_groups = 4 * (cus > 0 ? cus : 256);
-    L.any_even = P.any_even;
+    L.any_even = tb.any_even;
     *out = b;
     return ZM_OK;
 }
@@ -317,8 +350,8 @@ zm_status zm_batch_get_info(const zm_batch* b, zm_batch_info* out)
 {
     if (!b || !out) return ZM_ERR_INVALID_ARG;
     out->count = (int32_t)b->prm.size();
-    out->work_items[0] = b->plan.nitems[0];
-    out->work_items[1] = b->plan.nitems[1];
+    out->work_items[0] = out->work_items[1] = 0;
+    for (const auto& G : b->groups) out->work_items[G.precision] += G.nitems;
     out->persistent_groups = b->launch.persistent_groups;
     int64_t pairs = 0;
     for (const auto& p : b->prm) {

@@ -2,9 +2,12 @@
 // side (zm_batch_api.hip).  Not part of the public ABI.
 #pragma once
 
+#include "zm_host.h"
 #include "zm_internal.h"
 
 #include <hip/hip_runtime.h>
+
+#include <vector>
 
 namespace zm {
 
@@ -15,7 +18,7 @@ struct InstDesc {
     int precision;       // 0 = FP64 pairs, 1 = FP32 pairs
     int block_begin;     // first block of this instance in the point kernels
     int blocks;          // ceil(N / 256)
-    int pad_;
+    int tie_block_begin; // first block of this instance in the tie kernel
     double* Y[3];        // RK3 stage states, 5 planes each
     double* gam;         // 3 planes
     double* q;           // 1 plane
@@ -23,6 +26,7 @@ struct InstDesc {
     double* tie;         // 2 x 3 planes
     double* u;           // 3 planes
     double* V;           // 1 plane
+    int* flag;           // set to 1 by the update if this instance's state is not finite (may be NULL)
 };
 
 // One unit of the persistent pair sweep.
@@ -33,21 +37,54 @@ struct WorkItem {
     int pad_;
 };
 
+// Items of one persistent pair launch: same precision and targets per lane.
+struct PairGroup {
+    int precision;
+    int R;
+    int item_begin;
+    int nitems;
+};
+
+constexpr int kMaxPairGroups = 6;   // 2 precisions x R in {1, 2, 4}
+
 // Everything one batched RK3 stage needs (device pointers + host counts).
 struct BatchLaunch {
     const InstDesc* table;   // device, count entries, block_begin ascending
     int count;
     int total_blocks;
-    const WorkItem* items;   // device; FP64 items then FP32 items, each longest first
-    int nitems[2];
-    int item_begin[2];
-    int* counters;           // device, one work counter per precision
+    int total_tie_blocks;
+    const WorkItem* items;   // device; grouped by PairGroup, each group longest first
+    PairGroup groups[kMaxPairGroups];
+    int ngroups;
+    int* counters;           // device, one work counter per group
     int persistent_groups;   // workgroups of a persistent pair launch
     bool any_even;           // some instance has an even side (tie pass needed)
 };
 
+// Lanes per target of the tie kernel for an N-point mesh (host mirror of the
+// device rule; both come from zm_device.h's tie_lanes).
+int dev_tie_lanes(int N);
+
 // Enqueue one RK3 stage (surface, pairs, ties, reduce, update) for every
-// instance of the batch.
-hipError_t launch_batch_stage(const BatchLaunch& b, int stage, int* nonfinite, hipStream_t s);
+// instance of the batch.  Non-finite results are flagged per instance
+// through InstDesc::flag.
+hipError_t launch_batch_stage(const BatchLaunch& b, int stage, hipStream_t s);
+
+// Host-side tables for a set of instances: descriptors, pair work items
+// grouped by (precision, targets per lane) and ordered longest first within a
+// group, block offsets of the point kernels.
+struct TableBuild {
+    std::vector<InstDesc> table;
+    std::vector<WorkItem> items;
+    std::vector<PairGroup> groups;
+    int total_blocks = 0;
+    int total_tie_blocks = 0;
+    bool any_even = false;
+};
+
+// Member i: parameters, pair shape, workspace layout, base address of its
+// region and its non-finite flag (may be NULL).
+void build_tables(const zm_params* params, const PairShape* shapes, const Layout* layouts,
+                  char* const* bases, int* const* flags, int count, TableBuild& out);
 
 }  // namespace zm

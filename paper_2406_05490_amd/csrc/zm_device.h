@@ -14,7 +14,7 @@
 //                     arithmetic on the VALU; per-target sums blocked per row.
 //   pairs_f32_block   the same in FP32 pair arithmetic with tile-relative
 //                     coordinates and FP64 per-target sums.
-//   ties_point        split-tie correction for even n_a.
+//   ties_group        split-tie correction for even n_a (1-16 lanes per target).
 //   reduce_point      fixed-order sum over source splits and tie passes,
 //                     scale, Bernoulli potential V.
 //   update_point      D V (+ nu Lap w) and the SSP-RK3 stage combination.
@@ -32,12 +32,6 @@ constexpr int kThreads = 256;
 // Source-loop unroll depth and targets per lane of the pair kernel.
 #ifndef ZM_PAIR_UNROLL
 #define ZM_PAIR_UNROLL 2
-#endif
-#ifndef ZM_PAIR_R
-#define ZM_PAIR_R 4
-#endif
-#ifndef ZM_PAIR32_R
-#define ZM_PAIR32_R 4
 #endif
 
 // Periodic neighbour index along one axis; sets wrap to -1/0/+1.
@@ -622,11 +616,25 @@ __device__ __forceinline__ void tie_term(const Mesh& m, double xi, double yi, do
 // row (needs n2 even).  The pair kernel counted each tied source once at
 // the image s_hi; the correct weight is 1/2 at s_hi and 1/2 at s_lo on each
 // tied axis.  The corner (tied on both axes) is handled by pass 0.
-__device__ __forceinline__ void ties_point(const Mesh& m, int p, int pass,
+// Lanes that share one target's tie sources (L in {1, 4, 16}, chosen from the
+// mesh size only); their partial sums are combined by a fixed butterfly, so
+// the result does not depend on scheduling.  Small meshes use more lanes per
+// target for parallelism; large ones use one, which keeps the tie-column
+// gathers of neighbouring targets coalesced.
+__host__ __device__ inline int tie_lanes(int N) { return N >= 16384 ? 1 : (N >= 4096 ? 4 : 16); }
+
+// p: target point; lane in [0, L) of the target's lane group; pass 0
+// corrects the tie column (needs n1 even), pass 1 the tie row (needs n2
+// even).  The pair kernels counted each tied source once at the image s_hi;
+// the correct weight is 1/2 at s_hi and 1/2 at s_lo on each tied axis.  The
+// corner (tied on both axes) is handled by pass 0.  All lanes of a group
+// must call this together (it ends with cross-lane shuffles).
+template <int L>
+__device__ __forceinline__ void ties_group(const Mesh& m, int p, int lane, int pass,
                                            const double* __restrict__ z,
                                            const double* __restrict__ gam, double* __restrict__ tie)
 {
-    if (p >= m.N) return;
+    if (p >= m.N) return;   // the whole lane group leaves together
     const int N = m.N, n1 = m.n1, n2 = m.n2;
     const int i2 = p / n1;
     const int i1 = p - i2 * n1;
@@ -642,7 +650,7 @@ __device__ __forceinline__ void ties_point(const Mesh& m, int p, int pass,
             const double lo2 = a2.s_lo + m2, hi2 = a2.s_lo - 1 + m2;
             if (pass == 0 && even1) {
                 const int j1 = a1.b;
-                for (int j2 = 0; j2 < n2; ++j2) {
+                for (int j2 = lane; j2 < n2; j2 += L) {
                     const int pj = j2 * n1 + j1;
                     if (even2 && j2 == a2.b) {
                         tie_term(m, xi, yi, zi, z, gam, pj, lo1, lo2, 0.25, acc);
@@ -657,7 +665,7 @@ __device__ __forceinline__ void ties_point(const Mesh& m, int p, int pass,
                 }
             } else if (pass == 1 && even2) {
                 const int j2 = a2.b;
-                for (int j1 = 0; j1 < n1; ++j1) {
+                for (int j1 = lane; j1 < n1; j1 += L) {
                     if (even1 && j1 == a1.b) continue;
                     const int pj = j2 * n1 + j1;
                     const double S1 = (j1 < a1.b) ? lo1 : hi1;
@@ -667,10 +675,19 @@ __device__ __forceinline__ void ties_point(const Mesh& m, int p, int pass,
             }
         }
     }
-    double* out = tie + (size_t)pass * 3 * N;
-    out[p] = acc[0];
-    out[N + p] = acc[1];
-    out[2 * N + p] = acc[2];
+    // butterfly over the lane group: every lane ends with the same sum
+#pragma unroll
+    for (int off = L / 2; off > 0; off >>= 1) {
+        acc[0] += __shfl_xor(acc[0], off, L);
+        acc[1] += __shfl_xor(acc[1], off, L);
+        acc[2] += __shfl_xor(acc[2], off, L);
+    }
+    if (lane == 0) {
+        double* out = tie + (size_t)pass * 3 * N;
+        out[p] = acc[0];
+        out[N + p] = acc[1];
+        out[2 * N + p] = acc[2];
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -689,8 +706,17 @@ __device__ __forceinline__ void reduce_point(const Mesh& m, int p, int splits,
     double a[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
+        // sequential sum over the splits; loads are issued 8 at a time
         double s = 0.0;
-        for (int k = 0; k < splits; ++k) s += part[(k * 3 + c) * N + p];
+        int k = 0;
+        for (; k + 8 <= splits; k += 8) {
+            double v[8];
+#pragma unroll
+            for (int t = 0; t < 8; ++t) v[t] = part[((size_t)(k + t) * 3 + c) * N + p];
+#pragma unroll
+            for (int t = 0; t < 8; ++t) s += v[t];
+        }
+        for (; k < splits; ++k) s += part[((size_t)k * 3 + c) * N + p];
         if ((m.n1 & 1) == 0) s += tie[c * N + p];
         if ((m.n2 & 1) == 0) s += tie[(3 + c) * N + p];
         a[c] = m.coef * s;

@@ -13,7 +13,7 @@
 namespace zm {
 
 constexpr size_t kAlign = 256;
-constexpr int kMaxSide = 16384;
+constexpr int kMaxSide = 8192;
 constexpr int kMaxImages = 16;
 
 inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
@@ -54,7 +54,7 @@ inline const char* validate(const zm_params* p)
 {
     if (!p) return "params is NULL";
     if (p->n1 < 8 || p->n2 < 8) return "n1 and n2 must be >= 8";
-    if (p->n1 > kMaxSide || p->n2 > kMaxSide) return "n1 and n2 must be <= 16384";
+    if (p->n1 > kMaxSide || p->n2 > kMaxSide) return "n1 and n2 must be <= 8192";
     if (!(std::isfinite(p->period1) && p->period1 > 0.0)) return "period1 must be finite and > 0";
     if (!(std::isfinite(p->period2) && p->period2 > 0.0)) return "period2 must be finite and > 0";
     if (!(std::isfinite(p->eps) && p->eps > 0.0)) return "eps must be finite and > 0";

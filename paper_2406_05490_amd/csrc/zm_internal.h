@@ -29,9 +29,22 @@ struct PairShape {
     int rows_per_split;
 };
 
+// Shape for R targets per lane and `splits` source ranges (splits <= 0: the
+// default of >= 2048 workgroups).  Supported R: 1, 2, 4.
+PairShape make_pair_shape(int n1, int n2, int precision, int R, int splits);
+
+// Shape a new context or batch member uses: the process-wide tuning entry
+// for (n1, n2, precision) if one is set, else an untuned default.
 PairShape choose_pair_shape(int n1, int n2, int precision);
 
+// Process-wide tuning table (zm_tune.hip).  Returns true and fills R and
+// splits if (n1, n2, precision) has an entry.
+bool lookup_tuning(int n1, int n2, int precision, int* R, int* splits);
+
 // Each launcher enqueues one kernel on `s` and returns the launch status.
+
+// Synthetic positions (3 planes) and source strengths (3 planes) for tuning.
+hipError_t launch_tune_init(const Mesh& m, double* z, double* gam, hipStream_t s);
 hipError_t launch_surface(const Mesh& m, const double* z, const double* w,
                           double* gam, double* q, hipStream_t s);
 

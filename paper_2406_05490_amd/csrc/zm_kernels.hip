@@ -39,12 +39,14 @@ __global__ __launch_bounds__(kThreads) void k_pairs_f32(Mesh m, PairShape sh,
     dev::pairs_f32_block<R, PX>(m, sh, z, gam, part, blockIdx.x, blockIdx.y, lds0, lds1);
 }
 
-// blockIdx.y = pass (0: tie column, 1: tie row)
+// blockIdx.y = pass (0: tie column, 1: tie row); L threads per target
+template <int L>
 __global__ __launch_bounds__(kThreads) void k_ties(Mesh m, const double* __restrict__ z,
                                                    const double* __restrict__ gam,
                                                    double* __restrict__ tie)
 {
-    dev::ties_point(m, blockIdx.x * kThreads + threadIdx.x, blockIdx.y, z, gam, tie);
+    const int t = blockIdx.x * kThreads + threadIdx.x;
+    dev::ties_group<L>(m, t / L, t % L, blockIdx.y, z, gam, tie);
 }
 
 __global__ __launch_bounds__(kThreads) void k_reduce(Mesh m, int splits,
@@ -72,6 +74,23 @@ __global__ __launch_bounds__(kThreads) void k_update(Mesh m, int stage, const do
                       V, out_z, out_w, nonfinite);
 }
 
+// Synthetic tuning input: a gently curved mesh with a smooth source strength.
+__global__ __launch_bounds__(kThreads) void k_tune_init(Mesh m, double* __restrict__ z,
+                                                        double* __restrict__ gam)
+{
+    const int p = blockIdx.x * kThreads + threadIdx.x;
+    if (p >= m.N) return;
+    const int i2 = p / m.n1, i1 = p - i2 * m.n1;
+    const double x = -0.5 * m.L1 + i1 * m.h1, y = -0.5 * m.L2 + i2 * m.h2;
+    const double cx = cos(6.283185307179586 * x / m.L1), cy = cos(6.283185307179586 * y / m.L2);
+    z[p] = x;
+    z[m.N + p] = y;
+    z[2 * m.N + p] = 0.01 * cx * cy;
+    gam[p] = cy;
+    gam[m.N + p] = cx;
+    gam[2 * m.N + p] = 0.1 * cx * cy;
+}
+
 inline unsigned blocks_for(int n) { return (unsigned)((n + kThreads - 1) / kThreads); }
 
 }  // namespace
@@ -81,29 +100,48 @@ inline unsigned blocks_for(int n) { return (unsigned)((n + kThreads - 1) / kThre
 // launch shapes and launchers
 // ---------------------------------------------------------------------------
 
-PairShape choose_pair_shape(int n1, int n2, int precision)
+PairShape make_pair_shape(int n1, int n2, int precision, int R, int splits)
 {
     PairShape sh;
-    if (precision == 1) {
-        // FP32 pairs: compact patches keep tile-relative coordinates small
-        sh.R = ZM_PAIR32_R;
-        sh.cx = (n1 >= 32) ? 32 : (n1 >= 16 ? 16 : 8);
-    } else {
-        sh.R = ZM_PAIR_R;
-        sh.cx = (n1 >= 16) ? 16 : 8;
-    }
+    sh.R = R;
+    // FP32 pairs: compact patches keep tile-relative coordinates small
+    if (precision == 1) sh.cx = (n1 >= 32) ? 32 : (n1 >= 16 ? 16 : 8);
+    else sh.cx = (n1 >= 16) ? 16 : 8;
     sh.prow = (kThreads / sh.cx) * sh.R;
     sh.px = (n1 + sh.cx - 1) / sh.cx;
     sh.py = (n2 + sh.prow - 1) / sh.prow;
-    const int patches = sh.px * sh.py;
-    // Aim for >= 2048 workgroups (8 per CU on 256 CUs) by splitting the
-    // source rows; every split keeps at least one row.
-    int splits = (2048 + patches - 1) / patches;
+    if (splits <= 0) {
+        // default: >= 2048 workgroups (8 per CU on 256 CUs)
+        const int patches = sh.px * sh.py;
+        splits = (2048 + patches - 1) / patches;
+    }
     if (splits > n2) splits = n2;
     if (splits < 1) splits = 1;
     sh.rows_per_split = (n2 + splits - 1) / splits;
     sh.splits = (n2 + sh.rows_per_split - 1) / sh.rows_per_split;
     return sh;
+}
+
+PairShape choose_pair_shape(int n1, int n2, int precision)
+{
+    int R = 0, splits = 0;
+    if (lookup_tuning(n1, n2, precision, &R, &splits)) return make_pair_shape(n1, n2, precision, R, splits);
+    // Untuned default, from autotuner runs on MI355X (32^2 .. 1024^2): fewer
+    // targets per lane on small meshes (more waves in flight); FP32 prefers 2
+    // targets per lane on large meshes, FP64 4; twice the default source
+    // splits helps mid-size meshes.
+    const long N = (long)n1 * n2;
+    if (precision == 1) R = N >= 65536 ? 2 : (N >= 16384 ? 4 : (N >= 4096 ? 2 : 1));
+    else R = N >= 16384 ? 4 : (N >= 9216 ? 2 : 1);
+    const PairShape d = make_pair_shape(n1, n2, precision, R, 0);
+    const bool mid = precision == 1 ? (N >= 4096 && N < 65536) : (N >= 9216);
+    return mid ? make_pair_shape(n1, n2, precision, R, 2 * d.splits) : d;
+}
+
+hipError_t launch_tune_init(const Mesh& m, double* z, double* gam, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_tune_init, dim3(blocks_for(m.N)), dim3(kThreads), 0, s, m, z, gam);
+    return hipGetLastError();
 }
 
 hipError_t launch_surface(const Mesh& m, const double* z, const double* w, double* gam, double* q,
@@ -117,13 +155,15 @@ hipError_t launch_pairs_f64(const Mesh& m, const PairShape& sh, const double* z,
                             const double* gam, double* part, hipStream_t s)
 {
     const dim3 grid((unsigned)(sh.px * sh.py), (unsigned)sh.splits);
-    constexpr int R = ZM_PAIR_R;
-    if (sh.R == R && sh.cx == 16)
-        hipLaunchKernelGGL((k_pairs_f64<R, 16>), grid, dim3(kThreads), 0, s, m, sh, z, gam, part);
-    else if (sh.R == R && sh.cx == 8)
-        hipLaunchKernelGGL((k_pairs_f64<R, 8>), grid, dim3(kThreads), 0, s, m, sh, z, gam, part);
-    else
-        return hipErrorInvalidConfiguration;
+    const dim3 blk(kThreads);
+#define ZM_F64_CASE(RR, CC)                                                                       \
+    else if (sh.R == RR && sh.cx == CC)                                                           \
+        hipLaunchKernelGGL((k_pairs_f64<RR, CC>), grid, blk, 0, s, m, sh, z, gam, part);
+    if (false) {}
+    ZM_F64_CASE(1, 16) ZM_F64_CASE(1, 8) ZM_F64_CASE(2, 16) ZM_F64_CASE(2, 8)
+    ZM_F64_CASE(4, 16) ZM_F64_CASE(4, 8)
+    else return hipErrorInvalidConfiguration;
+#undef ZM_F64_CASE
     return hipGetLastError();
 }
 
@@ -131,22 +171,27 @@ hipError_t launch_pairs_f32(const Mesh& m, const PairShape& sh, const double* z,
                             const double* gam, double* part, hipStream_t s)
 {
     const dim3 grid((unsigned)(sh.px * sh.py), (unsigned)sh.splits);
-    constexpr int R = ZM_PAIR32_R;
-    if (sh.R == R && sh.cx == 32)
-        hipLaunchKernelGGL((k_pairs_f32<R, 32>), grid, dim3(kThreads), 0, s, m, sh, z, gam, part);
-    else if (sh.R == R && sh.cx == 16)
-        hipLaunchKernelGGL((k_pairs_f32<R, 16>), grid, dim3(kThreads), 0, s, m, sh, z, gam, part);
-    else if (sh.R == R && sh.cx == 8)
-        hipLaunchKernelGGL((k_pairs_f32<R, 8>), grid, dim3(kThreads), 0, s, m, sh, z, gam, part);
-    else
-        return hipErrorInvalidConfiguration;
+    const dim3 blk(kThreads);
+#define ZM_F32_CASE(RR, CC)                                                                       \
+    else if (sh.R == RR && sh.cx == CC)                                                           \
+        hipLaunchKernelGGL((k_pairs_f32<RR, CC>), grid, blk, 0, s, m, sh, z, gam, part);
+    if (false) {}
+    ZM_F32_CASE(1, 32) ZM_F32_CASE(1, 16) ZM_F32_CASE(1, 8) ZM_F32_CASE(2, 32)
+    ZM_F32_CASE(2, 16) ZM_F32_CASE(2, 8) ZM_F32_CASE(4, 32) ZM_F32_CASE(4, 16)
+    ZM_F32_CASE(4, 8)
+    else return hipErrorInvalidConfiguration;
+#undef ZM_F32_CASE
     return hipGetLastError();
 }
 
 hipError_t launch_ties(const Mesh& m, const double* z, const double* gam, double* tie,
                        hipStream_t s)
 {
-    hipLaunchKernelGGL(k_ties, dim3(blocks_for(m.N), 2), dim3(kThreads), 0, s, m, z, gam, tie);
+    const int L = dev::tie_lanes(m.N);
+    const dim3 grid(blocks_for(m.N * L), 2);
+    if (L == 1) hipLaunchKernelGGL(k_ties<1>, grid, dim3(kThreads), 0, s, m, z, gam, tie);
+    else if (L == 4) hipLaunchKernelGGL(k_ties<4>, grid, dim3(kThreads), 0, s, m, z, gam, tie);
+    else hipLaunchKernelGGL(k_ties<16>, grid, dim3(kThreads), 0, s, m, z, gam, tie);
     return hipGetLastError();
 }
 

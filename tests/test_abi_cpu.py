@@ -104,3 +104,36 @@ def test_batch_workspace_validation():
     assert zm.batch_workspace_bytes([zm.Params(16, 16, eps=1 / 16, flags=1)]) == 0
     lib = zm.load()
     assert lib.zm_batch_workspace_bytes(None, 1) == 0
+
+
+def test_tuning_table_host_side():
+    """The shape table is host state: set, read back, clear, reject bad."""
+    d = zm.tuning_get(96, 80, zm.ZM_FP64)
+    assert d[0] in (1, 2, 4) and 1 <= d[1] <= 80
+    zm.tuning_set(96, 80, zm.ZM_FP64, 2, 10)
+    assert zm.tuning_get(96, 80, zm.ZM_FP64) == (2, 10)
+    zm.tuning_set(96, 80, zm.ZM_FP64, 4, 1000)           # clamped to n2 rows
+    assert zm.tuning_get(96, 80, zm.ZM_FP64) == (4, 80)
+    zm.tuning_set(96, 80, zm.ZM_FP64)                     # remove
+    assert zm.tuning_get(96, 80, zm.ZM_FP64) == d
+    with pytest.raises(zm.ZMError):
+        zm.tuning_set(96, 80, zm.ZM_FP64, 3, 10)
+    with pytest.raises(zm.ZMError):
+        zm.tuning_set(4, 80, zm.ZM_FP64, 1, 1)
+    lib = zm.load()
+    assert lib.zm_autotune_workspace_bytes(ctypes.byref(zm.Params(64, 64, eps=1 / 64).c())) > 0
+
+
+def test_pool_host_side_validation():
+    p = zm.Params(64, 64, eps=1 / 64)
+    rb = zm.pool_request_bytes(p)
+    assert rb >= zm.workspace_bytes(p) - 256 and rb % 256 == 0
+    assert zm.pool_request_bytes(zm.Params(4, 64, eps=1.0)) == 0
+    assert zm.pool_request_bytes(zm.Params(64, 64, eps=1 / 64, flags=1)) == 0
+    lib = zm.load()
+    assert lib.zm_pool_workspace_bytes(1 << 30) > (1 << 30)
+    h = ctypes.c_void_p(5)
+    assert lib.zm_pool_create(ctypes.byref(h), 0, 0, 4096, 1 << 40, None) == zm.ZM_ERR_INVALID_ARG
+    assert h.value is None
+    assert lib.zm_pool_create(ctypes.byref(h), 1 << 20, 0, 4096, 1 << 10, None) == zm.ZM_ERR_WORKSPACE
+    assert lib.zm_pool_create(ctypes.byref(h), 1 << 20, 0x40, 4096, 1 << 40, None) == zm.ZM_ERR_INVALID_ARG
