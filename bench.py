@@ -53,6 +53,35 @@ def parse():
     return ap.parse_args()
 
 
+def library_source_hash() -> str:
+    """SHA-256 over the library's kernel and host sources (name, then bytes)."""
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2406_05490_amd", "csrc")
+    for f in sorted(glob.glob(os.path.join(csrc, "*.h")) + glob.glob(os.path.join(csrc, "*.hip"))):
+        h.update(os.path.basename(f).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel: str, workload: str):
+    """HBM bytes per launch from the committed counter summary of this kernel
+    and workload (FETCH_SIZE and WRITE_SIZE scaled by a plain copy's reading),
+    or None when there is none or the sources changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}.traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    if rec.get("kernel") != kernel or rec.get("workload") != workload:
+        return None
+    if rec.get("source_sha256") != library_source_hash():
+        return None
+    return rec["read_bytes_per_launch"] + rec["write_bytes_per_launch"]
+
+
 def copy_calibration(mib: int):
     import torch
     n = mib * (1 << 20) // 8
@@ -413,6 +442,7 @@ def main():
     avg_pair_s = pair_ms / 1e3 / max(launches, 1)
     achieved = FLOPS_PER_PAIR * info.pairs_per_eval / avg_pair_s / 1e12
     peak = PEAK_TFLOPS[wl.precision]
+    kernel = "k_pairs_f64f" if prec == zm.ZM_FP64 else "k_pairs_f32"
 
     out = {
         "metric": METRIC,
@@ -435,8 +465,9 @@ def main():
             "source_splits": info.source_splits, "targets_per_lane": info.targets_per_lane,
         },
         "roofline": {
-            "kernel": "k_pairs_f64" if prec == zm.ZM_FP64 else "k_pairs_f32", "bound": "alu", "achieved": achieved, "peak": peak,
-            "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,
+            "kernel": kernel, "bound": "alu", "achieved": achieved, "peak": peak,
+            "unit": "TFLOP/s", "frac": achieved / peak,
+            "traffic": measured_traffic(kernel, wl.name), "traffic_unit": "bytes/launch",
             "flops_per_pair": FLOPS_PER_PAIR, "pairs_per_launch": info.pairs_per_eval,
             "avg_launch_ms": avg_pair_s * 1e3, "launches": launches,
         },

@@ -103,7 +103,7 @@ __global__ __launch_bounds__(kThreads) void kb_pairs_f64(const InstDesc* __restr
                                                          int nitems, int* __restrict__ counter,
                                                          int stage)
 {
-    __shared__ double2 lds[2][3][kThreads];
+    __shared__ double2 lds[2][5][kThreads];
     __shared__ int next;
     for (;;) {
         if (threadIdx.x == 0) next = atomicAdd(counter, 1);
@@ -113,10 +113,12 @@ __global__ __launch_bounds__(kThreads) void kb_pairs_f64(const InstDesc* __restr
         if (it >= nitems) break;
         const WorkItem w = items[it];
         const InstDesc& d = T[w.inst];
-        if (d.sh.cx == 16)
-            dev::pairs_f64_block<R, 16>(d.m, d.sh, d.Y[stage], d.gam, d.part, w.patch, w.split, lds);
+        if (d.sh.cx == 32)
+            dev::pairs_f64f_block<R, 32>(d.m, d.sh, d.Y[stage], d.gam, d.part, w.patch, w.split, lds);
+        else if (d.sh.cx == 16)
+            dev::pairs_f64f_block<R, 16>(d.m, d.sh, d.Y[stage], d.gam, d.part, w.patch, w.split, lds);
         else
-            dev::pairs_f64_block<R, 8>(d.m, d.sh, d.Y[stage], d.gam, d.part, w.patch, w.split, lds);
+            dev::pairs_f64f_block<R, 8>(d.m, d.sh, d.Y[stage], d.gam, d.part, w.patch, w.split, lds);
         // the body ends with a barrier, so `next` and the LDS tiles are free
     }
 }

@@ -7,13 +7,14 @@
 //
 //   surface_point     tangents T_a (5-point, periodic, seam-corrected), source
 //                     strength gamma = w1 T2 - w2 T1, q = |gamma|^2/|T1 x T2|^2.
-//   pairs_f64_block   one (target patch, source row range) of the all-pairs
+//   pairs_f64f_block  one (target patch, source row range) of the all-pairs
 //                     Birkhoff-Rott sweep in FP64: sources staged 256 at a
 //                     time through LDS (coalesced plane loads, double
-//                     buffered), read back as wave-wide broadcasts; pair
-//                     arithmetic on the VALU; per-target sums blocked per row.
-//   pairs_f32_block   the same in FP32 pair arithmetic with tile-relative
-//                     coordinates and FP64 per-target sums.
+//                     buffered) as patch-relative coordinates, read back as
+//                     wave-wide broadcasts; factored pair arithmetic on the
+//                     VALU; per-target sums blocked per row segment.
+//   pairs_f32_block   the same in FP32 pair arithmetic (direct form) with
+//                     FP64 per-target sums.
 //   ties_group        split-tie correction for even n_a (1-16 lanes per target).
 //   reduce_point      fixed-order sum over source splits and tie passes,
 //                     scale, Bernoulli potential V.
@@ -33,6 +34,7 @@ constexpr int kThreads = 256;
 #ifndef ZM_PAIR_UNROLL
 #define ZM_PAIR_UNROLL 2
 #endif
+
 
 // Periodic neighbour index along one axis; sets wrap to -1/0/+1.
 __device__ __forceinline__ int nbr(int i, int d, int n, int& wrap)
@@ -120,7 +122,7 @@ __device__ __forceinline__ void surface_point(const Mesh& m, int p, const double
 }
 
 // ---------------------------------------------------------------------------
-// all-pairs BR sweep, float64
+// periodic image bookkeeping
 // ---------------------------------------------------------------------------
 
 // Image bookkeeping along one axis for target index i on n points:
@@ -146,212 +148,6 @@ __device__ __forceinline__ AxisImg axis_img(int i, int n)
 // already folded into xt.  Otherwise (seam band) the axis-1 shift is chosen
 // per source: sources with column < b1 sit at shift Sx_lo, the others at
 // Sx_hi.
-template <int R, bool CORE>
-__device__ __forceinline__ void pair_segment(const double2 (*__restrict__ buf)[kThreads], int k0,
-                                             int cnt, int j1s, int b1, double Sx_lo, double Sx_hi,
-                                             const double* xt, const double* yt, const double* zi,
-                                             double eps2, double (*sa)[3])
-{
-#pragma unroll ZM_PAIR_UNROLL
-    for (int c = 0; c < cnt; ++c) {
-        const double2 v0 = buf[0][k0 + c];
-        const double2 v1 = buf[1][k0 + c];
-        const double2 v2 = buf[2][k0 + c];
-        double xs = v0.x;
-        if (!CORE) xs = xs + ((j1s + c < b1) ? Sx_lo : Sx_hi);
-        const double ys = v0.y, zs = v1.x;
-        const double g1 = v1.y, g2 = v2.x, g3 = v2.y;
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const double r1 = xt[r] - xs;
-            const double r2 = yt[r] - ys;
-            const double r3 = zi[r] - zs;
-            const double s = fma(r1, r1, fma(r2, r2, fma(r3, r3, eps2)));
-            const double wgt = inv_cube_sqrt(s);
-            const double a1 = wgt * g1, a2 = wgt * g2, a3 = wgt * g3;
-            sa[r][0] = fma(r2, a3, sa[r][0]);
-            sa[r][0] = fma(-r3, a2, sa[r][0]);
-            sa[r][1] = fma(r3, a1, sa[r][1]);
-            sa[r][1] = fma(-r1, a3, sa[r][1]);
-            sa[r][2] = fma(r1, a2, sa[r][2]);
-            sa[r][2] = fma(-r2, a1, sa[r][2]);
-        }
-    }
-}
-
-// All-pairs sweep.  Workgroup = target patch (CX columns x prow rows; lane =
-// one column, R rows spaced 256/CX apart) x one range of source rows.  The
-// axis-1 image breakpoints b1 of the patch's columns form a band of CX
-// consecutive source columns (mod n1); outside it every lane's shift is
-// constant per row segment, inside it the shift is selected per source.
-// lds: [buffer][(x,y) (z,g1) (g2,g3)][source], 2 x 3 x 256 double2.
-template <int R, int CX>
-__device__ __forceinline__ void pairs_f64_block(const Mesh& m, const PairShape& sh,
-                                                const double* __restrict__ z,
-                                                const double* __restrict__ gam,
-                                                double* __restrict__ part, int patch, int split,
-                                                double2 (*lds)[3][kThreads])
-{
-    constexpr int RY = kThreads / CX;
-    constexpr int PR = RY * R;
-
-    const int N = m.N, n1 = m.n1, n2 = m.n2;
-    const int tid = threadIdx.x;
-    const int ptx = patch % sh.px;
-    const int pty = patch / sh.px;
-
-    const int row_begin = split * sh.rows_per_split;
-    const int row_end = min(n2, row_begin + sh.rows_per_split);
-    if (row_begin >= row_end) return;  // uniform over the workgroup
-
-    // ---- targets of this lane: one column, R rows -------------------------
-    const int c0 = ptx * CX;
-    const int col = c0 + (tid % CX);
-    const int rowg = tid / CX;
-    const bool col_ok = col < n1;
-    const int i1 = col_ok ? col : 0;
-    const AxisImg ax1 = axis_img(i1, n1);
-    // seam band of source columns: b1 of columns c0 .. c0+CX-1, mod n1
-    const int band_lo = axis_img(c0, n1).b;
-    const bool band_all = CX >= n1;
-    const bool band_wraps = band_lo + CX > n1;
-
-    double xi[R], yi[R], zi[R], xt[R], yt[R];
-    int b2[R], s2lo[R], pidx[R];
-    bool valid[R];
-#pragma unroll
-    for (int k = 0; k < R; ++k) {
-        const int r = pty * PR + rowg + RY * k;
-        valid[k] = col_ok && (r < n2);
-        const int i2 = (r < n2) ? r : 0;
-        pidx[k] = i2 * n1 + i1;
-        xi[k] = z[pidx[k]];
-        yi[k] = z[N + pidx[k]];
-        zi[k] = z[2 * N + pidx[k]];
-        const AxisImg ax2 = axis_img(i2, n2);
-        b2[k] = ax2.b;
-        s2lo[k] = ax2.s_lo;
-        xt[k] = xi[k];
-        yt[k] = yi[k];
-    }
-
-    double acc[R][3];
-#pragma unroll
-    for (int k = 0; k < R; ++k) acc[k][0] = acc[k][1] = acc[k][2] = 0.0;
-
-    const int src_begin = row_begin * n1;
-    const int src_end = row_end * n1;
-    const int ntiles = (src_end - src_begin + kThreads - 1) / kThreads;
-    const int side = 2 * m.K + 1;
-    const int total = ntiles * side * side;
-
-    // ---- staging: one source per thread per tile ---------------------------
-    double2 st0, st1, st2;
-    auto load_tile = [&](int t) {
-        const int tile = t % ntiles;
-        const int j = src_begin + tile * kThreads + tid;
-        if (j < src_end) {
-            st0 = make_double2(z[j], z[N + j]);
-            st1 = make_double2(z[2 * N + j], gam[j]);
-            st2 = make_double2(gam[N + j], gam[2 * N + j]);
-        } else {
-            st0 = st1 = st2 = make_double2(0.0, 0.0);
-        }
-    };
-    auto store_tile = [&](int buf) {
-        lds[buf][0][tid] = st0;
-        lds[buf][1][tid] = st1;
-        lds[buf][2][tid] = st2;
-    };
-
-    load_tile(0);
-    store_tile(0);
-    __syncthreads();
-
-    for (int t = 0; t < total; ++t) {
-        const int buf = t & 1;
-        if (t + 1 < total) load_tile(t + 1);
-
-        const int img = t / ntiles;
-        const int tile = t - img * ntiles;
-        const int m1 = img % side - m.K;
-        const int m2 = img / side - m.K;
-        const double Sx_lo = (double)(ax1.s_lo + m1) * m.L1;
-        const double Sx_hi = (double)(ax1.s_lo - 1 + m1) * m.L1;
-
-        const int j0 = src_begin + tile * kThreads;
-        const int cnt = min(kThreads, src_end - j0);
-        int j2 = j0 / n1;
-        int j1 = j0 - j2 * n1;
-        int k = 0;
-        while (k < cnt) {
-            const int seg = min(cnt - k, n1 - j1);   // this row's columns [j1, j1 + seg)
-#pragma unroll
-            for (int r = 0; r < R; ++r) {
-                const int s2 = (j2 < b2[r]) ? s2lo[r] : s2lo[r] - 1;
-                yt[r] = yi[r] - (double)(s2 + m2) * m.L2;
-            }
-            double sa[R][3];
-#pragma unroll
-            for (int r = 0; r < R; ++r) sa[r][0] = sa[r][1] = sa[r][2] = 0.0;
-
-            // split [j1, j1 + seg) at the band edges: core pieces and band pieces
-            int a = j1;
-            const int e = j1 + seg;
-            while (a < e) {
-                bool in_band;
-                int stop;
-                if (band_all) {
-                    in_band = true; stop = e;
-                } else if (!band_wraps) {
-                    if (a < band_lo) { in_band = false; stop = min(e, band_lo); }
-                    else if (a < band_lo + CX) { in_band = true; stop = min(e, band_lo + CX); }
-                    else { in_band = false; stop = e; }
-                } else {
-                    const int hi_end = band_lo + CX - n1;   // band = [band_lo, n1) + [0, hi_end)
-                    if (a < hi_end) { in_band = true; stop = min(e, hi_end); }
-                    else if (a < band_lo) { in_band = false; stop = min(e, band_lo); }
-                    else { in_band = true; stop = e; }
-                }
-                const int kk = k + (a - j1);
-                if (in_band) {
-                    pair_segment<R, false>(lds[buf], kk, stop - a, a, ax1.b, Sx_lo, Sx_hi, xi, yt,
-                                           zi, m.eps2, sa);
-                } else {
-                    const double Sx = (a < ax1.b) ? Sx_lo : Sx_hi;
-#pragma unroll
-                    for (int r = 0; r < R; ++r) xt[r] = xi[r] - Sx;
-                    pair_segment<R, true>(lds[buf], kk, stop - a, a, ax1.b, Sx_lo, Sx_hi, xt, yt,
-                                          zi, m.eps2, sa);
-                }
-                a = stop;
-            }
-#pragma unroll
-            for (int r = 0; r < R; ++r) {
-                acc[r][0] += sa[r][0];
-                acc[r][1] += sa[r][1];
-                acc[r][2] += sa[r][2];
-            }
-            k += seg;
-            j1 += seg;
-            if (j1 == n1) { j1 = 0; ++j2; }
-        }
-
-        if (t + 1 < total) store_tile(buf ^ 1);
-        __syncthreads();
-    }
-
-    double* out = part + (size_t)split * 3 * N;
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-        if (valid[r]) {
-            out[pidx[r]] = acc[r][0];
-            out[N + pidx[r]] = acc[r][1];
-            out[2 * N + pidx[r]] = acc[r][2];
-        }
-    }
-}
-
 // ---------------------------------------------------------------------------
 // all-pairs BR sweep, FP32 pair arithmetic, FP64 per-target sums
 // ---------------------------------------------------------------------------
@@ -591,6 +387,261 @@ __device__ __forceinline__ void pairs_f32_block(const Mesh& m, const PairShape& 
 }
 
 // ---------------------------------------------------------------------------
+// all-pairs BR sweep, FP64, factored form on patch-relative coordinates
+// ---------------------------------------------------------------------------
+//
+// With a = target - centre and b = source image - centre (the centre is a
+// target near the middle of a compact patch, source images taken as seen
+// from it), sum_j w_j (a - b_j) x g_j = a x (sum_j w_j g_j) - sum_j w_j c_j
+// with c_j = b_j x g_j computed once per source while staging.  Per pair
+// that leaves the distance, the weight and two 3-vector accumulations (17
+// VALU operations instead of 21).  The cancellation between the two terms is
+// bounded by |a| / |r| ~ the patch extent over the spacing for near pairs.
+// In the antipodal band, where a lane's image differs from the centre's, the
+// direct form is used with a per-source image correction.
+
+template <int R, bool BAND>
+__device__ __forceinline__ void pair_segment_f64f(const double2 (*__restrict__ buf)[kThreads],
+                                                  int k0, int cnt, int j1s, int b1, int s1lo,
+                                                  int bc1, int sc1lo, double L1, const double* ax, const double* ay,
+                                                  const double* az, double eps2,
+                                                  double (*A)[3], double (*B)[3])
+{
+#pragma unroll ZM_PAIR_UNROLL
+    for (int c = 0; c < cnt; ++c) {
+        const double2 v0 = buf[0][k0 + c];
+        const double2 v1 = buf[1][k0 + c];
+        const double2 v2 = buf[2][k0 + c];
+        double bx = v0.x;
+        const double by = v0.y, bz = v1.x;
+        const double g1 = v1.y, g2 = v2.x, g3 = v2.y;
+        if (BAND) {
+            const int jj = j1s + c;
+            const int si = (jj < b1) ? s1lo : s1lo - 1;
+            const int sc = (jj < bc1) ? sc1lo : sc1lo - 1;
+            bx = fma((double)(si - sc), L1, bx);
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const double r1 = ax[r] - bx;
+                const double r2 = ay[r] - by;
+                const double r3 = az[r] - bz;
+                const double s = fma(r1, r1, fma(r2, r2, fma(r3, r3, eps2)));
+                const double wgt = inv_cube_sqrt(s);
+                const double a1 = wgt * g1, a2 = wgt * g2, a3 = wgt * g3;
+                A[r][0] = fma(r2, a3, A[r][0]);
+                A[r][0] = fma(-r3, a2, A[r][0]);
+                A[r][1] = fma(r3, a1, A[r][1]);
+                A[r][1] = fma(-r1, a3, A[r][1]);
+                A[r][2] = fma(r1, a2, A[r][2]);
+                A[r][2] = fma(-r2, a1, A[r][2]);
+            }
+        } else {
+            const double2 v3 = buf[3][k0 + c];
+            const double2 v4 = buf[4][k0 + c];
+            const double c1 = v3.x, c2 = v3.y, c3 = v4.x;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const double r1 = ax[r] - bx;
+                const double r2 = ay[r] - by;
+                const double r3 = az[r] - bz;
+                const double s = fma(r1, r1, fma(r2, r2, fma(r3, r3, eps2)));
+                const double wgt = inv_cube_sqrt(s);
+                A[r][0] = fma(wgt, g1, A[r][0]);
+                A[r][1] = fma(wgt, g2, A[r][1]);
+                A[r][2] = fma(wgt, g3, A[r][2]);
+                B[r][0] = fma(wgt, c1, B[r][0]);
+                B[r][1] = fma(wgt, c2, B[r][1]);
+                B[r][2] = fma(wgt, c3, B[r][2]);
+            }
+        }
+    }
+}
+
+// lds: [buffer][(bx,by) (bz,g1) (g2,g3) (c1,c2) (c3,-)][source].
+// Workgroup = target patch of PX columns x (256/PX)*R rows (lane = one
+// column, R rows 256/PX apart) x one range of source rows.
+template <int R, int PX>
+__device__ __forceinline__ void pairs_f64f_block(const Mesh& m, const PairShape& sh,
+                                                 const double* __restrict__ z,
+                                                 const double* __restrict__ gam,
+                                                 double* __restrict__ part, int patch, int split,
+                                                 double2 (*lds)[5][kThreads])
+{
+    constexpr int RY = kThreads / PX;
+    constexpr int PY = RY * R;
+
+    const int N = m.N, n1 = m.n1, n2 = m.n2;
+    const int tid = threadIdx.x;
+    const int ptx = patch % sh.px;
+    const int pty = patch / sh.px;
+    const int row_begin = split * sh.rows_per_split;
+    const int row_end = min(n2, row_begin + sh.rows_per_split);
+    if (row_begin >= row_end) return;  // uniform over the workgroup
+
+    // ---- patch centre ----------------------------------------------------
+    const int c0 = ptx * PX, r0 = pty * PY;
+    const int ci1 = min(c0 + PX / 2, n1 - 1), ci2 = min(r0 + PY / 2, n2 - 1);
+    const int pc = ci2 * n1 + ci1;
+    const double cx = z[pc], cy = z[N + pc], cz = z[2 * N + pc];
+    const AxisImg cimg1 = axis_img(ci1, n1), cimg2 = axis_img(ci2, n2);
+    const int band_lo = axis_img(c0, n1).b;
+    const bool band_all = PX >= n1;
+    const bool band_wraps = band_lo + PX > n1;
+
+    // ---- targets of this lane --------------------------------------------
+    const int col = c0 + (tid % PX);
+    const int rowg = tid / PX;
+    const bool col_ok = col < n1;
+    const int i1 = col_ok ? col : ci1;
+    const AxisImg ax1 = axis_img(i1, n1);
+    double ax0[R], ay0[R], az[R], ax[R], ay[R];
+    int b2[R], s2lo[R], pidx[R];
+    bool valid[R];
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        const int r = r0 + rowg + RY * k;
+        valid[k] = col_ok && (r < n2);
+        const int i2 = (r < n2) ? r : ci2;
+        pidx[k] = i2 * n1 + i1;
+        ax0[k] = z[pidx[k]] - cx;
+        ay0[k] = z[N + pidx[k]] - cy;
+        az[k] = z[2 * N + pidx[k]] - cz;
+        const AxisImg a2 = axis_img(i2, n2);
+        b2[k] = a2.b;
+        s2lo[k] = a2.s_lo;
+    }
+    double U[R][3];
+#pragma unroll
+    for (int k = 0; k < R; ++k) U[k][0] = U[k][1] = U[k][2] = 0.0;
+
+    const int src_begin = row_begin * n1;
+    const int src_end = row_end * n1;
+    const int ntiles = (src_end - src_begin + kThreads - 1) / kThreads;
+    const int side = 2 * m.K + 1;
+    const int total = ntiles * side * side;
+
+    double2 st[5];
+    auto load_tile = [&](int t) {
+        const int tile = t % ntiles;
+        const int j = src_begin + tile * kThreads + tid;
+        if (j < src_end) {
+            const int j2 = j / n1, j1 = j - j2 * n1;
+            const int sc1 = (j1 < cimg1.b) ? cimg1.s_lo : cimg1.s_lo - 1;
+            const int sc2 = (j2 < cimg2.b) ? cimg2.s_lo : cimg2.s_lo - 1;
+            const double bx = (z[j] + (double)sc1 * m.L1) - cx;
+            const double by = (z[N + j] + (double)sc2 * m.L2) - cy;
+            const double bz = z[2 * N + j] - cz;
+            const double g1 = gam[j], g2 = gam[N + j], g3 = gam[2 * N + j];
+            st[0] = make_double2(bx, by);
+            st[1] = make_double2(bz, g1);
+            st[2] = make_double2(g2, g3);
+            st[3] = make_double2(by * g3 - bz * g2, bz * g1 - bx * g3);
+            st[4] = make_double2(bx * g2 - by * g1, 0.0);
+        } else {
+#pragma unroll
+            for (int q = 0; q < 5; ++q) st[q] = make_double2(0.0, 0.0);
+        }
+    };
+    auto store_tile = [&](int buf) {
+#pragma unroll
+        for (int q = 0; q < 5; ++q) lds[buf][q][tid] = st[q];
+    };
+
+    load_tile(0);
+    store_tile(0);
+    __syncthreads();
+
+    for (int t = 0; t < total; ++t) {
+        const int buf = t & 1;
+        if (t + 1 < total) load_tile(t + 1);
+        const int img = t / ntiles;
+        const int tile = t - img * ntiles;
+        const int m1 = img % side - m.K;
+        const int m2 = img / side - m.K;
+        const double dm1 = (double)m1 * m.L1;
+#pragma unroll
+        for (int r = 0; r < R; ++r) ax[r] = ax0[r] - dm1;
+
+        const int j0 = src_begin + tile * kThreads;
+        const int cnt = min(kThreads, src_end - j0);
+        int j2 = j0 / n1;
+        int j1 = j0 - j2 * n1;
+        int k = 0;
+        while (k < cnt) {
+            const int seg = min(cnt - k, n1 - j1);
+            const int sc2 = (j2 < cimg2.b) ? cimg2.s_lo : cimg2.s_lo - 1;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const int s2 = (j2 < b2[r]) ? s2lo[r] : s2lo[r] - 1;
+                ay[r] = ay0[r] - (double)(s2 - sc2 + m2) * m.L2;
+            }
+            int a = j1;
+            const int e = j1 + seg;
+            while (a < e) {
+                bool in_band;
+                int stop;
+                if (band_all) {
+                    in_band = true; stop = e;
+                } else if (!band_wraps) {
+                    if (a < band_lo) { in_band = false; stop = min(e, band_lo); }
+                    else if (a < band_lo + PX) { in_band = true; stop = min(e, band_lo + PX); }
+                    else { in_band = false; stop = e; }
+                } else {
+                    const int hi_end = band_lo + PX - n1;
+                    if (a < hi_end) { in_band = true; stop = min(e, hi_end); }
+                    else if (a < band_lo) { in_band = false; stop = min(e, band_lo); }
+                    else { in_band = true; stop = e; }
+                }
+                const int kk = k + (a - j1);
+                double A[R][3], B[R][3];
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    A[r][0] = A[r][1] = A[r][2] = 0.0;
+                    B[r][0] = B[r][1] = B[r][2] = 0.0;
+                }
+                if (in_band) {
+                    pair_segment_f64f<R, true>(lds[buf], kk, stop - a, a, ax1.b, ax1.s_lo, cimg1.b,
+                                               cimg1.s_lo, m.L1, ax, ay, az, m.eps2, A, B);
+                    // direct contributions
+#pragma unroll
+                    for (int r = 0; r < R; ++r) {
+                        U[r][0] += A[r][0];
+                        U[r][1] += A[r][1];
+                        U[r][2] += A[r][2];
+                    }
+                } else {
+                    pair_segment_f64f<R, false>(lds[buf], kk, stop - a, a, ax1.b, ax1.s_lo, cimg1.b,
+                                                cimg1.s_lo, m.L1, ax, ay, az, m.eps2, A, B);
+                    // a x A - B
+#pragma unroll
+                    for (int r = 0; r < R; ++r) {
+                        U[r][0] += (ay[r] * A[r][2] - az[r] * A[r][1]) - B[r][0];
+                        U[r][1] += (az[r] * A[r][0] - ax[r] * A[r][2]) - B[r][1];
+                        U[r][2] += (ax[r] * A[r][1] - ay[r] * A[r][0]) - B[r][2];
+                    }
+                }
+                a = stop;
+            }
+            k += seg;
+            j1 += seg;
+            if (j1 == n1) { j1 = 0; ++j2; }
+        }
+        if (t + 1 < total) store_tile(buf ^ 1);
+        __syncthreads();
+    }
+
+    double* out = part + (size_t)split * 3 * N;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        if (valid[r]) {
+            out[pidx[r]] = U[r][0];
+            out[N + pidx[r]] = U[r][1];
+            out[2 * N + pidx[r]] = U[r][2];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // split-tie correction
 // ---------------------------------------------------------------------------
 
@@ -612,10 +663,6 @@ __device__ __forceinline__ void tie_term(const Mesh& m, double xi, double yi, do
     acc[2] += wgt * (r1 * g2 - r2 * g1);
 }
 
-// pass 0 corrects the tie column (needs n1 even), 1 the tie
-// row (needs n2 even).  The pair kernel counted each tied source once at
-// the image s_hi; the correct weight is 1/2 at s_hi and 1/2 at s_lo on each
-// tied axis.  The corner (tied on both axes) is handled by pass 0.
 // Lanes that share one target's tie sources (L in {1, 4, 16}, chosen from the
 // mesh size only); their partial sums are combined by a fixed butterfly, so
 // the result does not depend on scheduling.  Small meshes use more lanes per

@@ -18,14 +18,14 @@ __global__ __launch_bounds__(kThreads) void k_surface(Mesh m, const double* __re
     dev::surface_point(m, blockIdx.x * kThreads + threadIdx.x, z, w, gam, q);
 }
 
-template <int R, int CX>
-__global__ __launch_bounds__(kThreads) void k_pairs_f64(Mesh m, PairShape sh,
-                                                        const double* __restrict__ z,
-                                                        const double* __restrict__ gam,
-                                                        double* __restrict__ part)
+template <int R, int PX>
+__global__ __launch_bounds__(kThreads) void k_pairs_f64f(Mesh m, PairShape sh,
+                                                         const double* __restrict__ z,
+                                                         const double* __restrict__ gam,
+                                                         double* __restrict__ part)
 {
-    __shared__ double2 lds[2][3][kThreads];
-    dev::pairs_f64_block<R, CX>(m, sh, z, gam, part, blockIdx.x, blockIdx.y, lds);
+    __shared__ double2 lds[2][5][kThreads];
+    dev::pairs_f64f_block<R, PX>(m, sh, z, gam, part, blockIdx.x, blockIdx.y, lds);
 }
 
 template <int R, int PX>
@@ -104,9 +104,9 @@ PairShape make_pair_shape(int n1, int n2, int precision, int R, int splits)
 {
     PairShape sh;
     sh.R = R;
-    // FP32 pairs: compact patches keep tile-relative coordinates small
-    if (precision == 1) sh.cx = (n1 >= 32) ? 32 : (n1 >= 16 ? 16 : 8);
-    else sh.cx = (n1 >= 16) ? 16 : 8;
+    // compact patches keep patch-relative coordinates small
+    (void)precision;
+    sh.cx = (n1 >= 32) ? 32 : (n1 >= 16 ? 16 : 8);
     sh.prow = (kThreads / sh.cx) * sh.R;
     sh.px = (n1 + sh.cx - 1) / sh.cx;
     sh.py = (n2 + sh.prow - 1) / sh.prow;
@@ -158,10 +158,11 @@ hipError_t launch_pairs_f64(const Mesh& m, const PairShape& sh, const double* z,
     const dim3 blk(kThreads);
 #define ZM_F64_CASE(RR, CC)                                                                       \
     else if (sh.R == RR && sh.cx == CC)                                                           \
-        hipLaunchKernelGGL((k_pairs_f64<RR, CC>), grid, blk, 0, s, m, sh, z, gam, part);
+        hipLaunchKernelGGL((k_pairs_f64f<RR, CC>), grid, blk, 0, s, m, sh, z, gam, part);
     if (false) {}
-    ZM_F64_CASE(1, 16) ZM_F64_CASE(1, 8) ZM_F64_CASE(2, 16) ZM_F64_CASE(2, 8)
-    ZM_F64_CASE(4, 16) ZM_F64_CASE(4, 8)
+    ZM_F64_CASE(1, 32) ZM_F64_CASE(1, 16) ZM_F64_CASE(1, 8) ZM_F64_CASE(2, 32)
+    ZM_F64_CASE(2, 16) ZM_F64_CASE(2, 8) ZM_F64_CASE(4, 32) ZM_F64_CASE(4, 16)
+    ZM_F64_CASE(4, 8)
     else return hipErrorInvalidConfiguration;
 #undef ZM_F64_CASE
     return hipGetLastError();
