@@ -56,13 +56,13 @@ __global__ __launch_bounds__(kThreads) void kb_surface(const InstDesc* __restric
 __global__ __launch_bounds__(kThreads) void kb_ties(const InstDesc* __restrict__ T, int count,
                                                     int stage)
 {
+    __shared__ double2 lds[3][kThreads];
     const int i = find_tie_instance(T, count, blockIdx.x);
     const InstDesc& d = T[i];
-    const int t = (blockIdx.x - d.tie_block_begin) * kThreads + threadIdx.x;
-    const int L = dev::tie_lanes(d.m.N);   // uniform over the block (one instance)
-    if (L == 1) dev::ties_group<1>(d.m, t, 0, blockIdx.y, d.Y[stage], d.gam, d.tie);
-    else if (L == 4) dev::ties_group<4>(d.m, t / 4, t % 4, blockIdx.y, d.Y[stage], d.gam, d.tie);
-    else dev::ties_group<16>(d.m, t / 16, t % 16, blockIdx.y, d.Y[stage], d.gam, d.tie);
+    // blocks past this instance's own tie shape leave at once (uniformly)
+    const int b = blockIdx.x - d.tie_block_begin;
+    if (blockIdx.y == 0) dev::ties_block<0>(d.m, b, d.Y[stage], d.gam, d.tie, lds);
+    else dev::ties_block<1>(d.m, b, d.Y[stage], d.gam, d.tie, lds);
 }
 
 __global__ __launch_bounds__(kThreads) void kb_reduce(const InstDesc* __restrict__ T, int count,
@@ -154,7 +154,7 @@ __global__ __launch_bounds__(kThreads) void kb_pairs_f32(const InstDesc* __restr
 
 }  // namespace
 
-int dev_tie_lanes(int N) { return dev::tie_lanes(N); }
+int dev_tie_blocks(int n1, int n2) { return dev::tie_blocks(n1, n2); }
 
 hipError_t launch_batch_stage(const BatchLaunch& b, int stage, hipStream_t s)
 {

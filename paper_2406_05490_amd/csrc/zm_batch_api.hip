@@ -145,7 +145,7 @@ void build_tables(const zm_params* params, const PairShape* shapes, const Layout
         d.blocks = (d.m.N + 255) / 256;
         block += d.blocks;
         d.tie_block_begin = tie_block;
-        tie_block += (d.m.N * dev_tie_lanes(d.m.N) + 255) / 256;
+        tie_block += dev_tie_blocks(d.m.n1, d.m.n2);
         char* base = bases[i];
         const Layout& L = layouts[i];
         d.Y[0] = reinterpret_cast<double*>(base + L.y0);

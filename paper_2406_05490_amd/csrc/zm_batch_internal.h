@@ -61,9 +61,9 @@ struct BatchLaunch {
     bool any_even;           // some instance has an even side (tie pass needed)
 };
 
-// Lanes per target of the tie kernel for an N-point mesh (host mirror of the
-// device rule; both come from zm_device.h's tie_lanes).
-int dev_tie_lanes(int N);
+// Workgroups of the tie kernel for an n1 x n2 mesh (host mirror of the
+// device rule in zm_device.h's tie_blocks).
+int dev_tie_blocks(int n1, int n2);
 
 // Enqueue one RK3 stage (surface, pairs, ties, reduce, update) for every
 // instance of the batch.  Non-finite results are flagged per instance

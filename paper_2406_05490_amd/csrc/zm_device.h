@@ -15,7 +15,7 @@
 //                     VALU; per-target sums blocked per row segment.
 //   pairs_f32_block   the same in FP32 pair arithmetic (direct form) with
 //                     FP64 per-target sums.
-//   ties_group        split-tie correction for even n_a (1-16 lanes per target).
+//   ties_block        split-tie correction for even n_a (tie line staged in LDS).
 //   reduce_point      fixed-order sum over source splits and tie passes,
 //                     scale, Bernoulli potential V.
 //   update_point      D V (+ nu Lap w) and the SSP-RK3 stage combination.
@@ -398,7 +398,23 @@ __device__ __forceinline__ void pairs_f32_block(const Mesh& m, const PairShape& 
 // VALU operations instead of 21).  The cancellation between the two terms is
 // bounded by |a| / |r| ~ the patch extent over the spacing for near pairs.
 // In the antipodal band, where a lane's image differs from the centre's, the
-// direct form is used with a per-source image correction.
+// direct form is used with a per-source image correction.  On meshes where a
+// patch is wide compared with the finest spacing (strongly anisotropic
+// spacings, or a patch that spans a short axis), that cancellation could
+// reach the FP64 tolerance, so there every source takes the direct form.
+
+// Largest patch half-extent, in units of the finest mesh spacing, for which
+// the factored form is used.
+constexpr double kFactoredMaxExtent = 32.0;
+
+__host__ __device__ inline bool factored_ok(const Mesh& m, int PX, int PY)
+{
+    const double ex = 0.5 * (double)(PX < m.n1 ? PX : m.n1) * m.h1;
+    const double ey = 0.5 * (double)(PY < m.n2 ? PY : m.n2) * m.h2;
+    const double h = m.h1 < m.h2 ? m.h1 : m.h2;
+    const double lim = kFactoredMaxExtent * h;
+    return ex * ex + ey * ey <= lim * lim;
+}
 
 template <int R, bool BAND>
 __device__ __forceinline__ void pair_segment_f64f(const double2 (*__restrict__ buf)[kThreads],
@@ -485,7 +501,7 @@ __device__ __forceinline__ void pairs_f64f_block(const Mesh& m, const PairShape&
     const double cx = z[pc], cy = z[N + pc], cz = z[2 * N + pc];
     const AxisImg cimg1 = axis_img(ci1, n1), cimg2 = axis_img(ci2, n2);
     const int band_lo = axis_img(c0, n1).b;
-    const bool band_all = PX >= n1;
+    const bool band_all = PX >= n1 || !factored_ok(m, PX, PY);
     const bool band_wraps = band_lo + PX > n1;
 
     // ---- targets of this lane --------------------------------------------
@@ -645,17 +661,67 @@ __device__ __forceinline__ void pairs_f64f_block(const Mesh& m, const PairShape&
 // split-tie correction
 // ---------------------------------------------------------------------------
 
-// Unscaled pair term f = (r x g) / (|r|^2 + eps^2)^(3/2) added with weight c.
-__device__ __forceinline__ void tie_term(const Mesh& m, double xi, double yi, double zi,
-                                         const double* __restrict__ z,
-                                         const double* __restrict__ gam, int pj, double S1,
-                                         double S2, double c, double acc[3])
+// Tie-kernel shape.  Pass 0 (n1 even) corrects the tie column, pass 1 (n2
+// even) the tie row.  All targets of one mesh column share their tie column,
+// all targets of one mesh row their tie row, so a workgroup takes a segment
+// of one such line of targets and stages the line's tie sources through LDS.
+// A line of len targets gets L lanes per target (a power of two, at most 32,
+// at least the smallest with 256 / L <= len); the lanes of a target split its
+// sources and are combined by a fixed butterfly, so the result does not
+// depend on scheduling.
+struct TieShape {
+    int lanes[2];      // L per pass
+    int segs[2];       // workgroups per line per pass
+    int blocks[2];     // workgroups per pass (0 if the pass is not needed)
+};
+
+__host__ __device__ inline int tie_lanes_for(int len)
 {
-    const int N = m.N;
-    const double r1 = xi - z[pj] - S1 * m.L1;
-    const double r2 = yi - z[N + pj] - S2 * m.L2;
-    const double r3 = zi - z[2 * N + pj];
-    const double g1 = gam[pj], g2 = gam[N + pj], g3 = gam[2 * N + pj];
+    int L = 1;
+    while (L < 32 && kThreads / L > len) L *= 2;
+    return L;
+}
+
+// On meshes of >= 16384 points more lanes per target are used until both
+// passes together have this many threads (enough waves to hide latency);
+// small meshes keep few lanes, which is faster there.
+#ifndef ZM_TIE_MIN_THREADS
+#define ZM_TIE_MIN_THREADS 524288
+#endif
+
+__host__ __device__ inline TieShape tie_shape(int n1, int n2)
+{
+    TieShape t;
+    const int len[2] = {n2, n1}, lines[2] = {n1, n2};
+    const bool need[2] = {(n1 & 1) == 0, (n2 & 1) == 0};
+    for (int P = 0; P < 2; ++P) {
+        t.lanes[P] = tie_lanes_for(len[P]);
+        while (n1 * n2 >= 16384 && t.lanes[P] < 32 &&
+               2L * n1 * n2 * t.lanes[P] < (long)ZM_TIE_MIN_THREADS)
+            t.lanes[P] *= 2;
+        const int per = kThreads / t.lanes[P];
+        t.segs[P] = (len[P] + per - 1) / per;
+        t.blocks[P] = need[P] ? lines[P] * t.segs[P] : 0;
+    }
+    return t;
+}
+
+// Workgroups of one tie launch (grid.y = 2 passes).
+__host__ __device__ inline int tie_blocks(int n1, int n2)
+{
+    const TieShape t = tie_shape(n1, n2);
+    return t.blocks[0] > t.blocks[1] ? t.blocks[0] : t.blocks[1];
+}
+
+// Adds c * (r x g) / (|r|^2 + eps^2)^(3/2) with r = (dx - S1 L1, dy - S2 L2, dz),
+// where (dx, dy, dz) = target - source.
+__device__ __forceinline__ void tie_term(const Mesh& m, double dx, double dy, double dz,
+                                         double g1, double g2, double g3, double S1, double S2,
+                                         double c, double acc[3])
+{
+    const double r1 = dx - S1 * m.L1;
+    const double r2 = dy - S2 * m.L2;
+    const double r3 = dz;
     const double s = r1 * r1 + r2 * r2 + r3 * r3 + m.eps2;
     const double wgt = c * inv_cube_sqrt(s);
     acc[0] += wgt * (r2 * g3 - r3 * g2);
@@ -663,73 +729,122 @@ __device__ __forceinline__ void tie_term(const Mesh& m, double xi, double yi, do
     acc[2] += wgt * (r1 * g2 - r2 * g1);
 }
 
-// Lanes that share one target's tie sources (L in {1, 4, 16}, chosen from the
-// mesh size only); their partial sums are combined by a fixed butterfly, so
-// the result does not depend on scheduling.  Small meshes use more lanes per
-// target for parallelism; large ones use one, which keeps the tie-column
-// gathers of neighbouring targets coalesced.
-__host__ __device__ inline int tie_lanes(int N) { return N >= 16384 ? 1 : (N >= 4096 ? 4 : 16); }
-
-// p: target point; lane in [0, L) of the target's lane group; pass 0
-// corrects the tie column (needs n1 even), pass 1 the tie row (needs n2
-// even).  The pair kernels counted each tied source once at the image s_hi;
-// the correct weight is 1/2 at s_hi and 1/2 at s_lo on each tied axis.  The
-// corner (tied on both axes) is handled by pass 0.  All lanes of a group
-// must call this together (it ends with cross-lane shuffles).
-template <int L>
-__device__ __forceinline__ void ties_group(const Mesh& m, int p, int lane, int pass,
+// One workgroup of the tie kernel: block blk of pass `pass` (see TieShape).
+// The pair kernels counted each tied source once at the image s_hi; the
+// correct weight is 1/2 at s_hi and 1/2 at s_lo on each tied axis, 1/4 at
+// each of the four images of the corner (tied on both axes, handled by pass
+// 0).  Writes tie[pass][3][N] for the block's targets.  lds: 3 x kThreads
+// (x, y) (z, g1) (g2, g3) of the staged tie sources.
+template <int PASS>
+__device__ __forceinline__ void ties_block(const Mesh& m, int blk,
                                            const double* __restrict__ z,
-                                           const double* __restrict__ gam, double* __restrict__ tie)
+                                           const double* __restrict__ gam,
+                                           double* __restrict__ tie,
+                                           double2 (*__restrict__ lds)[kThreads])
 {
-    if (p >= m.N) return;   // the whole lane group leaves together
+    constexpr int pass = PASS;
+    const TieShape ts = tie_shape(m.n1, m.n2);
+    if (blk >= ts.blocks[pass]) return;   // uniform over the workgroup
     const int N = m.N, n1 = m.n1, n2 = m.n2;
-    const int i2 = p / n1;
-    const int i1 = p - i2 * n1;
+    const bool even1 = (n1 & 1) == 0, even2 = (n2 & 1) == 0;
+    const int L = ts.lanes[pass];
+    const int per = kThreads / L;
+    const int line = blk / ts.segs[pass];
+    const int seg = blk - line * ts.segs[pass];
+    const int slot = threadIdx.x / L, lane = threadIdx.x % L;
+    const int len = pass == 0 ? n2 : n1;          // targets of the line = tie sources
+    const int k_t = seg * per + slot;             // target's place along the line
+    const bool active = k_t < len;
+    const int i1 = pass == 0 ? line : k_t;
+    const int i2 = pass == 0 ? k_t : line;
+    const int p = active ? i2 * n1 + i1 : 0;
     const AxisImg a1 = axis_img(i1, n1);
     const AxisImg a2 = axis_img(i2, n2);
-    const bool even1 = (n1 & 1) == 0, even2 = (n2 & 1) == 0;
     const double xi = z[p], yi = z[N + p], zi = z[2 * N + p];
+    // tie line: column a1.b (pass 0) or row a2.b (pass 1); a1.b and a2.b are
+    // the same for every target of the workgroup on the line's axis
+    const int tie_line = pass == 0 ? a1.b : a2.b;
     double acc[3] = {0.0, 0.0, 0.0};
 
-    for (int m2 = -m.K; m2 <= m.K; ++m2) {
-        for (int m1 = -m.K; m1 <= m.K; ++m1) {
-            const double lo1 = a1.s_lo + m1, hi1 = a1.s_lo - 1 + m1;
-            const double lo2 = a2.s_lo + m2, hi2 = a2.s_lo - 1 + m2;
-            if (pass == 0 && even1) {
-                const int j1 = a1.b;
-                for (int j2 = lane; j2 < n2; j2 += L) {
-                    const int pj = j2 * n1 + j1;
-                    if (even2 && j2 == a2.b) {
-                        tie_term(m, xi, yi, zi, z, gam, pj, lo1, lo2, 0.25, acc);
-                        tie_term(m, xi, yi, zi, z, gam, pj, lo1, hi2, 0.25, acc);
-                        tie_term(m, xi, yi, zi, z, gam, pj, hi1, lo2, 0.25, acc);
-                        tie_term(m, xi, yi, zi, z, gam, pj, hi1, hi2, -0.75, acc);
+    for (int c0 = 0; c0 < len; c0 += kThreads) {
+        const int cn = len - c0 < kThreads ? len - c0 : kThreads;
+        __syncthreads();   // previous chunk fully read
+        if ((int)threadIdx.x < cn) {
+            const int k = c0 + threadIdx.x;
+            const int pj = pass == 0 ? k * n1 + tie_line : tie_line * n1 + k;
+            lds[0][threadIdx.x] = make_double2(z[pj], z[N + pj]);
+            lds[1][threadIdx.x] = make_double2(z[2 * N + pj], gam[pj]);
+            lds[2][threadIdx.x] = make_double2(gam[N + pj], gam[2 * N + pj]);
+        }
+        __syncthreads();
+        if (!active) continue;
+        for (int m2 = -m.K; m2 <= m.K; ++m2) {
+            for (int m1 = -m.K; m1 <= m.K; ++m1) {
+                const double lo1 = a1.s_lo + m1, hi1 = a1.s_lo - 1 + m1;
+                const double lo2 = a2.s_lo + m2, hi2 = a2.s_lo - 1 + m2;
+                // Every source of the line takes +1/2 at one end image and -1/2
+                // at the other; the corner (pass 0) is completed below, the
+                // corner's place in the tie row (pass 1) gets weight 0.
+#pragma unroll 4
+                for (int kk = lane; kk < cn; kk += L) {
+                    const int k = c0 + kk;   // source index along the tie line
+                    const double2 v0 = lds[0][kk], v1 = lds[1][kk], v2 = lds[2][kk];
+                    const double dx = xi - v0.x, dy = yi - v0.y, dz = zi - v1.x;
+                    const double g1 = v1.y, g2 = v2.x, g3 = v2.y;
+                    if (PASS == 0) {
+                        // end images differ along axis 1: r = (r1a | r1b, r2, r3)
+                        const double r2 = dy - ((k < a2.b) ? lo2 : hi2) * m.L2;
+                        const double t = fma(r2, r2, fma(dz, dz, m.eps2));
+                        const double r1a = dx - lo1 * m.L1, r1b = dx - hi1 * m.L1;
+                        const double wa = 0.5 * inv_cube_sqrt(fma(r1a, r1a, t));
+                        const double wb = -0.5 * inv_cube_sqrt(fma(r1b, r1b, t));
+                        const double W = wa + wb, M = fma(wa, r1a, wb * r1b);
+                        acc[0] = fma(W, r2 * g3 - dz * g2, acc[0]);
+                        acc[1] = fma(W * dz, g1, fma(-M, g3, acc[1]));
+                        acc[2] = fma(M, g2, fma(-W * r2, g1, acc[2]));
                     } else {
-                        const double S2 = (j2 < a2.b) ? lo2 : hi2;
-                        tie_term(m, xi, yi, zi, z, gam, pj, lo1, S2, 0.5, acc);
-                        tie_term(m, xi, yi, zi, z, gam, pj, hi1, S2, -0.5, acc);
+                        // end images differ along axis 2: r = (r1, r2a | r2b, r3);
+                        // the corner's place in the row has weight 0
+                        const double c = (even1 && k == a1.b) ? 0.0 : 0.5;
+                        const double r1 = dx - ((k < a1.b) ? lo1 : hi1) * m.L1;
+                        const double t = fma(r1, r1, fma(dz, dz, m.eps2));
+                        const double r2a = dy - lo2 * m.L2, r2b = dy - hi2 * m.L2;
+                        const double wa = c * inv_cube_sqrt(fma(r2a, r2a, t));
+                        const double wb = -c * inv_cube_sqrt(fma(r2b, r2b, t));
+                        const double W = wa + wb, M = fma(wa, r2a, wb * r2b);
+                        acc[0] = fma(M, g3, fma(-W * dz, g2, acc[0]));
+                        acc[1] = fma(W, dz * g1 - r1 * g3, acc[1]);
+                        acc[2] = fma(W * r1, g2, fma(-M, g1, acc[2]));
                     }
-                }
-            } else if (pass == 1 && even2) {
-                const int j2 = a2.b;
-                for (int j1 = lane; j1 < n1; j1 += L) {
-                    if (even1 && j1 == a1.b) continue;
-                    const int pj = j2 * n1 + j1;
-                    const double S1 = (j1 < a1.b) ? lo1 : hi1;
-                    tie_term(m, xi, yi, zi, z, gam, pj, S1, lo2, 0.5, acc);
-                    tie_term(m, xi, yi, zi, z, gam, pj, S1, hi2, -0.5, acc);
                 }
             }
         }
     }
-    // butterfly over the lane group: every lane ends with the same sum
-#pragma unroll
+    if (pass == 0 && even2 && active && lane == 0) {
+        // corner (tied on both axes): the loop gave +1/2 at (lo1, hi2) and -1/2
+        // at (hi1, hi2); the weights are 1/4, 1/4, 1/4 at (lo1, lo2), (lo1, hi2),
+        // (hi1, lo2) and -3/4 at (hi1, hi2)
+        const int pj = a2.b * n1 + a1.b;
+        const double dx = xi - z[pj], dy = yi - z[N + pj], dz = zi - z[2 * N + pj];
+        const double g1 = gam[pj], g2 = gam[N + pj], g3 = gam[2 * N + pj];
+        for (int m2 = -m.K; m2 <= m.K; ++m2) {
+            for (int m1 = -m.K; m1 <= m.K; ++m1) {
+                const double lo1 = a1.s_lo + m1, hi1 = a1.s_lo - 1 + m1;
+                const double lo2 = a2.s_lo + m2, hi2 = a2.s_lo - 1 + m2;
+                tie_term(m, dx, dy, dz, g1, g2, g3, lo1, lo2, 0.25, acc);
+                tie_term(m, dx, dy, dz, g1, g2, g3, lo1, hi2, -0.25, acc);
+                tie_term(m, dx, dy, dz, g1, g2, g3, hi1, lo2, 0.25, acc);
+                tie_term(m, dx, dy, dz, g1, g2, g3, hi1, hi2, -0.25, acc);
+            }
+        }
+    }
+    // butterfly over the target's lanes (consecutive lanes of one wave)
     for (int off = L / 2; off > 0; off >>= 1) {
         acc[0] += __shfl_xor(acc[0], off, L);
         acc[1] += __shfl_xor(acc[1], off, L);
         acc[2] += __shfl_xor(acc[2], off, L);
     }
-    if (lane == 0) {
+    if (active && lane == 0) {
         double* out = tie + (size_t)pass * 3 * N;
         out[p] = acc[0];
         out[N + p] = acc[1];

@@ -40,13 +40,13 @@ __global__ __launch_bounds__(kThreads) void k_pairs_f32(Mesh m, PairShape sh,
 }
 
 // blockIdx.y = pass (0: tie column, 1: tie row); L threads per target
-template <int L>
 __global__ __launch_bounds__(kThreads) void k_ties(Mesh m, const double* __restrict__ z,
                                                    const double* __restrict__ gam,
                                                    double* __restrict__ tie)
 {
-    const int t = blockIdx.x * kThreads + threadIdx.x;
-    dev::ties_group<L>(m, t / L, t % L, blockIdx.y, z, gam, tie);
+    __shared__ double2 lds[3][kThreads];
+    if (blockIdx.y == 0) dev::ties_block<0>(m, blockIdx.x, z, gam, tie, lds);
+    else dev::ties_block<1>(m, blockIdx.x, z, gam, tie, lds);
 }
 
 __global__ __launch_bounds__(kThreads) void k_reduce(Mesh m, int splits,
@@ -188,11 +188,9 @@ hipError_t launch_pairs_f32(const Mesh& m, const PairShape& sh, const double* z,
 hipError_t launch_ties(const Mesh& m, const double* z, const double* gam, double* tie,
                        hipStream_t s)
 {
-    const int L = dev::tie_lanes(m.N);
-    const dim3 grid(blocks_for(m.N * L), 2);
-    if (L == 1) hipLaunchKernelGGL(k_ties<1>, grid, dim3(kThreads), 0, s, m, z, gam, tie);
-    else if (L == 4) hipLaunchKernelGGL(k_ties<4>, grid, dim3(kThreads), 0, s, m, z, gam, tie);
-    else hipLaunchKernelGGL(k_ties<16>, grid, dim3(kThreads), 0, s, m, z, gam, tie);
+    const int blocks = dev::tie_blocks(m.n1, m.n2);
+    if (blocks == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_ties, dim3(blocks, 2), dim3(kThreads), 0, s, m, z, gam, tie);
     return hipGetLastError();
 }
 

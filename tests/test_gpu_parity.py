@@ -43,7 +43,7 @@ def gpu_br(p, z, w, device):
 
 @pytest.mark.parametrize("n1,n2,seed", [
     (8, 8, 0), (64, 64, 1), (40, 24, 2), (33, 27, 3), (48, 96, 4), (17, 130, 5), (96, 40, 6),
-    (9, 8, 7),
+    (9, 8, 7), (300, 12, 8), (12, 520, 9), (160, 24, 10), (64, 200, 11),
 ])
 def test_br_velocity_matches_oracle(gpu, n1, n2, seed):
     p = params(n1, n2)
