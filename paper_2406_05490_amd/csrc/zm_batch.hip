@@ -129,8 +129,7 @@ __global__ __launch_bounds__(kThreads) void kb_pairs_f32(const InstDesc* __restr
                                                          int nitems, int* __restrict__ counter,
                                                          int stage)
 {
-    __shared__ float4 lds0[2][kThreads];
-    __shared__ float2 lds1[2][kThreads];
+    __shared__ dev::F32Tile tile;
     __shared__ int next;
     for (;;) {
         if (threadIdx.x == 0) next = atomicAdd(counter, 1);
@@ -142,13 +141,13 @@ __global__ __launch_bounds__(kThreads) void kb_pairs_f32(const InstDesc* __restr
         const InstDesc& d = T[w.inst];
         if (d.sh.cx == 32)
             dev::pairs_f32_block<R, 32>(d.m, d.sh, d.Y[stage], d.gam, d.part, w.patch, w.split,
-                                        lds0, lds1);
+                                        tile);
         else if (d.sh.cx == 16)
             dev::pairs_f32_block<R, 16>(d.m, d.sh, d.Y[stage], d.gam, d.part, w.patch, w.split,
-                                        lds0, lds1);
+                                        tile);
         else
             dev::pairs_f32_block<R, 8>(d.m, d.sh, d.Y[stage], d.gam, d.part, w.patch, w.split,
-                                       lds0, lds1);
+                                       tile);
     }
 }
 

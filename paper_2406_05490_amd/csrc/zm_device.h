@@ -163,24 +163,49 @@ __device__ __forceinline__ AxisImg axis_img(int i, int n)
 // source.  Pair terms and per-row partial sums are FP32; every row's partial
 // is added into FP64 per-target accumulators.
 
+// Away from the patch the same factored sum as the FP64 kernel is used
+// (a x sum w g - sum w c with c = b x g formed once per staged source): for a
+// source at distance |r| the rounding of the two terms is amplified by
+// about |a| / |r|, which is below 1/4 outside a near box of four patch
+// half-extents around the patch, so there it is no worse than the direct
+// form and takes 15 instead of 18 VALU operations per pair.  Inside the near
+// box, in the antipodal band and for extra image layers the direct form is
+// used.
+
 #ifndef ZM_PAIR32_UNROLL
 #define ZM_PAIR32_UNROLL 2
 #endif
+#ifndef ZM_F32_FACTORED
+#define ZM_F32_FACTORED 1
+#endif
 
-template <int R, bool BAND>
-__device__ __forceinline__ void pair_segment_f32(const float4* __restrict__ p0,
-                                                 const float2* __restrict__ p1, int k0, int cnt,
+// Near box half-width beyond the patch, in patch half-extents.
+constexpr double kF32NearExtents = 4.0;
+
+// Staged FP32 sources, double buffered: (bx, by, bz, g1), (g2, g3, c1, c2), c3.
+struct F32Tile {
+    float4 a[2][kThreads];
+    float4 b[2][kThreads];
+    float c[2][kThreads];
+};
+
+// MODE 0: direct form; 1: direct form with the antipodal-band image
+// correction; 2: factored form.  The row's partial is a x G - C: the
+// factored form adds w g to G and w c to C, the direct form subtracts
+// w (r x g) from C.
+template <int R, int MODE>
+__device__ __forceinline__ void pair_segment_f32(const F32Tile& T, int buf, int k0, int cnt,
                                                  int j1s, int b1, int s1lo, int bc1, int sc1lo,
                                                  float L1, float dm1, const float* ax,
                                                  const float* ay, const float* az, float eps2,
-                                                 float (*sa)[3])
+                                                 float (*G)[3], float (*C)[3])
 {
 #pragma unroll ZM_PAIR32_UNROLL
     for (int c = 0; c < cnt; ++c) {
-        const float4 v0 = p0[k0 + c];
-        const float2 v1 = p1[k0 + c];
+        const float4 v0 = T.a[buf][k0 + c];
+        const float4 v1 = T.b[buf][k0 + c];
         float bx = v0.x;
-        if (BAND) {
+        if (MODE == 1) {
             const int jj = j1s + c;
             const int si = (jj < b1) ? s1lo : s1lo - 1;
             const int sc = (jj < bc1) ? sc1lo : sc1lo - 1;
@@ -188,35 +213,64 @@ __device__ __forceinline__ void pair_segment_f32(const float4* __restrict__ p0,
         }
         const float by = v0.y, bz = v0.z;
         const float g1 = v0.w, g2 = v1.x, g3 = v1.y;
+        if (MODE == 2) {
+            const float c1 = v1.z, c2 = v1.w, c3 = T.c[buf][k0 + c];
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const float r1 = ax[r] - bx;
-            const float r2 = ay[r] - by;
-            const float r3 = az[r] - bz;
-            const float s = fmaf(r1, r1, fmaf(r2, r2, fmaf(r3, r3, eps2)));
-            const float y = __builtin_amdgcn_rsqf(s);
-            const float wgt = y * y * y;
-            const float a1 = wgt * g1, a2 = wgt * g2, a3 = wgt * g3;
-            sa[r][0] = fmaf(r2, a3, sa[r][0]);
-            sa[r][0] = fmaf(-r3, a2, sa[r][0]);
-            sa[r][1] = fmaf(r3, a1, sa[r][1]);
-            sa[r][1] = fmaf(-r1, a3, sa[r][1]);
-            sa[r][2] = fmaf(r1, a2, sa[r][2]);
-            sa[r][2] = fmaf(-r2, a1, sa[r][2]);
+            for (int r = 0; r < R; ++r) {
+                const float r1 = ax[r] - bx;
+                const float r2 = ay[r] - by;
+                const float r3 = az[r] - bz;
+                const float s = fmaf(r1, r1, fmaf(r2, r2, fmaf(r3, r3, eps2)));
+                const float y = __builtin_amdgcn_rsqf(s);
+                const float wgt = y * y * y;
+                G[r][0] = fmaf(wgt, g1, G[r][0]);
+                G[r][1] = fmaf(wgt, g2, G[r][1]);
+                G[r][2] = fmaf(wgt, g3, G[r][2]);
+                C[r][0] = fmaf(wgt, c1, C[r][0]);
+                C[r][1] = fmaf(wgt, c2, C[r][1]);
+                C[r][2] = fmaf(wgt, c3, C[r][2]);
+            }
+        } else {
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const float r1 = ax[r] - bx;
+                const float r2 = ay[r] - by;
+                const float r3 = az[r] - bz;
+                const float s = fmaf(r1, r1, fmaf(r2, r2, fmaf(r3, r3, eps2)));
+                const float y = __builtin_amdgcn_rsqf(s);
+                const float wgt = y * y * y;
+                const float a1 = wgt * g1, a2 = wgt * g2, a3 = wgt * g3;
+                // the row's sum is a x G - C: a direct term d enters as C -= d
+                C[r][0] = fmaf(-r2, a3, C[r][0]);
+                C[r][0] = fmaf(r3, a2, C[r][0]);
+                C[r][1] = fmaf(-r3, a1, C[r][1]);
+                C[r][1] = fmaf(r1, a3, C[r][1]);
+                C[r][2] = fmaf(-r1, a2, C[r][2]);
+                C[r][2] = fmaf(r2, a1, C[r][2]);
+            }
         }
     }
 }
 
+// Position of column a relative to the periodic interval [lo, lo + len) of
+// an n-column axis: whether a lies inside, and how many columns from a on
+// keep that state.
+__device__ __forceinline__ int interval_run(int a, int lo, int len, int n, bool& inside)
+{
+    int d = a - lo;
+    if (d < 0) d += n;
+    inside = d < len;
+    return inside ? len - d : n - d;
+}
+
 // Workgroup = target patch of PX columns x (256/PX)*R rows (lane = one
 // column, R rows 256/PX apart) x one range of source rows.
-// lds0: [buffer][source] (x, y, z, g1) relative to the patch centre;
-// lds1: [buffer][source] (g2, g3).
 template <int R, int PX>
 __device__ __forceinline__ void pairs_f32_block(const Mesh& m, const PairShape& sh,
                                                 const double* __restrict__ z,
                                                 const double* __restrict__ gam,
                                                 double* __restrict__ part, int patch, int split,
-                                                float4 (*lds0)[kThreads], float2 (*lds1)[kThreads])
+                                                F32Tile& T)
 {
     constexpr int RY = kThreads / PX;
     constexpr int PY = RY * R;
@@ -237,8 +291,16 @@ __device__ __forceinline__ void pairs_f32_block(const Mesh& m, const PairShape& 
     const AxisImg cimg1 = axis_img(ci1, n1), cimg2 = axis_img(ci2, n2);
     // antipodal band along axis 1: breakpoints of columns c0 .. c0+PX-1
     const int band_lo = axis_img(c0, n1).b;
-    const bool band_all = PX >= n1;
-    const bool band_wraps = band_lo + PX > n1;
+    const int band_len = PX >= n1 ? n1 : PX;
+
+    // near box: patch widened by kF32NearExtents patch half-extents
+    const double ext = 0.5 * sqrt((double)(PX * PX) * m.h1 * m.h1 + (double)(PY * PY) * m.h2 * m.h2);
+    const int d1 = (int)ceil(kF32NearExtents * ext / m.h1);
+    const int d2 = (int)ceil(kF32NearExtents * ext / m.h2);
+    const int near1_len = PX + 2 * d1 >= n1 ? n1 : PX + 2 * d1;
+    const int near1_lo = ((c0 - d1) % n1 + n1) % n1;
+    const int near2_len = PY + 2 * d2 >= n2 ? n2 : PY + 2 * d2;
+    const int near2_lo = ((r0 - d2) % n2 + n2) % n2;
 
     // ---- targets of this lane --------------------------------------------
     const int col = c0 + (tid % PX);
@@ -277,8 +339,8 @@ __device__ __forceinline__ void pairs_f32_block(const Mesh& m, const PairShape& 
     const float eps2f = (float)m.eps2;
 
     // ---- staging: source j relative to the centre, centre's image --------
-    float4 st0;
-    float2 st1;
+    float4 st0, st1;
+    float st2;
     auto load_tile = [&](int t) {
         const int tile = t % ntiles;
         const int j = src_begin + tile * kThreads + tid;
@@ -286,18 +348,24 @@ __device__ __forceinline__ void pairs_f32_block(const Mesh& m, const PairShape& 
             const int j2 = j / n1, j1 = j - j2 * n1;
             const int sc1 = (j1 < cimg1.b) ? cimg1.s_lo : cimg1.s_lo - 1;
             const int sc2 = (j2 < cimg2.b) ? cimg2.s_lo : cimg2.s_lo - 1;
-            st0 = make_float4((float)((z[j] + (double)sc1 * m.L1) - cx),
-                              (float)((z[N + j] + (double)sc2 * m.L2) - cy),
-                              (float)(z[2 * N + j] - cz), (float)gam[j]);
-            st1 = make_float2((float)gam[N + j], (float)gam[2 * N + j]);
+            const double bx = (z[j] + (double)sc1 * m.L1) - cx;
+            const double by = (z[N + j] + (double)sc2 * m.L2) - cy;
+            const double bz = z[2 * N + j] - cz;
+            const double g1 = gam[j], g2 = gam[N + j], g3 = gam[2 * N + j];
+            st0 = make_float4((float)bx, (float)by, (float)bz, (float)g1);
+            st1 = make_float4((float)g2, (float)g3, (float)(by * g3 - bz * g2),
+                              (float)(bz * g1 - bx * g3));
+            st2 = (float)(bx * g2 - by * g1);
         } else {
             st0 = make_float4(0.f, 0.f, 0.f, 0.f);
-            st1 = make_float2(0.f, 0.f);
+            st1 = make_float4(0.f, 0.f, 0.f, 0.f);
+            st2 = 0.f;
         }
     };
     auto store_tile = [&](int buf) {
-        lds0[buf][tid] = st0;
-        lds1[buf][tid] = st1;
+        T.a[buf][tid] = st0;
+        T.b[buf][tid] = st1;
+        T.c[buf][tid] = st2;
     };
 
     load_tile(0);
@@ -313,6 +381,7 @@ __device__ __forceinline__ void pairs_f32_block(const Mesh& m, const PairShape& 
         const int m2 = img / side - m.K;
         // extra image layers shift every source by (m1 L1, m2 L2)
         const float dm1 = (float)((double)m1 * m.L1);
+        const bool layer0 = m1 == 0 && m2 == 0;
 
         const int j0 = src_begin + tile * kThreads;
         const int cnt = min(kThreads, src_end - j0);
@@ -328,44 +397,46 @@ __device__ __forceinline__ void pairs_f32_block(const Mesh& m, const PairShape& 
                 const int s2 = (j2 < b2[r]) ? s2lo[r] : s2lo[r] - 1;
                 ayr[r] = (float)(ayd[r] - (double)(s2 - sc2 + m2) * m.L2);
             }
-            float sa[R][3];
+            bool near_row;
+            interval_run(j2, near2_lo, near2_len, n2, near_row);
+            const bool fact_row = ZM_F32_FACTORED && layer0;
+            float G[R][3], C[R][3];
 #pragma unroll
-            for (int r = 0; r < R; ++r) sa[r][0] = sa[r][1] = sa[r][2] = 0.f;
+            for (int r = 0; r < R; ++r) {
+                G[r][0] = G[r][1] = G[r][2] = 0.f;
+                C[r][0] = C[r][1] = C[r][2] = 0.f;
+            }
 
             int a = j1;
             const int e = j1 + seg;
             while (a < e) {
-                bool in_band;
-                int stop;
-                if (band_all) {
-                    in_band = true; stop = e;
-                } else if (!band_wraps) {
-                    if (a < band_lo) { in_band = false; stop = min(e, band_lo); }
-                    else if (a < band_lo + PX) { in_band = true; stop = min(e, band_lo + PX); }
-                    else { in_band = false; stop = e; }
-                } else {
-                    const int hi_end = band_lo + PX - n1;
-                    if (a < hi_end) { in_band = true; stop = min(e, hi_end); }
-                    else if (a < band_lo) { in_band = false; stop = min(e, band_lo); }
-                    else { in_band = true; stop = e; }
+                bool in_band, in_near = false;
+                int run = interval_run(a, band_lo, band_len, n1, in_band);
+                if (near_row) {
+                    const int rn = interval_run(a, near1_lo, near1_len, n1, in_near);
+                    run = min(run, rn);
                 }
+                const int stop = min(e, a + run);
                 const int kk = k + (a - j1);
                 if (in_band || m1 != 0) {
-                    pair_segment_f32<R, true>(lds0[buf], lds1[buf], kk, stop - a, a, ax1.b,
-                                              ax1.s_lo, cimg1.b, cimg1.s_lo, L1f, dm1, ax, ayr, az,
-                                              eps2f, sa);
+                    pair_segment_f32<R, 1>(T, buf, kk, stop - a, a, ax1.b, ax1.s_lo, cimg1.b,
+                                           cimg1.s_lo, L1f, dm1, ax, ayr, az, eps2f, G, C);
+                } else if (in_near || !fact_row) {
+                    pair_segment_f32<R, 0>(T, buf, kk, stop - a, a, ax1.b, ax1.s_lo, cimg1.b,
+                                           cimg1.s_lo, L1f, dm1, ax, ayr, az, eps2f, G, C);
                 } else {
-                    pair_segment_f32<R, false>(lds0[buf], lds1[buf], kk, stop - a, a, ax1.b,
-                                               ax1.s_lo, cimg1.b, cimg1.s_lo, L1f, dm1, ax, ayr,
-                                               az, eps2f, sa);
+                    pair_segment_f32<R, 2>(T, buf, kk, stop - a, a, ax1.b, ax1.s_lo, cimg1.b,
+                                           cimg1.s_lo, L1f, dm1, ax, ayr, az, eps2f, G, C);
                 }
                 a = stop;
             }
 #pragma unroll
             for (int r = 0; r < R; ++r) {
-                acc[r][0] += (double)sa[r][0];
-                acc[r][1] += (double)sa[r][1];
-                acc[r][2] += (double)sa[r][2];
+                // a x G - C, combined in FP64
+                const double gx = G[r][0], gy = G[r][1], gz = G[r][2];
+                acc[r][0] += ((double)ayr[r] * gz - (double)az[r] * gy) - (double)C[r][0];
+                acc[r][1] += ((double)az[r] * gx - (double)ax[r] * gz) - (double)C[r][1];
+                acc[r][2] += ((double)ax[r] * gy - (double)ayr[r] * gx) - (double)C[r][2];
             }
             k += seg;
             j1 += seg;

@@ -34,9 +34,8 @@ __global__ __launch_bounds__(kThreads) void k_pairs_f32(Mesh m, PairShape sh,
                                                         const double* __restrict__ gam,
                                                         double* __restrict__ part)
 {
-    __shared__ float4 lds0[2][kThreads];
-    __shared__ float2 lds1[2][kThreads];
-    dev::pairs_f32_block<R, PX>(m, sh, z, gam, part, blockIdx.x, blockIdx.y, lds0, lds1);
+    __shared__ dev::F32Tile tile;
+    dev::pairs_f32_block<R, PX>(m, sh, z, gam, part, blockIdx.x, blockIdx.y, tile);
 }
 
 // blockIdx.y = pass (0: tie column, 1: tie row); L threads per target
@@ -128,13 +127,13 @@ PairShape choose_pair_shape(int n1, int n2, int precision)
     if (lookup_tuning(n1, n2, precision, &R, &splits)) return make_pair_shape(n1, n2, precision, R, splits);
     // Untuned default, from autotuner runs on MI355X (32^2 .. 1024^2): fewer
     // targets per lane on small meshes (more waves in flight); FP32 prefers 2
-    // targets per lane on large meshes, FP64 4; twice the default source
-    // splits helps mid-size meshes.
+    // targets per lane from 64^2 up, FP64 4 from 128^2 up; twice the default
+    // source splits helps FP32 from 64^2 up and FP64 on mid-size meshes.
     const long N = (long)n1 * n2;
-    if (precision == 1) R = N >= 65536 ? 2 : (N >= 16384 ? 4 : (N >= 4096 ? 2 : 1));
+    if (precision == 1) R = N >= 4096 ? 2 : 1;
     else R = N >= 16384 ? 4 : (N >= 9216 ? 2 : 1);
     const PairShape d = make_pair_shape(n1, n2, precision, R, 0);
-    const bool mid = precision == 1 ? (N >= 4096 && N < 65536) : (N >= 9216);
+    const bool mid = precision == 1 ? (N >= 4096) : (N >= 9216);
     return mid ? make_pair_shape(n1, n2, precision, R, 2 * d.splits) : d;
 }
 
