@@ -65,13 +65,27 @@ __global__ __launch_bounds__(kThreads) void kb_ties(const InstDesc* __restrict__
     else dev::ties_block<1>(d.m, b, d.Y[stage], d.gam, d.tie, lds);
 }
 
+// The same search over the reduction's block offsets.
+__device__ __forceinline__ int find_reduce_instance(const InstDesc* __restrict__ T, int count, int b)
+{
+    int lo = 0, hi = count - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (T[mid].reduce_block_begin <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
 __global__ __launch_bounds__(kThreads) void kb_reduce(const InstDesc* __restrict__ T, int count,
                                                       int stage)
 {
-    const int i = find_instance(T, count, blockIdx.x);
+    const int i = find_reduce_instance(T, count, blockIdx.x);
     const InstDesc& d = T[i];
-    const int p = (blockIdx.x - d.block_begin) * kThreads + threadIdx.x;
-    dev::reduce_point(d.m, p, d.sh.splits, d.part, d.tie, d.q, d.Y[stage], d.u, d.V);
+    const int t = (blockIdx.x - d.reduce_block_begin) * kThreads + threadIdx.x;
+    // one instance per block, so the lane count is uniform over the block
+    dev::reduce_thread(d.m, t, dev::reduce_lanes(d.m.N, d.sh.splits), d.sh.splits, d.part, d.tie,
+                       d.q, d.Y[stage], d.u, d.V);
 }
 
 __global__ __launch_bounds__(kThreads) void kb_update(const InstDesc* __restrict__ T, int count,
@@ -154,6 +168,7 @@ __global__ __launch_bounds__(kThreads) void kb_pairs_f32(const InstDesc* __restr
 }  // namespace
 
 int dev_tie_blocks(int n1, int n2) { return dev::tie_blocks(n1, n2); }
+int dev_reduce_lanes(int N, int splits) { return dev::reduce_lanes(N, splits); }
 
 hipError_t launch_batch_stage(const BatchLaunch& b, int stage, hipStream_t s)
 {
@@ -181,7 +196,7 @@ hipError_t launch_batch_stage(const BatchLaunch& b, int stage, hipStream_t s)
     }
     if (b.any_even)
         hipLaunchKernelGGL(kb_ties, dim3(b.total_tie_blocks, 2), blk, 0, s, b.table, b.count, stage);
-    hipLaunchKernelGGL(kb_reduce, dim3(b.total_blocks), blk, 0, s, b.table, b.count, stage);
+    hipLaunchKernelGGL(kb_reduce, dim3(b.total_reduce_blocks), blk, 0, s, b.table, b.count, stage);
     hipLaunchKernelGGL(kb_update, dim3(b.total_blocks), blk, 0, s, b.table, b.count, stage);
     return hipGetLastError();
 }

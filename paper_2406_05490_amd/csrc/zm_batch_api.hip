@@ -134,7 +134,7 @@ void build_tables(const zm_params* params, const PairShape* shapes, const Layout
     out = TableBuild();
     out.table.resize(count);
     std::vector<std::pair<double, WorkItem>> keyed[kMaxPairGroups];
-    int block = 0, tie_block = 0;
+    int block = 0, tie_block = 0, reduce_block = 0;
     for (int i = 0; i < count; ++i) {
         InstDesc& d = out.table[i];
         std::memset(&d, 0, sizeof(d));
@@ -146,6 +146,8 @@ void build_tables(const zm_params* params, const PairShape* shapes, const Layout
         block += d.blocks;
         d.tie_block_begin = tie_block;
         tie_block += dev_tie_blocks(d.m.n1, d.m.n2);
+        d.reduce_block_begin = reduce_block;
+        reduce_block += (d.m.N * dev_reduce_lanes(d.m.N, shapes[i].splits) + 255) / 256;
         char* base = bases[i];
         const Layout& L = layouts[i];
         d.Y[0] = reinterpret_cast<double*>(base + L.y0);
@@ -174,6 +176,7 @@ void build_tables(const zm_params* params, const PairShape* shapes, const Layout
     }
     out.total_blocks = block;
     out.total_tie_blocks = tie_block;
+    out.total_reduce_blocks = reduce_block;
     static const int kR[3] = {1, 2, 4};
     for (int g = 0; g < kMaxPairGroups; ++g) {
         if (keyed[g].empty()) continue;
@@ -261,6 +264,7 @@ zm_status zm_batch_create(zm_batch** out, const zm_params* params, int32_t count
     L.count = count;
     L.total_blocks = tb.total_blocks;
     L.total_tie_blocks = tb.total_tie_blocks;
+    L.total_reduce_blocks = tb.total_reduce_blocks;
     L.items = ditems;
     L.ngroups = (int)tb.groups.size();
     for (int g = 0; g < L.ngroups; ++g) L.groups[g] = tb.groups[g];

@@ -19,6 +19,7 @@ struct InstDesc {
     int block_begin;     // first block of this instance in the point kernels
     int blocks;          // ceil(N / 256)
     int tie_block_begin; // first block of this instance in the tie kernel
+    int reduce_block_begin; // first block of this instance in the reduction
     double* Y[3];        // RK3 stage states, 5 planes each
     double* gam;         // 3 planes
     double* q;           // 1 plane
@@ -53,6 +54,7 @@ struct BatchLaunch {
     int count;
     int total_blocks;
     int total_tie_blocks;
+    int total_reduce_blocks;
     const WorkItem* items;   // device; grouped by PairGroup, each group longest first
     PairGroup groups[kMaxPairGroups];
     int ngroups;
@@ -64,6 +66,10 @@ struct BatchLaunch {
 // Workgroups of the tie kernel for an n1 x n2 mesh (host mirror of the
 // device rule in zm_device.h's tie_blocks).
 int dev_tie_blocks(int n1, int n2);
+
+// Lanes per point of the split reduction (host mirror of zm_device.h's
+// reduce_lanes).
+int dev_reduce_lanes(int N, int splits);
 
 // Enqueue one RK3 stage (surface, pairs, ties, reduce, update) for every
 // instance of the batch.  Non-finite results are flagged per instance
@@ -79,6 +85,7 @@ struct TableBuild {
     std::vector<PairGroup> groups;
     int total_blocks = 0;
     int total_tie_blocks = 0;
+    int total_reduce_blocks = 0;
     bool any_even = false;
 };
 

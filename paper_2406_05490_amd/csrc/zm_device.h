@@ -16,7 +16,7 @@
 //   pairs_f32_block   the same in FP32 pair arithmetic (direct form) with
 //                     FP64 per-target sums.
 //   ties_block        split-tie correction for even n_a (tie line staged in LDS).
-//   reduce_point      fixed-order sum over source splits and tie passes,
+//   reduce_group      fixed-order sum over source splits and tie passes,
 //                     scale, Bernoulli potential V.
 //   update_point      D V (+ nu Lap w) and the SSP-RK3 stage combination.
 #pragma once
@@ -927,38 +927,71 @@ __device__ __forceinline__ void ties_block(const Mesh& m, int blk,
 // reduction over source splits, Bernoulli potential
 // ---------------------------------------------------------------------------
 
-__device__ __forceinline__ void reduce_point(const Mesh& m, int p, int splits,
+// Lanes per point of the split reduction (1, 4 or 16, never more than the
+// splits): small meshes have few points, so several lanes share a point's
+// splits to keep enough loads in flight.
+__host__ __device__ inline int reduce_lanes(int N, int splits)
+{
+    int L = N >= 65536 ? 1 : (N >= 16384 ? 4 : 16);
+    while (L > 1 && L > splits) L >>= 2;
+    return L;
+}
+
+// u = coef * (sum over splits + tie passes) at point p, and V.  Lanes
+// lane = 0 .. L-1 of a group take the splits lane, lane + L, ... in order and
+// are combined by a fixed butterfly; lane 0 adds the tie passes and writes.
+// All lanes of a group must call this together.
+template <int L>
+__device__ __forceinline__ void reduce_group(const Mesh& m, int p, int lane, int splits,
                                              const double* __restrict__ part,
                                              const double* __restrict__ tie,
                                              const double* __restrict__ q,
                                              const double* __restrict__ z, double* __restrict__ u,
                                              double* __restrict__ V)
 {
-    if (p >= m.N) return;
+    if (p >= m.N) return;   // the whole lane group leaves together
     const size_t N = m.N;
     double a[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-        // sequential sum over the splits; loads are issued 8 at a time
+        // strided sum over the splits; loads are issued 8 at a time
         double s = 0.0;
-        int k = 0;
-        for (; k + 8 <= splits; k += 8) {
+        int k = lane;
+        for (; k + 7 * L < splits; k += 8 * L) {
             double v[8];
 #pragma unroll
-            for (int t = 0; t < 8; ++t) v[t] = part[((size_t)(k + t) * 3 + c) * N + p];
+            for (int t = 0; t < 8; ++t) v[t] = part[((size_t)(k + t * L) * 3 + c) * N + p];
 #pragma unroll
             for (int t = 0; t < 8; ++t) s += v[t];
         }
-        for (; k < splits; ++k) s += part[((size_t)k * 3 + c) * N + p];
+        for (; k < splits; k += L) s += part[((size_t)k * 3 + c) * N + p];
+#pragma unroll
+        for (int off = L / 2; off > 0; off >>= 1) s += __shfl_xor(s, off, L);
         if ((m.n1 & 1) == 0) s += tie[c * N + p];
         if ((m.n2 & 1) == 0) s += tie[(3 + c) * N + p];
         a[c] = m.coef * s;
-        u[c * N + p] = a[c];
     }
+    if (lane != 0) return;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) u[c * N + p] = a[c];
     if (V) {
         const double uu = a[0] * a[0] + a[1] * a[1] + a[2] * a[2];
         V[p] = m.atwood * ((uu - 0.25 * q[p]) - (2.0 * m.gravity) * z[2 * N + p]);
     }
+}
+
+// Dispatch on the lane count for thread t of a reduction over the mesh
+// (t / L is the point; L must be uniform over the wave).
+__device__ __forceinline__ void reduce_thread(const Mesh& m, int t, int L, int splits,
+                                              const double* __restrict__ part,
+                                              const double* __restrict__ tie,
+                                              const double* __restrict__ q,
+                                              const double* __restrict__ z,
+                                              double* __restrict__ u, double* __restrict__ V)
+{
+    if (L == 1) reduce_group<1>(m, t, 0, splits, part, tie, q, z, u, V);
+    else if (L == 4) reduce_group<4>(m, t >> 2, t & 3, splits, part, tie, q, z, u, V);
+    else reduce_group<16>(m, t >> 4, t & 15, splits, part, tie, q, z, u, V);
 }
 
 // ---------------------------------------------------------------------------

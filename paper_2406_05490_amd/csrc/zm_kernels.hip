@@ -56,7 +56,8 @@ __global__ __launch_bounds__(kThreads) void k_reduce(Mesh m, int splits,
                                                      double* __restrict__ u,
                                                      double* __restrict__ V)
 {
-    dev::reduce_point(m, blockIdx.x * kThreads + threadIdx.x, splits, part, tie, q, z, u, V);
+    dev::reduce_thread(m, blockIdx.x * kThreads + threadIdx.x, dev::reduce_lanes(m.N, splits), splits,
+                       part, tie, q, z, u, V);
 }
 
 // y0 may alias out (see update_point), so neither carries __restrict__.
@@ -196,7 +197,8 @@ hipError_t launch_ties(const Mesh& m, const double* z, const double* gam, double
 hipError_t launch_reduce(const Mesh& m, int splits, const double* part, const double* tie,
                          const double* q, const double* z, double* u, double* V, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_reduce, dim3(blocks_for(m.N)), dim3(kThreads), 0, s, m, splits, part, tie,
+    const int L = dev::reduce_lanes(m.N, splits);
+    hipLaunchKernelGGL(k_reduce, dim3(blocks_for(m.N * L)), dim3(kThreads), 0, s, m, splits, part, tie,
                        q, z, u, V);
     return hipGetLastError();
 }

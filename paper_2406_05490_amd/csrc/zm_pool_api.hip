@@ -231,6 +231,7 @@ zm_status rebuild(zm_pool* P)
     L.count = n;
     L.total_blocks = tb.total_blocks;
     L.total_tie_blocks = tb.total_tie_blocks;
+    L.total_reduce_blocks = tb.total_reduce_blocks;
     L.items = reinterpret_cast<const zm::WorkItem*>(tbase + P->tl.items);
     L.ngroups = (int)tb.groups.size();
     for (int g = 0; g < L.ngroups; ++g) L.groups[g] = tb.groups[g];
