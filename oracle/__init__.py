@@ -28,6 +28,7 @@ class _Problem(ctypes.Structure):
         ("period1", ctypes.c_double), ("period2", ctypes.c_double),
         ("atwood", ctypes.c_double), ("gravity", ctypes.c_double),
         ("eps", ctypes.c_double), ("nu", ctypes.c_double), ("dt", ctypes.c_double),
+        ("cutoff", ctypes.c_double),
     ]
 
 
@@ -44,10 +45,11 @@ class Problem:
     images: int = 0
     period1: float = 2.0
     period2: float = 2.0
+    cutoff: float = 0.0       # > 0: cutoff BR solver (3D distance)
 
     def c(self) -> _Problem:
         return _Problem(self.n1, self.n2, self.images, 0, self.period1, self.period2,
-                        self.atwood, self.gravity, self.eps, self.nu, self.dt)
+                        self.atwood, self.gravity, self.eps, self.nu, self.dt, self.cutoff)
 
     @property
     def n(self) -> int:

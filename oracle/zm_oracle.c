@@ -15,7 +15,9 @@
  *     (sec. 3.1, BoundaryCondition).
  *   - The Birkhoff-Rott velocity of every point from the position and
  *     vorticity of every other point (sec. 2, BRSolver), by brute-force
- *     all pairs (sec. 3.2.1, exact integral calculation).
+ *     all pairs (sec. 3.2.1, exact integral calculation), or restricted to
+ *     the sources within a 3D cutoff distance of each target (sec. 3.2.2,
+ *     cutoff-based approximate integral calculation).
  *   - The Z-Model derivatives of position and vorticity (sec. 2, ZModel)
  *     and a third-order Runge-Kutta step with three derivative evaluations
  *     (sec. 3.1, TimeIntegrator).
@@ -38,6 +40,10 @@
  *                                  time derivative is a reading of the
  *                                  model -- parity unpinned.
  *   zmo_rk3_step                : pinned (amplification factor, order 3).
+ *   cutoff BR (cutoff > 0)      : pinned (flat-sheet lattice-sum eigenvalue
+ *                                  over the disc |rho| < rc, equality with
+ *                                  the exact sum when rc covers the whole
+ *                                  period cell, brute force, symmetries).
  *
  * Arithmetic: plain double, 1.0/sqrt(s), Neumaier-compensated per-target
  * sums in a fixed sequential source order, no FMA contraction (build with
@@ -63,6 +69,7 @@ typedef struct {
     double eps;              /* desingularisation length                     */
     double nu;               /* optional artificial viscosity on w           */
     double dt;               /* time step                                    */
+    double cutoff;           /* > 0: cutoff BR solver with this 3D distance  */
 } zmo_problem;
 
 /* ------------------------------------------------------------------ */
@@ -280,6 +287,47 @@ static void br_one_target(const zmo_problem *P, const double *z, const double *g
     out[2] = coef * nm_value(&a3);
 }
 
+/* Cutoff BR, one target: the same kernel summed only over the sources whose
+ * nearest periodic image lies within the 3D distance rc of the target.  Per
+ * axis a = 1, 2 the image shift is the integer S_a nearest to
+ * (z_i,a - z_j,a) / L_a; with r = (z_i - z_j) - (S1 L1, S2 L2, 0), written
+ * out as r_a = (z_i,a - z_j,a) - S_a L_a, the source counts (weight 1) iff
+ * r1*r1 + r2*r2 + r3*r3 < rc*rc, evaluated left to right in plain double.
+ * rc <= 0.45 min(L1, L2), so at most one image of a source can be that
+ * close and a source (nearly) half a period away along an axis never is.  Sources in index
+ * order; no extra image layers. */
+static void br_cutoff_one_target(const zmo_problem *P, const double *z, const double *gamma,
+                                 int i1, int i2, double coef, double out[3])
+{
+    const int n1 = P->n1, n2 = P->n2;
+    const size_t N = (size_t)n1 * n2;
+    const double L1 = P->period1, L2 = P->period2;
+    const double eps_sq = P->eps * P->eps;
+    const double rc2 = P->cutoff * P->cutoff;
+    const size_t pi_ = (size_t)i2 * n1 + i1;
+    const double zi1 = z[pi_], zi2 = z[N + pi_], zi3 = z[2 * N + pi_];
+    neumaier a1 = {0, 0}, a2 = {0, 0}, a3 = {0, 0};
+
+    for (size_t pj = 0; pj < N; ++pj) {
+        const double d1 = zi1 - z[pj], d2 = zi2 - z[N + pj];
+        const double S1 = nearbyint(d1 / L1), S2 = nearbyint(d2 / L2);
+        const double r1 = d1 - S1 * L1;
+        const double r2 = d2 - S2 * L2;
+        const double r3 = zi3 - z[2 * N + pj];
+        const double dd = r1 * r1 + r2 * r2 + r3 * r3;
+        if (!(dd < rc2)) continue;
+        const double g1 = gamma[pj], g2 = gamma[N + pj], g3 = gamma[2 * N + pj];
+        const double inv = 1.0 / sqrt(dd + eps_sq);
+        const double kw = inv * inv * inv;
+        nm_add(&a1, kw * (r2 * g3 - r3 * g2));
+        nm_add(&a2, kw * (r3 * g1 - r1 * g3));
+        nm_add(&a3, kw * (r1 * g2 - r2 * g1));
+    }
+    out[0] = coef * nm_value(&a1);
+    out[1] = coef * nm_value(&a2);
+    out[2] = coef * nm_value(&a3);
+}
+
 /* BR velocity of the listed targets (point indices), or of all points when
  * targets == NULL.  u: 3 planes of length ntargets (or N).  gamma is the
  * source strength from zmo_surface.  Returns 0, or -1 on bad arguments. */
@@ -287,6 +335,9 @@ int zmo_br_from_gamma(const zmo_problem *P, const double *z, const double *gamma
                       int64_t ntargets, const int64_t *targets, double *u, int nthreads)
 {
     if (!P || P->n1 < 1 || P->n2 < 1 || !(P->eps > 0.0) || P->images < 0) return -1;
+    if (P->cutoff < 0.0 || (P->cutoff > 0.0 && (P->images != 0 || P->cutoff > 0.45 * P->period1 ||
+                                               P->cutoff > 0.45 * P->period2)))
+        return -1;
     const size_t N = (size_t)P->n1 * P->n2;
     const int64_t nt = targets ? ntargets : (int64_t)N;
     const double h1 = P->period1 / P->n1, h2 = P->period2 / P->n2;
@@ -297,7 +348,10 @@ int zmo_br_from_gamma(const zmo_problem *P, const double *z, const double *gamma
         int64_t p = targets ? targets[t] : t;
         if (p < 0 || (size_t)p >= N) { bad = 1; continue; }
         double o[3];
-        br_one_target(P, z, gamma, (int)(p % P->n1), (int)(p / P->n1), coef, o);
+        if (P->cutoff > 0.0)
+            br_cutoff_one_target(P, z, gamma, (int)(p % P->n1), (int)(p / P->n1), coef, o);
+        else
+            br_one_target(P, z, gamma, (int)(p % P->n1), (int)(p / P->n1), coef, o);
         u[t] = o[0];
         u[nt + t] = o[1];
         u[2 * nt + t] = o[2];
@@ -466,4 +520,4 @@ int zmo_rk3_step(const zmo_problem *P, double *z, double *w, int nsteps, int nth
     return 0;
 }
 
-int zmo_abi_version(void) { return 1; }
+int zmo_abi_version(void) { return 2; }

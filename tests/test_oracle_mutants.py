@@ -42,6 +42,11 @@ MUTANTS = {
                      "return P->atwood * ((uu - 0.25 * q) + (2.0 * P->gravity) * z3);"),
     "rk3_stage2_weights": ("y2[k] = 0.75 * y0[k] + 0.25 * (y1[k] + dt * F[k]);",
                            "y2[k] = 0.25 * y0[k] + 0.75 * (y1[k] + dt * F[k]);"),
+    "cutoff_no_image": ("const double r1 = d1 - S1 * L1;", "const double r1 = d1;"),
+    "cutoff_eps_changed": ("const double inv = 1.0 / sqrt(dd + eps_sq);",
+                           "const double inv = 1.0 / sqrt(dd + 0.25 * eps_sq);"),
+    "cutoff_radius_not_squared": ("const double rc2 = P->cutoff * P->cutoff;",
+                                  "const double rc2 = P->cutoff;"),
     "rk3_stage3_weights": ("double y3 = (1.0 / 3.0) * y0[k] + (2.0 / 3.0) * (y2[k] + dt * F[k]);",
                            "double y3 = (1.0 / 2.0) * y0[k] + (1.0 / 2.0) * (y2[k] + dt * F[k]);"),
 }
@@ -65,6 +70,7 @@ def test_mutant_is_caught(name, source, tmp_path):
                     "-shared", str(src), "-o", str(lib), "-lm"], check=True)
     env = dict(os.environ, ZMO_ORACLE_LIB=str(lib), OMP_NUM_THREADS="4")
     r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
-                        os.path.join(ROOT, "tests", "test_oracle_pins.py")],
+                        os.path.join(ROOT, "tests", "test_oracle_pins.py"),
+                        os.path.join(ROOT, "tests", "test_oracle_cutoff.py")],
                        cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
     assert r.returncode == 1, f"mutant {name} passed every pin:\n{r.stdout[-2000:]}"
