@@ -32,6 +32,13 @@
  *              exactly n_a/2 both end images count with weight 1/2; with
  *              image_layers = K > 0 the shifts (s1+m1, s2+m2),
  *              m in [-K, K]^2, are all summed;
+ *   cutoff     with cutoff = rc > 0 (sec. 3.2.2, cutoff-based approximate
+ *              integral) the same sum runs only over the sources whose
+ *              nearest periodic image (per axis the integer S_a nearest to
+ *              (z_i,a - z_j,a) / L_a) lies within the 3D distance rc:
+ *              r_a = (z_i,a - z_j,a) - S_a L_a, included iff
+ *              r1*r1 + r2*r2 + r3*r3 < rc*rc (evaluated in that order in
+ *              double), weight 1, no ties, rc <= 0.45 min(L1, L2), K = 0;
  *   q          |gamma|^2 / |T1 x T2|^2;
  *   V          A (|u|^2 - q/4 - 2 g z3);
  *   F(z, w)    z_t = u,  w_t = (D_1 V, D_2 V) + nu Lap(w);
@@ -99,6 +106,9 @@ typedef struct zm_params {
     int32_t  image_layers;     /* K >= 0 extra periodic image layers            */
     uint32_t flags;            /* ZM_FLAG_*                                     */
     int32_t  reserved;         /* must be 0                                     */
+    double   cutoff;           /* 0: exact all-pairs BR; > 0: cutoff BR with
+                                  this 3D distance (FP64 only, K = 0,
+                                  <= 0.45 min(L1, L2); single contexts only)  */
 } zm_params;
 
 typedef struct zm_ctx zm_ctx;  /* opaque */
@@ -159,7 +169,10 @@ typedef struct zm_launch_info {
 } zm_launch_info;
 
 /* Launch shape the pair kernel uses for this context (depends on n1, n2, K
- * and precision only). */
+ * and precision only).  For a cutoff context: one target per thread, target
+ * blocks of patch_cols x patch_rows cells, source_splits = partial sums per
+ * target (zm_cutoff_info.slots); pairs_per_eval stays N^2, the all-pairs
+ * count. */
 zm_status zm_get_launch_info(const zm_ctx *ctx, zm_launch_info *out);
 
 #define ZM_KERNEL_SURFACE 0  /* tangents, source strength, q        */
@@ -167,7 +180,8 @@ zm_status zm_get_launch_info(const zm_ctx *ctx, zm_launch_info *out);
 #define ZM_KERNEL_TIES    2  /* split-tie correction (even n_a)      */
 #define ZM_KERNEL_REDUCE  3  /* sum of source splits, V              */
 #define ZM_KERNEL_UPDATE  4  /* D V, RK3 stage combination           */
-#define ZM_KERNEL_COUNT   5
+#define ZM_KERNEL_CELLS   5  /* cutoff BR: cell binning and sorting  */
+#define ZM_KERNEL_COUNT   6
 
 typedef struct zm_kernel_stats {
     int64_t launches;           /* launches timed since the last read        */
@@ -181,6 +195,32 @@ zm_status zm_profile_enable(zm_ctx *ctx, int32_t on);
 /* Wait for the timed launches, write ZM_KERNEL_COUNT entries to out (indexed
  * by ZM_KERNEL_*) and reset the counters. */
 zm_status zm_profile_read(zm_ctx *ctx, zm_kernel_stats *out);
+
+/* ---- cutoff solver ---------------------------------------------------------- */
+/*
+ * A context with params.cutoff = rc > 0 evaluates the BR velocity with the
+ * cutoff solver: points are binned into a periodic grid of cells of side
+ * >= rc / cells_per_cutoff in x and y (z unbinned), sorted by cell (stable,
+ * so the source order and every result are deterministic), and each target
+ * visits the cells within cells_per_cutoff of its own.  With timing enabled
+ * (zm_profile_enable) the pair kernel also counts the pairs it tested and
+ * the pairs within rc.
+ */
+typedef struct zm_cutoff_info {
+    int32_t cells1, cells2;      /* cell grid along x / y                     */
+    int32_t cells_per_cutoff;    /* neighbour reach in cells                  */
+    int32_t block_cells;         /* target block side in cells                */
+    int32_t slots;               /* partial sums per target (reduced in order)*/
+    int32_t reserved;
+    int64_t pairs_tested;        /* pair evaluations, see below               */
+    int64_t pairs_accepted;      /* of those, pairs with |r| < rc             */
+} zm_cutoff_info;
+
+/* Cell grid of a cutoff context and the pair counts the timed evaluations
+ * (zm_profile_enable on) accumulated since timing was switched on or since
+ * the previous call, which this call resets.  Waits for the context
+ * stream.  ZM_ERR_UNSUPPORTED for an exact (cutoff = 0) context. */
+zm_status zm_cutoff_info_get(zm_ctx *ctx, zm_cutoff_info *out);
 
 /* ---- launch-shape tuning --------------------------------------------------- */
 /*
@@ -239,8 +279,9 @@ typedef struct zm_batch_info {
 size_t zm_batch_workspace_bytes(const zm_params *params, int32_t count);
 
 /* Create a batch on the current device.  params: `count` parameter sets
- * (copied).  batch_flags: ZM_FLAG_GRAPH and/or ZM_FLAG_CHECK_FINITE (the
- * per-instance params.flags must be 0).  Workspace and stream as for
+ * (copied; exact BR only: cutoff = 0, else ZM_ERR_UNSUPPORTED).  batch_flags:
+ * ZM_FLAG_GRAPH and/or ZM_FLAG_CHECK_FINITE (the per-instance params.flags
+ * must be 0).  Workspace and stream as for
  * zm_create.  Uploads the descriptor table and work list (waits for the
  * stream once).  On failure *out is NULL and zm_batch_last_error(NULL) says
  * why. */
@@ -313,7 +354,7 @@ size_t zm_pool_request_bytes(const zm_params *params);
 zm_status zm_pool_create(zm_pool **out, size_t budget_bytes, uint32_t flags, void *d_workspace,
                          size_t workspace_bytes, void *hip_stream);
 
-/* Queue a request: params (params.flags must be 0), initial state d_z (3
+/* Queue a request: params (params.flags must be 0, cutoff 0), initial state d_z (3
  * planes) / d_w (2 planes), steps >= 1.  The state is copied when the request
  * is admitted, so d_z / d_w must stay valid and unchanged until
  * zm_pool_query reports it no longer queued.  A request larger than the whole

@@ -26,7 +26,7 @@ ZM_FP32_PAIRS = 1
 ZM_FLAG_CHECK_FINITE = 0x1
 ZM_FLAG_GRAPH = 0x2
 
-KERNELS = ("surface", "pairs", "ties", "reduce", "update")
+KERNELS = ("surface", "pairs", "ties", "reduce", "update", "cells")
 
 
 class ZMError(RuntimeError):
@@ -43,7 +43,15 @@ class zm_params(ctypes.Structure):
         ("eps", ctypes.c_double), ("nu", ctypes.c_double), ("dt", ctypes.c_double),
         ("precision", ctypes.c_int32), ("image_layers", ctypes.c_int32),
         ("flags", ctypes.c_uint32), ("reserved", ctypes.c_int32),
+        ("cutoff", ctypes.c_double),
     ]
+
+
+class zm_cutoff_info(ctypes.Structure):
+    _fields_ = [("cells1", ctypes.c_int32), ("cells2", ctypes.c_int32),
+                ("cells_per_cutoff", ctypes.c_int32), ("block_cells", ctypes.c_int32),
+                ("slots", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("pairs_tested", ctypes.c_int64), ("pairs_accepted", ctypes.c_int64)]
 
 
 class zm_launch_info(ctypes.Structure):
@@ -90,7 +98,7 @@ class zm_batch_info(ctypes.Structure):
 EXPORTS = (
     "zm_workspace_bytes", "zm_create", "zm_init_state", "zm_br_velocity", "zm_rhs",
     "zm_step", "zm_get_state", "zm_destroy", "zm_status_string", "zm_last_error",
-    "zm_get_launch_info", "zm_profile_enable", "zm_profile_read",
+    "zm_get_launch_info", "zm_profile_enable", "zm_profile_read", "zm_cutoff_info_get",
     "zm_tuning_set", "zm_tuning_get", "zm_autotune_workspace_bytes", "zm_autotune",
     "zm_batch_workspace_bytes", "zm_batch_create", "zm_batch_init_state", "zm_batch_get_state",
     "zm_batch_step", "zm_batch_get_info", "zm_batch_destroy", "zm_batch_last_error",
@@ -145,6 +153,8 @@ def load(path: str = LIB_PATH):
     lib.zm_profile_enable.restype = ctypes.c_int32
     lib.zm_profile_read.argtypes = [vp, ctypes.POINTER(zm_kernel_stats)]
     lib.zm_profile_read.restype = ctypes.c_int32
+    lib.zm_cutoff_info_get.argtypes = [vp, ctypes.POINTER(zm_cutoff_info)]
+    lib.zm_cutoff_info_get.restype = ctypes.c_int32
     T = ctypes.POINTER(zm_pair_tuning)
     lib.zm_tuning_set.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, T]
     lib.zm_tuning_set.restype = ctypes.c_int32
@@ -219,11 +229,12 @@ class Params:
     precision: int = ZM_FP64
     image_layers: int = 0
     flags: int = 0
+    cutoff: float = 0.0       # > 0: cutoff BR solver with this 3D distance
 
     def c(self) -> zm_params:
         return zm_params(self.n1, self.n2, self.period1, self.period2, self.atwood,
                          self.gravity, self.eps, self.nu, self.dt, self.precision,
-                         self.image_layers, self.flags, 0)
+                         self.image_layers, self.flags, 0, self.cutoff)
 
     @property
     def n(self) -> int:
@@ -258,7 +269,11 @@ class Context:
         dev = torch.device("cuda", torch.cuda.current_device()) if device is None else device
         nbytes = workspace_bytes(p)
         if nbytes == 0:
-            raise ZMError(ZM_ERR_INVALID_ARG, "invalid parameters")
+            # let the library say why (invalid or unsupported parameters)
+            h = ctypes.c_void_p()
+            st = self.lib.zm_create(ctypes.byref(h), ctypes.byref(p.c()), None, 0, None)
+            raise ZMError(st if st != ZM_OK else ZM_ERR_INVALID_ARG,
+                          self.lib.zm_last_error(None).decode() or "invalid parameters")
         self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=dev)
         self.stream = torch.cuda.current_stream(dev) if stream is None else stream
         h = ctypes.c_void_p()
@@ -306,6 +321,11 @@ class Context:
         arr = (zm_kernel_stats * len(KERNELS))()
         self._raise(self.lib.zm_profile_read(self.handle, arr))
         return {k: (int(arr[i].launches), float(arr[i].total_ms)) for i, k in enumerate(KERNELS)}
+
+    def cutoff_info(self) -> zm_cutoff_info:
+        info = zm_cutoff_info()
+        self._raise(self.lib.zm_cutoff_info_get(self.handle, ctypes.byref(info)))
+        return info
 
     def destroy(self):
         if getattr(self, "handle", None) is not None:

@@ -4,6 +4,8 @@
 // the RK3 state buffers and the per-evaluation scratch, and enqueues the
 // kernel sequence on the caller's stream.  Per derivative evaluation:
 //   k_surface -> k_pairs -> [k_ties] -> k_reduce -> k_update
+// or, for a cutoff context,
+//   k_surface -> cell binning and sort -> k_cut_pairs -> k_reduce -> k_update
 #include "zm.h"
 #include "zm_host.h"
 #include "zm_internal.h"
@@ -51,6 +53,9 @@ struct zm_ctx {
     zm_kernel_stats stats[ZM_KERNEL_COUNT];
     hipStream_t capture_stream = nullptr;   // graph capture (non-blocking, default priority)
     hipGraphExec_t graph = nullptr;         // one captured RK3 step
+    bool cutoff = false;                    // cutoff BR solver
+    zm::CutGrid cut{};
+    zm::CutBuffers cb{};
 
     double* at(size_t off) { return reinterpret_cast<double*>(ws + off); }
     size_t N() const { return (size_t)mesh.N; }
@@ -110,6 +115,21 @@ zm_status eval_velocity(zm_ctx* c, const double* z, const double* w, double* u, 
     hipError_t e;
     e = timed(c, ZM_KERNEL_SURFACE, [&] { return zm::launch_surface(m, z, w, gam, q, stream); });
     if (e != hipSuccess) return hip_fail(c, e, "surface kernel launch");
+    if (c->cutoff) {
+        int half = 0;
+        e = timed(c, ZM_KERNEL_CELLS,
+                  [&] { return zm::launch_cut_cells(m, c->cut, z, gam, c->cb, &half, stream); });
+        if (e != hipSuccess) return hip_fail(c, e, "cell binning launch");
+        e = timed(c, ZM_KERNEL_PAIRS, [&] {
+            return zm::launch_cut_pairs(m, c->cut, c->cb, half, part, c->profiling, stream);
+        });
+        if (e != hipSuccess) return hip_fail(c, e, "cutoff pair kernel launch");
+        e = timed(c, ZM_KERNEL_REDUCE, [&] {
+            return zm::launch_reduce(m, c->cut.slots, part, tie, q, z, u, V, stream, false);
+        });
+        if (e != hipSuccess) return hip_fail(c, e, "reduce kernel launch");
+        return ZM_OK;
+    }
     e = timed(c, ZM_KERNEL_PAIRS, [&] {
         return c->prm.precision == ZM_FP32_PAIRS
                    ? zm::launch_pairs_f32(m, c->shape, z, gam, part, stream)
@@ -134,6 +154,7 @@ extern "C" {
 size_t zm_workspace_bytes(const zm_params* params)
 {
     if (validate(params)) return 0;
+    if (params->cutoff > 0.0 && params->precision != ZM_FP64) return 0;
     const zm::PairShape sh = zm::choose_pair_shape(params->n1, params->n2, params->precision);
     return make_layout(*params, sh).total;
 }
@@ -145,6 +166,10 @@ zm_status zm_create(zm_ctx** out, const zm_params* params, void* d_workspace,
     if (!out) { g_create_error = "out is NULL"; return ZM_ERR_INVALID_ARG; }
     *out = nullptr;
     if (const char* why = validate(params)) { g_create_error = why; return ZM_ERR_INVALID_ARG; }
+    if (params->cutoff > 0.0 && params->precision != ZM_FP64) {
+        g_create_error = "the cutoff solver is FP64 only";
+        return ZM_ERR_UNSUPPORTED;
+    }
     const zm::PairShape sh = zm::choose_pair_shape(params->n1, params->n2, params->precision);
     const Layout L = make_layout(*params, sh);
     if (!d_workspace || !aligned(d_workspace)) {
@@ -171,6 +196,22 @@ zm_status zm_create(zm_ctx** out, const zm_params* params, void* d_workspace,
     c->ws = reinterpret_cast<char*>(d_workspace);
     std::memset(c->stats, 0, sizeof(c->stats));
     c->mesh = zm::make_mesh(*params);
+    if (zm::has_cutoff(*params)) {
+        c->cutoff = true;
+        c->cut = zm::cut_grid_of(*params);
+        char* ws = c->ws;
+        for (int h = 0; h < 2; ++h) {
+            c->cb.keys[h] = reinterpret_cast<unsigned*>(ws + L.cut_keys[h]);
+            c->cb.vals[h] = reinterpret_cast<unsigned*>(ws + L.cut_vals[h]);
+        }
+        c->cb.hist = reinterpret_cast<unsigned*>(ws + L.cut_hist);
+        c->cb.start = reinterpret_cast<int*>(ws + L.cut_start);
+        c->cb.end = reinterpret_cast<int*>(ws + L.cut_end);
+        c->cb.bstart = reinterpret_cast<int*>(ws + L.cut_bstart);
+        c->cb.bend = reinterpret_cast<int*>(ws + L.cut_bend);
+        c->cb.src = reinterpret_cast<double*>(ws + L.cut_src);
+        c->cb.counts = reinterpret_cast<unsigned long long*>(ws + L.cut_counts);
+    }
     *out = c;
     return ZM_OK;
 }
@@ -383,6 +424,17 @@ const char* zm_last_error(const zm_ctx* c)
 zm_status zm_get_launch_info(const zm_ctx* c, zm_launch_info* out)
 {
     if (!c || !out) return ZM_ERR_INVALID_ARG;
+    if (c->cutoff) {
+        const zm::CutGrid& g = c->cut;
+        out->targets_per_lane = 1;
+        out->patch_cols = g.B;   // in cells
+        out->patch_rows = g.B;
+        out->source_splits = g.slots;
+        out->workgroups = g.nb1 * g.nb2 * g.slots;
+        out->threads_per_group = 256;
+        out->pairs_per_eval = (int64_t)c->mesh.N * (int64_t)c->mesh.N;
+        return ZM_OK;
+    }
     const zm::PairShape& sh = c->shape;
     out->targets_per_lane = sh.R;
     out->patch_cols = sh.cx;
@@ -398,7 +450,35 @@ zm_status zm_get_launch_info(const zm_ctx* c, zm_launch_info* out)
 zm_status zm_profile_enable(zm_ctx* c, int32_t on)
 {
     if (!c) return ZM_ERR_INVALID_ARG;
+    if (on && !c->profiling && c->cutoff) {
+        DeviceGuard g(c->device);
+        if (!g.ok) return fail(c, ZM_ERR_HIP, "cannot select the context device");
+        hipError_t e = zm::launch_cut_count_reset(c->cb.counts, c->stream);
+        if (e != hipSuccess) return hip_fail(c, e, "pair counter reset");
+    }
     c->profiling = (on != 0);
+    return ZM_OK;
+}
+
+zm_status zm_cutoff_info_get(zm_ctx* c, zm_cutoff_info* out)
+{
+    if (!c || !out) return ZM_ERR_INVALID_ARG;
+    if (!c->cutoff) return fail(c, ZM_ERR_UNSUPPORTED, "not a cutoff context");
+    DeviceGuard g(c->device);
+    if (!g.ok) return fail(c, ZM_ERR_HIP, "cannot select the context device");
+    unsigned long long h[2] = {0, 0};
+    hipError_t e = hipMemcpyAsync(h, c->cb.counts, sizeof(h), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e == hipSuccess) e = zm::launch_cut_count_reset(c->cb.counts, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "pair counter read");
+    out->cells1 = c->cut.nc1;
+    out->cells2 = c->cut.nc2;
+    out->cells_per_cutoff = c->cut.m;
+    out->block_cells = c->cut.B;
+    out->slots = c->cut.slots;
+    out->reserved = 0;
+    out->pairs_tested = (int64_t)h[0];
+    out->pairs_accepted = (int64_t)h[1];
     return ZM_OK;
 }
 
@@ -427,6 +507,6 @@ zm_status zm_profile_read(zm_ctx* c, zm_kernel_stats* out)
     return st;
 }
 
-int32_t zm_abi_version(void) { return 1; }
+int32_t zm_abi_version(void) { return 2; }
 
 }  // extern "C"

@@ -85,7 +85,7 @@ __global__ __launch_bounds__(kThreads) void kb_reduce(const InstDesc* __restrict
     const int t = (blockIdx.x - d.reduce_block_begin) * kThreads + threadIdx.x;
     // one instance per block, so the lane count is uniform over the block
     dev::reduce_thread(d.m, t, dev::reduce_lanes(d.m.N, d.sh.splits), d.sh.splits, d.part, d.tie,
-                       d.q, d.Y[stage], d.u, d.V);
+                       d.q, d.Y[stage], d.u, d.V, true);
 }
 
 __global__ __launch_bounds__(kThreads) void kb_update(const InstDesc* __restrict__ T, int count,

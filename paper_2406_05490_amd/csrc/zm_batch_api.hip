@@ -47,6 +47,7 @@ const char* plan_batch(const zm_params* params, int32_t count, BatchPlan& P)
     for (int i = 0; i < count; ++i) {
         if (const char* why = zm::validate(&params[i])) return why;
         if (params[i].flags != 0) return "per-instance flags must be 0 in a batch";
+        if (params[i].cutoff != 0.0) return "the cutoff solver is not available in a batch";
         const zm::PairShape sh =
             zm::choose_pair_shape(params[i].n1, params[i].n2, params[i].precision);
         const zm::Layout L = zm::make_layout(params[i], sh);
@@ -214,7 +215,9 @@ zm_status zm_batch_create(zm_batch** out, const zm_params* params, int32_t count
     if (const char* why = plan_batch(params, count, b->plan)) {
         g_batch_create_error = why;
         delete b;
-        return ZM_ERR_INVALID_ARG;
+        bool cut = false;
+        for (int i = 0; params && i < count; ++i) cut = cut || params[i].cutoff != 0.0;
+        return cut ? ZM_ERR_UNSUPPORTED : ZM_ERR_INVALID_ARG;
     }
     if (!zm::aligned(d_workspace) || workspace_bytes < b->plan.total) {
         g_batch_create_error = "workspace NULL, misaligned or smaller than zm_batch_workspace_bytes()";

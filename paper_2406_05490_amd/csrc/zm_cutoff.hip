@@ -1,0 +1,401 @@
+// Cutoff Birkhoff-Rott solver: the desingularised BR sum restricted to the
+// sources whose nearest periodic image lies within a 3D distance rc of the
+// target (the paper's cutoff-based approximate integral, sec. 3.2.2).  The
+// paper finds neighbours with a spatial search library over a 3D spatial
+// mesh; on one GPU a periodic cell grid rebuilt every evaluation does the
+// same job with a handful of kernels:
+//
+//   k_cut_keys      cell of every point (x, y wrapped into the period cell;
+//                   z is not binned: the interface is a sheet) -> sort key
+//   radix sort      stable LSD sort of (key, point) in 8-bit digits:
+//                   k_sort_hist (per-workgroup digit counts), k_sort_scan
+//                   (exclusive offsets, digit-major), k_sort_scatter (stable
+//                   ranks from wave ballots)
+//   k_cut_bounds    first / one-past-last sorted index of every cell and of
+//                   every target block
+//   k_cut_gather    positions, source strengths and wrap counts in sorted
+//                   order (structure of arrays)
+//   k_cut_pairs     one workgroup per (target block, row of neighbour
+//                   cells): each neighbour cell's sources are staged through
+//                   LDS and every target sums over them
+//
+// The inclusion test is evaluated exactly as the definition writes it
+// (r_a = (z_i,a - z_j,a) - S_a L_a, then r1*r1 + r2*r2 + r3*r3 < rc*rc, no
+// contraction), so every include / exclude decision is the same bit for bit
+// as in any other implementation of that definition.  All integer work is
+// exact and every floating-point sum runs in a fixed order: results are
+// bitwise reproducible.
+#include "zm_device.h"
+#include "zm_internal.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+
+namespace zm {
+namespace {
+
+using dev::kThreads;
+
+__host__ __device__ inline int floordiv(int a, int n) { return a >= 0 ? a / n : -((-a + n - 1) / n); }
+
+__host__ __device__ inline int cell_key(const CutGrid& g, int cx, int cy)
+{
+    const int bx = cx / g.B, lx = cx - bx * g.B;
+    const int by = cy / g.B, ly = cy - by * g.B;
+    return ((by * g.nb1 + bx) * g.B + ly) * g.B + lx;
+}
+
+// Wrap count k (x - k L lies in the period cell [x0, x0 + L)) and the cell
+// of the wrapped coordinate, clamped against rounding at the cell edges.
+__device__ inline void wrap_cell(double x, double x0, double L, double cw, int nc, int& k, int& c)
+{
+    const double f = floor((x - x0) / L);
+    k = (int)f;
+    const double xw = x - f * L;
+    c = (int)floor((xw - x0) / cw);
+    c = c < 0 ? 0 : (c >= nc ? nc - 1 : c);
+}
+
+__global__ __launch_bounds__(kThreads) void k_cut_keys(Mesh m, CutGrid g, const double* __restrict__ z,
+                                                       unsigned* __restrict__ keys,
+                                                       unsigned* __restrict__ vals)
+{
+    const int p = blockIdx.x * kThreads + threadIdx.x;
+    if (p >= m.N) return;
+    int kx, ky, cx, cy;
+    wrap_cell(z[p], g.x0, g.L1, g.cw1, g.nc1, kx, cx);
+    wrap_cell(z[m.N + p], g.y0, g.L2, g.cw2, g.nc2, ky, cy);
+    keys[p] = (unsigned)cell_key(g, cx, cy);
+    vals[p] = (unsigned)p;
+}
+
+// ---- stable LSD radix sort of (key, value), 8 bits per pass -----------------
+// Workgroup b owns the elements [b seg, (b + 1) seg); offsets are laid out
+// digit-major (digit d of every workgroup before digit d + 1), which makes the
+// scatter stable.
+
+__global__ __launch_bounds__(kThreads) void k_sort_hist(const unsigned* __restrict__ keys, int n,
+                                                        int shift, int seg,
+                                                        unsigned* __restrict__ hist)
+{
+    __shared__ unsigned h[256];
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    const int begin = blockIdx.x * seg;
+    const int end = min(n, begin + seg);
+    for (int i = begin + (int)threadIdx.x; i < end; i += kThreads)
+        atomicAdd(&h[(keys[i] >> shift) & 255u], 1u);
+    __syncthreads();
+    hist[threadIdx.x * gridDim.x + blockIdx.x] = h[threadIdx.x];
+}
+
+// Exclusive scan of total entries in place, one workgroup of 1024 threads:
+// each thread sums a contiguous chunk, the chunk sums are scanned in LDS,
+// then each chunk is rewritten with its running offset.
+__global__ __launch_bounds__(1024) void k_sort_scan(unsigned* __restrict__ a, int total)
+{
+    __shared__ unsigned s[1024];
+    const int t = threadIdx.x;
+    const int per = (total + 1023) / 1024;
+    const int lo = min(total, t * per), hi = min(total, lo + per);
+    unsigned sum = 0;
+    for (int i = lo; i < hi; ++i) sum += a[i];
+    s[t] = sum;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        const unsigned v = t >= off ? s[t - off] : 0u;
+        __syncthreads();
+        s[t] += v;
+        __syncthreads();
+    }
+    unsigned run = s[t] - sum;   // exclusive prefix of this chunk
+    for (int i = lo; i < hi; ++i) {
+        const unsigned v = a[i];
+        a[i] = run;
+        run += v;
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_sort_scatter(const unsigned* __restrict__ kin,
+                                                           const unsigned* __restrict__ vin,
+                                                           unsigned* __restrict__ kout,
+                                                           unsigned* __restrict__ vout, int n,
+                                                           int shift, int seg,
+                                                           const unsigned* __restrict__ offs)
+{
+    __shared__ unsigned base[256];
+    __shared__ unsigned wcnt[kThreads / 64][256];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    base[tid] = offs[tid * gridDim.x + blockIdx.x];
+    const int begin = blockIdx.x * seg;
+    const int end = min(n, begin + seg);
+    const unsigned long long below = (1ull << lane) - 1ull;
+    for (int c = begin; c < end; c += kThreads) {   // uniform over the workgroup
+        for (int q = 0; q < kThreads / 64; ++q) wcnt[q][tid] = 0;
+        __syncthreads();
+        const int i = c + tid;
+        const bool valid = i < end;
+        const unsigned key = valid ? kin[i] : 0u;
+        const unsigned d = (key >> shift) & 255u;
+        // lanes of this wave with the same digit
+        unsigned long long same = __ballot(valid);
+        for (int b = 0; b < 8; ++b) {
+            const bool bit = (d >> b) & 1u;
+            const unsigned long long ones = __ballot(valid && bit);
+            same &= bit ? ones : ~ones;
+        }
+        const unsigned rank = (unsigned)__popcll(same & below);
+        if (valid && rank == 0) wcnt[w][d] = (unsigned)__popcll(same);
+        __syncthreads();
+        if (valid) {
+            unsigned pos = base[d] + rank;
+            for (int q = 0; q < w; ++q) pos += wcnt[q][d];
+            kout[pos] = key;
+            vout[pos] = vin[i];
+        }
+        __syncthreads();
+        unsigned add = 0;
+        for (int q = 0; q < kThreads / 64; ++q) add += wcnt[q][tid];
+        base[tid] += add;
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_fill_int(int* __restrict__ a, int n, int v)
+{
+    const int i = blockIdx.x * kThreads + threadIdx.x;
+    if (i < n) a[i] = v;
+}
+
+__global__ void k_fill_u64(unsigned long long* __restrict__ a, int n)
+{
+    if ((int)threadIdx.x < n) a[threadIdx.x] = 0ull;
+}
+
+__global__ __launch_bounds__(kThreads) void k_cut_bounds(CutGrid g, int n,
+                                                         const unsigned* __restrict__ ks,
+                                                         int* __restrict__ start, int* __restrict__ end,
+                                                         int* __restrict__ bstart, int* __restrict__ bend)
+{
+    const int i = blockIdx.x * kThreads + threadIdx.x;
+    if (i >= n) return;
+    const unsigned bb = (unsigned)(g.B * g.B);
+    const unsigned key = ks[i], blk = key / bb;
+    if (i == 0 || ks[i - 1] != key) start[key] = i;
+    if (i == 0 || ks[i - 1] / bb != blk) bstart[blk] = i;
+    if (i == n - 1 || ks[i + 1] != key) end[key] = i + 1;
+    if (i == n - 1 || ks[i + 1] / bb != blk) bend[blk] = i + 1;
+}
+
+__global__ __launch_bounds__(kThreads) void k_cut_gather(Mesh m, CutGrid g, const double* __restrict__ z,
+                                                         const double* __restrict__ gam,
+                                                         const unsigned* __restrict__ order,
+                                                         double* __restrict__ src)
+{
+    const int i = blockIdx.x * kThreads + threadIdx.x;
+    const int N = m.N;
+    if (i >= N) return;
+    const int p = (int)order[i];
+    const double x = z[p], y = z[N + p];
+    int kx, ky, cx, cy;
+    wrap_cell(x, g.x0, g.L1, g.cw1, g.nc1, kx, cx);
+    wrap_cell(y, g.y0, g.L2, g.cw2, g.nc2, ky, cy);
+    src[i] = x;
+    src[N + i] = y;
+    src[2 * N + i] = z[2 * N + p];
+    src[3 * N + i] = gam[p];
+    src[4 * N + i] = gam[N + p];
+    src[5 * N + i] = gam[2 * N + p];
+    src[6 * N + i] = (double)kx;
+    src[7 * N + i] = (double)ky;
+}
+
+// One workgroup per (target block, neighbour row).  Lane = one target of the
+// block (256 at a time); the row's B + 2m cells are visited left to right,
+// each cell's sources in sorted order, staged 256 at a time as (x, y),
+// (z, g1), (g2, g3), (kx, ky).  A source in raw cell column cx_raw (before
+// wrapping) is the image shifted by wx = floor(cx_raw / nc1) periods, so the
+// image shift of the pair is S = k_i + wx - k_j (and the same along y).
+template <bool COUNT>
+__global__ __launch_bounds__(kThreads) void k_cut_pairs(Mesh m, CutGrid g,
+                                                        const double* __restrict__ src,
+                                                        const int* __restrict__ start,
+                                                        const int* __restrict__ end,
+                                                        const int* __restrict__ bstart,
+                                                        const int* __restrict__ bend,
+                                                        const unsigned* __restrict__ order,
+                                                        double* __restrict__ part,
+                                                        unsigned long long* __restrict__ counts)
+{
+    __shared__ double2 lds[4][kThreads];
+    const int blk = blockIdx.x, row = blockIdx.y;
+    const int T0 = bstart[blk], T1 = bend[blk];
+    if (T0 >= T1) return;   // empty target block: uniform over the workgroup
+    const int N = m.N;
+    const int tid = threadIdx.x;
+    const int bx = blk % g.nb1, by = blk / g.nb1;
+    const int cy_raw = by * g.B - g.m + row;
+    const int wy = floordiv(cy_raw, g.nc2), cy = cy_raw - wy * g.nc2;
+    unsigned long long tested = 0, accepted = 0;
+
+    for (int t0 = T0; t0 < T1; t0 += kThreads) {
+        const int i = t0 + tid;
+        const bool active = i < T1;
+        double xi = 0.0, yi = 0.0, zi = 0.0, kxi = 0.0, kyi = 0.0;
+        if (active) {
+            xi = src[i];
+            yi = src[N + i];
+            zi = src[2 * N + i];
+            kxi = src[6 * N + i];
+            kyi = src[7 * N + i];
+        }
+        double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0;
+        for (int col = 0; col < g.slots; ++col) {
+            const int cx_raw = bx * g.B - g.m + col;
+            const int wx = floordiv(cx_raw, g.nc1), cx = cx_raw - wx * g.nc1;
+            const int key = cell_key(g, cx, cy);
+            const int s0 = start[key], s1 = end[key];
+            const double Kx = kxi + (double)wx, Ky = kyi + (double)wy;
+            for (int j0 = s0; j0 < s1; j0 += kThreads) {
+                const int cnt = min(kThreads, s1 - j0);
+                __syncthreads();   // previous tile fully read
+                if (tid < cnt) {
+                    const int j = j0 + tid;
+                    lds[0][tid] = make_double2(src[j], src[N + j]);
+                    lds[1][tid] = make_double2(src[2 * N + j], src[3 * N + j]);
+                    lds[2][tid] = make_double2(src[4 * N + j], src[5 * N + j]);
+                    lds[3][tid] = make_double2(src[6 * N + j], src[7 * N + j]);
+                }
+                __syncthreads();
+                if (!active) continue;
+                for (int c = 0; c < cnt; ++c) {
+#pragma clang fp contract(off)
+                    const double2 v0 = lds[0][c], v1 = lds[1][c], v2 = lds[2][c], v3 = lds[3][c];
+                    const double d1 = xi - v0.x, d2 = yi - v0.y;
+                    const double S1 = Kx - v3.x, S2 = Ky - v3.y;
+                    const double r1 = d1 - S1 * g.L1;
+                    const double r2 = d2 - S2 * g.L2;
+                    const double r3 = zi - v1.x;
+                    const double dd = r1 * r1 + r2 * r2 + r3 * r3;
+                    const bool in = dd < g.rc2;
+                    const double wgt = in ? dev::inv_cube_sqrt(dd + m.eps2) : 0.0;
+                    const double a1 = wgt * v1.y, a2 = wgt * v2.x, a3 = wgt * v2.y;
+                    acc0 = fma(r2, a3, acc0);
+                    acc0 = fma(-r3, a2, acc0);
+                    acc1 = fma(r3, a1, acc1);
+                    acc1 = fma(-r1, a3, acc1);
+                    acc2 = fma(r1, a2, acc2);
+                    acc2 = fma(-r2, a1, acc2);
+                    if (COUNT) {
+                        tested += 1;
+                        accepted += in ? 1 : 0;
+                    }
+                }
+            }
+        }
+        if (active) {
+            const int p = (int)order[i];
+            double* out = part + (size_t)row * 3 * N;
+            out[p] = acc0;
+            out[N + p] = acc1;
+            out[2 * N + p] = acc2;
+        }
+    }
+    if (COUNT) {
+        for (int off = 32; off > 0; off >>= 1) {
+            tested += __shfl_xor(tested, off, 64);
+            accepted += __shfl_xor(accepted, off, 64);
+        }
+        if ((tid & 63) == 0) {
+            atomicAdd(&counts[0], tested);
+            atomicAdd(&counts[1], accepted);
+        }
+    }
+}
+
+inline unsigned grid_for(long n) { return (unsigned)((n + kThreads - 1) / kThreads); }
+
+}  // namespace
+
+CutGrid make_cut_grid(int n1, int n2, double L1, double L2, double rc)
+{
+    CutGrid g;
+    g.m = 2;
+    // cells no smaller than rc / m (with a margin against rounding at the
+    // cell edges) and no smaller than the mean mesh spacing
+    const double grow = 1.0 + 1e-9;
+    g.nc1 = std::max(1, std::min(n1, (int)std::floor(g.m * L1 / (rc * grow))));
+    g.nc2 = std::max(1, std::min(n2, (int)std::floor(g.m * L2 / (rc * grow))));
+    g.cw1 = L1 / g.nc1;
+    g.cw2 = L2 / g.nc2;
+    // target blocks of B x B cells hold >= ~128 points on average
+    const double per_cell = (double)n1 * n2 / ((double)g.nc1 * g.nc2);
+    g.B = std::max(1, (int)std::ceil(std::sqrt(128.0 / per_cell)));
+    g.B = std::min(g.B, std::min(g.nc1, g.nc2));
+    g.nb1 = (g.nc1 + g.B - 1) / g.B;
+    g.nb2 = (g.nc2 + g.B - 1) / g.B;
+    g.nkeys = g.nb1 * g.nb2 * g.B * g.B;
+    g.key_bits = 1;
+    while ((1L << g.key_bits) < (long)g.nkeys) ++g.key_bits;
+    g.slots = g.B + 2 * g.m;
+    const long N = (long)n1 * n2;
+    g.sort_blocks = (int)std::max(1L, std::min(1024L, (N + 1023) / 1024));
+    g.x0 = -0.5 * L1;
+    g.y0 = -0.5 * L2;
+    g.L1 = L1;
+    g.L2 = L2;
+    g.rc2 = rc * rc;
+    return g;
+}
+
+hipError_t launch_cut_cells(const Mesh& m, const CutGrid& g, const double* z, const double* gam,
+                            const CutBuffers& b, int* sorted_half, hipStream_t s)
+{
+    const int N = m.N;
+    const dim3 blk(kThreads);
+    hipLaunchKernelGGL(k_cut_keys, dim3(grid_for(N)), blk, 0, s, m, g, z, b.keys[0], b.vals[0]);
+    const int G = g.sort_blocks;
+    const int seg = ((N + G - 1) / G + kThreads - 1) / kThreads * kThreads;
+    int cur = 0;
+    for (int shift = 0; shift < g.key_bits; shift += 8) {
+        hipLaunchKernelGGL(k_sort_hist, dim3(G), blk, 0, s, b.keys[cur], N, shift, seg, b.hist);
+        hipLaunchKernelGGL(k_sort_scan, dim3(1), dim3(1024), 0, s, b.hist, 256 * G);
+        hipLaunchKernelGGL(k_sort_scatter, dim3(G), blk, 0, s, b.keys[cur], b.vals[cur],
+                           b.keys[cur ^ 1], b.vals[cur ^ 1], N, shift, seg, b.hist);
+        cur ^= 1;
+    }
+    const int nblk = g.nb1 * g.nb2;
+    hipLaunchKernelGGL(k_fill_int, dim3(grid_for(g.nkeys)), blk, 0, s, b.start, g.nkeys, 0);
+    hipLaunchKernelGGL(k_fill_int, dim3(grid_for(g.nkeys)), blk, 0, s, b.end, g.nkeys, 0);
+    hipLaunchKernelGGL(k_fill_int, dim3(grid_for(nblk)), blk, 0, s, b.bstart, nblk, 0);
+    hipLaunchKernelGGL(k_fill_int, dim3(grid_for(nblk)), blk, 0, s, b.bend, nblk, 0);
+    hipLaunchKernelGGL(k_cut_bounds, dim3(grid_for(N)), blk, 0, s, g, N, b.keys[cur], b.start,
+                       b.end, b.bstart, b.bend);
+    hipLaunchKernelGGL(k_cut_gather, dim3(grid_for(N)), blk, 0, s, m, g, z, gam, b.vals[cur], b.src);
+    *sorted_half = cur;
+    return hipGetLastError();
+}
+
+hipError_t launch_cut_pairs(const Mesh& m, const CutGrid& g, const CutBuffers& b,
+                            int sorted_half, double* part, bool count, hipStream_t s)
+{
+    const dim3 grid(g.nb1 * g.nb2, g.slots);
+    const unsigned* order = b.vals[sorted_half];
+    if (count)
+        hipLaunchKernelGGL(k_cut_pairs<true>, grid, dim3(kThreads), 0, s, m, g, b.src, b.start, b.end,
+                           b.bstart, b.bend, order, part, b.counts);
+    else
+        hipLaunchKernelGGL(k_cut_pairs<false>, grid, dim3(kThreads), 0, s, m, g, b.src, b.start,
+                           b.end, b.bstart, b.bend, order, part, b.counts);
+    return hipGetLastError();
+}
+
+hipError_t launch_cut_count_reset(unsigned long long* counts, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, s, counts, 2);
+    return hipGetLastError();
+}
+
+}  // namespace zm

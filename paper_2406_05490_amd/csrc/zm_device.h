@@ -939,7 +939,8 @@ __host__ __device__ inline int reduce_lanes(int N, int splits)
 
 // u = coef * (sum over splits + tie passes) at point p, and V.  Lanes
 // lane = 0 .. L-1 of a group take the splits lane, lane + L, ... in order and
-// are combined by a fixed butterfly; lane 0 adds the tie passes and writes.
+// are combined by a fixed butterfly; the tie passes (if ties) are added and
+// lane 0 writes.
 // All lanes of a group must call this together.
 template <int L>
 __device__ __forceinline__ void reduce_group(const Mesh& m, int p, int lane, int splits,
@@ -947,7 +948,7 @@ __device__ __forceinline__ void reduce_group(const Mesh& m, int p, int lane, int
                                              const double* __restrict__ tie,
                                              const double* __restrict__ q,
                                              const double* __restrict__ z, double* __restrict__ u,
-                                             double* __restrict__ V)
+                                             double* __restrict__ V, bool ties)
 {
     if (p >= m.N) return;   // the whole lane group leaves together
     const size_t N = m.N;
@@ -967,8 +968,8 @@ __device__ __forceinline__ void reduce_group(const Mesh& m, int p, int lane, int
         for (; k < splits; k += L) s += part[((size_t)k * 3 + c) * N + p];
 #pragma unroll
         for (int off = L / 2; off > 0; off >>= 1) s += __shfl_xor(s, off, L);
-        if ((m.n1 & 1) == 0) s += tie[c * N + p];
-        if ((m.n2 & 1) == 0) s += tie[(3 + c) * N + p];
+        if (ties && (m.n1 & 1) == 0) s += tie[c * N + p];
+        if (ties && (m.n2 & 1) == 0) s += tie[(3 + c) * N + p];
         a[c] = m.coef * s;
     }
     if (lane != 0) return;
@@ -987,11 +988,12 @@ __device__ __forceinline__ void reduce_thread(const Mesh& m, int t, int L, int s
                                               const double* __restrict__ tie,
                                               const double* __restrict__ q,
                                               const double* __restrict__ z,
-                                              double* __restrict__ u, double* __restrict__ V)
+                                              double* __restrict__ u, double* __restrict__ V,
+                                              bool ties)
 {
-    if (L == 1) reduce_group<1>(m, t, 0, splits, part, tie, q, z, u, V);
-    else if (L == 4) reduce_group<4>(m, t >> 2, t & 3, splits, part, tie, q, z, u, V);
-    else reduce_group<16>(m, t >> 4, t & 15, splits, part, tie, q, z, u, V);
+    if (L == 1) reduce_group<1>(m, t, 0, splits, part, tie, q, z, u, V, ties);
+    else if (L == 4) reduce_group<4>(m, t >> 2, t & 3, splits, part, tie, q, z, u, V, ties);
+    else reduce_group<16>(m, t >> 4, t & 15, splits, part, tie, q, z, u, V, ties);
 }
 
 // ---------------------------------------------------------------------------

@@ -22,17 +22,34 @@ inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 struct Layout {
     size_t y0, y1, y2;   // 5N doubles each (z1 z2 z3 w1 w2)
     size_t gam, q;       // 3N, N
-    size_t part;         // splits * 3N
+    size_t part;         // max(splits, cutoff slots) * 3N
     size_t tie;          // 6N
     size_t u, V;         // 3N, N
     size_t flag;         // one int
+    // cutoff solver only (size 0 otherwise)
+    size_t cut_keys[2], cut_vals[2];   // N unsigned each
+    size_t cut_hist;                   // 256 * sort_blocks unsigned
+    size_t cut_start, cut_end;         // nkeys int each
+    size_t cut_bstart, cut_bend;       // target blocks, int each
+    size_t cut_src;                    // 8N doubles
+    size_t cut_counts;                 // 2 uint64
     size_t total;
 };
+
+inline bool has_cutoff(const zm_params& p) { return p.cutoff > 0.0; }
+
+inline CutGrid cut_grid_of(const zm_params& p)
+{
+    return make_cut_grid(p.n1, p.n2, p.period1, p.period2, p.cutoff);
+}
 
 inline Layout make_layout(const zm_params& p, const zm::PairShape& sh)
 {
     const size_t N = (size_t)p.n1 * (size_t)p.n2;
     const size_t d = sizeof(double);
+    const bool cut = has_cutoff(p);
+    const CutGrid g = cut ? cut_grid_of(p) : CutGrid();
+    const int slots = cut ? (g.slots > sh.splits ? g.slots : sh.splits) : sh.splits;
     Layout L;
     size_t o = 0;
     auto take = [&](size_t bytes) { size_t at = o; o = align_up(o + bytes); return at; };
@@ -41,11 +58,23 @@ inline Layout make_layout(const zm_params& p, const zm::PairShape& sh)
     L.y2 = take(5 * N * d);
     L.gam = take(3 * N * d);
     L.q = take(N * d);
-    L.part = take((size_t)sh.splits * 3 * N * d);
+    L.part = take((size_t)slots * 3 * N * d);
     L.tie = take(6 * N * d);
     L.u = take(3 * N * d);
     L.V = take(N * d);
     L.flag = take(sizeof(int));
+    const size_t u4 = sizeof(unsigned);
+    L.cut_keys[0] = take(cut ? N * u4 : 0);
+    L.cut_keys[1] = take(cut ? N * u4 : 0);
+    L.cut_vals[0] = take(cut ? N * u4 : 0);
+    L.cut_vals[1] = take(cut ? N * u4 : 0);
+    L.cut_hist = take(cut ? (size_t)256 * g.sort_blocks * u4 : 0);
+    L.cut_start = take(cut ? (size_t)g.nkeys * sizeof(int) : 0);
+    L.cut_end = take(cut ? (size_t)g.nkeys * sizeof(int) : 0);
+    L.cut_bstart = take(cut ? (size_t)g.nb1 * g.nb2 * sizeof(int) : 0);
+    L.cut_bend = take(cut ? (size_t)g.nb1 * g.nb2 * sizeof(int) : 0);
+    L.cut_src = take(cut ? 8 * N * d : 0);
+    L.cut_counts = take(cut ? 2 * sizeof(unsigned long long) : 0);
     L.total = o;
     return L;
 }
@@ -66,6 +95,12 @@ inline const char* validate(const zm_params* p)
     if (p->image_layers < 0 || p->image_layers > kMaxImages) return "image_layers must be in [0, 16]";
     if (p->flags & ~(ZM_FLAG_CHECK_FINITE | ZM_FLAG_GRAPH)) return "unknown flag bits";
     if (p->reserved != 0) return "reserved must be 0";
+    if (!(std::isfinite(p->cutoff) && p->cutoff >= 0.0)) return "cutoff must be finite and >= 0";
+    if (p->cutoff > 0.0) {
+        if (p->cutoff > 0.45 * p->period1 || p->cutoff > 0.45 * p->period2)
+            return "cutoff must be <= 0.45 min(period1, period2)";
+        if (p->image_layers != 0) return "cutoff needs image_layers = 0";
+    }
     return nullptr;
 }
 

@@ -65,9 +65,62 @@ hipError_t launch_ties(const Mesh& m, const double* z, const double* gam, double
                        hipStream_t s);
 
 // u = coef * (sum_s part[s] + ties); optionally V = A (|u|^2 - q/4 - 2 g z3).
+// ties = false: no tie passes (the cutoff solver).
 hipError_t launch_reduce(const Mesh& m, int splits, const double* part, const double* tie,
                          const double* q, const double* z, double* u, double* V,
-                         hipStream_t s);
+                         hipStream_t s, bool ties = true);
+
+// ---- cutoff solver (zm_cutoff.hip) ----------------------------------------
+
+// Periodic cell grid of the cutoff solver.  Cells of side cw_a >= rc / m in
+// x and y; targets are processed in blocks of B x B cells, each against the
+// (B + 2m) x (B + 2m) cells around it, one row of those per workgroup, so a
+// target gets B + 2m partial sums ("slots").  Sort key of cell (cx, cy):
+// ((by nb1 + bx) B + ly) B + lx with (bx, lx) = divmod(cx, B), so the cells
+// of a target block are contiguous.
+struct CutGrid {
+    int m;               // neighbour reach in cells
+    int B;               // target block side in cells
+    int nc1, nc2;        // cells per axis
+    int nb1, nb2;        // target blocks per axis
+    int nkeys;           // nb1 nb2 B^2
+    int key_bits;        // bits of the sort key
+    int slots;           // B + 2m
+    int sort_blocks;     // workgroups of the radix-sort passes
+    double x0, y0;       // cell-grid origin (-L1/2, -L2/2)
+    double L1, L2;
+    double cw1, cw2;     // cell sides
+    double rc2;          // rc * rc
+};
+
+CutGrid make_cut_grid(int n1, int n2, double L1, double L2, double rc);
+
+// Device buffers of one cutoff evaluation (all in the caller's workspace).
+struct CutBuffers {
+    unsigned* keys[2];   // N each (radix-sort ping-pong)
+    unsigned* vals[2];   // N each
+    unsigned* hist;      // 256 * sort_blocks
+    int* start;          // nkeys: first sorted index of a cell
+    int* end;            // nkeys: one past the last
+    int* bstart;         // nb1 nb2: first sorted index of a target block
+    int* bend;
+    double* src;         // 8 N: sorted x, y, z, g1, g2, g3, kx, ky planes
+    unsigned long long* counts;  // 2: pairs tested, pairs within rc
+};
+
+// Bin every point into its cell and sort the points by cell (stable), then
+// gather positions, source strengths and wrap counts in sorted order.
+// Returns the index of the buffer pair holding the sorted (key, point).
+hipError_t launch_cut_cells(const Mesh& m, const CutGrid& g, const double* z, const double* gam,
+                            const CutBuffers& b, int* sorted_half, hipStream_t s);
+
+// Zero the two pair counters (a kernel, so it may sit in a captured graph).
+hipError_t launch_cut_count_reset(unsigned long long* counts, hipStream_t s);
+
+// part[slot][3][N] = unscaled cutoff sums per target and neighbour row.
+// count != 0: also add the tested / accepted pair counts to b.counts.
+hipError_t launch_cut_pairs(const Mesh& m, const CutGrid& g, const CutBuffers& b,
+                            int sorted_half, double* part, bool count, hipStream_t s);
 
 // F = (u, D V + nu Lap w) at state ys, then
 //   stage 0: out = ys + dt F

@@ -54,10 +54,10 @@ __global__ __launch_bounds__(kThreads) void k_reduce(Mesh m, int splits,
                                                      const double* __restrict__ q,
                                                      const double* __restrict__ z,
                                                      double* __restrict__ u,
-                                                     double* __restrict__ V)
+                                                     double* __restrict__ V, int ties)
 {
     dev::reduce_thread(m, blockIdx.x * kThreads + threadIdx.x, dev::reduce_lanes(m.N, splits), splits,
-                       part, tie, q, z, u, V);
+                       part, tie, q, z, u, V, ties != 0);
 }
 
 // y0 may alias out (see update_point), so neither carries __restrict__.
@@ -195,11 +195,12 @@ hipError_t launch_ties(const Mesh& m, const double* z, const double* gam, double
 }
 
 hipError_t launch_reduce(const Mesh& m, int splits, const double* part, const double* tie,
-                         const double* q, const double* z, double* u, double* V, hipStream_t s)
+                         const double* q, const double* z, double* u, double* V, hipStream_t s,
+                         bool ties)
 {
     const int L = dev::reduce_lanes(m.N, splits);
     hipLaunchKernelGGL(k_reduce, dim3(blocks_for(m.N * L)), dim3(kThreads), 0, s, m, splits, part, tie,
-                       q, z, u, V);
+                       q, z, u, V, ties ? 1 : 0);
     return hipGetLastError();
 }
 

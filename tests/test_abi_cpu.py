@@ -32,7 +32,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_abi_version_and_status_strings():
     lib = zm.load()
-    assert lib.zm_abi_version() == 1
+    assert lib.zm_abi_version() == 2
     assert zm.status_string(zm.ZM_OK) == "ok"
     for st in (zm.ZM_ERR_INVALID_ARG, zm.ZM_ERR_UNSUPPORTED, zm.ZM_ERR_WORKSPACE,
                zm.ZM_ERR_HIP, zm.ZM_ERR_NONFINITE, zm.ZM_ERR_CAPACITY):
@@ -41,8 +41,9 @@ def test_abi_version_and_status_strings():
 
 
 def test_struct_layout_matches_header():
-    # n1 n2 (8) + 7 doubles (56) + 4 int32 (16) = 80 bytes
-    assert ctypes.sizeof(_zm.zm_params) == 80
+    # n1 n2 (8) + 7 doubles (56) + 4 int32 (16) + cutoff (8) = 88 bytes
+    assert ctypes.sizeof(_zm.zm_params) == 88
+    assert ctypes.sizeof(_zm.zm_cutoff_info) == 40
     assert ctypes.sizeof(_zm.zm_launch_info) == 32
     assert ctypes.sizeof(_zm.zm_kernel_stats) == 16
 
@@ -51,12 +52,31 @@ def test_struct_layout_matches_header():
     dict(n1=7), dict(n2=4), dict(n1=20000), dict(eps=0.0), dict(eps=-1.0),
     dict(eps=float("nan")), dict(dt=0.0), dict(nu=-1.0), dict(period1=0.0),
     dict(atwood=float("inf")), dict(precision=7), dict(image_layers=-1),
-    dict(image_layers=17), dict(flags=0x80),
+    dict(image_layers=17), dict(flags=0x80), dict(cutoff=-0.1), dict(cutoff=float("nan")),
+    dict(cutoff=0.95), dict(cutoff=0.3, image_layers=1), dict(cutoff=0.3, precision=1),
 ])
 def test_workspace_bytes_rejects_invalid(bad):
     kw = dict(n1=16, n2=16, eps=1 / 16)
     kw.update(bad)
     assert zm.workspace_bytes(zm.Params(**kw)) == 0
+
+
+def test_cutoff_workspace_and_status():
+    """A cutoff context needs extra workspace (cell list, sorted copies); an
+    FP32 cutoff request is a valid one this build does not provide."""
+    a = zm.workspace_bytes(zm.Params(64, 64, eps=1 / 64))
+    b = zm.workspace_bytes(zm.Params(64, 64, eps=1 / 64, cutoff=0.3))
+    assert 0 < a < b and b % 256 == 0
+    st, _, msg = _create(zm.Params(64, 64, eps=1 / 64, cutoff=0.3, precision=1), None, 0)
+    assert st == zm.ZM_ERR_UNSUPPORTED and "FP64" in msg
+    st, _, msg = _create(zm.Params(64, 64, eps=1 / 64, cutoff=0.95), None, 0)
+    assert st == zm.ZM_ERR_INVALID_ARG and "cutoff" in msg
+
+
+def test_cutoff_refused_by_batches_and_pools():
+    p = zm.Params(32, 32, eps=1 / 32, cutoff=0.3)
+    assert zm.batch_workspace_bytes([p]) == 0
+    assert zm.pool_request_bytes(p) == 0
 
 
 def test_workspace_bytes_grows_with_mesh():

@@ -1,0 +1,208 @@
+"""Cutoff BR solver on the GPU (libzm.so through its C ABI) against the oracle.
+
+Bar: 1e-12 normwise relative error in float64 on the same seeded inputs.
+The include / exclude decision of every pair is taken from the same
+expression on both sides, so the accepted-pair count must match the
+definition exactly.  States are shifted across the periodic seam so that
+wrapped cells and image shifts are exercised.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import rocket_rig as rr
+from zm_testutil import relerr, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12
+
+
+def params(n1, n2, rc, **kw):
+    import paper_2406_05490_amd as zm
+    kw.setdefault("eps", 0.5 * 2.0 / n1)
+    return zm.Params(n1, n2, cutoff=rc, **kw)
+
+
+def oparams(p):
+    return oracle.Problem(p.n1, p.n2, eps=p.eps, atwood=p.atwood, gravity=p.gravity, dt=p.dt,
+                          nu=p.nu, period1=p.period1, period2=p.period2, cutoff=p.cutoff)
+
+
+def drifted_state(n1, n2, seed, height=0.1, drift=0.37):
+    z, w = rr.random_state(n1, n2, seed=seed, height=height)
+    z[0] += drift
+    z[1] -= 0.5 * drift
+    return z, w
+
+
+def gpu_br(p, z, w, device, count=False):
+    import paper_2406_05490_amd as zm
+    import torch
+    ctx = zm.Context(p)
+    if count:
+        ctx.profile_enable(True)
+    zd, wd = to_dev(z, device), to_dev(w, device)
+    ud = torch.empty(3 * p.n, dtype=torch.float64, device=device)
+    ctx.br_velocity(zd, wd, ud)
+    torch.cuda.synchronize()
+    return to_host(ud, (3, p.n)), ctx
+
+
+def accepted_pairs(z, rc, L=2.0):
+    """Pairs (i, j) with the nearest image of j within rc of i, by the
+    definition's expression (numpy, all pairs)."""
+    n = z.shape[1]
+    total = 0
+    for i in range(n):
+        d1 = z[0, i] - z[0]
+        d2 = z[1, i] - z[1]
+        r1 = d1 - np.rint(d1 / L) * L
+        r2 = d2 - np.rint(d2 / L) * L
+        r3 = z[2, i] - z[2]
+        total += int(np.count_nonzero(r1 * r1 + r2 * r2 + r3 * r3 < rc * rc))
+    return total
+
+
+@pytest.mark.parametrize("n1,n2,rc,seed", [
+    (24, 24, 0.3, 0), (40, 24, 0.45, 1), (17, 33, 0.2, 2), (64, 64, 0.15, 3), (48, 96, 0.5, 4),
+    (33, 9, 0.85, 5), (96, 40, 0.07, 6),
+])
+def test_cutoff_br_matches_oracle(gpu, n1, n2, rc, seed):
+    p = params(n1, n2, rc)
+    z, w = drifted_state(n1, n2, seed)
+    u, _ = gpu_br(p, z, w, gpu)
+    assert relerr(u, oracle.br_velocity(oparams(p), z, w)) < TOL64
+
+
+def test_cutoff_accepted_pair_count_exact(gpu):
+    n1, n2, rc = 40, 32, 0.35
+    p = params(n1, n2, rc)
+    z, w = drifted_state(n1, n2, 7)
+    _, ctx = gpu_br(p, z, w, gpu, count=True)
+    info = ctx.cutoff_info()
+    assert info.pairs_accepted == accepted_pairs(z, rc)
+    assert info.pairs_tested >= info.pairs_accepted
+    assert info.slots == info.block_cells + 2 * info.cells_per_cutoff
+    # the counters were reset by the read
+    assert ctx.cutoff_info().pairs_accepted == 0
+
+
+def test_cutoff_flat_sheet_eigenvector(gpu):
+    n, rc = 64, 0.31
+    p = params(n, n, rc, eps=1.0 / n)
+    z, _ = rr.flat_state(n, n)
+    A1, A2 = rr.grid(n, n)
+    k1, k2 = math.pi, 2 * math.pi
+    mu = np.cos(k1 * A1 + k2 * A2).ravel()
+    s = np.sin(k1 * A1 + k2 * A2).ravel()
+    w = np.stack([-k1 * s, -k2 * s])
+    u, _ = gpu_br(p, z, w, gpu)
+    lam = float(u[2] @ mu / (mu @ mu))
+    assert np.max(np.abs(u[:2])) <= 1e-15 * abs(lam)
+    assert np.max(np.abs(u[2] - lam * mu)) < 1e-12 * abs(lam)
+    assert relerr(u, oracle.br_velocity(oparams(p), z, w)) < TOL64
+
+
+def test_cutoff_rhs_matches_oracle(gpu):
+    import paper_2406_05490_amd as zm  # noqa: F401
+    import torch
+    n1, n2 = 32, 24
+    p = params(n1, n2, 0.4, atwood=0.7, gravity=1.3)
+    z, w = drifted_state(n1, n2, 8)
+    import paper_2406_05490_amd as zm
+    ctx = zm.Context(p)
+    zd, wd = to_dev(z, gpu), to_dev(w, gpu)
+    zt = torch.empty(3 * p.n, dtype=torch.float64, device=gpu)
+    wt = torch.empty(2 * p.n, dtype=torch.float64, device=gpu)
+    ctx.rhs(zd, wd, zt, wt)
+    torch.cuda.synchronize()
+    ozt, owt = oracle.rhs(oparams(p), z, w)
+    assert relerr(to_host(zt, (3, p.n)), ozt) < TOL64
+    assert relerr(to_host(wt, (2, p.n)), owt) < TOL64
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_cutoff_steps_match_oracle(gpu, graph):
+    import paper_2406_05490_amd as zm
+    import torch
+    n = 24
+    flags = zm.ZM_FLAG_GRAPH if graph else 0
+    p = params(n, n, 0.5, dt=2e-3, flags=flags)
+    z, _ = rr.single_mode(n, n, 0.05)
+    z[0] += 0.2
+    w = rr.synthetic_vorticity(n, n, seed=9, sigma=0.02)
+    ctx = zm.Context(p)
+    ctx.init_state(to_dev(z, gpu), to_dev(w, gpu))
+    ctx.step(3)
+    z1 = torch.empty(3 * p.n, dtype=torch.float64, device=gpu)
+    w1 = torch.empty(2 * p.n, dtype=torch.float64, device=gpu)
+    ctx.get_state(z1, w1)
+    torch.cuda.synchronize()
+    oz, ow = oracle.rk3(oparams(p), z, w, 3)
+    assert relerr(to_host(z1, (3, p.n)) - z, oz - z) < 1e-11
+    assert relerr(to_host(w1, (2, p.n)), ow) < 1e-11
+
+
+def test_cutoff_graph_replays_equal_eager(gpu):
+    import paper_2406_05490_amd as zm
+    import torch
+    n = 32
+    z, w = drifted_state(n, n, 10, height=0.05)
+    out = []
+    for flags in (0, zm.ZM_FLAG_GRAPH):
+        p = params(n, n, 0.3, flags=flags)
+        ctx = zm.Context(p)
+        ctx.init_state(to_dev(z, gpu), to_dev(w, gpu))
+        states = []
+        for _ in range(3):
+            ctx.step(1)
+            z1 = torch.empty(3 * p.n, dtype=torch.float64, device=gpu)
+            w1 = torch.empty(2 * p.n, dtype=torch.float64, device=gpu)
+            ctx.get_state(z1, w1)
+            torch.cuda.synchronize()
+            states.append((to_host(z1), to_host(w1)))
+        out.append(states)
+    for (za, wa), (zb, wb) in zip(*out):
+        assert np.array_equal(za, zb) and np.array_equal(wa, wb)
+
+
+def test_cutoff_repeat_bitwise(gpu):
+    n1, n2 = 80, 64
+    p = params(n1, n2, 0.25)
+    z, w = drifted_state(n1, n2, 11)
+    u1, _ = gpu_br(p, z, w, gpu)
+    u2, _ = gpu_br(p, z, w, gpu)
+    assert np.array_equal(u1, u2)
+
+
+def test_cutoff_256_sampled(gpu):
+    """256 x 256, 8 modes, rc = 0.2: sampled targets against the oracle."""
+    n = 256
+    p = params(n, n, 0.2)
+    z, _ = rr.multi_mode(n, n, 8, seed=1)
+    z[0] += 0.11
+    w = rr.synthetic_vorticity(n, n, seed=1)
+    u, _ = gpu_br(p, z, w, gpu)
+    idx = rr.sample_targets(n * n, 256, seed=12)
+    ref = oracle.br_velocity(oparams(p), z, w, targets=idx)
+    assert relerr(u[:, idx], ref) < TOL64
+
+
+def test_cutoff_tends_to_exact(gpu):
+    """The cutoff sum approaches the exact all-pairs sum as rc grows."""
+    import paper_2406_05490_amd as zm
+    n = 64
+    z, w = drifted_state(n, n, 13, height=0.05)
+    exact, _ = gpu_br(zm.Params(n, n, eps=1.0 / n), z, w, gpu)
+    errs = [relerr(gpu_br(params(n, n, rc), z, w, gpu)[0], exact) for rc in (0.1, 0.3, 0.6, 0.9)]
+    assert all(a > b for a, b in zip(errs, errs[1:]))
+
+
+def test_cutoff_not_in_batches(gpu):
+    import paper_2406_05490_amd as zm
+    with pytest.raises(zm.ZMError) as e:
+        zm.Batch([params(32, 32, 0.3)])
+    assert e.value.status in (zm.ZM_ERR_UNSUPPORTED, zm.ZM_ERR_INVALID_ARG)
