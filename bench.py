@@ -48,6 +48,8 @@ def parse():
     ap.add_argument("--tune-report", action="store_true",
                     help="only autotune the pair kernel for a range of mesh sides and print "
                          "the choice table (default shape vs tuned)")
+    ap.add_argument("--cutoff-only", action="store_true",
+                    help="only measure the cutoff solver (paper workloads, accuracy curve)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of this many MiB (counter calibration)")
     return ap.parse_args()
@@ -179,6 +181,79 @@ def small_mesh_latency(zm, torch, steps: int = 50):
         out[name + "_ms_per_step"] = (time.perf_counter() - t0) / steps * 1e3
         del ctx
     out["pairs_per_s_graph"] = 3 * wl.n * wl.n / (out["graph_ms_per_step"] / 1e3)
+    return out
+
+
+def cutoff_eval(zm, torch, p, z, w, reps: int = 3):
+    """Timed cutoff BR evaluations: per-kernel ms, accepted / tested pairs."""
+    dev = torch.device("cuda:0")
+    ctx = zm.Context(p)
+    zd = torch.from_numpy(np.ascontiguousarray(z).ravel()).to(dev)
+    wd = torch.from_numpy(np.ascontiguousarray(w).ravel()).to(dev)
+    ud = torch.empty_like(zd)
+    ctx.br_velocity(zd, wd, ud)
+    torch.cuda.synchronize()
+    ctx.profile_read()
+    ctx.profile_enable(True)
+    ctx.cutoff_info()
+    for _ in range(reps):
+        ctx.br_velocity(zd, wd, ud)
+    st = ctx.profile_read()
+    info = ctx.cutoff_info()
+    ms = {k: v[1] / max(v[0], 1) for k, v in st.items() if v[0]}
+    eval_ms = sum(ms.values())
+    acc = info.pairs_accepted / reps
+    tested = info.pairs_tested / reps
+    res = {"mesh": f"{p.n1}x{p.n2}", "cutoff": p.cutoff,
+           "cells": [info.cells1, info.cells2], "block_cells": info.block_cells,
+           "pairs_accepted_per_eval": acc, "pairs_tested_per_eval": tested,
+           "accepted_fraction_of_all_pairs": acc / float(p.n) ** 2,
+           "kernel_ms": ms, "eval_ms": eval_ms,
+           "accepted_pairs_per_s": acc / (ms["pairs"] / 1e3),
+           "pair_kernel_tflops_accepted": FLOPS_PER_PAIR * acc / (ms["pairs"] / 1e3) / 1e12}
+    res["pair_kernel_frac_of_fp64_peak"] = res["pair_kernel_tflops_accepted"] / PEAK_TFLOPS["fp64"]
+    return res, ud
+
+
+def cutoff_section(zm, torch):
+    """Cutoff BR solver: the paper's two cutoff workloads (per-GPU meshes,
+    cutoff as the same fraction of the interface width: 0.2 of 6 and 0.5 of
+    6 on a width-2 period cell), and the accuracy-vs-cutoff curve on the
+    256 x 256 eight-mode interface against the exact all-pairs sweep."""
+    out = {}
+    n = 768
+    z, _ = rr.multi_mode(n, n, 8, seed=1)
+    w = rr.synthetic_vorticity(n, n, seed=1)
+    rc = 0.2 * 2.0 / 6.0
+    out["multimode768"], _ = cutoff_eval(zm, torch, zm.Params(n, n, eps=1.0 / n, cutoff=rc), z, w)
+    n = 512
+    z, _ = rr.single_mode(n, n, 0.05)
+    w = rr.synthetic_vorticity(n, n, seed=2)
+    rc = 0.5 * 2.0 / 6.0
+    out["singlemode512"], _ = cutoff_eval(zm, torch, zm.Params(n, n, eps=1.0 / n, cutoff=rc), z, w)
+    # accuracy against the exact sweep
+    n = 256
+    z, _ = rr.multi_mode(n, n, 8, seed=1)
+    w = rr.synthetic_vorticity(n, n, seed=1)
+    dev = torch.device("cuda:0")
+    exact_ctx = zm.Context(zm.Params(n, n, eps=1.0 / n))
+    ue = torch.empty(3 * n * n, dtype=torch.float64, device=dev)
+    zd = torch.from_numpy(z.ravel()).to(dev); wd = torch.from_numpy(w.ravel()).to(dev)
+    exact_ctx.br_velocity(zd, wd, ue)
+    exact_ctx.profile_enable(True)
+    exact_ctx.br_velocity(zd, wd, ue)
+    est = exact_ctx.profile_read()
+    exact_ms = sum(v[1] / max(v[0], 1) for v in est.values() if v[0])
+    ue_h = ue.cpu().numpy()
+    scale = float(np.max(np.abs(ue_h)))
+    curve = []
+    for rc in (0.05, 0.1, 0.2, 0.3, 0.45, 0.6, 0.9):
+        r, uc = cutoff_eval(zm, torch, zm.Params(n, n, eps=1.0 / n, cutoff=rc), z, w, reps=2)
+        err = float(np.max(np.abs(uc.cpu().numpy() - ue_h)) / scale)
+        curve.append({"cutoff": rc, "max_rel_err_vs_exact": err, "eval_ms": r["eval_ms"],
+                      "speedup_vs_exact": exact_ms / r["eval_ms"],
+                      "accepted_fraction_of_all_pairs": r["accepted_fraction_of_all_pairs"]})
+    out["accuracy_vs_cutoff_256"] = {"exact_eval_ms": exact_ms, "curve": curve}
     return out
 
 
@@ -398,6 +473,9 @@ def main():
     import torch
     import paper_2406_05490_amd as zm
 
+    if args.cutoff_only:
+        print(json.dumps({"cutoff": cutoff_section(zm, torch)}), flush=True)
+        return
     if args.tune_report:
         print(json.dumps({"tune_report": tune_report(zm, torch)}), flush=True)
         return
@@ -479,6 +557,7 @@ def main():
         out["br_sweep_1m"] = br_sweep_1m(zm, torch)
         out["ensemble64_fp32_graph"] = ensemble64(zm, torch)
         out["periodic64_latency"] = small_mesh_latency(zm, torch)
+        out["cutoff"] = cutoff_section(zm, torch)
     if args.serve_seconds > 0:
         out["serving"] = serving(zm, torch, window_s=args.serve_seconds)
     if args.cpu_seconds > 0:
