@@ -14,10 +14,10 @@
 //   k_cut_bounds    first / one-past-last sorted index of every cell and of
 //                   every target block
 //   k_cut_gather    positions, source strengths and wrap counts in sorted
-//                   order (structure of arrays)
-//   k_cut_pairs     one workgroup per (target block, row of neighbour
-//                   cells): each neighbour cell's sources are staged through
-//                   LDS and every target sums over them
+//                   order, one 64-byte record per point
+//   k_cut_pairs     one wave per (target block, row of neighbour cells):
+//                   each neighbour cell's sources are read with wave-uniform
+//                   scalar loads and every target (lane) sums over them
 //
 // The inclusion test is evaluated exactly as the definition writes it
 // (r_a = (z_i,a - z_j,a) - S_a L_a, then r1*r1 + r2*r2 + r3*r3 < rc*rc, no
@@ -202,55 +202,58 @@ __global__ __launch_bounds__(kThreads) void k_cut_gather(Mesh m, CutGrid g, cons
     int kx, ky, cx, cy;
     wrap_cell(x, g.x0, g.L1, g.cw1, g.nc1, kx, cx);
     wrap_cell(y, g.y0, g.L2, g.cw2, g.nc2, ky, cy);
-    src[i] = x;
-    src[N + i] = y;
-    src[2 * N + i] = z[2 * N + p];
-    src[3 * N + i] = gam[p];
-    src[4 * N + i] = gam[N + p];
-    src[5 * N + i] = gam[2 * N + p];
-    src[6 * N + i] = (double)kx;
-    src[7 * N + i] = (double)ky;
+    double* r = src + (size_t)i * 8;
+    r[0] = x;
+    r[1] = y;
+    r[2] = z[2 * N + p];
+    r[3] = gam[p];
+    r[4] = gam[N + p];
+    r[5] = gam[2 * N + p];
+    r[6] = (double)kx;
+    r[7] = (double)ky;
 }
 
-// One workgroup per (target block, neighbour row).  Lane = one target of the
-// block (256 at a time); the row's B + 2m cells are visited left to right,
-// each cell's sources in sorted order, staged 256 at a time as (x, y),
-// (z, g1), (g2, g3), (kx, ky).  A source in raw cell column cx_raw (before
-// wrapping) is the image shifted by wx = floor(cx_raw / nc1) periods, so the
-// image shift of the pair is S = k_i + wx - k_j (and the same along y).
+// One wave per (target block, neighbour row, chunk slot).  Lane = one target
+// of the block: the wave takes the block's chunks of 64 targets z, z + C,
+// z + 2C, ... (C = g.chunks, about the mean number of chunks per block, so
+// that there are many waves even when the blocks are few); the row's B + 2m
+// cells are visited left to right,
+// each cell's sources in sorted order.  Every lane of the wave reads the same
+// source, so a source is one 64-byte record (x, y, z, g1, g2, g3, kx, ky)
+// fetched with wave-uniform (scalar) loads and used straight from scalar
+// registers: no LDS, no barriers.  A source in raw cell column cx_raw
+// (before wrapping) is the image shifted by wx = floor(cx_raw / nc1)
+// periods, so the image shift of the pair is S = k_i + wx - k_j (and the
+// same along y).
+constexpr int kCutThreads = 64;
+
 template <bool COUNT>
-__global__ __launch_bounds__(kThreads) void k_cut_pairs(Mesh m, CutGrid g,
-                                                        const double* __restrict__ src,
-                                                        const int* __restrict__ start,
-                                                        const int* __restrict__ end,
-                                                        const int* __restrict__ bstart,
-                                                        const int* __restrict__ bend,
-                                                        const unsigned* __restrict__ order,
-                                                        double* __restrict__ part,
-                                                        unsigned long long* __restrict__ counts)
+__global__ __launch_bounds__(kCutThreads) void k_cut_pairs(Mesh m, CutGrid g,
+                                                           const double* __restrict__ src,
+                                                           const int* __restrict__ start,
+                                                           const int* __restrict__ end,
+                                                           const int* __restrict__ bstart,
+                                                           const int* __restrict__ bend,
+                                                           const unsigned* __restrict__ order,
+                                                           double* __restrict__ part,
+                                                           unsigned long long* __restrict__ counts)
 {
-    __shared__ double2 lds[4][kThreads];
     const int blk = blockIdx.x, row = blockIdx.y;
     const int T0 = bstart[blk], T1 = bend[blk];
-    if (T0 >= T1) return;   // empty target block: uniform over the workgroup
+    if (T0 + (int)blockIdx.z * kCutThreads >= T1) return;   // nothing left: uniform
     const int N = m.N;
-    const int tid = threadIdx.x;
+    const int lane = threadIdx.x;
     const int bx = blk % g.nb1, by = blk / g.nb1;
     const int cy_raw = by * g.B - g.m + row;
     const int wy = floordiv(cy_raw, g.nc2), cy = cy_raw - wy * g.nc2;
     unsigned long long tested = 0, accepted = 0;
 
-    for (int t0 = T0; t0 < T1; t0 += kThreads) {
-        const int i = t0 + tid;
+    // chunks of 64 targets, blockIdx.z, blockIdx.z + chunks, ...
+    for (int t0 = T0 + (int)blockIdx.z * kCutThreads; t0 < T1; t0 += g.chunks * kCutThreads) {
+        const int i = t0 + lane;
         const bool active = i < T1;
-        double xi = 0.0, yi = 0.0, zi = 0.0, kxi = 0.0, kyi = 0.0;
-        if (active) {
-            xi = src[i];
-            yi = src[N + i];
-            zi = src[2 * N + i];
-            kxi = src[6 * N + i];
-            kyi = src[7 * N + i];
-        }
+        const double* ti = src + (size_t)(active ? i : T0) * 8;
+        const double xi = ti[0], yi = ti[1], zi = ti[2], kxi = ti[6], kyi = ti[7];
         double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0;
         for (int col = 0; col < g.slots; ++col) {
             const int cx_raw = bx * g.B - g.m + col;
@@ -258,40 +261,28 @@ __global__ __launch_bounds__(kThreads) void k_cut_pairs(Mesh m, CutGrid g,
             const int key = cell_key(g, cx, cy);
             const int s0 = start[key], s1 = end[key];
             const double Kx = kxi + (double)wx, Ky = kyi + (double)wy;
-            for (int j0 = s0; j0 < s1; j0 += kThreads) {
-                const int cnt = min(kThreads, s1 - j0);
-                __syncthreads();   // previous tile fully read
-                if (tid < cnt) {
-                    const int j = j0 + tid;
-                    lds[0][tid] = make_double2(src[j], src[N + j]);
-                    lds[1][tid] = make_double2(src[2 * N + j], src[3 * N + j]);
-                    lds[2][tid] = make_double2(src[4 * N + j], src[5 * N + j]);
-                    lds[3][tid] = make_double2(src[6 * N + j], src[7 * N + j]);
-                }
-                __syncthreads();
-                if (!active) continue;
-                for (int c = 0; c < cnt; ++c) {
+#pragma unroll 2
+            for (int j = s0; j < s1; ++j) {
 #pragma clang fp contract(off)
-                    const double2 v0 = lds[0][c], v1 = lds[1][c], v2 = lds[2][c], v3 = lds[3][c];
-                    const double d1 = xi - v0.x, d2 = yi - v0.y;
-                    const double S1 = Kx - v3.x, S2 = Ky - v3.y;
-                    const double r1 = d1 - S1 * g.L1;
-                    const double r2 = d2 - S2 * g.L2;
-                    const double r3 = zi - v1.x;
-                    const double dd = r1 * r1 + r2 * r2 + r3 * r3;
-                    const bool in = dd < g.rc2;
-                    const double wgt = in ? dev::inv_cube_sqrt(dd + m.eps2) : 0.0;
-                    const double a1 = wgt * v1.y, a2 = wgt * v2.x, a3 = wgt * v2.y;
-                    acc0 = fma(r2, a3, acc0);
-                    acc0 = fma(-r3, a2, acc0);
-                    acc1 = fma(r3, a1, acc1);
-                    acc1 = fma(-r1, a3, acc1);
-                    acc2 = fma(r1, a2, acc2);
-                    acc2 = fma(-r2, a1, acc2);
-                    if (COUNT) {
-                        tested += 1;
-                        accepted += in ? 1 : 0;
-                    }
+                const double* sj = src + (size_t)j * 8;   // same address in every lane
+                const double d1 = xi - sj[0], d2 = yi - sj[1];
+                const double S1 = Kx - sj[6], S2 = Ky - sj[7];
+                const double r1 = d1 - S1 * g.L1;
+                const double r2 = d2 - S2 * g.L2;
+                const double r3 = zi - sj[2];
+                const double dd = r1 * r1 + r2 * r2 + r3 * r3;
+                const bool in = dd < g.rc2;
+                const double wgt = in ? dev::inv_cube_sqrt(dd + m.eps2) : 0.0;
+                const double a1 = wgt * sj[3], a2 = wgt * sj[4], a3 = wgt * sj[5];
+                acc0 = fma(r2, a3, acc0);
+                acc0 = fma(-r3, a2, acc0);
+                acc1 = fma(r3, a1, acc1);
+                acc1 = fma(-r1, a3, acc1);
+                acc2 = fma(r1, a2, acc2);
+                acc2 = fma(-r2, a1, acc2);
+                if (COUNT) {
+                    tested += active ? 1 : 0;
+                    accepted += (active && in) ? 1 : 0;
                 }
             }
         }
@@ -308,7 +299,7 @@ __global__ __launch_bounds__(kThreads) void k_cut_pairs(Mesh m, CutGrid g,
             tested += __shfl_xor(tested, off, 64);
             accepted += __shfl_xor(accepted, off, 64);
         }
-        if ((tid & 63) == 0) {
+        if (lane == 0) {
             atomicAdd(&counts[0], tested);
             atomicAdd(&counts[1], accepted);
         }
@@ -341,6 +332,8 @@ CutGrid make_cut_grid(int n1, int n2, double L1, double L2, double rc)
     while ((1L << g.key_bits) < (long)g.nkeys) ++g.key_bits;
     g.slots = g.B + 2 * g.m;
     const long N = (long)n1 * n2;
+    const long per_block = (N + (long)g.nb1 * g.nb2 - 1) / ((long)g.nb1 * g.nb2);
+    g.chunks = (int)std::max(1L, std::min(65535L, (per_block + 63) / 64));
     g.sort_blocks = (int)std::max(1L, std::min(1024L, (N + 1023) / 1024));
     g.x0 = -0.5 * L1;
     g.y0 = -0.5 * L2;
@@ -381,13 +374,13 @@ hipError_t launch_cut_cells(const Mesh& m, const CutGrid& g, const double* z, co
 hipError_t launch_cut_pairs(const Mesh& m, const CutGrid& g, const CutBuffers& b,
                             int sorted_half, double* part, bool count, hipStream_t s)
 {
-    const dim3 grid(g.nb1 * g.nb2, g.slots);
+    const dim3 grid(g.nb1 * g.nb2, g.slots, g.chunks);
     const unsigned* order = b.vals[sorted_half];
     if (count)
-        hipLaunchKernelGGL(k_cut_pairs<true>, grid, dim3(kThreads), 0, s, m, g, b.src, b.start, b.end,
-                           b.bstart, b.bend, order, part, b.counts);
+        hipLaunchKernelGGL(k_cut_pairs<true>, grid, dim3(kCutThreads), 0, s, m, g, b.src, b.start,
+                           b.end, b.bstart, b.bend, order, part, b.counts);
     else
-        hipLaunchKernelGGL(k_cut_pairs<false>, grid, dim3(kThreads), 0, s, m, g, b.src, b.start,
+        hipLaunchKernelGGL(k_cut_pairs<false>, grid, dim3(kCutThreads), 0, s, m, g, b.src, b.start,
                            b.end, b.bstart, b.bend, order, part, b.counts);
     return hipGetLastError();
 }

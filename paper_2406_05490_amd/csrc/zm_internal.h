@@ -86,6 +86,7 @@ struct CutGrid {
     int nkeys;           // nb1 nb2 B^2
     int key_bits;        // bits of the sort key
     int slots;           // B + 2m
+    int chunks;          // waves per (target block, row): ~ mean 64-target chunks per block
     int sort_blocks;     // workgroups of the radix-sort passes
     double x0, y0;       // cell-grid origin (-L1/2, -L2/2)
     double L1, L2;
@@ -104,7 +105,7 @@ struct CutBuffers {
     int* end;            // nkeys: one past the last
     int* bstart;         // nb1 nb2: first sorted index of a target block
     int* bend;
-    double* src;         // 8 N: sorted x, y, z, g1, g2, g3, kx, ky planes
+    double* src;         // 8 N: per sorted point (x, y, z, g1, g2, g3, kx, ky)
     unsigned long long* counts;  // 2: pairs tested, pairs within rc
 };
 
