@@ -55,15 +55,18 @@ def parse():
     return ap.parse_args()
 
 
+PAIR_KERNEL_SOURCES = ("zm_device.h", "zm_internal.h", "zm_kernels.hip")
+
+
 def library_source_hash() -> str:
-    """SHA-256 over the library's kernel and host sources (name, then bytes)."""
-    import glob
+    """SHA-256 over the sources that define the single-instance pair kernels
+    (name, then bytes, in this order)."""
     import hashlib
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2406_05490_amd", "csrc")
-    for f in sorted(glob.glob(os.path.join(csrc, "*.h")) + glob.glob(os.path.join(csrc, "*.hip"))):
-        h.update(os.path.basename(f).encode())
-        with open(f, "rb") as fh:
+    for f in PAIR_KERNEL_SOURCES:
+        h.update(f.encode())
+        with open(os.path.join(csrc, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
 

@@ -91,30 +91,46 @@ __global__ __launch_bounds__(kThreads) void k_sort_hist(const unsigned* __restri
     hist[threadIdx.x * gridDim.x + blockIdx.x] = h[threadIdx.x];
 }
 
-// Exclusive scan of total entries in place, one workgroup of 1024 threads:
-// each thread sums a contiguous chunk, the chunk sums are scanned in LDS,
-// then each chunk is rewritten with its running offset.
-__global__ __launch_bounds__(1024) void k_sort_scan(unsigned* __restrict__ a, int total)
+// Exclusive scan of total entries in place, one workgroup of 1024 threads,
+// in tiles of 8 Ki entries: a tile is loaded into LDS with coalesced reads,
+// each thread scans 8 consecutive entries, the thread sums are scanned in
+// LDS with the running total of the previous tiles, and the tile is written
+// back coalesced.
+constexpr int kScanThreads = 1024;
+constexpr int kScanPer = 8;
+
+__global__ __launch_bounds__(kScanThreads) void k_sort_scan(unsigned* __restrict__ a, int total)
 {
-    __shared__ unsigned s[1024];
+    __shared__ unsigned tile[kScanThreads * kScanPer];
+    __shared__ unsigned s[kScanThreads];
+    __shared__ unsigned carry;
     const int t = threadIdx.x;
-    const int per = (total + 1023) / 1024;
-    const int lo = min(total, t * per), hi = min(total, lo + per);
-    unsigned sum = 0;
-    for (int i = lo; i < hi; ++i) sum += a[i];
-    s[t] = sum;
-    __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {
-        const unsigned v = t >= off ? s[t - off] : 0u;
+    if (t == 0) carry = 0;
+    for (int base = 0; base < total; base += kScanThreads * kScanPer) {
+        const int n = min(kScanThreads * kScanPer, total - base);
+        for (int q = t; q < kScanThreads * kScanPer; q += kScanThreads)
+            tile[q] = q < n ? a[base + q] : 0u;
         __syncthreads();
-        s[t] += v;
+        unsigned sum = 0;
+        for (int q = 0; q < kScanPer; ++q) sum += tile[t * kScanPer + q];
+        s[t] = sum;
         __syncthreads();
-    }
-    unsigned run = s[t] - sum;   // exclusive prefix of this chunk
-    for (int i = lo; i < hi; ++i) {
-        const unsigned v = a[i];
-        a[i] = run;
-        run += v;
+        for (int off = 1; off < kScanThreads; off <<= 1) {
+            const unsigned v = t >= off ? s[t - off] : 0u;
+            __syncthreads();
+            s[t] += v;
+            __syncthreads();
+        }
+        unsigned run = carry + s[t] - sum;   // exclusive prefix of this thread's entries
+        for (int q = 0; q < kScanPer; ++q) {
+            const unsigned v = tile[t * kScanPer + q];
+            tile[t * kScanPer + q] = run;
+            run += v;
+        }
+        __syncthreads();
+        for (int q = t; q < n; q += kScanThreads) a[base + q] = tile[q];
+        if (t == kScanThreads - 1) carry += s[t];
+        __syncthreads();
     }
 }
 
@@ -354,7 +370,7 @@ hipError_t launch_cut_cells(const Mesh& m, const CutGrid& g, const double* z, co
     int cur = 0;
     for (int shift = 0; shift < g.key_bits; shift += 8) {
         hipLaunchKernelGGL(k_sort_hist, dim3(G), blk, 0, s, b.keys[cur], N, shift, seg, b.hist);
-        hipLaunchKernelGGL(k_sort_scan, dim3(1), dim3(1024), 0, s, b.hist, 256 * G);
+        hipLaunchKernelGGL(k_sort_scan, dim3(1), dim3(kScanThreads), 0, s, b.hist, 256 * G);
         hipLaunchKernelGGL(k_sort_scatter, dim3(G), blk, 0, s, b.keys[cur], b.vals[cur],
                            b.keys[cur ^ 1], b.vals[cur ^ 1], N, shift, seg, b.hist);
         cur ^= 1;
