@@ -24,7 +24,7 @@ _LIB_PATH = os.environ.get("ZMO_ORACLE_LIB", _LIB_PATH)
 class _Problem(ctypes.Structure):
     _fields_ = [
         ("n1", ctypes.c_int32), ("n2", ctypes.c_int32),
-        ("images", ctypes.c_int32), ("pad_", ctypes.c_int32),
+        ("images", ctypes.c_int32), ("model", ctypes.c_int32),
         ("period1", ctypes.c_double), ("period2", ctypes.c_double),
         ("atwood", ctypes.c_double), ("gravity", ctypes.c_double),
         ("eps", ctypes.c_double), ("nu", ctypes.c_double), ("dt", ctypes.c_double),
@@ -46,9 +46,10 @@ class Problem:
     period1: float = 2.0
     period2: float = 2.0
     cutoff: float = 0.0       # > 0: cutoff BR solver (3D distance)
+    model: int = 0            # 0: high order (BR sum), 1: low order (FFT velocity)
 
     def c(self) -> _Problem:
-        return _Problem(self.n1, self.n2, self.images, 0, self.period1, self.period2,
+        return _Problem(self.n1, self.n2, self.images, self.model, self.period1, self.period2,
                         self.atwood, self.gravity, self.eps, self.nu, self.dt, self.cutoff)
 
     @property

@@ -17,7 +17,10 @@
  *     vorticity of every other point (sec. 2, BRSolver), by brute-force
  *     all pairs (sec. 3.2.1, exact integral calculation), or restricted to
  *     the sources within a 3D cutoff distance of each target (sec. 3.2.2,
- *     cutoff-based approximate integral calculation).
+ *     cutoff-based approximate integral calculation); or, for the low-order
+ *     model (sec. 2: the low-order solver approximates the BR integral with
+ *     FFTs), the flat-sheet velocity 1/2 (R1 w1 + R2 w2) along the unit
+ *     normal, R_a the Riesz transform over the periodic mesh.
  *   - The Z-Model derivatives of position and vorticity (sec. 2, ZModel)
  *     and a third-order Runge-Kutta step with three derivative evaluations
  *     (sec. 3.1, TimeIntegrator).
@@ -41,9 +44,12 @@
  *                                  model -- parity unpinned.
  *   zmo_rk3_step                : pinned (amplification factor, order 3).
  *   cutoff BR (cutoff > 0)      : pinned (flat-sheet lattice-sum eigenvalue
- *                                  over the disc |rho| < rc, equality with
- *                                  the exact sum when rc covers the whole
- *                                  period cell, brute force, symmetries).
+ *                                  over the disc |rho| < rc, brute force,
+ *                                  symmetries, convergence to the exact sum).
+ *   low-order velocity (model 1): pinned (flat-sheet symbol -|k|/2 exactly,
+ *                                  a library FFT on random fields, the
+ *                                  Nyquist rule, the linear growth rate
+ *                                  A g (k . k~) / |k| through RK3).
  *
  * Arithmetic: plain double, 1.0/sqrt(s), Neumaier-compensated per-target
  * sums in a fixed sequential source order, no FMA contraction (build with
@@ -62,7 +68,7 @@
 typedef struct {
     int32_t n1, n2;          /* mesh points along alpha_1, alpha_2           */
     int32_t images;          /* K >= 0 extra periodic image layers           */
-    int32_t pad_;
+    int32_t model;           /* 0: high order (BR sum), 1: low order (FFT)   */
     double period1, period2; /* L1, L2 (parameter and x/y period)            */
     double atwood;           /* A                                            */
     double gravity;          /* g (gravity is -g e3)                         */
@@ -328,6 +334,8 @@ static void br_cutoff_one_target(const zmo_problem *P, const double *z, const do
     out[2] = coef * nm_value(&a3);
 }
 
+static int low_order_velocity(const zmo_problem *P, const double *z, const double *w, double *u);
+
 /* BR velocity of the listed targets (point indices), or of all points when
  * targets == NULL.  u: 3 planes of length ntargets (or N).  gamma is the
  * source strength from zmo_surface.  Returns 0, or -1 on bad arguments. */
@@ -363,6 +371,12 @@ int zmo_br_velocity(const zmo_problem *P, const double *z, const double *w,
                     int64_t ntargets, const int64_t *targets, double *u, int nthreads)
 {
     if (!P || P->n1 < 1 || P->n2 < 1) return -1;
+    if (P->model == 1) {   /* low order: every point, no sampling */
+        if (targets || P->cutoff != 0.0 || P->images != 0) return -1;
+        (void)set_threads(nthreads);
+        return low_order_velocity(P, z, w, u);
+    }
+    if (P->model != 0) return -1;
     const size_t N = (size_t)P->n1 * P->n2;
     double *buf = (double *)malloc(sizeof(double) * 10 * N);
     if (!buf) return -1;
@@ -371,6 +385,88 @@ int zmo_br_velocity(const zmo_problem *P, const double *z, const double *w,
     int rc = zmo_br_from_gamma(P, z, gamma, ntargets, targets, u, nthreads);
     free(buf);
     return rc;
+}
+
+/* ------------------------------------------------------------------ */
+/* low-order velocity                                                  */
+/* ------------------------------------------------------------------ */
+
+/* Signed mode number of DFT index m on an n-point axis: m for m < n/2,
+ * m - n above; *nyq = 1 for the unpaired mode m = n/2 of an even n. */
+static int signed_mode(int m, int n, int *nyq)
+{
+    *nyq = (2 * m == n);
+    return 2 * m < n ? m : m - n;
+}
+
+/* Low-order velocity u = S n^ with S = 1/2 (R1 w1 + R2 w2): the Riesz
+ * transforms R_a act on the mode exp(i k.alpha) as i k_a / |k|, with
+ * k_a = 2 pi m_a / L_a (m_a signed), 0 for k = 0 and, along axis a, 0 at
+ * the unpaired mode m_a = n_a/2 of an even n_a (a real field cannot carry
+ * i k_a there).  n^ = (T1 x T2) / |T1 x T2|.  Plain double sums: forward
+ * DFT w^_a(m) = (1/N) sum_j w_a(j) exp(-2 pi i (m1 j1/n1 + m2 j2/n2)),
+ * then S(i) = Re sum_m S^(m) exp(+2 pi i (m1 i1/n1 + m2 i2/n2)). */
+static int low_order_velocity(const zmo_problem *P, const double *z, const double *w, double *u)
+{
+    const int n1 = P->n1, n2 = P->n2;
+    const size_t N = (size_t)n1 * n2;
+    double *buf = (double *)malloc(sizeof(double) * (6 * N + 3 * N));
+    if (!buf) return -1;
+    double *t1 = buf, *t2 = buf + 3 * N, *sre = buf + 6 * N, *sim = buf + 7 * N, *S = buf + 8 * N;
+    zmo_tangents(P, z, t1, t2);
+    /* S^ on every mode */
+#pragma omp parallel for schedule(static)
+    for (size_t mm = 0; mm < N; ++mm) {
+        const int m1 = (int)(mm % n1), m2 = (int)(mm / n1);
+        int nyq1, nyq2;
+        const int s1 = signed_mode(m1, n1, &nyq1), s2 = signed_mode(m2, n2, &nyq2);
+        const double k1 = 2.0 * M_PI * s1 / P->period1, k2 = 2.0 * M_PI * s2 / P->period2;
+        const double kk = sqrt(k1 * k1 + k2 * k2);
+        double c1 = 0.0, c2 = 0.0;   /* symbols divided by i */
+        if (kk > 0.0) {
+            c1 = nyq1 ? 0.0 : k1 / kk;
+            c2 = nyq2 ? 0.0 : k2 / kk;
+        }
+        neumaier ar = {0, 0}, ai = {0, 0};
+        for (int j2 = 0; j2 < n2; ++j2)
+            for (int j1 = 0; j1 < n1; ++j1) {
+                const size_t pj = (size_t)j2 * n1 + j1;
+                /* phase in turns, reduced exactly in integers */
+                const double ph = (double)((long)m1 * j1 % n1) / n1 + (double)((long)m2 * j2 % n2) / n2;
+                const double c = cos(2.0 * M_PI * ph), sn = sin(2.0 * M_PI * ph);
+                /* (1/2) i (c1 w1 + c2 w2) exp(-i 2 pi ph) */
+                const double f = 0.5 * (c1 * w[pj] + c2 * w[N + pj]);
+                nm_add(&ar, f * sn);    /* Re(i f (c - i sn)) = f sn */
+                nm_add(&ai, f * c);     /* Im(i f (c - i sn)) = f c  */
+            }
+        sre[mm] = nm_value(&ar) / (double)N;
+        sim[mm] = nm_value(&ai) / (double)N;
+    }
+    /* inverse DFT, real part */
+#pragma omp parallel for schedule(static)
+    for (size_t pi_ = 0; pi_ < N; ++pi_) {
+        const int i1 = (int)(pi_ % n1), i2 = (int)(pi_ / n1);
+        neumaier a = {0, 0};
+        for (int m2 = 0; m2 < n2; ++m2)
+            for (int m1 = 0; m1 < n1; ++m1) {
+                const size_t mm = (size_t)m2 * n1 + m1;
+                const double ph = (double)((long)m1 * i1 % n1) / n1 + (double)((long)m2 * i2 % n2) / n2;
+                /* Re((sre + i sim)(c + i sn)) */
+                nm_add(&a, sre[mm] * cos(2.0 * M_PI * ph) - sim[mm] * sin(2.0 * M_PI * ph));
+            }
+        S[pi_] = nm_value(&a);
+    }
+    for (size_t p = 0; p < N; ++p) {
+        const double a1 = t1[p], a2 = t1[N + p], a3 = t1[2 * N + p];
+        const double b1 = t2[p], b2 = t2[N + p], b3 = t2[2 * N + p];
+        const double nx = a2 * b3 - a3 * b2, ny = a3 * b1 - a1 * b3, nz = a1 * b2 - a2 * b1;
+        const double inv = 1.0 / sqrt(nx * nx + ny * ny + nz * nz);
+        u[p] = S[p] * (nx * inv);
+        u[N + p] = S[p] * (ny * inv);
+        u[2 * N + p] = S[p] * (nz * inv);
+    }
+    free(buf);
+    return 0;
 }
 
 /* ------------------------------------------------------------------ */
@@ -398,7 +494,14 @@ int zmo_rhs(const zmo_problem *P, const double *z, const double *w,
     double *t1 = buf, *t2 = buf + 3 * N, *gamma = buf + 6 * N, *q = buf + 9 * N;
     double *V = buf + 10 * N, *lap = buf + 11 * N;
     zmo_surface(P, z, w, t1, t2, gamma, q);
-    int rc = zmo_br_from_gamma(P, z, gamma, 0, NULL, zt, nthreads);
+    int rc;
+    if (P->model == 1) {
+        if (P->cutoff != 0.0 || P->images != 0) { free(buf); return -1; }
+        (void)set_threads(nthreads);
+        rc = low_order_velocity(P, z, w, zt);
+    } else {
+        rc = P->model == 0 ? zmo_br_from_gamma(P, z, gamma, 0, NULL, zt, nthreads) : -1;
+    }
     if (rc) { free(buf); return rc; }
     for (size_t p = 0; p < N; ++p)
         V[p] = bernoulli(P, zt[p], zt[N + p], zt[2 * N + p], q[p], z[2 * N + p]);
@@ -427,7 +530,7 @@ int zmo_rhs_sampled(const zmo_problem *P, const double *z, const double *w,
                     int64_t ntargets, const int64_t *targets,
                     double *zt, double *wt, int nthreads)
 {
-    if (!P || P->n1 < 1 || P->n2 < 1 || ntargets < 0 || !targets) return -1;
+    if (!P || P->n1 < 1 || P->n2 < 1 || ntargets < 0 || !targets || P->model != 0) return -1;
     const int n1 = P->n1, n2 = P->n2;
     const size_t N = (size_t)n1 * n2;
     const double h1 = P->period1 / n1, h2 = P->period2 / n2;
@@ -520,4 +623,4 @@ int zmo_rk3_step(const zmo_problem *P, double *z, double *w, int nsteps, int nth
     return 0;
 }
 
-int zmo_abi_version(void) { return 2; }
+int zmo_abi_version(void) { return 3; }

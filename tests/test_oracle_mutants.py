@@ -47,6 +47,12 @@ MUTANTS = {
                            "const double inv = 1.0 / sqrt(dd + 0.25 * eps_sq);"),
     "cutoff_radius_not_squared": ("const double rc2 = P->cutoff * P->cutoff;",
                                   "const double rc2 = P->cutoff;"),
+    "low_half_dropped": ("const double f = 0.5 * (c1 * w[pj] + c2 * w[N + pj]);",
+                         "const double f = (c1 * w[pj] + c2 * w[N + pj]);"),
+    "low_symbol_sign": ("c1 = nyq1 ? 0.0 : k1 / kk;", "c1 = nyq1 ? 0.0 : -k1 / kk;"),
+    "low_symbol_power": ("const double kk = sqrt(k1 * k1 + k2 * k2);",
+                         "const double kk = (k1 * k1 + k2 * k2);"),
+    "low_normal_component": ("u[N + p] = S[p] * (ny * inv);", "u[N + p] = S[p] * (nx * inv);"),
     "rk3_stage3_weights": ("double y3 = (1.0 / 3.0) * y0[k] + (2.0 / 3.0) * (y2[k] + dt * F[k]);",
                            "double y3 = (1.0 / 2.0) * y0[k] + (1.0 / 2.0) * (y2[k] + dt * F[k]);"),
 }
@@ -71,6 +77,7 @@ def test_mutant_is_caught(name, source, tmp_path):
     env = dict(os.environ, ZMO_ORACLE_LIB=str(lib), OMP_NUM_THREADS="4")
     r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
                         os.path.join(ROOT, "tests", "test_oracle_pins.py"),
-                        os.path.join(ROOT, "tests", "test_oracle_cutoff.py")],
+                        os.path.join(ROOT, "tests", "test_oracle_cutoff.py"),
+                        os.path.join(ROOT, "tests", "test_oracle_loworder.py")],
                        cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
     assert r.returncode == 1, f"mutant {name} passed every pin:\n{r.stdout[-2000:]}"
