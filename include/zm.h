@@ -39,6 +39,13 @@
  *              r_a = (z_i,a - z_j,a) - S_a L_a, included iff
  *              r1*r1 + r2*r2 + r3*r3 < rc*rc (evaluated in that order in
  *              double), weight 1, no ties, rc <= 0.45 min(L1, L2), K = 0;
+ *   low order  with model = ZM_MODEL_LOW the BR sum is replaced by its
+ *              flat-sheet approximation (sec. 2: the low-order solver uses
+ *              FFTs for the BR integral): u = 1/2 (R1 w1 + R2 w2) n^ with
+ *              n^ = T1 x T2 / |T1 x T2| and R_a the Riesz transform over the
+ *              periodic mesh, symbol i k_a / |k| on exp(i k.alpha),
+ *              k_a = 2 pi m_a / L_a, zero at k = 0 and, along axis a, at the
+ *              unpaired mode m_a = n_a / 2;
  *   q          |gamma|^2 / |T1 x T2|^2;
  *   V          A (|u|^2 - q/4 - 2 g z3);
  *   F(z, w)    z_t = u,  w_t = (D_1 V, D_2 V) + nu Lap(w);
@@ -84,6 +91,10 @@ typedef int32_t zm_status;
 #define ZM_FP32_PAIRS  1  /* pair terms in float32 on tile-relative coordinates;
                              per-target sums, state, ties and RK3 in float64   */
 
+/* ---- model order ----------------------------------------------------------- */
+#define ZM_MODEL_HIGH  0  /* u from the Birkhoff-Rott sum (exact or cutoff)      */
+#define ZM_MODEL_LOW   1  /* u = 1/2 (R1 w1 + R2 w2) n^ by FFT (low order)       */
+
 /* ---- flags ---------------------------------------------------------------- */
 #define ZM_FLAG_CHECK_FINITE 0x1u /* zm_step checks the state after each call
                                      and returns ZM_ERR_NONFINITE (this makes
@@ -105,7 +116,9 @@ typedef struct zm_params {
     int32_t  precision;        /* ZM_FP64 or ZM_FP32_PAIRS                      */
     int32_t  image_layers;     /* K >= 0 extra periodic image layers            */
     uint32_t flags;            /* ZM_FLAG_*                                     */
-    int32_t  reserved;         /* must be 0                                     */
+    int32_t  model;            /* ZM_MODEL_HIGH or ZM_MODEL_LOW (FP64, no cutoff,
+                                  K = 0; sides powers of two <= 4096; single
+                                  contexts only)                               */
     double   cutoff;           /* 0: exact all-pairs BR; > 0: cutoff BR with
                                   this 3D distance (FP64 only, K = 0,
                                   <= 0.45 min(L1, L2); single contexts only)  */
@@ -181,7 +194,8 @@ zm_status zm_get_launch_info(const zm_ctx *ctx, zm_launch_info *out);
 #define ZM_KERNEL_REDUCE  3  /* sum of source splits, V              */
 #define ZM_KERNEL_UPDATE  4  /* D V, RK3 stage combination           */
 #define ZM_KERNEL_CELLS   5  /* cutoff BR: cell binning and sorting  */
-#define ZM_KERNEL_COUNT   6
+#define ZM_KERNEL_FFT     6  /* low order: FFT velocity and V        */
+#define ZM_KERNEL_COUNT   7
 
 typedef struct zm_kernel_stats {
     int64_t launches;           /* launches timed since the last read        */

@@ -23,10 +23,12 @@ ZM_ERR_CAPACITY = -6
 
 ZM_FP64 = 0
 ZM_FP32_PAIRS = 1
+ZM_MODEL_HIGH = 0
+ZM_MODEL_LOW = 1
 ZM_FLAG_CHECK_FINITE = 0x1
 ZM_FLAG_GRAPH = 0x2
 
-KERNELS = ("surface", "pairs", "ties", "reduce", "update", "cells")
+KERNELS = ("surface", "pairs", "ties", "reduce", "update", "cells", "fft")
 
 
 class ZMError(RuntimeError):
@@ -42,7 +44,7 @@ class zm_params(ctypes.Structure):
         ("atwood", ctypes.c_double), ("gravity", ctypes.c_double),
         ("eps", ctypes.c_double), ("nu", ctypes.c_double), ("dt", ctypes.c_double),
         ("precision", ctypes.c_int32), ("image_layers", ctypes.c_int32),
-        ("flags", ctypes.c_uint32), ("reserved", ctypes.c_int32),
+        ("flags", ctypes.c_uint32), ("model", ctypes.c_int32),
         ("cutoff", ctypes.c_double),
     ]
 
@@ -230,11 +232,12 @@ class Params:
     image_layers: int = 0
     flags: int = 0
     cutoff: float = 0.0       # > 0: cutoff BR solver with this 3D distance
+    model: int = ZM_MODEL_HIGH
 
     def c(self) -> zm_params:
         return zm_params(self.n1, self.n2, self.period1, self.period2, self.atwood,
                          self.gravity, self.eps, self.nu, self.dt, self.precision,
-                         self.image_layers, self.flags, 0, self.cutoff)
+                         self.image_layers, self.flags, self.model, self.cutoff)
 
     @property
     def n(self) -> int:

@@ -6,6 +6,8 @@
 //   k_surface -> k_pairs -> [k_ties] -> k_reduce -> k_update
 // or, for a cutoff context,
 //   k_surface -> cell binning and sort -> k_cut_pairs -> k_reduce -> k_update
+// or, for the low-order model,
+//   k_surface -> FFT velocity (pack, FFTs, transposes, symbol) -> k_update
 #include "zm.h"
 #include "zm_host.h"
 #include "zm_internal.h"
@@ -56,6 +58,8 @@ struct zm_ctx {
     bool cutoff = false;                    // cutoff BR solver
     zm::CutGrid cut{};
     zm::CutBuffers cb{};
+    bool low = false;                       // low-order model (FFT velocity)
+    zm::LowBuffers lb{};
 
     double* at(size_t off) { return reinterpret_cast<double*>(ws + off); }
     size_t N() const { return (size_t)mesh.N; }
@@ -115,6 +119,12 @@ zm_status eval_velocity(zm_ctx* c, const double* z, const double* w, double* u, 
     hipError_t e;
     e = timed(c, ZM_KERNEL_SURFACE, [&] { return zm::launch_surface(m, z, w, gam, q, stream); });
     if (e != hipSuccess) return hip_fail(c, e, "surface kernel launch");
+    if (c->low) {
+        e = timed(c, ZM_KERNEL_FFT,
+                  [&] { return zm::launch_low_velocity(m, z, w, q, c->lb, u, V, stream); });
+        if (e != hipSuccess) return hip_fail(c, e, "FFT velocity launch");
+        return ZM_OK;
+    }
     if (c->cutoff) {
         int half = 0;
         e = timed(c, ZM_KERNEL_CELLS,
@@ -155,6 +165,10 @@ size_t zm_workspace_bytes(const zm_params* params)
 {
     if (validate(params)) return 0;
     if (params->cutoff > 0.0 && params->precision != ZM_FP64) return 0;
+    if (params->model == ZM_MODEL_LOW &&
+        (params->precision != ZM_FP64 || !zm::low_order_supported_side(params->n1) ||
+         !zm::low_order_supported_side(params->n2)))
+        return 0;
     const zm::PairShape sh = zm::choose_pair_shape(params->n1, params->n2, params->precision);
     return make_layout(*params, sh).total;
 }
@@ -168,6 +182,12 @@ zm_status zm_create(zm_ctx** out, const zm_params* params, void* d_workspace,
     if (const char* why = validate(params)) { g_create_error = why; return ZM_ERR_INVALID_ARG; }
     if (params->cutoff > 0.0 && params->precision != ZM_FP64) {
         g_create_error = "the cutoff solver is FP64 only";
+        return ZM_ERR_UNSUPPORTED;
+    }
+    if (params->model == ZM_MODEL_LOW &&
+        (params->precision != ZM_FP64 || !zm::low_order_supported_side(params->n1) ||
+         !zm::low_order_supported_side(params->n2))) {
+        g_create_error = "the low-order model needs FP64 and sides that are powers of two <= 4096";
         return ZM_ERR_UNSUPPORTED;
     }
     const zm::PairShape sh = zm::choose_pair_shape(params->n1, params->n2, params->precision);
@@ -196,6 +216,14 @@ zm_status zm_create(zm_ctx** out, const zm_params* params, void* d_workspace,
     c->ws = reinterpret_cast<char*>(d_workspace);
     std::memset(c->stats, 0, sizeof(c->stats));
     c->mesh = zm::make_mesh(*params);
+    if (params->model == ZM_MODEL_LOW) {
+        c->low = true;
+        char* ws = c->ws;
+        c->lb.a = reinterpret_cast<double2*>(ws + L.lo_a);
+        c->lb.b = reinterpret_cast<double2*>(ws + L.lo_b);
+        c->lb.tw1 = reinterpret_cast<double2*>(ws + L.lo_tw1);
+        c->lb.tw2 = reinterpret_cast<double2*>(ws + L.lo_tw2);
+    }
     if (zm::has_cutoff(*params)) {
         c->cutoff = true;
         c->cut = zm::cut_grid_of(*params);
@@ -507,6 +535,6 @@ zm_status zm_profile_read(zm_ctx* c, zm_kernel_stats* out)
     return st;
 }
 
-int32_t zm_abi_version(void) { return 2; }
+int32_t zm_abi_version(void) { return 3; }
 
 }  // extern "C"

@@ -74,11 +74,10 @@ __device__ __forceinline__ double inv_cube_sqrt(double s)
 // surface derivatives
 // ---------------------------------------------------------------------------
 
-__device__ __forceinline__ void surface_point(const Mesh& m, int p, const double* __restrict__ z,
-                                              const double* __restrict__ w,
-                                              double* __restrict__ gam, double* __restrict__ q)
+// Tangents T1 = D1 z, T2 = D2 z at point p (5-point, seam-corrected).
+__device__ __forceinline__ void tangents_at(const Mesh& m, int p, const double* __restrict__ z,
+                                            double T1[3], double T2[3])
 {
-    if (p >= m.N) return;
     const int N = m.N;
     const int i2 = p / m.n1;
     const int i1 = p - i2 * m.n1;
@@ -93,7 +92,6 @@ __device__ __forceinline__ void surface_point(const Mesh& m, int p, const double
         pa[k] = i2 * m.n1 + j1;
         pb[k] = j2 * m.n1 + i1;
     }
-    double T1[3], T2[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         const double* f = z + (size_t)c * N;
@@ -108,6 +106,16 @@ __device__ __forceinline__ void surface_point(const Mesh& m, int p, const double
         T1[c] = d1_5pt(a[0], a[1], a[2], a[3], m.h1);
         T2[c] = d1_5pt(b[0], b[1], b[2], b[3], m.h2);
     }
+}
+
+__device__ __forceinline__ void surface_point(const Mesh& m, int p, const double* __restrict__ z,
+                                              const double* __restrict__ w,
+                                              double* __restrict__ gam, double* __restrict__ q)
+{
+    if (p >= m.N) return;
+    const int N = m.N;
+    double T1[3], T2[3];
+    tangents_at(m, p, z, T1, T2);
     const double w1 = w[p], w2 = w[N + p];
     const double g1 = w1 * T2[0] - w2 * T1[0];
     const double g2 = w1 * T2[1] - w2 * T1[1];

@@ -33,6 +33,9 @@ struct Layout {
     size_t cut_bstart, cut_bend;       // target blocks, int each
     size_t cut_src;                    // 8N doubles
     size_t cut_counts;                 // 2 uint64
+    // low-order model only (size 0 otherwise)
+    size_t lo_a, lo_b;                 // N double2 each
+    size_t lo_tw1, lo_tw2;             // n1/2, n2/2 double2
     size_t total;
 };
 
@@ -75,6 +78,12 @@ inline Layout make_layout(const zm_params& p, const zm::PairShape& sh)
     L.cut_bend = take(cut ? (size_t)g.nb1 * g.nb2 * sizeof(int) : 0);
     L.cut_src = take(cut ? 8 * N * d : 0);
     L.cut_counts = take(cut ? 2 * sizeof(unsigned long long) : 0);
+    const bool low = p.model == ZM_MODEL_LOW;
+    const size_t c16 = 2 * sizeof(double);
+    L.lo_a = take(low ? N * c16 : 0);
+    L.lo_b = take(low ? N * c16 : 0);
+    L.lo_tw1 = take(low ? (size_t)(p.n1 / 2) * c16 : 0);
+    L.lo_tw2 = take(low ? (size_t)(p.n2 / 2) * c16 : 0);
     L.total = o;
     return L;
 }
@@ -94,7 +103,9 @@ inline const char* validate(const zm_params* p)
     if (p->precision != ZM_FP64 && p->precision != ZM_FP32_PAIRS) return "unknown precision";
     if (p->image_layers < 0 || p->image_layers > kMaxImages) return "image_layers must be in [0, 16]";
     if (p->flags & ~(ZM_FLAG_CHECK_FINITE | ZM_FLAG_GRAPH)) return "unknown flag bits";
-    if (p->reserved != 0) return "reserved must be 0";
+    if (p->model != ZM_MODEL_HIGH && p->model != ZM_MODEL_LOW) return "unknown model";
+    if (p->model == ZM_MODEL_LOW && (p->cutoff != 0.0 || p->image_layers != 0))
+        return "the low-order model takes no cutoff and no image layers";
     if (!(std::isfinite(p->cutoff) && p->cutoff >= 0.0)) return "cutoff must be finite and >= 0";
     if (p->cutoff > 0.0) {
         if (p->cutoff > 0.45 * p->period1 || p->cutoff > 0.45 * p->period2)

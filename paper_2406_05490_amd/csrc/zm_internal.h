@@ -115,6 +115,24 @@ struct CutBuffers {
 hipError_t launch_cut_cells(const Mesh& m, const CutGrid& g, const double* z, const double* gam,
                             const CutBuffers& b, int* sorted_half, hipStream_t s);
 
+// ---- low-order model (zm_lowfft.hip) ----------------------------------------
+
+// Scratch of the FFT velocity: two N-point complex arrays, two twiddle tables.
+struct LowBuffers {
+    double2* a;
+    double2* b;
+    double2* tw1;        // n1 / 2
+    double2* tw2;        // n2 / 2
+};
+
+// Sides the FFT path handles: powers of two from 8 to 4096.
+bool low_order_supported_side(int n);
+
+// u (3 planes) = 1/2 (R1 w1 + R2 w2) n^ and, if V != NULL,
+// V = A (|u|^2 - q/4 - 2 g z3).
+hipError_t launch_low_velocity(const Mesh& m, const double* z, const double* w, const double* q,
+                               const LowBuffers& b, double* u, double* V, hipStream_t s);
+
 // Zero the two pair counters (a kernel, so it may sit in a captured graph).
 hipError_t launch_cut_count_reset(unsigned long long* counts, hipStream_t s);
 

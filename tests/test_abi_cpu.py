@@ -32,7 +32,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_abi_version_and_status_strings():
     lib = zm.load()
-    assert lib.zm_abi_version() == 2
+    assert lib.zm_abi_version() == 3
     assert zm.status_string(zm.ZM_OK) == "ok"
     for st in (zm.ZM_ERR_INVALID_ARG, zm.ZM_ERR_UNSUPPORTED, zm.ZM_ERR_WORKSPACE,
                zm.ZM_ERR_HIP, zm.ZM_ERR_NONFINITE, zm.ZM_ERR_CAPACITY):
@@ -54,6 +54,8 @@ def test_struct_layout_matches_header():
     dict(atwood=float("inf")), dict(precision=7), dict(image_layers=-1),
     dict(image_layers=17), dict(flags=0x80), dict(cutoff=-0.1), dict(cutoff=float("nan")),
     dict(cutoff=0.95), dict(cutoff=0.3, image_layers=1), dict(cutoff=0.3, precision=1),
+    dict(model=2), dict(model=1, cutoff=0.3), dict(model=1, image_layers=1),
+    dict(model=1, precision=1), dict(model=1, n1=24),
 ])
 def test_workspace_bytes_rejects_invalid(bad):
     kw = dict(n1=16, n2=16, eps=1 / 16)
@@ -71,6 +73,19 @@ def test_cutoff_workspace_and_status():
     assert st == zm.ZM_ERR_UNSUPPORTED and "FP64" in msg
     st, _, msg = _create(zm.Params(64, 64, eps=1 / 64, cutoff=0.95), None, 0)
     assert st == zm.ZM_ERR_INVALID_ARG and "cutoff" in msg
+
+
+def test_low_order_workspace_and_status():
+    a = zm.workspace_bytes(zm.Params(64, 64, eps=1 / 64))
+    b = zm.workspace_bytes(zm.Params(64, 64, eps=1 / 64, model=zm.ZM_MODEL_LOW))
+    assert 0 < a < b and b % 256 == 0
+    st, _, msg = _create(zm.Params(48, 64, eps=1 / 48, model=zm.ZM_MODEL_LOW), None, 0)
+    assert st == zm.ZM_ERR_UNSUPPORTED and "powers of two" in msg
+    st, _, msg = _create(zm.Params(64, 64, eps=1 / 64, model=zm.ZM_MODEL_LOW, cutoff=0.3), None, 0)
+    assert st == zm.ZM_ERR_INVALID_ARG
+    p = zm.Params(32, 32, eps=1 / 32, model=zm.ZM_MODEL_LOW)
+    assert zm.batch_workspace_bytes([p]) == 0
+    assert zm.pool_request_bytes(p) == 0
 
 
 def test_cutoff_refused_by_batches_and_pools():
