@@ -50,6 +50,8 @@ def parse():
                          "the choice table (default shape vs tuned)")
     ap.add_argument("--cutoff-only", action="store_true",
                     help="only measure the cutoff solver (paper workloads, accuracy curve)")
+    ap.add_argument("--low-order-only", action="store_true",
+                    help="only measure the low-order (FFT) model at 4096 x 4096")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of this many MiB (counter calibration)")
     return ap.parse_args()
@@ -258,6 +260,42 @@ def cutoff_section(zm, torch):
                       "accepted_fraction_of_all_pairs": r["accepted_fraction_of_all_pairs"]})
     out["accuracy_vs_cutoff_256"] = {"exact_eval_ms": exact_ms, "curve": curve}
     return out
+
+
+def low_order_section(zm, torch, n: int = 4096, steps: int = 5):
+    """Low-order model (FFT velocity): RK3 steps on an n x n eight-mode
+    interface (n = 4096 stands in for the paper's 4864 x 4864 per-GPU mesh,
+    the largest power of two below it), per-kernel times, mesh points
+    advanced per second, and the HBM rate of the FFT velocity against its
+    traffic (complex field read and written by 4 row-FFT passes, 2
+    transposes, the symbol pass; the pack and velocity passes)."""
+    z, _ = rr.multi_mode(n, n, 8, seed=1)
+    w = rr.synthetic_vorticity(n, n, seed=1)
+    dev = torch.device("cuda:0")
+    p = zm.Params(n, n, eps=1.0 / n, dt=1e-3, model=zm.ZM_MODEL_LOW)
+    ctx = zm.Context(p)
+    ctx.init_state(torch.from_numpy(z.ravel()).to(dev), torch.from_numpy(w.ravel()).to(dev))
+    ctx.step(1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.step(steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ctx.profile_enable(True)
+    ctx.step(1)
+    st = ctx.profile_read()
+    ms = {k: v[1] / v[0] for k, v in st.items() if v[0]}
+    N = n * n
+    # bytes of one FFT-velocity evaluation: 16 B complex per point, read +
+    # written by 4 FFT passes, 2 transposes and the symbol pass (which also
+    # reads the partner mode), pack (16 B read, 16 B write), velocity
+    # (z 24 B with neighbours from cache, S 16 B, q 8 B in; u 24 B, V 8 B out)
+    fft_bytes = N * (7 * 32 + 16 + 32 + 80)
+    return {"mesh": f"{n}x{n}", "steps": steps, "ms_per_step": wall / steps * 1e3,
+            "points_per_s": N * steps / wall, "kernel_ms_per_eval": ms,
+            "fft_velocity_bytes_per_eval": fft_bytes,
+            "fft_velocity_gb_per_s": fft_bytes / (ms["fft"] / 1e3) / 1e9,
+            "fft_velocity_frac_of_hbm": fft_bytes / (ms["fft"] / 1e3) / 8e12}
 
 
 def pair_kernel_ms(zm, torch, n: int, prec: int, reps: int = 3) -> float:
@@ -479,6 +517,9 @@ def main():
     if args.cutoff_only:
         print(json.dumps({"cutoff": cutoff_section(zm, torch)}), flush=True)
         return
+    if args.low_order_only:
+        print(json.dumps({"low_order_4096": low_order_section(zm, torch)}), flush=True)
+        return
     if args.tune_report:
         print(json.dumps({"tune_report": tune_report(zm, torch)}), flush=True)
         return
@@ -561,6 +602,7 @@ def main():
         out["ensemble64_fp32_graph"] = ensemble64(zm, torch)
         out["periodic64_latency"] = small_mesh_latency(zm, torch)
         out["cutoff"] = cutoff_section(zm, torch)
+        out["low_order_4096"] = low_order_section(zm, torch)
     if args.serve_seconds > 0:
         out["serving"] = serving(zm, torch, window_s=args.serve_seconds)
     if args.cpu_seconds > 0:
