@@ -29,6 +29,7 @@ class _Problem(ctypes.Structure):
         ("atwood", ctypes.c_double), ("gravity", ctypes.c_double),
         ("eps", ctypes.c_double), ("nu", ctypes.c_double), ("dt", ctypes.c_double),
         ("cutoff", ctypes.c_double),
+        ("boundary", ctypes.c_int32), ("pad_", ctypes.c_int32),
     ]
 
 
@@ -47,10 +48,12 @@ class Problem:
     period2: float = 2.0
     cutoff: float = 0.0       # > 0: cutoff BR solver (3D distance)
     model: int = 0            # 0: high order (BR sum), 1: low order (FFT velocity)
+    boundary: int = 0         # 0: periodic, 1: free (extrapolated ghosts, no images)
 
     def c(self) -> _Problem:
         return _Problem(self.n1, self.n2, self.images, self.model, self.period1, self.period2,
-                        self.atwood, self.gravity, self.eps, self.nu, self.dt, self.cutoff)
+                        self.atwood, self.gravity, self.eps, self.nu, self.dt, self.cutoff,
+                        self.boundary, 0)
 
     @property
     def n(self) -> int:

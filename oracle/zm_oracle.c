@@ -12,7 +12,8 @@
  *     and two vorticity components w = (w1,w2) on a regular N1 x N2 mesh.
  *   - Two-node-deep stencils for tangents and Laplacians (sec. 3.1,
  *     SurfaceMesh) with periodic coordinate correction across the seam
- *     (sec. 3.1, BoundaryCondition).
+ *     (sec. 3.1, BoundaryCondition), or, for a non-periodic sheet, values
+ *     extrapolated into the boundary cells (same passage).
  *   - The Birkhoff-Rott velocity of every point from the position and
  *     vorticity of every other point (sec. 2, BRSolver), by brute-force
  *     all pairs (sec. 3.2.1, exact integral calculation), or restricted to
@@ -46,6 +47,9 @@
  *   cutoff BR (cutoff > 0)      : pinned (flat-sheet lattice-sum eigenvalue
  *                                  over the disc |rho| < rc, brute force,
  *                                  symmetries, convergence to the exact sum).
+ *   free boundary (boundary 1)  : pinned (extrapolated stencils exact on
+ *                                  cubics, free-space brute force, rigid
+ *                                  translation and reflection symmetries).
  *   low-order velocity (model 1): pinned (flat-sheet symbol -|k|/2 exactly,
  *                                  a library FFT on random fields, the
  *                                  Nyquist rule, the linear growth rate
@@ -76,6 +80,8 @@ typedef struct {
     double nu;               /* optional artificial viscosity on w           */
     double dt;               /* time step                                    */
     double cutoff;           /* > 0: cutoff BR solver with this 3D distance  */
+    int32_t boundary;        /* 0: periodic, 1: free (non-periodic sheet)    */
+    int32_t pad_;
 } zmo_problem;
 
 /* ------------------------------------------------------------------ */
@@ -91,13 +97,43 @@ static int wrap_index(int i, int n, int *wraps)
     return i;
 }
 
+/* Free boundary: ghost value at index i (i = -2, -1 or n, n+1) of a line
+ * g(0..n-1) by cubic extrapolation from the four nearest points (the fourth
+ * difference across the boundary vanishes):
+ *   g(-1) = 4 g0 - 6 g1 + 4 g2 - g3,  g(-2) = 10 g0 - 20 g1 + 15 g2 - 4 g3,
+ * and the mirror images at the far end. */
+static double ghost(const double *base, size_t stride, int n, int i)
+{
+    if (i < 0) {
+        const double g0 = base[0], g1 = base[stride], g2 = base[2 * stride], g3 = base[3 * stride];
+        return i == -1 ? 4.0 * g0 - 6.0 * g1 + 4.0 * g2 - g3
+                       : 10.0 * g0 - 20.0 * g1 + 15.0 * g2 - 4.0 * g3;
+    }
+    const double g0 = base[(size_t)(n - 1) * stride], g1 = base[(size_t)(n - 2) * stride];
+    const double g2 = base[(size_t)(n - 3) * stride], g3 = base[(size_t)(n - 4) * stride];
+    return i == n ? 4.0 * g0 - 6.0 * g1 + 4.0 * g2 - g3
+                  : 10.0 * g0 - 20.0 * g1 + 15.0 * g2 - 4.0 * g3;
+}
+
+/* A plane (or one position component) at a possibly out-of-range index on
+ * a free-boundary mesh: in range as stored, else extrapolated along the
+ * axis that is out of range (5-point stencils leave one axis at a time). */
+static double free_at(const zmo_problem *P, const double *f, int i1, int i2)
+{
+    const int n1 = P->n1, n2 = P->n2;
+    if (i1 < 0 || i1 >= n1) return ghost(f + (size_t)i2 * n1, 1, n1, i1);
+    if (i2 < 0 || i2 >= n2) return ghost(f + i1, (size_t)n1, n2, i2);
+    return f[(size_t)i2 * n1 + i1];
+}
+
 /* Position component c at (possibly out-of-range) mesh index (i1,i2):
  * periodic in the index; z1 gains +-L1 per wrap along alpha_1, z2 gains
  * +-L2 per wrap along alpha_2 (the periodic coordinate correction);
- * z3 is plainly periodic. */
+ * z3 is plainly periodic.  Free boundary: extrapolated ghosts. */
 static double z_at(const zmo_problem *P, const double *z, int c, int i1, int i2)
 {
     const int n1 = P->n1, n2 = P->n2;
+    if (P->boundary == 1) return free_at(P, z + (size_t)c * n1 * n2, i1, i2);
     int w1, w2;
     int j1 = wrap_index(i1, n1, &w1);
     int j2 = wrap_index(i2, n2, &w2);
@@ -107,9 +143,11 @@ static double z_at(const zmo_problem *P, const double *z, int c, int i1, int i2)
     return v;
 }
 
-/* A periodic scalar plane at a possibly out-of-range index. */
+/* A periodic scalar plane at a possibly out-of-range index (free boundary:
+ * extrapolated ghosts). */
 static double f_at(const zmo_problem *P, const double *f, int i1, int i2)
 {
+    if (P->boundary == 1) return free_at(P, f, i1, i2);
     int w1, w2;
     int j1 = wrap_index(i1, P->n1, &w1);
     int j2 = wrap_index(i2, P->n2, &w2);
@@ -223,6 +261,11 @@ void zmo_laplacian(const zmo_problem *P, const double *f, double *out)
  * trapezoid rule over the period cell centred on the target). */
 static int axis_images(int i, int j, int n, int shift[2], double weight[2])
 {
+    if (n < 0) {               /* free boundary (caller passes -n): no images */
+        shift[0] = 0;
+        weight[0] = 1.0;
+        return 1;
+    }
     int d = ((j - i) % n + n) % n;   /* in [0, n) */
     if (2 * d < n) {                 /* o = d */
         shift[0] = (i + d - j) / n;
@@ -259,10 +302,10 @@ static void br_one_target(const zmo_problem *P, const double *z, const double *g
 
     for (int j2 = 0; j2 < n2; ++j2) {
         int s2[2]; double c2[2];
-        int k2 = axis_images(i2, j2, n2, s2, c2);
+        int k2 = axis_images(i2, j2, P->boundary == 1 ? -n2 : n2, s2, c2);
         for (int j1 = 0; j1 < n1; ++j1) {
             int s1[2]; double c1[2];
-            int k1 = axis_images(i1, j1, n1, s1, c1);
+            int k1 = axis_images(i1, j1, P->boundary == 1 ? -n1 : n1, s1, c1);
             const size_t pj = (size_t)j2 * n1 + j1;
             const double zj1 = z[pj], zj2 = z[N + pj], zj3 = z[2 * N + pj];
             const double g1 = gamma[pj], g2 = gamma[N + pj], g3 = gamma[2 * N + pj];
@@ -346,6 +389,9 @@ int zmo_br_from_gamma(const zmo_problem *P, const double *z, const double *gamma
     if (P->cutoff < 0.0 || (P->cutoff > 0.0 && (P->images != 0 || P->cutoff > 0.45 * P->period1 ||
                                                P->cutoff > 0.45 * P->period2)))
         return -1;
+    if (P->boundary != 0 && (P->boundary != 1 || P->images != 0 || P->cutoff != 0.0 ||
+                             P->n1 < 4 || P->n2 < 4))
+        return -1;
     const size_t N = (size_t)P->n1 * P->n2;
     const int64_t nt = targets ? ntargets : (int64_t)N;
     const double h1 = P->period1 / P->n1, h2 = P->period2 / P->n2;
@@ -372,7 +418,7 @@ int zmo_br_velocity(const zmo_problem *P, const double *z, const double *w,
 {
     if (!P || P->n1 < 1 || P->n2 < 1) return -1;
     if (P->model == 1) {   /* low order: every point, no sampling */
-        if (targets || P->cutoff != 0.0 || P->images != 0) return -1;
+        if (targets || P->cutoff != 0.0 || P->images != 0 || P->boundary != 0) return -1;
         (void)set_threads(nthreads);
         return low_order_velocity(P, z, w, u);
     }
@@ -496,7 +542,7 @@ int zmo_rhs(const zmo_problem *P, const double *z, const double *w,
     zmo_surface(P, z, w, t1, t2, gamma, q);
     int rc;
     if (P->model == 1) {
-        if (P->cutoff != 0.0 || P->images != 0) { free(buf); return -1; }
+        if (P->cutoff != 0.0 || P->images != 0 || P->boundary != 0) { free(buf); return -1; }
         (void)set_threads(nthreads);
         rc = low_order_velocity(P, z, w, zt);
     } else {
@@ -530,7 +576,9 @@ int zmo_rhs_sampled(const zmo_problem *P, const double *z, const double *w,
                     int64_t ntargets, const int64_t *targets,
                     double *zt, double *wt, int nthreads)
 {
-    if (!P || P->n1 < 1 || P->n2 < 1 || ntargets < 0 || !targets || P->model != 0) return -1;
+    if (!P || P->n1 < 1 || P->n2 < 1 || ntargets < 0 || !targets || P->model != 0 ||
+        P->boundary != 0)
+        return -1;
     const int n1 = P->n1, n2 = P->n2;
     const size_t N = (size_t)n1 * n2;
     const double h1 = P->period1 / n1, h2 = P->period2 / n2;
@@ -623,4 +671,4 @@ int zmo_rk3_step(const zmo_problem *P, double *z, double *w, int nsteps, int nth
     return 0;
 }
 
-int zmo_abi_version(void) { return 3; }
+int zmo_abi_version(void) { return 4; }

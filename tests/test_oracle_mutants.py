@@ -53,6 +53,12 @@ MUTANTS = {
     "low_symbol_power": ("const double kk = sqrt(k1 * k1 + k2 * k2);",
                          "const double kk = (k1 * k1 + k2 * k2);"),
     "low_normal_component": ("u[N + p] = S[p] * (ny * inv);", "u[N + p] = S[p] * (nx * inv);"),
+    "free_ghost_quadratic": ("return i == -1 ? 4.0 * g0 - 6.0 * g1 + 4.0 * g2 - g3",
+                             "return i == -1 ? 3.0 * g0 - 3.0 * g1 + 1.0 * g2 - 0.0 * g3"),
+    "free_far_ghost": ("    return i == n ? 4.0 * g0 - 6.0 * g1 + 4.0 * g2 - g3",
+                       "    return i == n ? 4.0 * g0 - 6.0 * g1 + 4.0 * g2 - 2.0 * g3"),
+    "free_images_kept": ("int k1 = axis_images(i1, j1, P->boundary == 1 ? -n1 : n1, s1, c1);",
+                         "int k1 = axis_images(i1, j1, n1, s1, c1);"),
     "rk3_stage3_weights": ("double y3 = (1.0 / 3.0) * y0[k] + (2.0 / 3.0) * (y2[k] + dt * F[k]);",
                            "double y3 = (1.0 / 2.0) * y0[k] + (1.0 / 2.0) * (y2[k] + dt * F[k]);"),
 }
@@ -78,6 +84,7 @@ def test_mutant_is_caught(name, source, tmp_path):
     r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
                         os.path.join(ROOT, "tests", "test_oracle_pins.py"),
                         os.path.join(ROOT, "tests", "test_oracle_cutoff.py"),
-                        os.path.join(ROOT, "tests", "test_oracle_loworder.py")],
+                        os.path.join(ROOT, "tests", "test_oracle_loworder.py"),
+                        os.path.join(ROOT, "tests", "test_oracle_free.py")],
                        cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
     assert r.returncode == 1, f"mutant {name} passed every pin:\n{r.stdout[-2000:]}"
