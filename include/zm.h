@@ -39,6 +39,12 @@
  *              r_a = (z_i,a - z_j,a) - S_a L_a, included iff
  *              r1*r1 + r2*r2 + r3*r3 < rc*rc (evaluated in that order in
  *              double), weight 1, no ties, rc <= 0.45 min(L1, L2), K = 0;
+ *   free sheet with boundary = ZM_BOUNDARY_FREE (sec. 3.1, BoundaryCondition:
+ *              non-periodic values are extrapolated into the boundary cells)
+ *              the stencils take ghost values from a cubic extrapolation,
+ *              g(-1) = 4 g0 - 6 g1 + 4 g2 - g3, g(-2) = 10 g0 - 20 g1 + 15 g2
+ *              - 4 g3 (and mirrored at the far end), for z, w and V, and
+ *              the BR sum has no images and no ties (r = z_i - z_j);
  *   low order  with model = ZM_MODEL_LOW the BR sum is replaced by its
  *              flat-sheet approximation (sec. 2: the low-order solver uses
  *              FFTs for the BR integral): u = 1/2 (R1 w1 + R2 w2) n^ with
@@ -95,6 +101,10 @@ typedef int32_t zm_status;
 #define ZM_MODEL_HIGH  0  /* u from the Birkhoff-Rott sum (exact or cutoff)      */
 #define ZM_MODEL_LOW   1  /* u = 1/2 (R1 w1 + R2 w2) n^ by FFT (low order)       */
 
+/* ---- boundary of the sheet -------------------------------------------------- */
+#define ZM_BOUNDARY_PERIODIC 0  /* doubly periodic (images, seam correction)    */
+#define ZM_BOUNDARY_FREE     1  /* non-periodic: ghosts extrapolated, no images */
+
 /* ---- flags ---------------------------------------------------------------- */
 #define ZM_FLAG_CHECK_FINITE 0x1u /* zm_step checks the state after each call
                                      and returns ZM_ERR_NONFINITE (this makes
@@ -122,6 +132,10 @@ typedef struct zm_params {
     double   cutoff;           /* 0: exact all-pairs BR; > 0: cutoff BR with
                                   this 3D distance (FP64 only, K = 0,
                                   <= 0.45 min(L1, L2); single contexts only)  */
+    int32_t  boundary;         /* ZM_BOUNDARY_PERIODIC or ZM_BOUNDARY_FREE (free:
+                                  high order, exact BR, K = 0; single contexts
+                                  only)                                        */
+    int32_t  reserved;         /* must be 0                                     */
 } zm_params;
 
 typedef struct zm_ctx zm_ctx;  /* opaque */

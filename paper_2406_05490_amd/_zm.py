@@ -25,6 +25,8 @@ ZM_FP64 = 0
 ZM_FP32_PAIRS = 1
 ZM_MODEL_HIGH = 0
 ZM_MODEL_LOW = 1
+ZM_BOUNDARY_PERIODIC = 0
+ZM_BOUNDARY_FREE = 1
 ZM_FLAG_CHECK_FINITE = 0x1
 ZM_FLAG_GRAPH = 0x2
 
@@ -46,6 +48,7 @@ class zm_params(ctypes.Structure):
         ("precision", ctypes.c_int32), ("image_layers", ctypes.c_int32),
         ("flags", ctypes.c_uint32), ("model", ctypes.c_int32),
         ("cutoff", ctypes.c_double),
+        ("boundary", ctypes.c_int32), ("reserved", ctypes.c_int32),
     ]
 
 
@@ -233,11 +236,13 @@ class Params:
     flags: int = 0
     cutoff: float = 0.0       # > 0: cutoff BR solver with this 3D distance
     model: int = ZM_MODEL_HIGH
+    boundary: int = ZM_BOUNDARY_PERIODIC
 
     def c(self) -> zm_params:
         return zm_params(self.n1, self.n2, self.period1, self.period2, self.atwood,
                          self.gravity, self.eps, self.nu, self.dt, self.precision,
-                         self.image_layers, self.flags, self.model, self.cutoff)
+                         self.image_layers, self.flags, self.model, self.cutoff,
+                         self.boundary, 0)
 
     @property
     def n(self) -> int:

@@ -146,12 +146,13 @@ zm_status eval_velocity(zm_ctx* c, const double* z, const double* w, double* u, 
                    : zm::launch_pairs_f64(m, c->shape, z, gam, part, stream);
     });
     if (e != hipSuccess) return hip_fail(c, e, "pair kernel launch");
-    if ((m.n1 % 2) == 0 || (m.n2 % 2) == 0) {
+    const bool ties = m.periodic && ((m.n1 % 2) == 0 || (m.n2 % 2) == 0);
+    if (ties) {
         e = timed(c, ZM_KERNEL_TIES, [&] { return zm::launch_ties(m, z, gam, tie, stream); });
         if (e != hipSuccess) return hip_fail(c, e, "tie kernel launch");
     }
     e = timed(c, ZM_KERNEL_REDUCE, [&] {
-        return zm::launch_reduce(m, c->shape.splits, part, tie, q, z, u, V, stream);
+        return zm::launch_reduce(m, c->shape.splits, part, tie, q, z, u, V, stream, m.periodic != 0);
     });
     if (e != hipSuccess) return hip_fail(c, e, "reduce kernel launch");
     return ZM_OK;
@@ -535,6 +536,6 @@ zm_status zm_profile_read(zm_ctx* c, zm_kernel_stats* out)
     return st;
 }
 
-int32_t zm_abi_version(void) { return 3; }
+int32_t zm_abi_version(void) { return 4; }
 
 }  // extern "C"

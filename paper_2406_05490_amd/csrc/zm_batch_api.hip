@@ -49,6 +49,7 @@ const char* plan_batch(const zm_params* params, int32_t count, BatchPlan& P)
         if (params[i].flags != 0) return "per-instance flags must be 0 in a batch";
         if (params[i].cutoff != 0.0) return "the cutoff solver is not available in a batch";
         if (params[i].model != ZM_MODEL_HIGH) return "the low-order model is not available in a batch";
+        if (params[i].boundary != ZM_BOUNDARY_PERIODIC) return "free sheets are not available in a batch";
         const zm::PairShape sh =
             zm::choose_pair_shape(params[i].n1, params[i].n2, params[i].precision);
         const zm::Layout L = zm::make_layout(params[i], sh);
@@ -218,7 +219,8 @@ zm_status zm_batch_create(zm_batch** out, const zm_params* params, int32_t count
         delete b;
         bool cut = false;
         for (int i = 0; params && i < count; ++i)
-            cut = cut || params[i].cutoff != 0.0 || params[i].model != ZM_MODEL_HIGH;
+            cut = cut || params[i].cutoff != 0.0 || params[i].model != ZM_MODEL_HIGH ||
+                  params[i].boundary != ZM_BOUNDARY_PERIODIC;
         return cut ? ZM_ERR_UNSUPPORTED : ZM_ERR_INVALID_ARG;
     }
     if (!zm::aligned(d_workspace) || workspace_bytes < b->plan.total) {

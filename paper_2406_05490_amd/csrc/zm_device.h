@@ -46,6 +46,45 @@ __device__ __forceinline__ int nbr(int i, int d, int n, int& wrap)
     return j;
 }
 
+// Value of a line g(0..n-1) (g[k * stride]) at j in [-2, n+1]; outside the
+// line (free boundary) the ghost value of a cubic extrapolation from the four
+// nearest points: g(-1) = 4 g0 - 6 g1 + 4 g2 - g3,
+// g(-2) = 10 g0 - 20 g1 + 15 g2 - 4 g3, and the mirror images at the far end.
+__device__ __forceinline__ double line_at(const double* __restrict__ g, size_t stride, int n, int j)
+{
+    if (j >= 0 && j < n) return g[(size_t)j * stride];
+    const bool lo = j < 0;
+    const size_t s = stride;
+    const double g0 = lo ? g[0] : g[(size_t)(n - 1) * s];
+    const double g1 = lo ? g[s] : g[(size_t)(n - 2) * s];
+    const double g2 = lo ? g[2 * s] : g[(size_t)(n - 3) * s];
+    const double g3 = lo ? g[3 * s] : g[(size_t)(n - 4) * s];
+    const bool first = (j == -1) || (j == n);
+    return first ? 4.0 * g0 - 6.0 * g1 + 4.0 * g2 - g3
+                 : 10.0 * g0 - 20.0 * g1 + 15.0 * g2 - 4.0 * g3;
+}
+
+// The four 5-point neighbours (offsets -2, -1, +1, +2) of index i on the line
+// g (g[k * stride], n points).  Periodic: wrapped, plus `shift` per wrap (the
+// seam correction of the matching coordinate, 0 otherwise).  Free:
+// extrapolated ghosts.
+__device__ __forceinline__ void stencil4(bool periodic, const double* __restrict__ g, size_t stride,
+                                         int n, int i, double shift, double v[4])
+{
+    const int offs[4] = {-2, -1, 1, 2};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        if (periodic) {
+            int w;
+            const int j = nbr(i, offs[k], n, w);
+            v[k] = g[(size_t)j * stride];
+            if (w != 0) v[k] = v[k] + (double)w * shift;
+        } else {
+            v[k] = line_at(g, stride, n, i + offs[k]);
+        }
+    }
+}
+
 __device__ __forceinline__ double d1_5pt(double fm2, double fm1, double fp1, double fp2, double h)
 {
     return (8.0 * (fp1 - fm1) - (fp2 - fm2)) / (12.0 * h);
@@ -74,35 +113,21 @@ __device__ __forceinline__ double inv_cube_sqrt(double s)
 // surface derivatives
 // ---------------------------------------------------------------------------
 
-// Tangents T1 = D1 z, T2 = D2 z at point p (5-point, seam-corrected).
+// Tangents T1 = D1 z, T2 = D2 z at point p (5-point; seam-corrected on a
+// periodic sheet, extrapolated ghosts on a free one).
 __device__ __forceinline__ void tangents_at(const Mesh& m, int p, const double* __restrict__ z,
                                             double T1[3], double T2[3])
 {
     const int N = m.N;
     const int i2 = p / m.n1;
     const int i1 = p - i2 * m.n1;
-
-    int wa[4], wb[4];
-    int pa[4], pb[4];
-    const int offs[4] = {-2, -1, 1, 2};
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const int j1 = nbr(i1, offs[k], m.n1, wa[k]);
-        const int j2 = nbr(i2, offs[k], m.n2, wb[k]);
-        pa[k] = i2 * m.n1 + j1;
-        pb[k] = j2 * m.n1 + i1;
-    }
+    const bool per = m.periodic != 0;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         const double* f = z + (size_t)c * N;
         double a[4], b[4];
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            a[k] = f[pa[k]];
-            b[k] = f[pb[k]];
-            if (c == 0 && wa[k] != 0) a[k] = a[k] + (double)wa[k] * m.L1;
-            if (c == 1 && wb[k] != 0) b[k] = b[k] + (double)wb[k] * m.L2;
-        }
+        stencil4(per, f + (size_t)i2 * m.n1, 1, m.n1, i1, c == 0 ? m.L1 : 0.0, a);
+        stencil4(per, f + i1, (size_t)m.n1, m.n2, i2, c == 1 ? m.L2 : 0.0, b);
         T1[c] = d1_5pt(a[0], a[1], a[2], a[3], m.h1);
         T2[c] = d1_5pt(b[0], b[1], b[2], b[3], m.h2);
     }
@@ -140,6 +165,21 @@ struct AxisImg {
     int b;
     int s_lo;
 };
+
+__device__ __forceinline__ AxisImg axis_img(int i, int n);
+
+// axis_img on a mesh: a free sheet has no images (every source at shift 0,
+// the breakpoint past the end of the axis).
+__device__ __forceinline__ AxisImg axis_img_m(const Mesh& m, int i, int n)
+{
+    if (!m.periodic) {
+        AxisImg a;
+        a.b = n;
+        a.s_lo = 0;
+        return a;
+    }
+    return axis_img(i, n);
+}
 
 __device__ __forceinline__ AxisImg axis_img(int i, int n)
 {
@@ -296,10 +336,11 @@ __device__ __forceinline__ void pairs_f32_block(const Mesh& m, const PairShape& 
     const int ci1 = min(c0 + PX / 2, n1 - 1), ci2 = min(r0 + PY / 2, n2 - 1);
     const int pc = ci2 * n1 + ci1;
     const double cx = z[pc], cy = z[N + pc], cz = z[2 * N + pc];
-    const AxisImg cimg1 = axis_img(ci1, n1), cimg2 = axis_img(ci2, n2);
+    const AxisImg cimg1 = axis_img_m(m, ci1, n1), cimg2 = axis_img_m(m, ci2, n2);
     // antipodal band along axis 1: breakpoints of columns c0 .. c0+PX-1
-    const int band_lo = axis_img(c0, n1).b;
-    const int band_len = PX >= n1 ? n1 : PX;
+    // (none on a free sheet)
+    const int band_lo = axis_img_m(m, c0, n1).b;
+    const int band_len = !m.periodic ? 0 : (PX >= n1 ? n1 : PX);
 
     // near box: patch widened by kF32NearExtents patch half-extents
     const double ext = 0.5 * sqrt((double)(PX * PX) * m.h1 * m.h1 + (double)(PY * PY) * m.h2 * m.h2);
@@ -315,7 +356,7 @@ __device__ __forceinline__ void pairs_f32_block(const Mesh& m, const PairShape& 
     const int rowg = tid / PX;
     const bool col_ok = col < n1;
     const int i1 = col_ok ? col : ci1;
-    const AxisImg ax1 = axis_img(i1, n1);
+    const AxisImg ax1 = axis_img_m(m, i1, n1);
     float ax[R], az[R], ay[R];
     double ayd[R];
     int b2[R], s2lo[R], pidx[R];
@@ -330,7 +371,7 @@ __device__ __forceinline__ void pairs_f32_block(const Mesh& m, const PairShape& 
         ayd[k] = z[N + pidx[k]] - cy;
         az[k] = (float)(z[2 * N + pidx[k]] - cz);
         ay[k] = (float)ayd[k];
-        const AxisImg a2 = axis_img(i2, n2);
+        const AxisImg a2 = axis_img_m(m, i2, n2);
         b2[k] = a2.b;
         s2lo[k] = a2.s_lo;
     }
@@ -578,17 +619,17 @@ __device__ __forceinline__ void pairs_f64f_block(const Mesh& m, const PairShape&
     const int ci1 = min(c0 + PX / 2, n1 - 1), ci2 = min(r0 + PY / 2, n2 - 1);
     const int pc = ci2 * n1 + ci1;
     const double cx = z[pc], cy = z[N + pc], cz = z[2 * N + pc];
-    const AxisImg cimg1 = axis_img(ci1, n1), cimg2 = axis_img(ci2, n2);
-    const int band_lo = axis_img(c0, n1).b;
+    const AxisImg cimg1 = axis_img_m(m, ci1, n1), cimg2 = axis_img_m(m, ci2, n2);
+    const int band_lo = axis_img_m(m, c0, n1).b;   // n1 (no band) on a free sheet
     const bool band_all = PX >= n1 || !factored_ok(m, PX, PY);
-    const bool band_wraps = band_lo + PX > n1;
+    const bool band_wraps = m.periodic && band_lo + PX > n1;
 
     // ---- targets of this lane --------------------------------------------
     const int col = c0 + (tid % PX);
     const int rowg = tid / PX;
     const bool col_ok = col < n1;
     const int i1 = col_ok ? col : ci1;
-    const AxisImg ax1 = axis_img(i1, n1);
+    const AxisImg ax1 = axis_img_m(m, i1, n1);
     double ax0[R], ay0[R], az[R], ax[R], ay[R];
     int b2[R], s2lo[R], pidx[R];
     bool valid[R];
@@ -601,7 +642,7 @@ __device__ __forceinline__ void pairs_f64f_block(const Mesh& m, const PairShape&
         ax0[k] = z[pidx[k]] - cx;
         ay0[k] = z[N + pidx[k]] - cy;
         az[k] = z[2 * N + pidx[k]] - cz;
-        const AxisImg a2 = axis_img(i2, n2);
+        const AxisImg a2 = axis_img_m(m, i2, n2);
         b2[k] = a2.b;
         s2lo[k] = a2.s_lo;
     }
@@ -1022,24 +1063,26 @@ __device__ __forceinline__ void update_point(const Mesh& m, int p, int stage, co
     const int N = m.N, n1 = m.n1, n2 = m.n2;
     const int i2 = p / n1;
     const int i1 = p - i2 * n1;
-    int wr;
-    const int a_m2 = i2 * n1 + nbr(i1, -2, n1, wr), a_m1 = i2 * n1 + nbr(i1, -1, n1, wr);
-    const int a_p1 = i2 * n1 + nbr(i1, 1, n1, wr), a_p2 = i2 * n1 + nbr(i1, 2, n1, wr);
-    const int b_m2 = nbr(i2, -2, n2, wr) * n1 + i1, b_m1 = nbr(i2, -1, n2, wr) * n1 + i1;
-    const int b_p1 = nbr(i2, 1, n2, wr) * n1 + i1, b_p2 = nbr(i2, 2, n2, wr) * n1 + i1;
+    const bool per = m.periodic != 0;
 
     double F[5];
     F[0] = u[p];
     F[1] = u[N + p];
     F[2] = u[2 * N + p];
-    F[3] = d1_5pt(V[a_m2], V[a_m1], V[a_p1], V[a_p2], m.h1);
-    F[4] = d1_5pt(V[b_m2], V[b_m1], V[b_p1], V[b_p2], m.h2);
+    double va[4], vb[4];
+    stencil4(per, V + (size_t)i2 * n1, 1, n1, i1, 0.0, va);
+    stencil4(per, V + i1, (size_t)n1, n2, i2, 0.0, vb);
+    F[3] = d1_5pt(va[0], va[1], va[2], va[3], m.h1);
+    F[4] = d1_5pt(vb[0], vb[1], vb[2], vb[3], m.h2);
     if (m.nu != 0.0) {
 #pragma unroll
         for (int c = 0; c < 2; ++c) {
             const double* f = ys_w + (size_t)c * N;
-            const double lap = d2_5pt(f[a_m2], f[a_m1], f[p], f[a_p1], f[a_p2], m.h1) +
-                               d2_5pt(f[b_m2], f[b_m1], f[p], f[b_p1], f[b_p2], m.h2);
+            double fa[4], fb[4];
+            stencil4(per, f + (size_t)i2 * n1, 1, n1, i1, 0.0, fa);
+            stencil4(per, f + i1, (size_t)n1, n2, i2, 0.0, fb);
+            const double lap = d2_5pt(fa[0], fa[1], f[p], fa[2], fa[3], m.h1) +
+                               d2_5pt(fb[0], fb[1], f[p], fb[2], fb[3], m.h2);
             F[3 + c] = F[3 + c] + m.nu * lap;
         }
     }

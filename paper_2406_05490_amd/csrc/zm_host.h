@@ -106,6 +106,12 @@ inline const char* validate(const zm_params* p)
     if (p->model != ZM_MODEL_HIGH && p->model != ZM_MODEL_LOW) return "unknown model";
     if (p->model == ZM_MODEL_LOW && (p->cutoff != 0.0 || p->image_layers != 0))
         return "the low-order model takes no cutoff and no image layers";
+    if (p->boundary != ZM_BOUNDARY_PERIODIC && p->boundary != ZM_BOUNDARY_FREE)
+        return "unknown boundary";
+    if (p->boundary == ZM_BOUNDARY_FREE &&
+        (p->model != ZM_MODEL_HIGH || p->cutoff != 0.0 || p->image_layers != 0))
+        return "a free sheet needs the high-order model, no cutoff and no image layers";
+    if (p->reserved != 0) return "reserved must be 0";
     if (!(std::isfinite(p->cutoff) && p->cutoff >= 0.0)) return "cutoff must be finite and >= 0";
     if (p->cutoff > 0.0) {
         if (p->cutoff > 0.45 * p->period1 || p->cutoff > 0.45 * p->period2)
@@ -156,6 +162,8 @@ inline Mesh make_mesh(const zm_params& p)
     m.gravity = p.gravity;
     m.nu = p.nu;
     m.dt = p.dt;
+    m.periodic = p.boundary == ZM_BOUNDARY_FREE ? 0 : 1;
+    m.pad_ = 0;
     return m;
 }
 

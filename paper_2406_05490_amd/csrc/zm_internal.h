@@ -17,6 +17,8 @@ struct Mesh {
     double eps2;         // eps^2
     double coef;         // -(h1 h2) / (4 pi)
     double atwood, gravity, nu, dt;
+    int periodic;        // 1: periodic sheet; 0: free (extrapolated ghosts, no images)
+    int pad_;
 };
 
 // Launch shape of the all-pairs kernel.

@@ -254,7 +254,7 @@ size_t zm_pool_workspace_bytes(size_t budget_bytes)
 size_t zm_pool_request_bytes(const zm_params* params)
 {
     if (zm::validate(params) || params->flags != 0 || params->cutoff != 0.0 ||
-        params->model != ZM_MODEL_HIGH)
+        params->model != ZM_MODEL_HIGH || params->boundary != ZM_BOUNDARY_PERIODIC)
         return 0;
     return request_bytes(*params, nullptr, nullptr);
 }
@@ -305,6 +305,8 @@ zm_status zm_pool_submit(zm_pool* P, const zm_params* params, const double* d_z,
         return pfail(P, ZM_ERR_UNSUPPORTED, "the cutoff solver is not available in a pool");
     if (params->model != ZM_MODEL_HIGH)
         return pfail(P, ZM_ERR_UNSUPPORTED, "the low-order model is not available in a pool");
+    if (params->boundary != ZM_BOUNDARY_PERIODIC)
+        return pfail(P, ZM_ERR_UNSUPPORTED, "free sheets are not available in a pool");
     if (steps < 1) return pfail(P, ZM_ERR_INVALID_ARG, "steps must be >= 1");
     if (!zm::aligned(d_z) || !zm::aligned(d_w))
         return pfail(P, ZM_ERR_INVALID_ARG, "state pointers must be non-NULL and 256-byte aligned");

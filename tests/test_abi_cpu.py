@@ -32,7 +32,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_abi_version_and_status_strings():
     lib = zm.load()
-    assert lib.zm_abi_version() == 3
+    assert lib.zm_abi_version() == 4
     assert zm.status_string(zm.ZM_OK) == "ok"
     for st in (zm.ZM_ERR_INVALID_ARG, zm.ZM_ERR_UNSUPPORTED, zm.ZM_ERR_WORKSPACE,
                zm.ZM_ERR_HIP, zm.ZM_ERR_NONFINITE, zm.ZM_ERR_CAPACITY):
@@ -41,8 +41,8 @@ def test_abi_version_and_status_strings():
 
 
 def test_struct_layout_matches_header():
-    # n1 n2 (8) + 7 doubles (56) + 4 int32 (16) + cutoff (8) = 88 bytes
-    assert ctypes.sizeof(_zm.zm_params) == 88
+    # n1 n2 (8) + 7 doubles (56) + 4 int32 (16) + cutoff (8) + 2 int32 (8)
+    assert ctypes.sizeof(_zm.zm_params) == 96
     assert ctypes.sizeof(_zm.zm_cutoff_info) == 40
     assert ctypes.sizeof(_zm.zm_launch_info) == 32
     assert ctypes.sizeof(_zm.zm_kernel_stats) == 16
@@ -56,6 +56,8 @@ def test_struct_layout_matches_header():
     dict(cutoff=0.95), dict(cutoff=0.3, image_layers=1), dict(cutoff=0.3, precision=1),
     dict(model=2), dict(model=1, cutoff=0.3), dict(model=1, image_layers=1),
     dict(model=1, precision=1), dict(model=1, n1=24),
+    dict(boundary=2), dict(boundary=1, cutoff=0.3), dict(boundary=1, model=1),
+    dict(boundary=1, image_layers=1),
 ])
 def test_workspace_bytes_rejects_invalid(bad):
     kw = dict(n1=16, n2=16, eps=1 / 16)

@@ -1,0 +1,107 @@
+"""Free (non-periodic) sheet on the GPU (libzm.so through its C ABI) against
+the oracle: extrapolated ghosts in the stencils, BR sum without images.
+
+Bar: 1e-12 normwise relative error for float64, 1e-5 for the FP32 pair form.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import rocket_rig as rr
+from zm_testutil import relerr, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12
+
+
+def params(n1, n2, **kw):
+    import paper_2406_05490_amd as zm
+    kw.setdefault("eps", 0.5 * 2.0 / n1)
+    return zm.Params(n1, n2, boundary=zm.ZM_BOUNDARY_FREE, **kw)
+
+
+def oparams(p):
+    return oracle.Problem(p.n1, p.n2, eps=p.eps, atwood=p.atwood, gravity=p.gravity, dt=p.dt,
+                          nu=p.nu, period1=p.period1, period2=p.period2, boundary=1)
+
+
+def gpu_u(p, z, w, device):
+    import paper_2406_05490_amd as zm
+    import torch
+    ctx = zm.Context(p)
+    ud = torch.empty(3 * p.n, dtype=torch.float64, device=device)
+    ctx.br_velocity(to_dev(z, device), to_dev(w, device), ud)
+    torch.cuda.synchronize()
+    return to_host(ud, (3, p.n))
+
+
+@pytest.mark.parametrize("n1,n2,seed", [(8, 8, 0), (24, 16, 1), (33, 27, 2), (64, 64, 3),
+                                        (96, 40, 4), (17, 130, 5)])
+def test_free_br_matches_oracle(gpu, n1, n2, seed):
+    p = params(n1, n2)
+    z, w = rr.random_state(n1, n2, seed=seed, height=0.1)
+    assert relerr(gpu_u(p, z, w, gpu), oracle.br_velocity(oparams(p), z, w)) < TOL64
+
+
+@pytest.mark.parametrize("n1,n2,seed", [(64, 64, 6), (130, 48, 7)])
+def test_free_fp32_pairs_match_oracle(gpu, n1, n2, seed):
+    p = params(n1, n2, precision=1)
+    z, w = rr.random_state(n1, n2, seed=seed, height=0.1)
+    assert relerr(gpu_u(p, z, w, gpu), oracle.br_velocity(oparams(p), z, w)) < 1e-5
+
+
+def test_free_rhs_matches_oracle(gpu):
+    import paper_2406_05490_amd as zm
+    import torch
+    n1, n2 = 40, 24
+    p = params(n1, n2, atwood=0.7, gravity=1.3, nu=2e-3)
+    z, w = rr.random_state(n1, n2, seed=8, height=0.1)
+    ctx = zm.Context(p)
+    zt = torch.empty(3 * p.n, dtype=torch.float64, device=gpu)
+    wt = torch.empty(2 * p.n, dtype=torch.float64, device=gpu)
+    ctx.rhs(to_dev(z, gpu), to_dev(w, gpu), zt, wt)
+    torch.cuda.synchronize()
+    ozt, owt = oracle.rhs(oparams(p), z, w)
+    assert relerr(to_host(zt, (3, p.n)), ozt) < TOL64
+    assert relerr(to_host(wt, (2, p.n)), owt) < TOL64
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_free_steps_match_oracle(gpu, graph):
+    import paper_2406_05490_amd as zm
+    import torch
+    n = 32
+    p = params(n, n, dt=2e-3, flags=zm.ZM_FLAG_GRAPH if graph else 0)
+    z, _ = rr.single_mode(n, n, 0.05)
+    w = rr.synthetic_vorticity(n, n, seed=9, sigma=0.02)
+    ctx = zm.Context(p)
+    ctx.init_state(to_dev(z, gpu), to_dev(w, gpu))
+    ctx.step(3)
+    z1 = torch.empty(3 * p.n, dtype=torch.float64, device=gpu)
+    w1 = torch.empty(2 * p.n, dtype=torch.float64, device=gpu)
+    ctx.get_state(z1, w1)
+    torch.cuda.synchronize()
+    oz, ow = oracle.rk3(oparams(p), z, w, 3)
+    assert relerr(to_host(z1, (3, p.n)) - z, oz - z) < 1e-11
+    assert relerr(to_host(w1, (2, p.n)), ow) < 1e-11
+
+
+def test_free_256_sampled(gpu):
+    n = 256
+    p = params(n, n)
+    z, _ = rr.single_mode(n, n, 0.05)
+    w = rr.synthetic_vorticity(n, n, seed=10)
+    u = gpu_u(p, z, w, gpu)
+    idx = rr.sample_targets(n * n, 256, seed=11)
+    # include the edges and corners, where the sheet ends
+    idx = np.unique(np.concatenate([idx, [0, n - 1, n * (n - 1), n * n - 1, n // 2, n * (n // 2)]]))
+    ref = oracle.br_velocity(oparams(p), z, w, targets=idx)
+    assert relerr(u[:, idx], ref) < TOL64
+
+
+def test_free_repeat_bitwise(gpu):
+    n1, n2 = 80, 64
+    p = params(n1, n2)
+    z, w = rr.random_state(n1, n2, seed=12, height=0.05)
+    assert np.array_equal(gpu_u(p, z, w, gpu), gpu_u(p, z, w, gpu))
