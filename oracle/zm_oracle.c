@@ -49,7 +49,10 @@
  *                                  symmetries, convergence to the exact sum).
  *   free boundary (boundary 1)  : pinned (extrapolated stencils exact on
  *                                  cubics, free-space brute force, rigid
- *                                  translation and reflection symmetries).
+ *                                  translation and reflection symmetries;
+ *                                  with a cutoff: the exact free sum once rc
+ *                                  exceeds the sheet's diameter, brute-force
+ *                                  pair counts).
  *   low-order velocity (model 1): pinned (flat-sheet symbol -|k|/2 exactly,
  *                                  a library FFT on random fields, the
  *                                  Nyquist rule, the linear growth rate
@@ -344,7 +347,8 @@ static void br_one_target(const zmo_problem *P, const double *z, const double *g
  * r1*r1 + r2*r2 + r3*r3 < rc*rc, evaluated left to right in plain double.
  * rc <= 0.45 min(L1, L2), so at most one image of a source can be that
  * close and a source (nearly) half a period away along an axis never is.  Sources in index
- * order; no extra image layers. */
+ * order; no extra image layers.  Free sheet (boundary 1): no images, S = 0,
+ * r = z_i - z_j, and any rc > 0. */
 static void br_cutoff_one_target(const zmo_problem *P, const double *z, const double *gamma,
                                  int i1, int i2, double coef, double out[3])
 {
@@ -353,13 +357,15 @@ static void br_cutoff_one_target(const zmo_problem *P, const double *z, const do
     const double L1 = P->period1, L2 = P->period2;
     const double eps_sq = P->eps * P->eps;
     const double rc2 = P->cutoff * P->cutoff;
+    const int free_sheet = P->boundary == 1;
     const size_t pi_ = (size_t)i2 * n1 + i1;
     const double zi1 = z[pi_], zi2 = z[N + pi_], zi3 = z[2 * N + pi_];
     neumaier a1 = {0, 0}, a2 = {0, 0}, a3 = {0, 0};
 
     for (size_t pj = 0; pj < N; ++pj) {
         const double d1 = zi1 - z[pj], d2 = zi2 - z[N + pj];
-        const double S1 = nearbyint(d1 / L1), S2 = nearbyint(d2 / L2);
+        const double S1 = free_sheet ? 0.0 : nearbyint(d1 / L1);
+        const double S2 = free_sheet ? 0.0 : nearbyint(d2 / L2);
         const double r1 = d1 - S1 * L1;
         const double r2 = d2 - S2 * L2;
         const double r3 = zi3 - z[2 * N + pj];
@@ -386,11 +392,11 @@ int zmo_br_from_gamma(const zmo_problem *P, const double *z, const double *gamma
                       int64_t ntargets, const int64_t *targets, double *u, int nthreads)
 {
     if (!P || P->n1 < 1 || P->n2 < 1 || !(P->eps > 0.0) || P->images < 0) return -1;
-    if (P->cutoff < 0.0 || (P->cutoff > 0.0 && (P->images != 0 || P->cutoff > 0.45 * P->period1 ||
-                                               P->cutoff > 0.45 * P->period2)))
+    if (P->cutoff < 0.0 || (P->cutoff > 0.0 && (P->images != 0 ||
+                                               (P->boundary == 0 && (P->cutoff > 0.45 * P->period1 ||
+                                                                     P->cutoff > 0.45 * P->period2)))))
         return -1;
-    if (P->boundary != 0 && (P->boundary != 1 || P->images != 0 || P->cutoff != 0.0 ||
-                             P->n1 < 4 || P->n2 < 4))
+    if (P->boundary != 0 && (P->boundary != 1 || P->images != 0 || P->n1 < 4 || P->n2 < 4))
         return -1;
     const size_t N = (size_t)P->n1 * P->n2;
     const int64_t nt = targets ? ntargets : (int64_t)N;

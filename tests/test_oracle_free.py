@@ -6,7 +6,9 @@ images.  Checked against:
   * polynomials the extrapolated stencils must differentiate exactly;
   * a pure-Python free-space brute force;
   * rigid translation (any vector) and mirror symmetry through x = const,
-    which also exercises the two ends' ghost formulas.
+    which also exercises the two ends' ghost formulas;
+  * with a cutoff: a free-space brute force over the pairs within rc, and
+    the exact free sum once rc exceeds the sheet's diameter.
 """
 import math
 
@@ -108,8 +110,64 @@ def test_free_differs_from_periodic_at_the_edges_only_through_ghosts_and_images(
     assert not np.allclose(tf1[:, ~inner.ravel()], tp1[:, ~inner.ravel()], rtol=0, atol=1e-14)
 
 
+def brute_free_cutoff(n1, n2, z, gamma, eps, rc, L=2.0):
+    """Free-space sum over the sources strictly within rc of the target
+    (3D distance, no images)."""
+    N = n1 * n2
+    coef = -(L / n1) * (L / n2) / (4 * math.pi)
+    u = np.zeros((3, N))
+    count = 0
+    for i in range(N):
+        acc = [0.0, 0.0, 0.0]
+        for j in range(N):
+            r = [z[0][i] - z[0][j], z[1][i] - z[1][j], z[2][i] - z[2][j]]
+            dd = r[0] ** 2 + r[1] ** 2 + r[2] ** 2
+            if not dd < rc * rc:
+                continue
+            count += 1
+            wgt = (dd + eps * eps) ** -1.5
+            g = gamma[:, j]
+            acc[0] += wgt * (r[1] * g[2] - r[2] * g[1])
+            acc[1] += wgt * (r[2] * g[0] - r[0] * g[2])
+            acc[2] += wgt * (r[0] * g[1] - r[1] * g[0])
+        u[:, i] = [coef * a for a in acc]
+    return u, count
+
+
+@pytest.mark.parametrize("n1,n2,rc,seed", [(8, 8, 0.3, 6), (10, 9, 0.75, 7), (9, 12, 1.3, 8)])
+def test_free_cutoff_matches_brute_force(n1, n2, rc, seed):
+    """rc up to 0.65 of the side: a periodic sheet would take the nearer
+    image of a far-apart pair, a free one never does."""
+    P = prob(n1, n2, cutoff=rc)
+    z, w = rr.random_state(n1, n2, seed=seed, height=0.2)
+    _, _, gam, _ = oracle.surface(P, z, w)
+    ref, count = brute_free_cutoff(n1, n2, z, gam, P.eps, rc)
+    assert 0 < count < (n1 * n2) ** 2
+    assert relerr(oracle.br_velocity(P, z, w), ref) < 1e-13
+
+
+def test_free_cutoff_beyond_the_diameter_is_the_exact_sum():
+    """Once rc exceeds every pair distance the cutoff sum is the exact free
+    sum: same terms, same order."""
+    n = 12
+    z, w = rr.random_state(n, n, seed=9, height=0.2)
+    z[0] += 5.0                          # far outside the period cell: nothing wraps
+    exact = oracle.br_velocity(prob(n), z, w)
+    assert relerr(oracle.br_velocity(prob(n, cutoff=3.5), z, w), exact) < 1e-15
+
+
+def test_free_cutoff_rhs_and_steps_run():
+    n = 12
+    P = prob(n, cutoff=0.6, dt=1e-3)
+    z, _ = rr.single_mode(n, n, 0.05)
+    w = rr.synthetic_vorticity(n, n, seed=10, sigma=0.02)
+    z1, w1 = oracle.rk3(P, z, w, 2)
+    assert np.all(np.isfinite(z1)) and np.all(np.isfinite(w1))
+    assert not np.array_equal(w1, w)
+
+
 def test_free_rejects_unsupported():
     z, w = rr.random_state(8, 8, seed=5)
-    for kw in ({"images": 1}, {"cutoff": 0.3}, {"model": 1}):
+    for kw in ({"images": 1}, {"model": 1}, {"cutoff": -0.1}):
         with pytest.raises(ValueError):
             oracle.br_velocity(prob(8, **kw), z, w)

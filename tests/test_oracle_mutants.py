@@ -59,6 +59,8 @@ MUTANTS = {
                        "    return i == n ? 4.0 * g0 - 6.0 * g1 + 4.0 * g2 - 2.0 * g3"),
     "free_images_kept": ("int k1 = axis_images(i1, j1, P->boundary == 1 ? -n1 : n1, s1, c1);",
                          "int k1 = axis_images(i1, j1, n1, s1, c1);"),
+    "free_cutoff_images_kept": ("const double S1 = free_sheet ? 0.0 : nearbyint(d1 / L1);",
+                                "const double S1 = nearbyint(d1 / L1);"),
     "rk3_stage3_weights": ("double y3 = (1.0 / 3.0) * y0[k] + (2.0 / 3.0) * (y2[k] + dt * F[k]);",
                            "double y3 = (1.0 / 2.0) * y0[k] + (1.0 / 2.0) * (y2[k] + dt * F[k]);"),
 }
