@@ -39,12 +39,14 @@
  *              r_a = (z_i,a - z_j,a) - S_a L_a, included iff
  *              r1*r1 + r2*r2 + r3*r3 < rc*rc (evaluated in that order in
  *              double), weight 1, no ties, rc <= 0.45 min(L1, L2), K = 0;
+ *              on a free sheet S_a = 0 (r = z_i - z_j) and any rc > 0;
  *   free sheet with boundary = ZM_BOUNDARY_FREE (sec. 3.1, BoundaryCondition:
  *              non-periodic values are extrapolated into the boundary cells)
  *              the stencils take ghost values from a cubic extrapolation,
  *              g(-1) = 4 g0 - 6 g1 + 4 g2 - g3, g(-2) = 10 g0 - 20 g1 + 15 g2
  *              - 4 g3 (and mirrored at the far end), for z, w and V, and
- *              the BR sum has no images and no ties (r = z_i - z_j);
+ *              the BR sum has no images and no ties (r = z_i - z_j),
+ *              exact or with a cutoff;
  *   low order  with model = ZM_MODEL_LOW the BR sum is replaced by its
  *              flat-sheet approximation (sec. 2: the low-order solver uses
  *              FFTs for the BR integral): u = 1/2 (R1 w1 + R2 w2) n^ with
@@ -130,11 +132,11 @@ typedef struct zm_params {
                                   K = 0; sides powers of two <= 4096; single
                                   contexts only)                               */
     double   cutoff;           /* 0: exact all-pairs BR; > 0: cutoff BR with
-                                  this 3D distance (FP64 only, K = 0,
-                                  <= 0.45 min(L1, L2); single contexts only)  */
+                                  this 3D distance (FP64 only, K = 0; on a
+                                  periodic sheet <= 0.45 min(L1, L2); single
+                                  contexts only)                               */
     int32_t  boundary;         /* ZM_BOUNDARY_PERIODIC or ZM_BOUNDARY_FREE (free:
-                                  high order, exact BR, K = 0; single contexts
-                                  only)                                        */
+                                  high order, K = 0; single contexts only)     */
     int32_t  reserved;         /* must be 0                                     */
 } zm_params;
 
@@ -227,8 +229,10 @@ zm_status zm_profile_read(zm_ctx *ctx, zm_kernel_stats *out);
 /* ---- cutoff solver ---------------------------------------------------------- */
 /*
  * A context with params.cutoff = rc > 0 evaluates the BR velocity with the
- * cutoff solver: points are binned into a periodic grid of cells of side
- * >= rc / cells_per_cutoff in x and y (z unbinned), sorted by cell (stable,
+ * cutoff solver: points are binned into a grid of cells of side
+ * >= rc / cells_per_cutoff in x and y over the period cell [-L_a/2, L_a/2)
+ * (z unbinned; periodic sheet: coordinates wrap; free sheet: cells clamp to
+ * the box, so points that left it fill the edge cells), sorted by cell (stable,
  * so the source order and every result are deterministic), and each target
  * visits the cells within cells_per_cutoff of its own.  With timing enabled
  * (zm_profile_enable) the pair kernel also counts the pairs it tested and

@@ -1,6 +1,7 @@
 // Cutoff Birkhoff-Rott solver: the desingularised BR sum restricted to the
-// sources whose nearest periodic image lies within a 3D distance rc of the
-// target (the paper's cutoff-based approximate integral, sec. 3.2.2).  The
+// sources whose nearest periodic image (on a free sheet: the source itself)
+// lies within a 3D distance rc of the target (the paper's cutoff-based
+// approximate integral, sec. 3.2.2).  The
 // paper finds neighbours with a spatial search library over a 3D spatial
 // mesh; on one GPU a periodic cell grid rebuilt every evaluation does the
 // same job with a handful of kernels:
@@ -47,10 +48,23 @@ __host__ __device__ inline int cell_key(const CutGrid& g, int cx, int cy)
     return ((by * g.nb1 + bx) * g.B + ly) * g.B + lx;
 }
 
-// Wrap count k (x - k L lies in the period cell [x0, x0 + L)) and the cell
-// of the wrapped coordinate, clamped against rounding at the cell edges.
-__device__ inline void wrap_cell(double x, double x0, double L, double cw, int nc, int& k, int& c)
+// Periodic grid: wrap count k (x - k L lies in the period cell [x0, x0 + L))
+// and the cell of the wrapped coordinate, clamped against rounding at the
+// cell edges.  Free sheet: k = 0 and the cell of x itself, clamped to the
+// box [0, nc) (in double, before the conversion, so that any x, even one far
+// outside the box, gives an index in range).  Clamping never increases the
+// cell distance of two points, so every pair within rc still lies within m
+// cells of each other; the edge cells only get fuller once the sheet has
+// rolled out of the box.
+__device__ inline void wrap_cell(bool periodic, double x, double x0, double L, double cw, int nc,
+                                 int& k, int& c)
 {
+    if (!periodic) {
+        const double f = floor((x - x0) / cw);
+        k = 0;
+        c = (int)fmin(fmax(f, 0.0), (double)(nc - 1));
+        return;
+    }
     const double f = floor((x - x0) / L);
     k = (int)f;
     const double xw = x - f * L;
@@ -65,8 +79,8 @@ __global__ __launch_bounds__(kThreads) void k_cut_keys(Mesh m, CutGrid g, const 
     const int p = blockIdx.x * kThreads + threadIdx.x;
     if (p >= m.N) return;
     int kx, ky, cx, cy;
-    wrap_cell(z[p], g.x0, g.L1, g.cw1, g.nc1, kx, cx);
-    wrap_cell(z[m.N + p], g.y0, g.L2, g.cw2, g.nc2, ky, cy);
+    wrap_cell(g.periodic, z[p], g.x0, g.L1, g.cw1, g.nc1, kx, cx);
+    wrap_cell(g.periodic, z[m.N + p], g.y0, g.L2, g.cw2, g.nc2, ky, cy);
     keys[p] = (unsigned)cell_key(g, cx, cy);
     vals[p] = (unsigned)p;
 }
@@ -216,8 +230,8 @@ __global__ __launch_bounds__(kThreads) void k_cut_gather(Mesh m, CutGrid g, cons
     const int p = (int)order[i];
     const double x = z[p], y = z[N + p];
     int kx, ky, cx, cy;
-    wrap_cell(x, g.x0, g.L1, g.cw1, g.nc1, kx, cx);
-    wrap_cell(y, g.y0, g.L2, g.cw2, g.nc2, ky, cy);
+    wrap_cell(g.periodic, x, g.x0, g.L1, g.cw1, g.nc1, kx, cx);
+    wrap_cell(g.periodic, y, g.y0, g.L2, g.cw2, g.nc2, ky, cy);
     double* r = src + (size_t)i * 8;
     r[0] = x;
     r[1] = y;
@@ -240,7 +254,9 @@ __global__ __launch_bounds__(kThreads) void k_cut_gather(Mesh m, CutGrid g, cons
 // registers: no LDS, no barriers.  A source in raw cell column cx_raw
 // (before wrapping) is the image shifted by wx = floor(cx_raw / nc1)
 // periods, so the image shift of the pair is S = k_i + wx - k_j (and the
-// same along y).
+// same along y).  On a free sheet nothing wraps: cells outside the grid are
+// skipped, every wrap count is 0 and S = 0, so r = z_i - z_j exactly (the
+// wave of a row outside the grid still writes its zero partial sums).
 constexpr int kCutThreads = 64;
 
 template <bool COUNT>
@@ -262,6 +278,7 @@ __global__ __launch_bounds__(kCutThreads) void k_cut_pairs(Mesh m, CutGrid g,
     const int bx = blk % g.nb1, by = blk / g.nb1;
     const int cy_raw = by * g.B - g.m + row;
     const int wy = floordiv(cy_raw, g.nc2), cy = cy_raw - wy * g.nc2;
+    const bool row_in = g.periodic || wy == 0;
     unsigned long long tested = 0, accepted = 0;
 
     // chunks of 64 targets, blockIdx.z, blockIdx.z + chunks, ...
@@ -274,6 +291,7 @@ __global__ __launch_bounds__(kCutThreads) void k_cut_pairs(Mesh m, CutGrid g,
         for (int col = 0; col < g.slots; ++col) {
             const int cx_raw = bx * g.B - g.m + col;
             const int wx = floordiv(cx_raw, g.nc1), cx = cx_raw - wx * g.nc1;
+            if (!row_in || (!g.periodic && wx != 0)) continue;   // wave-uniform
             const int key = cell_key(g, cx, cy);
             const int s0 = start[key], s1 = end[key];
             const double Kx = kxi + (double)wx, Ky = kyi + (double)wy;
@@ -326,10 +344,12 @@ inline unsigned grid_for(long n) { return (unsigned)((n + kThreads - 1) / kThrea
 
 }  // namespace
 
-CutGrid make_cut_grid(int n1, int n2, double L1, double L2, double rc)
+CutGrid make_cut_grid(int n1, int n2, double L1, double L2, double rc, bool periodic)
 {
     CutGrid g;
     g.m = 2;
+    g.periodic = periodic ? 1 : 0;
+    g.pad_ = 0;
     // cells no smaller than rc / m (with a margin against rounding at the
     // cell edges) and no smaller than the mean mesh spacing
     const double grow = 1.0 + 1e-9;

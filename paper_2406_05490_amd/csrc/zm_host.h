@@ -43,7 +43,8 @@ inline bool has_cutoff(const zm_params& p) { return p.cutoff > 0.0; }
 
 inline CutGrid cut_grid_of(const zm_params& p)
 {
-    return make_cut_grid(p.n1, p.n2, p.period1, p.period2, p.cutoff);
+    return make_cut_grid(p.n1, p.n2, p.period1, p.period2, p.cutoff,
+                         p.boundary != ZM_BOUNDARY_FREE);
 }
 
 inline Layout make_layout(const zm_params& p, const zm::PairShape& sh)
@@ -108,14 +109,14 @@ inline const char* validate(const zm_params* p)
         return "the low-order model takes no cutoff and no image layers";
     if (p->boundary != ZM_BOUNDARY_PERIODIC && p->boundary != ZM_BOUNDARY_FREE)
         return "unknown boundary";
-    if (p->boundary == ZM_BOUNDARY_FREE &&
-        (p->model != ZM_MODEL_HIGH || p->cutoff != 0.0 || p->image_layers != 0))
-        return "a free sheet needs the high-order model, no cutoff and no image layers";
+    if (p->boundary == ZM_BOUNDARY_FREE && (p->model != ZM_MODEL_HIGH || p->image_layers != 0))
+        return "a free sheet needs the high-order model and no image layers";
     if (p->reserved != 0) return "reserved must be 0";
     if (!(std::isfinite(p->cutoff) && p->cutoff >= 0.0)) return "cutoff must be finite and >= 0";
     if (p->cutoff > 0.0) {
-        if (p->cutoff > 0.45 * p->period1 || p->cutoff > 0.45 * p->period2)
-            return "cutoff must be <= 0.45 min(period1, period2)";
+        if (p->boundary == ZM_BOUNDARY_PERIODIC &&
+            (p->cutoff > 0.45 * p->period1 || p->cutoff > 0.45 * p->period2))
+            return "cutoff must be <= 0.45 min(period1, period2) on a periodic sheet";
         if (p->image_layers != 0) return "cutoff needs image_layers = 0";
     }
     return nullptr;

@@ -90,13 +90,15 @@ struct CutGrid {
     int slots;           // B + 2m
     int chunks;          // waves per (target block, row): ~ mean 64-target chunks per block
     int sort_blocks;     // workgroups of the radix-sort passes
+    int periodic;        // 1: cells wrap with the period; 0 (free sheet): cells clamp to the box
+    int pad_;
     double x0, y0;       // cell-grid origin (-L1/2, -L2/2)
     double L1, L2;
     double cw1, cw2;     // cell sides
     double rc2;          // rc * rc
 };
 
-CutGrid make_cut_grid(int n1, int n2, double L1, double L2, double rc);
+CutGrid make_cut_grid(int n1, int n2, double L1, double L2, double rc, bool periodic);
 
 // Device buffers of one cutoff evaluation (all in the caller's workspace).
 struct CutBuffers {

@@ -56,8 +56,8 @@ def test_struct_layout_matches_header():
     dict(cutoff=0.95), dict(cutoff=0.3, image_layers=1), dict(cutoff=0.3, precision=1),
     dict(model=2), dict(model=1, cutoff=0.3), dict(model=1, image_layers=1),
     dict(model=1, precision=1), dict(model=1, n1=24),
-    dict(boundary=2), dict(boundary=1, cutoff=0.3), dict(boundary=1, model=1),
-    dict(boundary=1, image_layers=1),
+    dict(boundary=2), dict(boundary=1, model=1), dict(boundary=1, image_layers=1),
+    dict(boundary=1, cutoff=-0.5),
 ])
 def test_workspace_bytes_rejects_invalid(bad):
     kw = dict(n1=16, n2=16, eps=1 / 16)
@@ -75,6 +75,14 @@ def test_cutoff_workspace_and_status():
     assert st == zm.ZM_ERR_UNSUPPORTED and "FP64" in msg
     st, _, msg = _create(zm.Params(64, 64, eps=1 / 64, cutoff=0.95), None, 0)
     assert st == zm.ZM_ERR_INVALID_ARG and "cutoff" in msg
+
+
+def test_free_sheet_cutoff_takes_any_radius():
+    """A free sheet has no images, so the cutoff is not bounded by the period."""
+    a = zm.workspace_bytes(zm.Params(64, 64, eps=1 / 64, boundary=zm.ZM_BOUNDARY_FREE, cutoff=0.3))
+    b = zm.workspace_bytes(zm.Params(64, 64, eps=1 / 64, boundary=zm.ZM_BOUNDARY_FREE, cutoff=5.0))
+    assert a > 0 and b > 0
+    assert zm.workspace_bytes(zm.Params(64, 64, eps=1 / 64, cutoff=5.0)) == 0
 
 
 def test_low_order_workspace_and_status():

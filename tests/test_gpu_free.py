@@ -105,3 +105,119 @@ def test_free_repeat_bitwise(gpu):
     p = params(n1, n2)
     z, w = rr.random_state(n1, n2, seed=12, height=0.05)
     assert np.array_equal(gpu_u(p, z, w, gpu), gpu_u(p, z, w, gpu))
+
+
+# ---- cutoff BR on a free sheet ---------------------------------------------
+
+def cut_params(n1, n2, rc, **kw):
+    return params(n1, n2, cutoff=rc, **kw)
+
+
+def ocut(p):
+    P = oparams(p)
+    P.cutoff = p.cutoff
+    return P
+
+
+def free_pairs_within(z, rc):
+    """Pairs (i, j) with |z_i - z_j| < rc (no images), by the definition's
+    expression (numpy, all pairs)."""
+    total = 0
+    for i in range(z.shape[1]):
+        r1, r2, r3 = z[0, i] - z[0], z[1, i] - z[1], z[2, i] - z[2]
+        total += int(np.count_nonzero(r1 * r1 + r2 * r2 + r3 * r3 < rc * rc))
+    return total
+
+
+@pytest.mark.parametrize("n1,n2,rc,shift,seed", [
+    (24, 24, 0.3, 0.0, 20), (40, 24, 0.45, 0.6, 21), (17, 33, 0.2, -0.9, 22),
+    (64, 64, 0.15, 0.0, 23), (33, 9, 1.3, 0.3, 24), (48, 40, 4.0, 0.0, 25),
+])
+def test_free_cutoff_matches_oracle(gpu, n1, n2, rc, shift, seed):
+    """Shifted states put part of the sheet outside the cell box (clamped
+    edge cells); rc = 1.3 exceeds half the side, rc = 4 the whole sheet."""
+    p = cut_params(n1, n2, rc)
+    z, w = rr.random_state(n1, n2, seed=seed, height=0.1)
+    z[0] += shift
+    z[1] -= 0.5 * shift
+    assert relerr(gpu_u(p, z, w, gpu), oracle.br_velocity(ocut(p), z, w)) < TOL64
+
+
+def test_free_cutoff_accepted_pair_count_exact(gpu):
+    import paper_2406_05490_amd as zm
+    import torch
+    n1, n2, rc = 40, 32, 0.35
+    p = cut_params(n1, n2, rc)
+    z, w = rr.random_state(n1, n2, seed=26, height=0.1)
+    z[0] += 0.7                          # a quarter of the sheet beyond the box
+    ctx = zm.Context(p)
+    ctx.profile_enable(True)
+    ud = torch.empty(3 * p.n, dtype=torch.float64, device=gpu)
+    ctx.br_velocity(to_dev(z, gpu), to_dev(w, gpu), ud)
+    torch.cuda.synchronize()
+    info = ctx.cutoff_info()
+    assert info.pairs_accepted == free_pairs_within(z, rc)
+    assert info.pairs_tested >= info.pairs_accepted
+
+
+def test_free_cutoff_beyond_diameter_equals_exact(gpu):
+    n = 48
+    z, w = rr.random_state(n, n, seed=27, height=0.1)
+    exact = gpu_u(params(n, n), z, w, gpu)
+    assert relerr(gpu_u(cut_params(n, n, 3.0), z, w, gpu), exact) < TOL64
+
+
+def test_free_cutoff_converges_to_exact(gpu):
+    """Far-field contributions: the cutoff velocity of an evolved free sheet
+    approaches the exact one monotonically as rc grows."""
+    import paper_2406_05490_amd as zm
+    import torch
+    n = 64
+    p = params(n, n, dt=5e-3)
+    z, _ = rr.single_mode(n, n, 0.05)
+    w = np.zeros((2, n * n))
+    ctx = zm.Context(p)
+    ctx.init_state(to_dev(z, gpu), to_dev(w, gpu))
+    ctx.step(40)
+    z1 = torch.empty(3 * p.n, dtype=torch.float64, device=gpu)
+    w1 = torch.empty(2 * p.n, dtype=torch.float64, device=gpu)
+    ctx.get_state(z1, w1)
+    torch.cuda.synchronize()
+    zs, ws = to_host(z1, (3, p.n)), to_host(w1, (2, p.n))
+    exact = gpu_u(p, zs, ws, gpu)
+    errs = [relerr(gpu_u(cut_params(n, n, rc), zs, ws, gpu), exact) for rc in (0.2, 0.4, 0.8, 1.6)]
+    assert all(a > b for a, b in zip(errs, errs[1:]))
+    assert errs[-1] < 0.05
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_free_cutoff_steps_match_oracle(gpu, graph):
+    import paper_2406_05490_amd as zm
+    import torch
+    n = 24
+    p = cut_params(n, n, 0.5, dt=2e-3, flags=zm.ZM_FLAG_GRAPH if graph else 0)
+    z, _ = rr.single_mode(n, n, 0.05)
+    w = rr.synthetic_vorticity(n, n, seed=28, sigma=0.02)
+    ctx = zm.Context(p)
+    ctx.init_state(to_dev(z, gpu), to_dev(w, gpu))
+    ctx.step(3)
+    z1 = torch.empty(3 * p.n, dtype=torch.float64, device=gpu)
+    w1 = torch.empty(2 * p.n, dtype=torch.float64, device=gpu)
+    ctx.get_state(z1, w1)
+    torch.cuda.synchronize()
+    oz, ow = oracle.rk3(ocut(p), z, w, 3)
+    assert relerr(to_host(z1, (3, p.n)) - z, oz - z) < 1e-11
+    assert relerr(to_host(w1, (2, p.n)), ow) < 1e-11
+
+
+def test_free_cutoff_256_sampled(gpu):
+    n = 256
+    p = cut_params(n, n, 0.25)
+    z, _ = rr.single_mode(n, n, 0.05)
+    z[0] *= 1.1                          # the outer columns lie beyond the box
+    w = rr.synthetic_vorticity(n, n, seed=29)
+    u = gpu_u(p, z, w, gpu)
+    idx = rr.sample_targets(n * n, 256, seed=30)
+    idx = np.unique(np.concatenate([idx, [0, n - 1, n * (n - 1), n * n - 1]]))
+    ref = oracle.br_velocity(ocut(p), z, w, targets=idx)
+    assert relerr(u[:, idx], ref) < TOL64
