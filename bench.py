@@ -52,6 +52,9 @@ def parse():
                     help="only measure the cutoff solver (paper workloads, accuracy curve)")
     ap.add_argument("--low-order-only", action="store_true",
                     help="only measure the low-order (FFT) model at 4096 x 4096")
+    ap.add_argument("--free-only", action="store_true",
+                    help="only measure the non-periodic single-mode case (exact, cutoff, "
+                         "far-field check)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of this many MiB (counter calibration)")
     return ap.parse_args()
@@ -259,6 +262,84 @@ def cutoff_section(zm, torch):
                       "speedup_vs_exact": exact_ms / r["eval_ms"],
                       "accepted_fraction_of_all_pairs": r["accepted_fraction_of_all_pairs"]})
     out["accuracy_vs_cutoff_256"] = {"exact_eval_ms": exact_ms, "curve": curve}
+    return out
+
+
+def free_section(zm, torch):
+    """Non-periodic single-mode interface (the paper's second test case:
+    extrapolated ghosts, no images):
+      exact256      RK3 steps at 256 x 256, FP64, exact BR: ms/step, pairs/s,
+                    pair-kernel TFLOP/s;
+      cutoff512     one cutoff BR evaluation at 512 x 512, rc = 1/6 (0.5 of a
+                    6-wide domain scaled to the width-2 sheet);
+      far_field128  the far-field check: 128 x 128 from a 0.05 single mode,
+                    eps = 2h = 1/32 (with eps = h/2 the unfiltered sheet
+                    reaches its singularity before t = 2 at this mesh),
+                    A = 0.5, g = 1, dt = 5e-3, 400 steps (t = 2) with the exact
+                    sum and with cutoffs 0.15 .. 1.2; peak-to-peak z3 of each
+                    run and the deviation of every point from the exact
+                    trajectory, in the edge band (|alpha_a| > 0.75) and inside."""
+    dev = torch.device("cuda:0")
+    out = {}
+    n, steps = 256, 20
+    z, _ = rr.single_mode(n, n, 0.05)
+    w = rr.synthetic_vorticity(n, n, seed=3)
+    p = zm.Params(n, n, eps=1.0 / n, dt=1e-3, boundary=zm.ZM_BOUNDARY_FREE)
+    ctx = zm.Context(p)
+    ctx.init_state(torch.from_numpy(z.ravel()).to(dev), torch.from_numpy(w.ravel()).to(dev))
+    ctx.step(1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.step(steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ctx.profile_enable(True)
+    ctx.step(1)
+    st = ctx.profile_read()
+    ppe = ctx.launch_info().pairs_per_eval
+    pair_ms = st["pairs"][1] / max(st["pairs"][0], 1)
+    out["exact256"] = {"mesh": f"{n}x{n}", "steps": steps, "ms_per_step": wall / steps * 1e3,
+                       "pairs_per_s": 3 * ppe * steps / wall, "pair_kernel_ms": pair_ms,
+                       "pair_kernel_tflops": FLOPS_PER_PAIR * ppe / (pair_ms / 1e3) / 1e12}
+    out["exact256"]["pair_kernel_frac_of_fp64_peak"] = (out["exact256"]["pair_kernel_tflops"] /
+                                                         PEAK_TFLOPS["fp64"])
+    del ctx
+    n = 512
+    z, _ = rr.single_mode(n, n, 0.05)
+    w = rr.synthetic_vorticity(n, n, seed=2)
+    out["cutoff512"], _ = cutoff_eval(zm, torch, zm.Params(n, n, eps=1.0 / n, cutoff=1.0 / 6.0,
+                                                           boundary=zm.ZM_BOUNDARY_FREE), z, w)
+    n, steps = 128, 400
+    z, _ = rr.single_mode(n, n, 0.05)
+    w = np.zeros((2, n * n))
+    A1, A2 = rr.grid(n, n)
+    edge = ((np.abs(A1) > 0.75) | (np.abs(A2) > 0.75)).ravel()
+    runs = {}
+    for rc in (0.0, 0.15, 0.3, 0.6, 1.2):
+        p = zm.Params(n, n, eps=4.0 / n, dt=5e-3, cutoff=rc, boundary=zm.ZM_BOUNDARY_FREE)
+        ctx = zm.Context(p)
+        ctx.init_state(torch.from_numpy(z.ravel()).to(dev), torch.from_numpy(w.ravel()).to(dev))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.step(steps)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) / steps * 1e3
+        zd = torch.empty(3 * p.n, dtype=torch.float64, device=dev)
+        wd = torch.empty(2 * p.n, dtype=torch.float64, device=dev)
+        ctx.get_state(zd, wd)
+        runs[rc] = (zd.cpu().numpy().reshape(3, -1), ms)
+        del ctx
+    ze = runs[0.0][0]
+    curve = []
+    for rc, (zc, ms) in runs.items():
+        d = np.linalg.norm(zc - ze, axis=0)
+        curve.append({"cutoff": rc, "ms_per_step": ms,
+                      "z3_peak_to_peak": float(zc[2].max() - zc[2].min()),
+                      "dev_max": float(d.max()), "dev_mean_edge": float(d[edge].mean()),
+                      "dev_mean_inner": float(d[~edge].mean()),
+                      "finite": bool(np.all(np.isfinite(zc)))})
+    out["far_field128"] = {"mesh": f"{n}x{n}", "eps": 4.0 / n, "steps": steps, "t_end": steps * 5e-3,
+                           "runs": curve}
     return out
 
 
@@ -520,6 +601,9 @@ def main():
     if args.low_order_only:
         print(json.dumps({"low_order_4096": low_order_section(zm, torch)}), flush=True)
         return
+    if args.free_only:
+        print(json.dumps({"free_single_mode": free_section(zm, torch)}), flush=True)
+        return
     if args.tune_report:
         print(json.dumps({"tune_report": tune_report(zm, torch)}), flush=True)
         return
@@ -603,6 +687,7 @@ def main():
         out["periodic64_latency"] = small_mesh_latency(zm, torch)
         out["cutoff"] = cutoff_section(zm, torch)
         out["low_order_4096"] = low_order_section(zm, torch)
+        out["free_single_mode"] = free_section(zm, torch)
     if args.serve_seconds > 0:
         out["serving"] = serving(zm, torch, window_s=args.serve_seconds)
     if args.cpu_seconds > 0:
