@@ -47,7 +47,8 @@ class Problem:
     period1: float = 2.0
     period2: float = 2.0
     cutoff: float = 0.0       # > 0: cutoff BR solver (3D distance)
-    model: int = 0            # 0: high order (BR sum), 1: low order (FFT velocity)
+    model: int = 0            # 0: high order (BR sum), 1: low order (FFT velocity),
+                              # 2: medium order (BR moves the sheet, FFT velocity in V)
     boundary: int = 0         # 0: periodic, 1: free (extrapolated ghosts, no images)
 
     def c(self) -> _Problem:

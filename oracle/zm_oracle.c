@@ -53,6 +53,11 @@
  *                                  with a cutoff: the exact free sum once rc
  *                                  exceeds the sheet's diameter, brute-force
  *                                  pair counts).
+ *   medium order (model 2)      : built from pinned parts (z_t is the
+ *                                  high-order one, w_t the low-order one,
+ *                                  bitwise); which velocity enters where is
+ *                                  a reading of the paper -- parity
+ *                                  unpinned for the coupling itself.
  *   low-order velocity (model 1): pinned (flat-sheet symbol -|k|/2 exactly,
  *                                  a library FFT on random fields, the
  *                                  Nyquist rule, the linear growth rate
@@ -75,7 +80,9 @@
 typedef struct {
     int32_t n1, n2;          /* mesh points along alpha_1, alpha_2           */
     int32_t images;          /* K >= 0 extra periodic image layers           */
-    int32_t model;           /* 0: high order (BR sum), 1: low order (FFT)   */
+    int32_t model;           /* 0: high order (BR sum), 1: low order (FFT),
+                                2: medium order (BR moves the sheet, the FFT
+                                velocity drives the vorticity)              */
     double period1, period2; /* L1, L2 (parameter and x/y period)            */
     double atwood;           /* A                                            */
     double gravity;          /* g (gravity is -g e3)                         */
@@ -419,6 +426,8 @@ int zmo_br_from_gamma(const zmo_problem *P, const double *z, const double *gamma
     return bad ? -1 : 0;
 }
 
+/* The velocity that moves the sheet: the BR sum for the high- and
+ * medium-order models, the flat-sheet FFT velocity for the low-order one. */
 int zmo_br_velocity(const zmo_problem *P, const double *z, const double *w,
                     int64_t ntargets, const int64_t *targets, double *u, int nthreads)
 {
@@ -428,7 +437,7 @@ int zmo_br_velocity(const zmo_problem *P, const double *z, const double *w,
         (void)set_threads(nthreads);
         return low_order_velocity(P, z, w, u);
     }
-    if (P->model != 0) return -1;
+    if (P->model != 0 && !(P->model == 2 && P->boundary == 0)) return -1;
     const size_t N = (size_t)P->n1 * P->n2;
     double *buf = (double *)malloc(sizeof(double) * 10 * N);
     if (!buf) return -1;
@@ -533,7 +542,12 @@ static double bernoulli(const zmo_problem *P, double u1, double u2, double u3, d
 }
 
 /* F(z, w) = (z_t, w_t) with z_t = u (BR velocity) and
- * w_t = (D1 V, D2 V) + nu * Lap(w).  zt: 3 planes, wt: 2 planes. */
+ * w_t = (D1 V, D2 V) + nu * Lap(w).  zt: 3 planes, wt: 2 planes.
+ * Low order: u is the flat-sheet FFT velocity throughout.  Medium order
+ * (sec. 2: it couples the FFT solver with the far-field BR solver, and uses
+ * the FFTs for the change in vorticity; periodic sheets only, as the FFT
+ * is): z_t is the BR velocity (exact or cutoff) and the |u|^2 of V is that
+ * of the FFT velocity. */
 int zmo_rhs(const zmo_problem *P, const double *z, const double *w,
             double *zt, double *wt, int nthreads)
 {
@@ -541,22 +555,31 @@ int zmo_rhs(const zmo_problem *P, const double *z, const double *w,
     const int n1 = P->n1, n2 = P->n2;
     const size_t N = (size_t)n1 * n2;
     const double h1 = P->period1 / n1, h2 = P->period2 / n2;
-    double *buf = (double *)malloc(sizeof(double) * 13 * N);
+    double *buf = (double *)malloc(sizeof(double) * 16 * N);
     if (!buf) return -1;
     double *t1 = buf, *t2 = buf + 3 * N, *gamma = buf + 6 * N, *q = buf + 9 * N;
-    double *V = buf + 10 * N, *lap = buf + 11 * N;
+    double *V = buf + 10 * N, *lap = buf + 11 * N, *ulo = buf + 13 * N;
     zmo_surface(P, z, w, t1, t2, gamma, q);
     int rc;
+    const double *uv = zt;   /* the velocity in V */
     if (P->model == 1) {
         if (P->cutoff != 0.0 || P->images != 0 || P->boundary != 0) { free(buf); return -1; }
         (void)set_threads(nthreads);
         rc = low_order_velocity(P, z, w, zt);
+    } else if (P->model == 2) {
+        if (P->boundary != 0) { free(buf); return -1; }
+        rc = zmo_br_from_gamma(P, z, gamma, 0, NULL, zt, nthreads);
+        if (!rc) {
+            (void)set_threads(nthreads);
+            rc = low_order_velocity(P, z, w, ulo);
+        }
+        uv = ulo;
     } else {
         rc = P->model == 0 ? zmo_br_from_gamma(P, z, gamma, 0, NULL, zt, nthreads) : -1;
     }
     if (rc) { free(buf); return rc; }
     for (size_t p = 0; p < N; ++p)
-        V[p] = bernoulli(P, zt[p], zt[N + p], zt[2 * N + p], q[p], z[2 * N + p]);
+        V[p] = bernoulli(P, uv[p], uv[N + p], uv[2 * N + p], q[p], z[2 * N + p]);
     for (int i2 = 0; i2 < n2; ++i2)
         for (int i1 = 0; i1 < n1; ++i1) {
             size_t p = (size_t)i2 * n1 + i1;

@@ -61,6 +61,7 @@ MUTANTS = {
                          "int k1 = axis_images(i1, j1, n1, s1, c1);"),
     "free_cutoff_images_kept": ("const double S1 = free_sheet ? 0.0 : nearbyint(d1 / L1);",
                                 "const double S1 = nearbyint(d1 / L1);"),
+    "medium_v_from_br": ("        uv = ulo;", "        uv = zt;"),
     "rk3_stage3_weights": ("double y3 = (1.0 / 3.0) * y0[k] + (2.0 / 3.0) * (y2[k] + dt * F[k]);",
                            "double y3 = (1.0 / 2.0) * y0[k] + (1.0 / 2.0) * (y2[k] + dt * F[k]);"),
 }
@@ -87,6 +88,7 @@ def test_mutant_is_caught(name, source, tmp_path):
                         os.path.join(ROOT, "tests", "test_oracle_pins.py"),
                         os.path.join(ROOT, "tests", "test_oracle_cutoff.py"),
                         os.path.join(ROOT, "tests", "test_oracle_loworder.py"),
-                        os.path.join(ROOT, "tests", "test_oracle_free.py")],
+                        os.path.join(ROOT, "tests", "test_oracle_free.py"),
+                        os.path.join(ROOT, "tests", "test_oracle_medium.py")],
                        cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
     assert r.returncode == 1, f"mutant {name} passed every pin:\n{r.stdout[-2000:]}"
