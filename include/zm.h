@@ -54,6 +54,12 @@
  *              periodic mesh, symbol i k_a / |k| on exp(i k.alpha),
  *              k_a = 2 pi m_a / L_a, zero at k = 0 and, along axis a, at the
  *              unpaired mode m_a = n_a / 2;
+ *   medium     with model = ZM_MODEL_MEDIUM (sec. 2: the medium order
+ *              couples the FFT solver with the BR solver; sec. 6: it uses
+ *              the FFTs for the change in vorticity) z_t = u is the BR
+ *              velocity (exact or cutoff) and the |u|^2 of V is that of the
+ *              low-order FFT velocity; periodic sheets, sides powers of two
+ *              <= 4096; zm_br_velocity returns the BR velocity;
  *   q          |gamma|^2 / |T1 x T2|^2;
  *   V          A (|u|^2 - q/4 - 2 g z3);
  *   F(z, w)    z_t = u,  w_t = (D_1 V, D_2 V) + nu Lap(w);
@@ -102,6 +108,7 @@ typedef int32_t zm_status;
 /* ---- model order ----------------------------------------------------------- */
 #define ZM_MODEL_HIGH  0  /* u from the Birkhoff-Rott sum (exact or cutoff)      */
 #define ZM_MODEL_LOW   1  /* u = 1/2 (R1 w1 + R2 w2) n^ by FFT (low order)       */
+#define ZM_MODEL_MEDIUM 2 /* z_t from the BR sum, |u|^2 in V from the FFT one   */
 
 /* ---- boundary of the sheet -------------------------------------------------- */
 #define ZM_BOUNDARY_PERIODIC 0  /* doubly periodic (images, seam correction)    */
@@ -128,9 +135,11 @@ typedef struct zm_params {
     int32_t  precision;        /* ZM_FP64 or ZM_FP32_PAIRS                      */
     int32_t  image_layers;     /* K >= 0 extra periodic image layers            */
     uint32_t flags;            /* ZM_FLAG_*                                     */
-    int32_t  model;            /* ZM_MODEL_HIGH or ZM_MODEL_LOW (FP64, no cutoff,
+    int32_t  model;            /* ZM_MODEL_HIGH, ZM_MODEL_LOW (FP64, no cutoff,
                                   K = 0; sides powers of two <= 4096; single
-                                  contexts only)                               */
+                                  contexts only) or ZM_MODEL_MEDIUM (periodic,
+                                  sides powers of two <= 4096; single contexts
+                                  only)                                        */
     double   cutoff;           /* 0: exact all-pairs BR; > 0: cutoff BR with
                                   this 3D distance (FP64 only, K = 0; on a
                                   periodic sheet <= 0.45 min(L1, L2); single

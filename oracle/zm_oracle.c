@@ -544,10 +544,10 @@ static double bernoulli(const zmo_problem *P, double u1, double u2, double u3, d
 /* F(z, w) = (z_t, w_t) with z_t = u (BR velocity) and
  * w_t = (D1 V, D2 V) + nu * Lap(w).  zt: 3 planes, wt: 2 planes.
  * Low order: u is the flat-sheet FFT velocity throughout.  Medium order
- * (sec. 2: it couples the FFT solver with the far-field BR solver, and uses
- * the FFTs for the change in vorticity; periodic sheets only, as the FFT
- * is): z_t is the BR velocity (exact or cutoff) and the |u|^2 of V is that
- * of the FFT velocity. */
+ * (sec. 2: it couples the FFT solver with the far-field BR solver; sec. 6:
+ * it uses the FFTs for the change in vorticity; periodic sheets only, as the
+ * FFT is): z_t is the BR velocity (exact or cutoff) and the |u|^2 of V is
+ * that of the FFT velocity. */
 int zmo_rhs(const zmo_problem *P, const double *z, const double *w,
             double *zt, double *wt, int nthreads)
 {

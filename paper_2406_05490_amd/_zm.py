@@ -25,6 +25,7 @@ ZM_FP64 = 0
 ZM_FP32_PAIRS = 1
 ZM_MODEL_HIGH = 0
 ZM_MODEL_LOW = 1
+ZM_MODEL_MEDIUM = 2
 ZM_BOUNDARY_PERIODIC = 0
 ZM_BOUNDARY_FREE = 1
 ZM_FLAG_CHECK_FINITE = 0x1

@@ -59,6 +59,7 @@ struct zm_ctx {
     zm::CutGrid cut{};
     zm::CutBuffers cb{};
     bool low = false;                       // low-order model (FFT velocity)
+    bool medium = false;                    // medium order: BR moves the sheet, FFT velocity in V
     zm::LowBuffers lb{};
 
     double* at(size_t off) { return reinterpret_cast<double*>(ws + off); }
@@ -107,7 +108,23 @@ hipError_t timed(zm_ctx* c, int kernel, F&& launch)
     return hipSuccess;
 }
 
-// u (3 planes) = BR velocity of (z, w); optionally V as well.
+// Medium order: the Bernoulli potential V from the FFT (flat-sheet)
+// velocity, after the BR sum has produced the sheet velocity (q from the
+// surface pass).  Nothing to do for the other models or without V.
+zm_status medium_potential(zm_ctx* c, const double* z, const double* w, double* V,
+                           hipStream_t stream)
+{
+    if (!c->medium || !V) return ZM_OK;
+    const double* q = c->at(c->layout.q);
+    hipError_t e = timed(c, ZM_KERNEL_FFT, [&] {
+        return zm::launch_low_velocity(c->mesh, z, w, q, c->lb, nullptr, V, stream);
+    });
+    if (e != hipSuccess) return hip_fail(c, e, "FFT velocity launch");
+    return ZM_OK;
+}
+
+// u (3 planes) = the velocity that moves the sheet (BR sum, or the FFT
+// velocity for the low-order model); optionally V as well.
 zm_status eval_velocity(zm_ctx* c, const double* z, const double* w, double* u, double* V,
                         hipStream_t stream)
 {
@@ -135,10 +152,11 @@ zm_status eval_velocity(zm_ctx* c, const double* z, const double* w, double* u, 
         });
         if (e != hipSuccess) return hip_fail(c, e, "cutoff pair kernel launch");
         e = timed(c, ZM_KERNEL_REDUCE, [&] {
-            return zm::launch_reduce(m, c->cut.slots, part, tie, q, z, u, V, stream, false);
+            return zm::launch_reduce(m, c->cut.slots, part, tie, q, z, u, c->medium ? nullptr : V,
+                                     stream, false);
         });
         if (e != hipSuccess) return hip_fail(c, e, "reduce kernel launch");
-        return ZM_OK;
+        return medium_potential(c, z, w, V, stream);
     }
     e = timed(c, ZM_KERNEL_PAIRS, [&] {
         return c->prm.precision == ZM_FP32_PAIRS
@@ -152,10 +170,11 @@ zm_status eval_velocity(zm_ctx* c, const double* z, const double* w, double* u, 
         if (e != hipSuccess) return hip_fail(c, e, "tie kernel launch");
     }
     e = timed(c, ZM_KERNEL_REDUCE, [&] {
-        return zm::launch_reduce(m, c->shape.splits, part, tie, q, z, u, V, stream, m.periodic != 0);
+        return zm::launch_reduce(m, c->shape.splits, part, tie, q, z, u, c->medium ? nullptr : V,
+                                 stream, m.periodic != 0);
     });
     if (e != hipSuccess) return hip_fail(c, e, "reduce kernel launch");
-    return ZM_OK;
+    return medium_potential(c, z, w, V, stream);
 }
 
 }  // namespace
@@ -169,6 +188,9 @@ size_t zm_workspace_bytes(const zm_params* params)
     if (params->model == ZM_MODEL_LOW &&
         (params->precision != ZM_FP64 || !zm::low_order_supported_side(params->n1) ||
          !zm::low_order_supported_side(params->n2)))
+        return 0;
+    if (params->model == ZM_MODEL_MEDIUM && (!zm::low_order_supported_side(params->n1) ||
+                                             !zm::low_order_supported_side(params->n2)))
         return 0;
     const zm::PairShape sh = zm::choose_pair_shape(params->n1, params->n2, params->precision);
     return make_layout(*params, sh).total;
@@ -189,6 +211,11 @@ zm_status zm_create(zm_ctx** out, const zm_params* params, void* d_workspace,
         (params->precision != ZM_FP64 || !zm::low_order_supported_side(params->n1) ||
          !zm::low_order_supported_side(params->n2))) {
         g_create_error = "the low-order model needs FP64 and sides that are powers of two <= 4096";
+        return ZM_ERR_UNSUPPORTED;
+    }
+    if (params->model == ZM_MODEL_MEDIUM && (!zm::low_order_supported_side(params->n1) ||
+                                             !zm::low_order_supported_side(params->n2))) {
+        g_create_error = "the medium-order model needs sides that are powers of two <= 4096";
         return ZM_ERR_UNSUPPORTED;
     }
     const zm::PairShape sh = zm::choose_pair_shape(params->n1, params->n2, params->precision);
@@ -217,8 +244,9 @@ zm_status zm_create(zm_ctx** out, const zm_params* params, void* d_workspace,
     c->ws = reinterpret_cast<char*>(d_workspace);
     std::memset(c->stats, 0, sizeof(c->stats));
     c->mesh = zm::make_mesh(*params);
-    if (params->model == ZM_MODEL_LOW) {
-        c->low = true;
+    if (params->model == ZM_MODEL_LOW || params->model == ZM_MODEL_MEDIUM) {
+        c->low = params->model == ZM_MODEL_LOW;
+        c->medium = params->model == ZM_MODEL_MEDIUM;
         char* ws = c->ws;
         c->lb.a = reinterpret_cast<double2*>(ws + L.lo_a);
         c->lb.b = reinterpret_cast<double2*>(ws + L.lo_b);

@@ -79,7 +79,7 @@ inline Layout make_layout(const zm_params& p, const zm::PairShape& sh)
     L.cut_bend = take(cut ? (size_t)g.nb1 * g.nb2 * sizeof(int) : 0);
     L.cut_src = take(cut ? 8 * N * d : 0);
     L.cut_counts = take(cut ? 2 * sizeof(unsigned long long) : 0);
-    const bool low = p.model == ZM_MODEL_LOW;
+    const bool low = p.model == ZM_MODEL_LOW || p.model == ZM_MODEL_MEDIUM;   // FFT buffers
     const size_t c16 = 2 * sizeof(double);
     L.lo_a = take(low ? N * c16 : 0);
     L.lo_b = take(low ? N * c16 : 0);
@@ -104,7 +104,8 @@ inline const char* validate(const zm_params* p)
     if (p->precision != ZM_FP64 && p->precision != ZM_FP32_PAIRS) return "unknown precision";
     if (p->image_layers < 0 || p->image_layers > kMaxImages) return "image_layers must be in [0, 16]";
     if (p->flags & ~(ZM_FLAG_CHECK_FINITE | ZM_FLAG_GRAPH)) return "unknown flag bits";
-    if (p->model != ZM_MODEL_HIGH && p->model != ZM_MODEL_LOW) return "unknown model";
+    if (p->model != ZM_MODEL_HIGH && p->model != ZM_MODEL_LOW && p->model != ZM_MODEL_MEDIUM)
+        return "unknown model";
     if (p->model == ZM_MODEL_LOW && (p->cutoff != 0.0 || p->image_layers != 0))
         return "the low-order model takes no cutoff and no image layers";
     if (p->boundary != ZM_BOUNDARY_PERIODIC && p->boundary != ZM_BOUNDARY_FREE)

@@ -11,7 +11,9 @@
 //   k_transpose    32 x 32 tiles through LDS
 //   k_riesz        S^ from c^(m) and conj(c^(-m)) (splits the two real
 //                  fields), symbol, 1/N
-//   k_low_velocity u = Re(S) n^ and V = A (|u|^2 - q/4 - 2 g z3)
+//   k_low_velocity u = Re(S) n^ and V = A (|u|^2 - q/4 - 2 g z3) (u is not
+//                  stored for the medium-order model, whose sheet moves with
+//                  the BR velocity: there the FFT velocity only enters V)
 //
 // Layouts: forward  A[i2][i1] -> rows -> A[i2][m1] -> T -> B[m1][i2] -> rows
 // -> B[m1][m2]; symbol B -> A[m1][m2]; inverse A -> rows -> A[m1][i2] -> T
@@ -145,9 +147,11 @@ __global__ __launch_bounds__(kThreads) void k_low_velocity(Mesh m, const double*
     const double inv = 1.0 / sqrt(nx * nx + ny * ny + nz * nz);
     const double s = S[p].x;
     const double u1 = s * (nx * inv), u2 = s * (ny * inv), u3 = s * (nz * inv);
-    u[p] = u1;
-    u[N + p] = u2;
-    u[2 * N + p] = u3;
+    if (u) {   // null for the medium-order model, which only needs V
+        u[p] = u1;
+        u[N + p] = u2;
+        u[2 * N + p] = u3;
+    }
     if (V) {
         const double uu = u1 * u1 + u2 * u2 + u3 * u3;
         V[p] = m.atwood * ((uu - 0.25 * q[p]) - (2.0 * m.gravity) * z[2 * N + p]);

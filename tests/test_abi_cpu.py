@@ -54,10 +54,10 @@ def test_struct_layout_matches_header():
     dict(atwood=float("inf")), dict(precision=7), dict(image_layers=-1),
     dict(image_layers=17), dict(flags=0x80), dict(cutoff=-0.1), dict(cutoff=float("nan")),
     dict(cutoff=0.95), dict(cutoff=0.3, image_layers=1), dict(cutoff=0.3, precision=1),
-    dict(model=2), dict(model=1, cutoff=0.3), dict(model=1, image_layers=1),
+    dict(model=1, cutoff=0.3), dict(model=1, image_layers=1),
     dict(model=1, precision=1), dict(model=1, n1=24),
     dict(boundary=2), dict(boundary=1, model=1), dict(boundary=1, image_layers=1),
-    dict(boundary=1, cutoff=-0.5),
+    dict(boundary=1, cutoff=-0.5), dict(model=3), dict(model=2, boundary=1),
 ])
 def test_workspace_bytes_rejects_invalid(bad):
     kw = dict(n1=16, n2=16, eps=1 / 16)
@@ -83,6 +83,22 @@ def test_free_sheet_cutoff_takes_any_radius():
     b = zm.workspace_bytes(zm.Params(64, 64, eps=1 / 64, boundary=zm.ZM_BOUNDARY_FREE, cutoff=5.0))
     assert a > 0 and b > 0
     assert zm.workspace_bytes(zm.Params(64, 64, eps=1 / 64, cutoff=5.0)) == 0
+
+
+def test_medium_order_workspace_and_status():
+    """Medium order: the BR workspace plus the FFT buffers; power-of-two sides."""
+    hi = zm.workspace_bytes(zm.Params(64, 64, eps=1 / 64))
+    me = zm.workspace_bytes(zm.Params(64, 64, eps=1 / 64, model=zm.ZM_MODEL_MEDIUM))
+    assert 0 < hi < me and me % 256 == 0
+    assert zm.workspace_bytes(zm.Params(64, 64, eps=1 / 64, model=zm.ZM_MODEL_MEDIUM, cutoff=0.3)) > me
+    assert zm.workspace_bytes(zm.Params(64, 64, eps=1 / 64, model=zm.ZM_MODEL_MEDIUM,
+                                        precision=zm.ZM_FP32_PAIRS)) > 0
+    assert zm.workspace_bytes(zm.Params(48, 64, eps=1 / 48, model=zm.ZM_MODEL_MEDIUM)) == 0
+    st, _, msg = _create(zm.Params(48, 64, eps=1 / 48, model=zm.ZM_MODEL_MEDIUM), None, 0)
+    assert st == zm.ZM_ERR_UNSUPPORTED and "powers of two" in msg
+    p = zm.Params(32, 32, eps=1 / 32, model=zm.ZM_MODEL_MEDIUM)
+    assert zm.batch_workspace_bytes([p]) == 0
+    assert zm.pool_request_bytes(p) == 0
 
 
 def test_low_order_workspace_and_status():
