@@ -52,6 +52,8 @@ def parse():
                     help="only measure the cutoff solver (paper workloads, accuracy curve)")
     ap.add_argument("--low-order-only", action="store_true",
                     help="only measure the low-order (FFT) model at 4096 x 4096")
+    ap.add_argument("--medium-only", action="store_true",
+                    help="only measure the medium-order model against the high-order one")
     ap.add_argument("--free-only", action="store_true",
                     help="only measure the non-periodic single-mode case (exact, cutoff, "
                          "far-field check)")
@@ -343,6 +345,39 @@ def free_section(zm, torch):
     return out
 
 
+def medium_section(zm, torch, steps: int = 3):
+    """Medium-order model (BR moves the sheet, FFT velocity in the vorticity
+    law) against the high-order model on the same inputs: ms per RK3 step and
+    per-kernel ms per evaluation, for the exact sum at 512 x 512 and for the
+    cutoff sum (rc = 0.2 of a 6-wide domain scaled to width 2) at
+    1024 x 1024; eight modes with the synthetic vorticity."""
+    dev = torch.device("cuda:0")
+    out = {}
+    for name, n, rc in (("exact512", 512, 0.0), ("cutoff1024", 1024, 0.2 * 2.0 / 6.0)):
+        z, _ = rr.multi_mode(n, n, 8, seed=1)
+        w = rr.synthetic_vorticity(n, n, seed=1)
+        row = {"mesh": f"{n}x{n}", "cutoff": rc}
+        for label, model in (("high", zm.ZM_MODEL_HIGH), ("medium", zm.ZM_MODEL_MEDIUM)):
+            p = zm.Params(n, n, eps=1.0 / n, dt=1e-3, cutoff=rc, model=model)
+            ctx = zm.Context(p)
+            ctx.init_state(torch.from_numpy(z.ravel()).to(dev), torch.from_numpy(w.ravel()).to(dev))
+            ctx.step(1)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ctx.step(steps)
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) / steps * 1e3
+            ctx.profile_enable(True)
+            ctx.step(1)
+            st = ctx.profile_read()
+            row[label] = {"ms_per_step": ms,
+                          "kernel_ms_per_eval": {k: v[1] / v[0] for k, v in st.items() if v[0]}}
+            del ctx
+        row["medium_over_high"] = row["medium"]["ms_per_step"] / row["high"]["ms_per_step"]
+        out[name] = row
+    return out
+
+
 def low_order_section(zm, torch, n: int = 4096, steps: int = 5):
     """Low-order model (FFT velocity): RK3 steps on an n x n eight-mode
     interface (n = 4096 stands in for the paper's 4864 x 4864 per-GPU mesh,
@@ -601,6 +636,9 @@ def main():
     if args.low_order_only:
         print(json.dumps({"low_order_4096": low_order_section(zm, torch)}), flush=True)
         return
+    if args.medium_only:
+        print(json.dumps({"medium_order": medium_section(zm, torch)}), flush=True)
+        return
     if args.free_only:
         print(json.dumps({"free_single_mode": free_section(zm, torch)}), flush=True)
         return
@@ -688,6 +726,7 @@ def main():
         out["cutoff"] = cutoff_section(zm, torch)
         out["low_order_4096"] = low_order_section(zm, torch)
         out["free_single_mode"] = free_section(zm, torch)
+        out["medium_order"] = medium_section(zm, torch)
     if args.serve_seconds > 0:
         out["serving"] = serving(zm, torch, window_s=args.serve_seconds)
     if args.cpu_seconds > 0:
