@@ -268,6 +268,7 @@ zm_status zm_create(zm_ctx** out, const zm_params* params, void* d_workspace,
         c->cb.bend = reinterpret_cast<int*>(ws + L.cut_bend);
         c->cb.src = reinterpret_cast<double*>(ws + L.cut_src);
         c->cb.counts = reinterpret_cast<unsigned long long*>(ws + L.cut_counts);
+        c->cb.kflag = reinterpret_cast<int*>(ws + L.cut_kflag);
     }
     *out = c;
     return ZM_OK;

@@ -18,7 +18,10 @@
 //                   order, one 64-byte record per point
 //   k_cut_pairs     one wave per (target block, row of neighbour cells):
 //                   each neighbour cell's sources are read with wave-uniform
-//                   scalar loads and every target (lane) sums over them
+//                   scalar loads and every target (lane) sums over them;
+//                   the image-shift arithmetic is dropped where no wrap
+//                   count is involved, and a source no lane accepts skips
+//                   the kernel evaluation
 //
 // The inclusion test is evaluated exactly as the definition writes it
 // (r_a = (z_i,a - z_j,a) - S_a L_a, then r1*r1 + r2*r2 + r3*r3 < rc*rc, no
@@ -222,7 +225,8 @@ __global__ __launch_bounds__(kThreads) void k_cut_bounds(CutGrid g, int n,
 __global__ __launch_bounds__(kThreads) void k_cut_gather(Mesh m, CutGrid g, const double* __restrict__ z,
                                                          const double* __restrict__ gam,
                                                          const unsigned* __restrict__ order,
-                                                         double* __restrict__ src)
+                                                         double* __restrict__ src,
+                                                         int* __restrict__ kflag)
 {
     const int i = blockIdx.x * kThreads + threadIdx.x;
     const int N = m.N;
@@ -241,6 +245,7 @@ __global__ __launch_bounds__(kThreads) void k_cut_gather(Mesh m, CutGrid g, cons
     r[5] = gam[2 * N + p];
     r[6] = (double)kx;
     r[7] = (double)ky;
+    if (kx != 0 || ky != 0) kflag[cell_key(g, cx, cy)] = 1;   // same value from every writer
 }
 
 // One wave per (target block, neighbour row, chunk slot).  Lane = one target
@@ -259,6 +264,78 @@ __global__ __launch_bounds__(kThreads) void k_cut_gather(Mesh m, CutGrid g, cons
 // wave of a row outside the grid still writes its zero partial sums).
 constexpr int kCutThreads = 64;
 
+// Image-shift handling of one (wave, neighbour cell) visit:
+//   kShiftNone     every target of the wave and every source of the cell has
+//                  wrap count 0 and the cell is not wrapped: S = 0, r = d
+//                  (d - 0 L is d bit for bit);
+//   kShiftUniform  wrap counts all 0 but the cell is wrapped: S = (wx, wy)
+//                  for every pair, S_a L_a formed once;
+//   kShiftPerLane  S = k_i + w - k_j per pair.
+// All three give the same r as the definition's r_a = d_a - S_a L_a.
+enum { kShiftNone = 0, kShiftUniform = 1, kShiftPerLane = 2 };
+
+struct CutTarget {
+    double x, y, z;     // target position
+    double Kx, Ky;      // k_i + wx, k_i + wy (per-lane shift mode)
+    bool active;        // lane holds a real target
+    uint64_t amask;     // lanes of the wave that hold real targets
+};
+
+// Sum the sources [s0, s1) of one cell into the lane's accumulators.  The
+// next source record is loaded while the current one is used; a source that
+// no lane of the wave accepts skips the kernel evaluation (a wave-uniform
+// branch: the accepted set, and so every sum, is unchanged).
+template <int SHIFT, bool COUNT>
+__device__ __forceinline__ void cut_cell(const Mesh& m, const CutGrid& g,
+                                         const double* __restrict__ src, int s0, int s1,
+                                         const CutTarget& t, double SL1, double SL2,
+                                         double& acc0, double& acc1, double& acc2,
+                                         unsigned long long& tested,
+                                         unsigned long long& accepted)
+{
+    if (s0 >= s1) return;
+    const double* sj = src + (size_t)s0 * 8;
+    double nx = sj[0], ny = sj[1], nz = sj[2], n1 = sj[3], n2 = sj[4], n3 = sj[5];
+    double nk1 = sj[6], nk2 = sj[7];
+    for (int j = s0; j < s1; ++j) {
+#pragma clang fp contract(off)
+        const double bx = nx, by = ny, bz = nz, g1 = n1, g2 = n2, g3 = n3;
+        const double k1 = nk1, k2 = nk2;
+        const double* sn = src + (size_t)(j + 1 < s1 ? j + 1 : j) * 8;   // same in every lane
+        nx = sn[0]; ny = sn[1]; nz = sn[2]; n1 = sn[3]; n2 = sn[4]; n3 = sn[5];
+        nk1 = sn[6]; nk2 = sn[7];
+        const double d1 = t.x - bx, d2 = t.y - by;
+        double r1, r2;
+        if (SHIFT == kShiftNone) {
+            r1 = d1;
+            r2 = d2;
+        } else if (SHIFT == kShiftUniform) {
+            r1 = d1 - SL1;
+            r2 = d2 - SL2;
+        } else {
+            const double S1 = t.Kx - k1, S2 = t.Ky - k2;
+            r1 = d1 - S1 * g.L1;
+            r2 = d2 - S2 * g.L2;
+        }
+        const double r3 = t.z - bz;
+        const double dd = r1 * r1 + r2 * r2 + r3 * r3;
+        const bool in = dd < g.rc2;
+        if (COUNT) {
+            tested += t.active ? 1 : 0;
+            accepted += (t.active && in) ? 1 : 0;
+        }
+        if ((__builtin_amdgcn_ballot_w64(in) & t.amask) == 0ull) continue;
+        const double wgt = in ? dev::inv_cube_sqrt(dd + m.eps2) : 0.0;
+        const double a1 = wgt * g1, a2 = wgt * g2, a3 = wgt * g3;
+        acc0 = fma(r2, a3, acc0);
+        acc0 = fma(-r3, a2, acc0);
+        acc1 = fma(r3, a1, acc1);
+        acc1 = fma(-r1, a3, acc1);
+        acc2 = fma(r1, a2, acc2);
+        acc2 = fma(-r2, a1, acc2);
+    }
+}
+
 template <bool COUNT>
 __global__ __launch_bounds__(kCutThreads) void k_cut_pairs(Mesh m, CutGrid g,
                                                            const double* __restrict__ src,
@@ -266,6 +343,7 @@ __global__ __launch_bounds__(kCutThreads) void k_cut_pairs(Mesh m, CutGrid g,
                                                            const int* __restrict__ end,
                                                            const int* __restrict__ bstart,
                                                            const int* __restrict__ bend,
+                                                           const int* __restrict__ kflag,
                                                            const unsigned* __restrict__ order,
                                                            double* __restrict__ part,
                                                            unsigned long long* __restrict__ counts)
@@ -284,9 +362,16 @@ __global__ __launch_bounds__(kCutThreads) void k_cut_pairs(Mesh m, CutGrid g,
     // chunks of 64 targets, blockIdx.z, blockIdx.z + chunks, ...
     for (int t0 = T0 + (int)blockIdx.z * kCutThreads; t0 < T1; t0 += g.chunks * kCutThreads) {
         const int i = t0 + lane;
-        const bool active = i < T1;
-        const double* ti = src + (size_t)(active ? i : T0) * 8;
-        const double xi = ti[0], yi = ti[1], zi = ti[2], kxi = ti[6], kyi = ti[7];
+        CutTarget t;
+        t.active = i < T1;
+        t.amask = __builtin_amdgcn_ballot_w64(t.active);
+        const double* ti = src + (size_t)(t.active ? i : T0) * 8;
+        t.x = ti[0];
+        t.y = ti[1];
+        t.z = ti[2];
+        const double kxi = ti[6], kyi = ti[7];
+        // every target of the wave unwrapped (inactive lanes hold a real target of the block)
+        const bool targets_k0 = __builtin_amdgcn_ballot_w64(kxi != 0.0 || kyi != 0.0) == 0ull;
         double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0;
         for (int col = 0; col < g.slots; ++col) {
             const int cx_raw = bx * g.B - g.m + col;
@@ -294,33 +379,23 @@ __global__ __launch_bounds__(kCutThreads) void k_cut_pairs(Mesh m, CutGrid g,
             if (!row_in || (!g.periodic && wx != 0)) continue;   // wave-uniform
             const int key = cell_key(g, cx, cy);
             const int s0 = start[key], s1 = end[key];
-            const double Kx = kxi + (double)wx, Ky = kyi + (double)wy;
-#pragma unroll 2
-            for (int j = s0; j < s1; ++j) {
-#pragma clang fp contract(off)
-                const double* sj = src + (size_t)j * 8;   // same address in every lane
-                const double d1 = xi - sj[0], d2 = yi - sj[1];
-                const double S1 = Kx - sj[6], S2 = Ky - sj[7];
-                const double r1 = d1 - S1 * g.L1;
-                const double r2 = d2 - S2 * g.L2;
-                const double r3 = zi - sj[2];
-                const double dd = r1 * r1 + r2 * r2 + r3 * r3;
-                const bool in = dd < g.rc2;
-                const double wgt = in ? dev::inv_cube_sqrt(dd + m.eps2) : 0.0;
-                const double a1 = wgt * sj[3], a2 = wgt * sj[4], a3 = wgt * sj[5];
-                acc0 = fma(r2, a3, acc0);
-                acc0 = fma(-r3, a2, acc0);
-                acc1 = fma(r3, a1, acc1);
-                acc1 = fma(-r1, a3, acc1);
-                acc2 = fma(r1, a2, acc2);
-                acc2 = fma(-r2, a1, acc2);
-                if (COUNT) {
-                    tested += active ? 1 : 0;
-                    accepted += (active && in) ? 1 : 0;
+            if (targets_k0 && kflag[key] == 0) {
+                if (wx == 0 && wy == 0) {
+                    cut_cell<kShiftNone, COUNT>(m, g, src, s0, s1, t, 0.0, 0.0, acc0, acc1, acc2,
+                                                tested, accepted);
+                } else {
+                    const double SL1 = (double)wx * g.L1, SL2 = (double)wy * g.L2;
+                    cut_cell<kShiftUniform, COUNT>(m, g, src, s0, s1, t, SL1, SL2, acc0, acc1,
+                                                   acc2, tested, accepted);
                 }
+            } else {
+                t.Kx = kxi + (double)wx;
+                t.Ky = kyi + (double)wy;
+                cut_cell<kShiftPerLane, COUNT>(m, g, src, s0, s1, t, 0.0, 0.0, acc0, acc1, acc2,
+                                               tested, accepted);
             }
         }
-        if (active) {
+        if (t.active) {
             const int p = (int)order[i];
             double* out = part + (size_t)row * 3 * N;
             out[p] = acc0;
@@ -400,9 +475,11 @@ hipError_t launch_cut_cells(const Mesh& m, const CutGrid& g, const double* z, co
     hipLaunchKernelGGL(k_fill_int, dim3(grid_for(g.nkeys)), blk, 0, s, b.end, g.nkeys, 0);
     hipLaunchKernelGGL(k_fill_int, dim3(grid_for(nblk)), blk, 0, s, b.bstart, nblk, 0);
     hipLaunchKernelGGL(k_fill_int, dim3(grid_for(nblk)), blk, 0, s, b.bend, nblk, 0);
+    hipLaunchKernelGGL(k_fill_int, dim3(grid_for(g.nkeys)), blk, 0, s, b.kflag, g.nkeys, 0);
     hipLaunchKernelGGL(k_cut_bounds, dim3(grid_for(N)), blk, 0, s, g, N, b.keys[cur], b.start,
                        b.end, b.bstart, b.bend);
-    hipLaunchKernelGGL(k_cut_gather, dim3(grid_for(N)), blk, 0, s, m, g, z, gam, b.vals[cur], b.src);
+    hipLaunchKernelGGL(k_cut_gather, dim3(grid_for(N)), blk, 0, s, m, g, z, gam, b.vals[cur], b.src,
+                       b.kflag);
     *sorted_half = cur;
     return hipGetLastError();
 }
@@ -414,10 +491,10 @@ hipError_t launch_cut_pairs(const Mesh& m, const CutGrid& g, const CutBuffers& b
     const unsigned* order = b.vals[sorted_half];
     if (count)
         hipLaunchKernelGGL(k_cut_pairs<true>, grid, dim3(kCutThreads), 0, s, m, g, b.src, b.start,
-                           b.end, b.bstart, b.bend, order, part, b.counts);
+                           b.end, b.bstart, b.bend, b.kflag, order, part, b.counts);
     else
         hipLaunchKernelGGL(k_cut_pairs<false>, grid, dim3(kCutThreads), 0, s, m, g, b.src, b.start,
-                           b.end, b.bstart, b.bend, order, part, b.counts);
+                           b.end, b.bstart, b.bend, b.kflag, order, part, b.counts);
     return hipGetLastError();
 }
 

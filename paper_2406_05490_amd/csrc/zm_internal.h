@@ -110,6 +110,7 @@ struct CutBuffers {
     int* bstart;         // nb1 nb2: first sorted index of a target block
     int* bend;
     double* src;         // 8 N: per sorted point (x, y, z, g1, g2, g3, kx, ky)
+    int* kflag;          // nkeys: nonzero if a point of the cell has a wrap count != 0
     unsigned long long* counts;  // 2: pairs tested, pairs within rc
 };
 
