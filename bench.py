@@ -383,8 +383,9 @@ def low_order_section(zm, torch, n: int = 4096, steps: int = 5):
     interface (n = 4096 stands in for the paper's 4864 x 4864 per-GPU mesh,
     the largest power of two below it), per-kernel times, mesh points
     advanced per second, and the HBM rate of the FFT velocity against its
-    traffic (complex field read and written by 4 row-FFT passes, 2
-    transposes, the symbol pass; the pack and velocity passes)."""
+    algorithmic traffic: pack + row FFT (w in, complex out), transpose,
+    FFT-symbol-inverse-FFT rows, transpose, inverse row FFT + velocity
+    (complex, z, w in; u, V out)."""
     z, _ = rr.multi_mode(n, n, 8, seed=1)
     w = rr.synthetic_vorticity(n, n, seed=1)
     dev = torch.device("cuda:0")
@@ -402,11 +403,11 @@ def low_order_section(zm, torch, n: int = 4096, steps: int = 5):
     st = ctx.profile_read()
     ms = {k: v[1] / v[0] for k, v in st.items() if v[0]}
     N = n * n
-    # bytes of one FFT-velocity evaluation: 16 B complex per point, read +
-    # written by 4 FFT passes, 2 transposes and the symbol pass (which also
-    # reads the partner mode), pack (16 B read, 16 B write), velocity
-    # (z 24 B with neighbours from cache, S 16 B, q 8 B in; u 24 B, V 8 B out)
-    fft_bytes = N * (7 * 32 + 16 + 32 + 80)
+    # bytes of one FFT-velocity evaluation per point: pack + FFT rows (w 16
+    # in, 16 out), two transposes and the symbol rows (16 in + 16 out each),
+    # inverse FFT + velocity (complex 16, z 24 with neighbours from cache,
+    # w 16 in; u 24, V 8 out)
+    fft_bytes = N * (32 + 3 * 32 + 88)
     return {"mesh": f"{n}x{n}", "steps": steps, "ms_per_step": wall / steps * 1e3,
             "points_per_s": N * steps / wall, "kernel_ms_per_eval": ms,
             "fft_velocity_bytes_per_eval": fft_bytes,

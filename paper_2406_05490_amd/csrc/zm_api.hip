@@ -109,15 +109,14 @@ hipError_t timed(zm_ctx* c, int kernel, F&& launch)
 }
 
 // Medium order: the Bernoulli potential V from the FFT (flat-sheet)
-// velocity, after the BR sum has produced the sheet velocity (q from the
-// surface pass).  Nothing to do for the other models or without V.
+// velocity, after the BR sum has produced the sheet velocity.  Nothing to
+// do for the other models or without V.
 zm_status medium_potential(zm_ctx* c, const double* z, const double* w, double* V,
                            hipStream_t stream)
 {
     if (!c->medium || !V) return ZM_OK;
-    const double* q = c->at(c->layout.q);
     hipError_t e = timed(c, ZM_KERNEL_FFT, [&] {
-        return zm::launch_low_velocity(c->mesh, z, w, q, c->lb, nullptr, V, stream);
+        return zm::launch_low_velocity(c->mesh, z, w, c->lb, nullptr, V, stream);
     });
     if (e != hipSuccess) return hip_fail(c, e, "FFT velocity launch");
     return ZM_OK;
@@ -134,14 +133,14 @@ zm_status eval_velocity(zm_ctx* c, const double* z, const double* w, double* u, 
     double* part = c->at(c->layout.part);
     double* tie = c->at(c->layout.tie);
     hipError_t e;
-    e = timed(c, ZM_KERNEL_SURFACE, [&] { return zm::launch_surface(m, z, w, gam, q, stream); });
-    if (e != hipSuccess) return hip_fail(c, e, "surface kernel launch");
-    if (c->low) {
+    if (c->low) {   // the FFT velocity needs no source strengths
         e = timed(c, ZM_KERNEL_FFT,
-                  [&] { return zm::launch_low_velocity(m, z, w, q, c->lb, u, V, stream); });
+                  [&] { return zm::launch_low_velocity(m, z, w, c->lb, u, V, stream); });
         if (e != hipSuccess) return hip_fail(c, e, "FFT velocity launch");
         return ZM_OK;
     }
+    e = timed(c, ZM_KERNEL_SURFACE, [&] { return zm::launch_surface(m, z, w, gam, q, stream); });
+    if (e != hipSuccess) return hip_fail(c, e, "surface kernel launch");
     if (c->cutoff) {
         int half = 0;
         e = timed(c, ZM_KERNEL_CELLS,

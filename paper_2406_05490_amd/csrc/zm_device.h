@@ -113,15 +113,24 @@ __device__ __forceinline__ double inv_cube_sqrt(double s)
 // surface derivatives
 // ---------------------------------------------------------------------------
 
+// Boundary kind of a stencil: PER = 1 periodic, 0 free, -1 read from the
+// mesh at run time (both stencils compiled in).
+template <int PER>
+__device__ __forceinline__ bool periodic_of(const Mesh& m)
+{
+    return PER < 0 ? m.periodic != 0 : PER != 0;
+}
+
 // Tangents T1 = D1 z, T2 = D2 z at point p (5-point; seam-corrected on a
 // periodic sheet, extrapolated ghosts on a free one).
+template <int PER = -1>
 __device__ __forceinline__ void tangents_at(const Mesh& m, int p, const double* __restrict__ z,
                                             double T1[3], double T2[3])
 {
     const int N = m.N;
     const int i2 = p / m.n1;
     const int i1 = p - i2 * m.n1;
-    const bool per = m.periodic != 0;
+    const bool per = periodic_of<PER>(m);
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         const double* f = z + (size_t)c * N;
@@ -1052,6 +1061,7 @@ __device__ __forceinline__ void reduce_thread(const Mesh& m, int t, int L, int s
 // y0 may alias out (the last stage writes the new state over y0 in place,
 // each thread reading its own point before writing it), so neither carries
 // __restrict__.
+template <int PER = -1>
 __device__ __forceinline__ void update_point(const Mesh& m, int p, int stage, const double* y0_z,
                                              const double* y0_w, const double* __restrict__ ys_z,
                                              const double* __restrict__ ys_w,
@@ -1063,7 +1073,7 @@ __device__ __forceinline__ void update_point(const Mesh& m, int p, int stage, co
     const int N = m.N, n1 = m.n1, n2 = m.n2;
     const int i2 = p / n1;
     const int i1 = p - i2 * n1;
-    const bool per = m.periodic != 0;
+    const bool per = periodic_of<PER>(m);
 
     double F[5];
     F[0] = u[p];

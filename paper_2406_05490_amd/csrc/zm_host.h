@@ -36,7 +36,7 @@ struct Layout {
     size_t cut_kflag;                  // nkeys int
     // low-order model only (size 0 otherwise)
     size_t lo_a, lo_b;                 // N double2 each
-    size_t lo_tw1, lo_tw2;             // n1/2, n2/2 double2
+    size_t lo_tw1, lo_tw2;             // n1, n2 double2
     size_t total;
 };
 
@@ -85,8 +85,8 @@ inline Layout make_layout(const zm_params& p, const zm::PairShape& sh)
     const size_t c16 = 2 * sizeof(double);
     L.lo_a = take(low ? N * c16 : 0);
     L.lo_b = take(low ? N * c16 : 0);
-    L.lo_tw1 = take(low ? (size_t)(p.n1 / 2) * c16 : 0);
-    L.lo_tw2 = take(low ? (size_t)(p.n2 / 2) * c16 : 0);
+    L.lo_tw1 = take(low ? (size_t)p.n1 * c16 : 0);
+    L.lo_tw2 = take(low ? (size_t)p.n2 * c16 : 0);
     L.total = o;
     return L;
 }

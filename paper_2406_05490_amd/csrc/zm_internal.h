@@ -126,16 +126,17 @@ hipError_t launch_cut_cells(const Mesh& m, const CutGrid& g, const double* z, co
 struct LowBuffers {
     double2* a;
     double2* b;
-    double2* tw1;        // n1 / 2
-    double2* tw2;        // n2 / 2
+    double2* tw1;        // n1: exp(-2 pi i t / n1)
+    double2* tw2;        // n2
 };
 
 // Sides the FFT path handles: powers of two from 8 to 4096.
 bool low_order_supported_side(int n);
 
-// u (3 planes) = 1/2 (R1 w1 + R2 w2) n^ and, if V != NULL,
-// V = A (|u|^2 - q/4 - 2 g z3).
-hipError_t launch_low_velocity(const Mesh& m, const double* z, const double* w, const double* q,
+// u (3 planes, if u != NULL) = 1/2 (R1 w1 + R2 w2) n^ and, if V != NULL,
+// V = A (|u|^2 - q/4 - 2 g z3) with q = |w1 T2 - w2 T1|^2 / |T1 x T2|^2
+// formed in place (no surface pass needed).
+hipError_t launch_low_velocity(const Mesh& m, const double* z, const double* w,
                                const LowBuffers& b, double* u, double* V, hipStream_t s);
 
 // Zero the two pair counters (a kernel, so it may sit in a captured graph).

@@ -61,6 +61,7 @@ __global__ __launch_bounds__(kThreads) void k_reduce(Mesh m, int splits,
 }
 
 // y0 may alias out (see update_point), so neither carries __restrict__.
+template <int PER>
 __global__ __launch_bounds__(kThreads) void k_update(Mesh m, int stage, const double* y0_z,
                                                      const double* y0_w,
                                                      const double* __restrict__ ys_z,
@@ -70,8 +71,8 @@ __global__ __launch_bounds__(kThreads) void k_update(Mesh m, int stage, const do
                                                      double* out_z, double* out_w,
                                                      int* __restrict__ nonfinite)
 {
-    dev::update_point(m, blockIdx.x * kThreads + threadIdx.x, stage, y0_z, y0_w, ys_z, ys_w, u,
-                      V, out_z, out_w, nonfinite);
+    dev::update_point<PER>(m, blockIdx.x * kThreads + threadIdx.x, stage, y0_z, y0_w, ys_z, ys_w,
+                           u, V, out_z, out_w, nonfinite);
 }
 
 // Synthetic tuning input: a gently curved mesh with a smooth source strength.
@@ -208,8 +209,12 @@ hipError_t launch_update(const Mesh& m, int stage, const double* y0_z, const dou
                          const double* ys_z, const double* ys_w, const double* u, const double* V,
                          double* out_z, double* out_w, int* nonfinite, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_update, dim3(blocks_for(m.N)), dim3(kThreads), 0, s, m, stage, y0_z, y0_w,
-                       ys_z, ys_w, u, V, out_z, out_w, nonfinite);
+    if (m.periodic)
+        hipLaunchKernelGGL(k_update<1>, dim3(blocks_for(m.N)), dim3(kThreads), 0, s, m, stage, y0_z,
+                           y0_w, ys_z, ys_w, u, V, out_z, out_w, nonfinite);
+    else
+        hipLaunchKernelGGL(k_update<0>, dim3(blocks_for(m.N)), dim3(kThreads), 0, s, m, stage, y0_z,
+                           y0_w, ys_z, ys_w, u, V, out_z, out_w, nonfinite);
     return hipGetLastError();
 }
 

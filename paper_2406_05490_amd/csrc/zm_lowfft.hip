@@ -1,24 +1,40 @@
 // Low-order Z-Model velocity: the BR integral replaced by its flat-sheet
 // approximation u = 1/2 (R1 w1 + R2 w2) n^, R_a the Riesz transform over
 // the periodic parameter mesh (symbol i k_a / |k|), evaluated with FFTs
-// (the paper's low-order solver, sec. 2).  One complex 2D FFT carries both
-// real vorticity components (c = w1 + i w2), one inverse FFT returns S:
+// (the paper's low-order solver, sec. 2).
 //
-//   k_twiddle      exp(-2 pi i k / n), k < n/2, per axis
-//   k_pack         c = w1 + i w2, rows = i2
-//   k_fft_rows     radix-2 FFT of every row in LDS (bit-reversed load,
-//                  in-place decimation-in-time stages)
-//   k_transpose    32 x 32 tiles through LDS
-//   k_riesz        S^ from c^(m) and conj(c^(-m)) (splits the two real
-//                  fields), symbol, 1/N
-//   k_low_velocity u = Re(S) n^ and V = A (|u|^2 - q/4 - 2 g z3) (u is not
-//                  stored for the medium-order model, whose sheet moves with
-//                  the BR velocity: there the FFT velocity only enters V)
+// Both real vorticity components ride in one complex field c = w1 + i w2.
+// The symbols c_a = k_a / |k| are odd in k at every mode (they are set to 0
+// at k = 0 and, along axis a, at the unpaired mode m_a = n_a / 2), so
+// i c_a maps real fields to real fields, and
+//   S = 1/2 (R1 w1 + R2 w2) = Re IFFT[ (c2 + i c1) / 2 * FFT(c) ]
+// (the real part keeps R1 w1 + R2 w2 and drops R1 w2 - R2 w1): no partner
+// mode -m is needed, so the symbol is applied between the forward and the
+// inverse transform of the same row.  Five kernels:
 //
-// Layouts: forward  A[i2][i1] -> rows -> A[i2][m1] -> T -> B[m1][i2] -> rows
-// -> B[m1][m2]; symbol B -> A[m1][m2]; inverse A -> rows -> A[m1][i2] -> T
-// -> B[i2][m1] -> rows -> B[i2][i1] = S.  Sides are powers of two up to
-// 4096 (one row of complex doubles fills at most 64 KiB of LDS).
+//   k_lo_pack_rows   row i2: c = w1 + i w2, forward FFT over i1 -> A[i2][m1]
+//   k_transpose      32 x 32 tiles through LDS -> B[m1][i2]
+//   k_lo_symbol_rows row m1: forward FFT over i2, times (c2 + i c1) / (2N),
+//                    inverse FFT over m2 -> B[m1][i2]
+//   k_transpose      -> A[i2][m1]
+//   k_lo_inv_rows    row i2: inverse FFT over m1 -> S(i1, i2) = Re (one
+//                    double plane, in the spent second complex buffer)
+//   k_lo_point       per point: u = S n^ (unit normal from the 5-point
+//                    tangents), q from w and the tangents,
+//                    V = A (|u|^2 - q/4 - 2 g z3) (a plain point kernel: the
+//                    stencil loads want the occupancy the FFT rows lack)
+//
+// Row FFTs: one row of n = 2^L <= 4096 complex doubles per 256-thread
+// workgroup, held in LDS (at most 64 KiB); Stockham auto-sort passes of
+// radix 16 (and one of radix 2, 4 or 8 for the remaining bits), each thread
+// owning one radix-R butterfly per pass in registers: load R inputs at
+// stride n / R, twiddle input r by w_{Ns R}^{r k} (k = j mod Ns; w^r by
+// repeated multiplication from one table entry), radix-R DFT (radix-2
+// decimation-in-frequency network, constant twiddles), store at
+// (j - k) R + k + r Ns.  The LDS index is XOR-swizzled within groups of 16
+// (e ^ ((e >> 4) & 15)) so that the stride-R stores of the first pass do not
+// fall into one bank.  Twiddle tables exp(-2 pi i t / n), t < n, are built by
+// k_twiddle in each evaluation.
 #include "zm_device.h"
 #include "zm_internal.h"
 
@@ -28,57 +44,236 @@ namespace zm {
 namespace {
 
 using dev::kThreads;
+constexpr int kFftThreads = 256;   // n / R <= 256 for every pass when n <= 4096
 
-__global__ __launch_bounds__(kThreads) void k_twiddle(int n, double2* __restrict__ tw)
+__global__ __launch_bounds__(kThreads) void k_twiddle(int n1, double2* __restrict__ tw1, int n2,
+                                                      double2* __restrict__ tw2)
 {
-    const int k = blockIdx.x * kThreads + threadIdx.x;
-    if (k >= n / 2) return;
+    const int t = blockIdx.x * kThreads + threadIdx.x;
     double s, c;
-    sincospi(-2.0 * (double)k / (double)n, &s, &c);
-    tw[k] = make_double2(c, s);
+    if (t < n1) {
+        sincospi(-2.0 * (double)t / (double)n1, &s, &c);
+        tw1[t] = make_double2(c, s);
+    }
+    if (t < n2) {
+        sincospi(-2.0 * (double)t / (double)n2, &s, &c);
+        tw2[t] = make_double2(c, s);
+    }
 }
 
-__global__ __launch_bounds__(kThreads) void k_pack(int N, const double* __restrict__ w,
-                                                   double2* __restrict__ a)
-{
-    const int p = blockIdx.x * kThreads + threadIdx.x;
-    if (p < N) a[p] = make_double2(w[p], w[N + p]);
-}
+__device__ __forceinline__ int sw(int e) { return e ^ ((e >> 4) & 15); }
 
 __device__ __forceinline__ double2 cmul(double2 a, double2 b)
 {
     return make_double2(fma(a.x, b.x, -a.y * b.y), fma(a.x, b.y, a.y * b.x));
 }
 
-// One row of n = 2^logn complex values per workgroup, in place.  inv: use
-// conj(twiddle) (unnormalised inverse).
+// cos(2 pi m / 16), 0 <= m < 8
+__device__ __forceinline__ double cos16(int m)
+{
+    switch (m) {
+    case 0: return 1.0;
+    case 1: return 0.92387953251128674;
+    case 2: return 0.70710678118654752;
+    case 3: return 0.38268343236508977;
+    case 4: return 0.0;
+    case 5: return -0.38268343236508977;
+    case 6: return -0.70710678118654752;
+    default: return -0.92387953251128674;
+    }
+}
+
+// t times exp(-2 pi i m / 16) (INV: exp(+2 pi i m / 16)); m is a constant
+// after unrolling, so the branches fold.
 template <bool INV>
-__global__ __launch_bounds__(kThreads) void k_fft_rows(double2* __restrict__ a, int logn,
-                                                       const double2* __restrict__ tw)
+__device__ __forceinline__ double2 rot16(double2 t, int m)
+{
+    if (m == 0) return t;
+    if (m == 4) return INV ? make_double2(-t.y, t.x) : make_double2(t.y, -t.x);
+    const double c = cos16(m);
+    const double sn = m < 4 ? cos16(4 - m) : cos16(m - 4);   // sin(2 pi m / 16) > 0
+    const double s = INV ? sn : -sn;
+    return make_double2(t.x * c - t.y * s, t.x * s + t.y * c);
+}
+
+// Radix-R DFT of v[0..R) in registers (decimation in frequency): on return
+// v[r] holds X[brev_R(r)].
+template <int R, bool INV>
+__device__ __forceinline__ void dft(double2 (&v)[16])
+{
+#pragma unroll
+    for (int span = R / 2; span >= 1; span >>= 1) {
+#pragma unroll
+        for (int s0 = 0; s0 < R; s0 += 2 * span) {
+#pragma unroll
+            for (int k = 0; k < span; ++k) {
+                const double2 a = v[s0 + k], b = v[s0 + k + span];
+                v[s0 + k] = make_double2(a.x + b.x, a.y + b.y);
+                v[s0 + k + span] = rot16<INV>(make_double2(a.x - b.x, a.y - b.y), k * (8 / span));
+            }
+        }
+    }
+}
+
+template <int R>
+__device__ constexpr int brev(int r)
+{
+    int o = 0;
+    for (int b = 1, t = R >> 1; b < R; b <<= 1, t >>= 1)
+        if (r & b) o |= t;
+    return o;
+}
+
+// One Stockham pass of radix R over the LDS row x (n points, Ns = product
+// of the radices already applied).  Every thread reaches both barriers.
+template <int R, bool INV>
+__device__ __forceinline__ void fft_pass(double2* x, int n, int Ns, const double2* __restrict__ tw)
+{
+    const int nb = n / R;
+    const int j = threadIdx.x;
+    double2 v[16];
+    int k = 0;
+    if (j < nb) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[r] = x[sw(j + r * nb)];
+        k = j & (Ns - 1);
+        if (k != 0) {
+            double2 w1 = tw[k * (n / (Ns * R))];
+            if (INV) w1.y = -w1.y;
+            double2 w = w1;
+#pragma unroll
+            for (int r = 1; r < R; ++r) {
+                v[r] = cmul(v[r], w);
+                if (r + 1 < R) w = cmul(w, w1);
+            }
+        }
+        dft<R, INV>(v);
+    }
+    __syncthreads();
+    if (j < nb) {
+        const int base = (j - k) * R + k;
+#pragma unroll
+        for (int r = 0; r < R; ++r) x[sw(base + r * Ns)] = v[brev<R>(r)];
+    }
+    __syncthreads();
+}
+
+// Unnormalised DFT (INV: conjugate twiddles) of the LDS row x, n = 2^logn.
+template <bool INV>
+__device__ void fft_row(double2* x, int logn, const double2* __restrict__ tw)
+{
+    const int n = 1 << logn;
+    int Ns = 1, rem = logn;
+    while (rem >= 4) {
+        fft_pass<16, INV>(x, n, Ns, tw);
+        Ns <<= 4;
+        rem -= 4;
+    }
+    if (rem == 3) fft_pass<8, INV>(x, n, Ns, tw);
+    else if (rem == 2) fft_pass<4, INV>(x, n, Ns, tw);
+    else if (rem == 1) fft_pass<2, INV>(x, n, Ns, tw);
+}
+
+// Row i2: c = w1 + i w2 over i1, forward FFT -> A[i2][m1].
+__global__ __launch_bounds__(kFftThreads) void k_lo_pack_rows(int logn, int N,
+                                                              const double* __restrict__ w,
+                                                              const double2* __restrict__ tw,
+                                                              double2* __restrict__ A)
 {
     extern __shared__ double2 x[];
     const int n = 1 << logn;
-    double2* row = a + (size_t)blockIdx.x * n;
-    for (int j = threadIdx.x; j < n; j += kThreads) {
-        const int r = (int)(__brev((unsigned)j) >> (32 - logn));
-        x[r] = row[j];
+    const size_t row = (size_t)blockIdx.x * n;
+    for (int e = threadIdx.x; e < n; e += kFftThreads)
+        x[sw(e)] = make_double2(w[row + e], w[N + row + e]);
+    __syncthreads();
+    fft_row<false>(x, logn, tw);
+    for (int e = threadIdx.x; e < n; e += kFftThreads) A[row + e] = x[sw(e)];
+}
+
+// Row m1 of B (length n2 over i2): forward FFT over i2, times the symbol
+// (c2 + i c1) / (2 N) at (m1, m2), inverse FFT over m2, in place.
+__global__ __launch_bounds__(kFftThreads) void k_lo_symbol_rows(int n1, int logn2, double L1,
+                                                                double L2,
+                                                                const double2* __restrict__ tw,
+                                                                double2* __restrict__ B)
+{
+    extern __shared__ double2 x[];
+    const int n2 = 1 << logn2;
+    const int m1 = blockIdx.x;
+    double2* row = B + (size_t)m1 * n2;
+    for (int e = threadIdx.x; e < n2; e += kFftThreads) x[sw(e)] = row[e];
+    __syncthreads();
+    fft_row<false>(x, logn2, tw);
+    const int s1 = 2 * m1 < n1 ? m1 : m1 - n1;
+    const double k1 = 2.0 * M_PI * s1 / L1;
+    const double h = 0.5 / ((double)n1 * (double)n2);
+    for (int m2 = threadIdx.x; m2 < n2; m2 += kFftThreads) {
+        const int s2 = 2 * m2 < n2 ? m2 : m2 - n2;
+        const double k2 = 2.0 * M_PI * s2 / L2;
+        const double kk = sqrt(k1 * k1 + k2 * k2);
+        double c1 = 0.0, c2 = 0.0;
+        if (kk > 0.0) {
+            c1 = (2 * m1 == n1) ? 0.0 : k1 / kk;
+            c2 = (2 * m2 == n2) ? 0.0 : k2 / kk;
+        }
+        const double2 v = x[sw(m2)];
+        const double mx = c2 * h, my = c1 * h;   // (c2 + i c1) / (2N)
+        x[sw(m2)] = make_double2(v.x * mx - v.y * my, v.x * my + v.y * mx);
     }
     __syncthreads();
-    for (int s = 1; s <= logn; ++s) {
-        const int half = 1 << (s - 1);
-        const int stride = n >> s;   // twiddle index step: exp(-2 pi i pos / 2^s)
-        for (int b = threadIdx.x; b < n / 2; b += kThreads) {
-            const int grp = b >> (s - 1), pos = b & (half - 1);
-            const int i0 = (grp << s) + pos, i1 = i0 + half;
-            double2 w = tw[pos * stride];
-            if (INV) w.y = -w.y;
-            const double2 u = x[i0], v = cmul(x[i1], w);
-            x[i0] = make_double2(u.x + v.x, u.y + v.y);
-            x[i1] = make_double2(u.x - v.x, u.y - v.y);
+    fft_row<true>(x, logn2, tw);
+    for (int e = threadIdx.x; e < n2; e += kFftThreads) row[e] = x[sw(e)];
+}
+
+// Row i2 of A (over m1): inverse FFT over m1, S = Re -> S[i2][i1].
+__global__ __launch_bounds__(kFftThreads) void k_lo_inv_rows(int logn, const double2* __restrict__ tw,
+                                                             const double2* __restrict__ A,
+                                                             double* __restrict__ S)
+{
+    extern __shared__ double2 x[];
+    const int n = 1 << logn;
+    const size_t row = (size_t)blockIdx.x * n;
+    for (int e = threadIdx.x; e < n; e += kFftThreads) x[sw(e)] = A[row + e];
+    __syncthreads();
+    fft_row<true>(x, logn, tw);
+    for (int e = threadIdx.x; e < n; e += kFftThreads) S[row + e] = x[sw(e)].x;
+}
+
+// Per point: the velocity u = S n^ (not stored when u is null) and V.
+__global__ __launch_bounds__(kThreads) void k_lo_point(Mesh m, const double* __restrict__ S,
+                                                       const double* __restrict__ z,
+                                                       const double* __restrict__ w,
+                                                       double* __restrict__ u,
+                                                       double* __restrict__ V)
+{
+    const int N = m.N;
+    const int p = blockIdx.x * kThreads + threadIdx.x;
+    if (p >= N) return;
+    {
+        double T1[3], T2[3];
+        dev::tangents_at<1>(m, p, z, T1, T2);
+        const double nx = T1[1] * T2[2] - T1[2] * T2[1];
+        const double ny = T1[2] * T2[0] - T1[0] * T2[2];
+        const double nz = T1[0] * T2[1] - T1[1] * T2[0];
+        const double nn = nx * nx + ny * ny + nz * nz;
+        const double inv = 1.0 / sqrt(nn);
+        const double s = S[p];
+        const double u1 = s * (nx * inv), u2 = s * (ny * inv), u3 = s * (nz * inv);
+        if (u) {   // null for the medium-order model, which only needs V
+            u[p] = u1;
+            u[N + p] = u2;
+            u[2 * N + p] = u3;
         }
-        __syncthreads();
+        if (V) {
+            const double w1 = w[p], w2 = w[N + p];
+            const double g1 = w1 * T2[0] - w2 * T1[0];
+            const double g2 = w1 * T2[1] - w2 * T1[1];
+            const double g3 = w1 * T2[2] - w2 * T1[2];
+            const double q = (g1 * g1 + g2 * g2 + g3 * g3) / nn;
+            const double uu = u1 * u1 + u2 * u2 + u3 * u3;
+            V[p] = m.atwood * ((uu - 0.25 * q) - (2.0 * m.gravity) * z[2 * N + p]);
+        }
     }
-    for (int j = threadIdx.x; j < n; j += kThreads) row[j] = x[j];
 }
 
 // out[c][r] = in[r][c] for an rows x cols array; 32 x 32 tiles, 256 threads.
@@ -100,64 +295,6 @@ __global__ __launch_bounds__(kThreads) void k_transpose(const double2* __restric
     }
 }
 
-// b holds c^ as [m1][m2] (n1 rows of n2); writes S^ = (1/2) i (c1 w1^ +
-// c2 w2^) / N into a, same layout, with w1^ = (c^(m) + conj(c^(-m))) / 2 and
-// w2^ = (c^(m) - conj(c^(-m))) / (2 i); symbols c_a = k_a / |k| (zero at
-// k = 0 and, along axis a, at the unpaired mode m_a = n_a / 2).
-__global__ __launch_bounds__(kThreads) void k_riesz(int n1, int n2, double L1, double L2,
-                                                    const double2* __restrict__ b,
-                                                    double2* __restrict__ a)
-{
-    const int idx = blockIdx.x * kThreads + threadIdx.x;
-    if (idx >= n1 * n2) return;
-    const int m1 = idx / n2, m2 = idx - m1 * n2;
-    const int s1 = 2 * m1 < n1 ? m1 : m1 - n1;
-    const int s2 = 2 * m2 < n2 ? m2 : m2 - n2;
-    const double k1 = 2.0 * M_PI * s1 / L1, k2 = 2.0 * M_PI * s2 / L2;
-    const double kk = sqrt(k1 * k1 + k2 * k2);
-    double c1 = 0.0, c2 = 0.0;
-    if (kk > 0.0) {
-        c1 = (2 * m1 == n1) ? 0.0 : k1 / kk;
-        c2 = (2 * m2 == n2) ? 0.0 : k2 / kk;
-    }
-    const int q1 = m1 == 0 ? 0 : n1 - m1, q2 = m2 == 0 ? 0 : n2 - m2;
-    const double2 c = b[idx];
-    const double2 d = b[q1 * n2 + q2];
-    // (i c1 (c + conj d) + c2 (c - conj d)) / (4 N)
-    const double sx = c.x + d.x, sy = c.y - d.y;   // c + conj(d)
-    const double tx = c.x - d.x, ty = c.y + d.y;   // c - conj(d)
-    const double inv4n = 0.25 / ((double)n1 * (double)n2);
-    a[idx] = make_double2((-c1 * sy + c2 * tx) * inv4n, (c1 * sx + c2 * ty) * inv4n);
-}
-
-__global__ __launch_bounds__(kThreads) void k_low_velocity(Mesh m, const double* __restrict__ z,
-                                                           const double2* __restrict__ S,
-                                                           const double* __restrict__ q,
-                                                           double* __restrict__ u,
-                                                           double* __restrict__ V)
-{
-    const int p = blockIdx.x * kThreads + threadIdx.x;
-    if (p >= m.N) return;
-    const int N = m.N;
-    double T1[3], T2[3];
-    dev::tangents_at(m, p, z, T1, T2);
-    const double nx = T1[1] * T2[2] - T1[2] * T2[1];
-    const double ny = T1[2] * T2[0] - T1[0] * T2[2];
-    const double nz = T1[0] * T2[1] - T1[1] * T2[0];
-    const double inv = 1.0 / sqrt(nx * nx + ny * ny + nz * nz);
-    const double s = S[p].x;
-    const double u1 = s * (nx * inv), u2 = s * (ny * inv), u3 = s * (nz * inv);
-    if (u) {   // null for the medium-order model, which only needs V
-        u[p] = u1;
-        u[N + p] = u2;
-        u[2 * N + p] = u3;
-    }
-    if (V) {
-        const double uu = u1 * u1 + u2 * u2 + u3 * u3;
-        V[p] = m.atwood * ((uu - 0.25 * q[p]) - (2.0 * m.gravity) * z[2 * N + p]);
-    }
-}
-
 inline unsigned grid_for(long n) { return (unsigned)((n + kThreads - 1) / kThreads); }
 
 int log2i(int n)
@@ -165,17 +302,6 @@ int log2i(int n)
     int l = 0;
     while ((1 << l) < n) ++l;
     return l;
-}
-
-hipError_t fft_rows(double2* a, int rows, int n, const double2* tw, bool inv, hipStream_t s)
-{
-    const int logn = log2i(n);
-    const size_t lds = sizeof(double2) * (size_t)n;
-    if (inv)
-        hipLaunchKernelGGL(k_fft_rows<true>, dim3(rows), dim3(kThreads), lds, s, a, logn, tw);
-    else
-        hipLaunchKernelGGL(k_fft_rows<false>, dim3(rows), dim3(kThreads), lds, s, a, logn, tw);
-    return hipGetLastError();
 }
 
 hipError_t transpose(const double2* in, double2* out, int rows, int cols, hipStream_t s)
@@ -189,23 +315,24 @@ hipError_t transpose(const double2* in, double2* out, int rows, int cols, hipStr
 
 bool low_order_supported_side(int n) { return n >= 8 && n <= 4096 && (n & (n - 1)) == 0; }
 
-hipError_t launch_low_velocity(const Mesh& m, const double* z, const double* w, const double* q,
+hipError_t launch_low_velocity(const Mesh& m, const double* z, const double* w,
                                const LowBuffers& b, double* u, double* V, hipStream_t s)
 {
     const int n1 = m.n1, n2 = m.n2, N = m.N;
+    const int l1 = log2i(n1), l2 = log2i(n2);
     hipError_t e;
-    hipLaunchKernelGGL(k_twiddle, dim3(grid_for(n1 / 2)), dim3(kThreads), 0, s, n1, b.tw1);
-    hipLaunchKernelGGL(k_twiddle, dim3(grid_for(n2 / 2)), dim3(kThreads), 0, s, n2, b.tw2);
-    hipLaunchKernelGGL(k_pack, dim3(grid_for(N)), dim3(kThreads), 0, s, N, w, b.a);
-    if ((e = fft_rows(b.a, n2, n1, b.tw1, false, s)) != hipSuccess) return e;   // A[i2][m1]
-    if ((e = transpose(b.a, b.b, n2, n1, s)) != hipSuccess) return e;          // B[m1][i2]
-    if ((e = fft_rows(b.b, n1, n2, b.tw2, false, s)) != hipSuccess) return e;  // B[m1][m2]
-    hipLaunchKernelGGL(k_riesz, dim3(grid_for(N)), dim3(kThreads), 0, s, n1, n2, m.L1, m.L2, b.b,
-                       b.a);                                                    // A = S^[m1][m2]
-    if ((e = fft_rows(b.a, n1, n2, b.tw2, true, s)) != hipSuccess) return e;   // A[m1][i2]
-    if ((e = transpose(b.a, b.b, n1, n2, s)) != hipSuccess) return e;          // B[i2][m1]
-    if ((e = fft_rows(b.b, n2, n1, b.tw1, true, s)) != hipSuccess) return e;   // B[i2][i1] = S
-    hipLaunchKernelGGL(k_low_velocity, dim3(grid_for(N)), dim3(kThreads), 0, s, m, z, b.b, q, u, V);
+    hipLaunchKernelGGL(k_twiddle, dim3(grid_for(n1 > n2 ? n1 : n2)), dim3(kThreads), 0, s, n1,
+                       b.tw1, n2, b.tw2);
+    hipLaunchKernelGGL(k_lo_pack_rows, dim3(n2), dim3(kFftThreads), sizeof(double2) * n1, s, l1, N,
+                       w, b.tw1, b.a);                                        // A[i2][m1]
+    if ((e = transpose(b.a, b.b, n2, n1, s)) != hipSuccess) return e;       // B[m1][i2]
+    hipLaunchKernelGGL(k_lo_symbol_rows, dim3(n1), dim3(kFftThreads), sizeof(double2) * n2, s, n1,
+                       l2, m.L1, m.L2, b.tw2, b.b);                           // B[m1][i2]: S^ filtered
+    if ((e = transpose(b.b, b.a, n1, n2, s)) != hipSuccess) return e;       // A[i2][m1]
+    double* S = reinterpret_cast<double*>(b.b);   // B is spent after the second transpose
+    hipLaunchKernelGGL(k_lo_inv_rows, dim3(n2), dim3(kFftThreads), sizeof(double2) * n1, s, l1, b.tw1,
+                       b.a, S);
+    hipLaunchKernelGGL(k_lo_point, dim3(grid_for(N)), dim3(kThreads), 0, s, m, S, z, w, u, V);
     return hipGetLastError();
 }
 
