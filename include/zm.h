@@ -152,14 +152,21 @@ typedef struct zm_params {
 typedef struct zm_ctx zm_ctx;  /* opaque */
 
 /* Bytes of device workspace a context with these parameters needs (0 if the
- * parameters are invalid).  Pure host function. */
+ * parameters are invalid or the configuration is one zm_create refuses with
+ * ZM_ERR_UNSUPPORTED).  Pure host function. */
 size_t zm_workspace_bytes(const zm_params *params);
 
 /* Create a context on the current device.  d_workspace: caller-owned device
  * memory of at least zm_workspace_bytes(params) bytes, 256-byte aligned, kept
  * alive and unused by the caller until zm_destroy.  hip_stream: the
  * hipStream_t all work is enqueued on (NULL = null stream).  On success *out
- * receives the context; on failure *out is set to NULL. */
+ * receives the context; on failure *out is set to NULL.
+ * ZM_ERR_UNSUPPORTED for valid requests this library does not serve: FP32
+ * cutoff; low order on sides that are not powers of two <= 4096 (also
+ * medium order); and the FP32 pair form on meshes so anisotropic that a
+ * pair patch spans more than 128 finest mesh spacings (its FP32
+ * patch-relative coordinates would lose the 1e-5 bound there; FP64 serves
+ * them). */
 zm_status zm_create(zm_ctx **out, const zm_params *params,
                     void *d_workspace, size_t workspace_bytes, void *hip_stream);
 
@@ -283,12 +290,14 @@ zm_status zm_tuning_set(int32_t n1, int32_t n2, int32_t precision, const zm_pair
 /* The shape a new context of this size would use (entry or default). */
 zm_status zm_tuning_get(int32_t n1, int32_t n2, int32_t precision, zm_pair_tuning *out);
 
-/* Workspace bytes zm_autotune needs for these parameters (0 if invalid). */
+/* Workspace bytes zm_autotune needs for these parameters (0 if invalid, or
+ * if the FP32 pair form is refused on this mesh: see zm_create). */
 size_t zm_autotune_workspace_bytes(const zm_params *params);
 
 /* Time the pair kernel on synthetic data of this mesh size for every
  * candidate shape (targets per lane 1, 2, 4 x source splits around the
- * default), store the fastest in the table and return it (best, and its
+ * default; for FP32 only the shapes the FP32 form accepts on this mesh,
+ * ZM_ERR_UNSUPPORTED if none), store the fastest in the table and return it (best, and its
  * time per launch in best_ms; either may be NULL).  Synchronous: waits for
  * its own work on hip_stream.  Uses only the caller's workspace. */
 zm_status zm_autotune(const zm_params *params, void *d_workspace, size_t workspace_bytes,

@@ -192,6 +192,7 @@ size_t zm_workspace_bytes(const zm_params* params)
                                              !zm::low_order_supported_side(params->n2)))
         return 0;
     const zm::PairShape sh = zm::choose_pair_shape(params->n1, params->n2, params->precision);
+    if (params->model != ZM_MODEL_LOW && zm::fp32_shape_problem(*params, sh)) return 0;
     return make_layout(*params, sh).total;
 }
 
@@ -218,6 +219,12 @@ zm_status zm_create(zm_ctx** out, const zm_params* params, void* d_workspace,
         return ZM_ERR_UNSUPPORTED;
     }
     const zm::PairShape sh = zm::choose_pair_shape(params->n1, params->n2, params->precision);
+    if (params->model != ZM_MODEL_LOW) {
+        if (const char* why = zm::fp32_shape_problem(*params, sh)) {
+            g_create_error = why;
+            return ZM_ERR_UNSUPPORTED;
+        }
+    }
     const Layout L = make_layout(*params, sh);
     if (!d_workspace || !aligned(d_workspace)) {
         g_create_error = "workspace is NULL or not 256-byte aligned";

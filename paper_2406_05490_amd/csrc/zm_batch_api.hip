@@ -52,6 +52,7 @@ const char* plan_batch(const zm_params* params, int32_t count, BatchPlan& P)
         if (params[i].boundary != ZM_BOUNDARY_PERIODIC) return "free sheets are not available in a batch";
         const zm::PairShape sh =
             zm::choose_pair_shape(params[i].n1, params[i].n2, params[i].precision);
+        if (const char* why = zm::fp32_shape_problem(params[i], sh)) return why;
         const zm::Layout L = zm::make_layout(params[i], sh);
         P.shapes.push_back(sh);
         P.layouts.push_back(L);
@@ -220,7 +221,10 @@ zm_status zm_batch_create(zm_batch** out, const zm_params* params, int32_t count
         bool cut = false;
         for (int i = 0; params && i < count; ++i)
             cut = cut || params[i].cutoff != 0.0 || params[i].model != ZM_MODEL_HIGH ||
-                  params[i].boundary != ZM_BOUNDARY_PERIODIC;
+                  params[i].boundary != ZM_BOUNDARY_PERIODIC ||
+                  (!zm::validate(&params[i]) &&
+                   zm::fp32_shape_problem(params[i], zm::choose_pair_shape(params[i].n1, params[i].n2,
+                                                                           params[i].precision)));
         return cut ? ZM_ERR_UNSUPPORTED : ZM_ERR_INVALID_ARG;
     }
     if (!zm::aligned(d_workspace) || workspace_bytes < b->plan.total) {

@@ -91,6 +91,29 @@ inline Layout make_layout(const zm_params& p, const zm::PairShape& sh)
     return L;
 }
 
+// FP32 pair form: sources are staged as FP32 offsets from a patch centre,
+// so a pair's r carries an absolute error of about ulp(patch extent) while
+// near pairs sit about one mesh spacing apart.  The form keeps its error
+// bound (1e-5 normwise; 6.5e-7 measured at 36 spacings) while the patch
+// extent stays within this many finest spacings; beyond it (very
+// anisotropic meshes, e.g. 8192 x 8 on a square period) the FP32 form is
+// refused and FP64 must be used.
+constexpr double kF32MaxExtentSpacings = 128.0;
+
+// Reason the FP32 pair form cannot serve these params with this shape, or
+// nullptr (always nullptr for FP64).
+inline const char* fp32_shape_problem(const zm_params& p, const zm::PairShape& sh)
+{
+    if (p.precision != ZM_FP32_PAIRS) return nullptr;
+    const double h1 = p.period1 / p.n1, h2 = p.period2 / p.n2;
+    const double cols = sh.cx < p.n1 ? sh.cx : p.n1;
+    const double rows = sh.prow < p.n2 ? sh.prow : p.n2;
+    const double ext = std::sqrt(cols * cols * h1 * h1 + rows * rows * h2 * h2);
+    if (ext <= kF32MaxExtentSpacings * std::fmin(h1, h2)) return nullptr;
+    return "the FP32 pair form needs patches within 128 finest mesh spacings (this mesh is too "
+           "anisotropic for it); use FP64";
+}
+
 inline const char* validate(const zm_params* p)
 {
     if (!p) return "params is NULL";

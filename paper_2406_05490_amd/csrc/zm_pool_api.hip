@@ -256,6 +256,9 @@ size_t zm_pool_request_bytes(const zm_params* params)
     if (zm::validate(params) || params->flags != 0 || params->cutoff != 0.0 ||
         params->model != ZM_MODEL_HIGH || params->boundary != ZM_BOUNDARY_PERIODIC)
         return 0;
+    if (zm::fp32_shape_problem(*params,
+                               zm::choose_pair_shape(params->n1, params->n2, params->precision)))
+        return 0;
     return request_bytes(*params, nullptr, nullptr);
 }
 
@@ -307,6 +310,9 @@ zm_status zm_pool_submit(zm_pool* P, const zm_params* params, const double* d_z,
         return pfail(P, ZM_ERR_UNSUPPORTED, "the low-order model is not available in a pool");
     if (params->boundary != ZM_BOUNDARY_PERIODIC)
         return pfail(P, ZM_ERR_UNSUPPORTED, "free sheets are not available in a pool");
+    if (const char* why = zm::fp32_shape_problem(
+            *params, zm::choose_pair_shape(params->n1, params->n2, params->precision)))
+        return pfail(P, ZM_ERR_UNSUPPORTED, why);
     if (steps < 1) return pfail(P, ZM_ERR_INVALID_ARG, "steps must be >= 1");
     if (!zm::aligned(d_z) || !zm::aligned(d_w))
         return pfail(P, ZM_ERR_INVALID_ARG, "state pointers must be non-NULL and 256-byte aligned");

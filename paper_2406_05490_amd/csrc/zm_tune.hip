@@ -24,12 +24,14 @@ bool valid_tuning(const zm_pair_tuning& t)
 }
 
 // Candidate shapes: R in {1, 2, 4} x splits in {s0/4, s0/2, s0, 2 s0} where s0
-// is the default split count for that R, clamped to [1, n2], deduplicated.
+// is the default split count for that R, clamped to [1, n2], deduplicated;
+// for the FP32 form only the R whose patches keep its error bound.
 std::vector<zm::PairShape> candidates(const zm_params& p)
 {
     std::vector<zm::PairShape> out;
     for (int R : {1, 2, 4}) {
         const zm::PairShape d = zm::make_pair_shape(p.n1, p.n2, p.precision, R, 0);
+        if (zm::fp32_shape_problem(p, d)) continue;
         for (int f : {-2, -1, 0, 1}) {
             int s = f < 0 ? d.splits >> (-f) : d.splits << f;
             const zm::PairShape sh = zm::make_pair_shape(p.n1, p.n2, p.precision, R, std::max(1, s));
@@ -102,7 +104,7 @@ zm_status zm_tuning_get(int32_t n1, int32_t n2, int32_t precision, zm_pair_tunin
 
 size_t zm_autotune_workspace_bytes(const zm_params* params)
 {
-    if (zm::validate(params)) return 0;
+    if (zm::validate(params) || candidates(*params).empty()) return 0;
     return tune_layout(*params).total;
 }
 
@@ -110,6 +112,7 @@ zm_status zm_autotune(const zm_params* params, void* d_workspace, size_t workspa
                       void* hip_stream, zm_pair_tuning* best, double* best_ms)
 {
     if (zm::validate(params)) return ZM_ERR_INVALID_ARG;
+    if (candidates(*params).empty()) return ZM_ERR_UNSUPPORTED;   // FP32 form refused on this mesh
     const TuneLayout L = tune_layout(*params);
     if (!zm::aligned(d_workspace) || workspace_bytes < L.total) return ZM_ERR_WORKSPACE;
     hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);

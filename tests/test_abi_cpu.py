@@ -85,6 +85,23 @@ def test_free_sheet_cutoff_takes_any_radius():
     assert zm.workspace_bytes(zm.Params(64, 64, eps=1 / 64, cutoff=5.0)) == 0
 
 
+def test_fp32_refused_on_very_anisotropic_meshes():
+    """The FP32 pair form needs pair patches within 128 finest mesh spacings;
+    8192 x 8 on a square period spans thousands.  FP64 serves the same mesh;
+    square meshes always pass."""
+    for n1, n2 in ((8192, 8), (8, 8192), (4096, 16)):
+        p32 = zm.Params(n1, n2, eps=1e-3, precision=zm.ZM_FP32_PAIRS)
+        assert zm.workspace_bytes(p32) == 0
+        st, _, msg = _create(p32, None, 0)
+        assert st == zm.ZM_ERR_UNSUPPORTED and "anisotropic" in msg
+        assert zm.workspace_bytes(zm.Params(n1, n2, eps=1e-3)) > 0
+        assert zm.batch_workspace_bytes([p32]) == 0
+        assert zm.pool_request_bytes(p32) == 0
+    for n in (8, 12, 33, 64, 256, 1024, 8192):
+        assert zm.workspace_bytes(zm.Params(n, n, eps=1.0 / n, precision=zm.ZM_FP32_PAIRS)) > 0
+    assert zm.workspace_bytes(zm.Params(1024, 256, eps=1e-3, precision=zm.ZM_FP32_PAIRS)) > 0
+
+
 def test_medium_order_workspace_and_status():
     """Medium order: the BR workspace plus the FFT buffers; power-of-two sides."""
     hi = zm.workspace_bytes(zm.Params(64, 64, eps=1 / 64))
