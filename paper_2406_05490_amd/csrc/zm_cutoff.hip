@@ -281,10 +281,63 @@ struct CutTarget {
     uint64_t amask;     // lanes of the wave that hold real targets
 };
 
-// Sum the sources [s0, s1) of one cell into the lane's accumulators.  The
-// next source record is loaded while the current one is used; a source that
-// no lane of the wave accepts skips the kernel evaluation (a wave-uniform
-// branch: the accepted set, and so every sum, is unchanged).
+// One source record in scalar registers.
+struct SrcRec {
+    double x, y, z, g1, g2, g3, k1, k2;
+};
+
+__device__ __forceinline__ SrcRec load_rec(const double* __restrict__ src, int j)
+{
+    const double* s = src + (size_t)j * 8;   // the same address in every lane
+    return SrcRec{s[0], s[1], s[2], s[3], s[4], s[5], s[6], s[7]};
+}
+
+// One (target, source) pair: d1 = x_i - x_j is formed by the caller.  A
+// source that no lane of the wave accepts skips the kernel evaluation (a
+// wave-uniform branch: the accepted set, and so every sum, is unchanged).
+template <int SHIFT, bool COUNT>
+__device__ __forceinline__ void cut_pair(const Mesh& m, const CutGrid& g, const CutTarget& t,
+                                         const SrcRec& b, double d1, double SL1, double SL2,
+                                         double& acc0, double& acc1, double& acc2,
+                                         unsigned long long& tested, unsigned long long& accepted)
+{
+#pragma clang fp contract(off)
+    const double d2 = t.y - b.y;
+    double r1, r2;
+    if (SHIFT == kShiftNone) {
+        r1 = d1;
+        r2 = d2;
+    } else if (SHIFT == kShiftUniform) {
+        r1 = d1 - SL1;
+        r2 = d2 - SL2;
+    } else {
+        const double S1 = t.Kx - b.k1, S2 = t.Ky - b.k2;
+        r1 = d1 - S1 * g.L1;
+        r2 = d2 - S2 * g.L2;
+    }
+    const double r3 = t.z - b.z;
+    const double dd = r1 * r1 + r2 * r2 + r3 * r3;
+    const bool in = dd < g.rc2;
+    if (COUNT) {
+        tested += t.active ? 1 : 0;
+        accepted += (t.active && in) ? 1 : 0;
+    }
+    if ((__builtin_amdgcn_ballot_w64(in) & t.amask) == 0ull) return;
+    const double wgt = in ? dev::inv_cube_sqrt(dd + m.eps2) : 0.0;
+    const double a1 = wgt * b.g1, a2 = wgt * b.g2, a3 = wgt * b.g3;
+    acc0 = fma(r2, a3, acc0);
+    acc0 = fma(-r3, a2, acc0);
+    acc1 = fma(r3, a1, acc1);
+    acc1 = fma(-r1, a3, acc1);
+    acc2 = fma(r1, a2, acc2);
+    acc2 = fma(-r2, a1, acc2);
+}
+
+// Sum the sources [s0, s1) of one cell into the lane's accumulators, two at
+// a time.  Scalar loads may return out of order, so a wait is always a wait
+// for every load in flight: the next pair is issued only after the current
+// pair has arrived (its first use sits before a scheduling barrier), which
+// leaves a whole pair of evaluations to hide the next pair's latency.
 template <int SHIFT, bool COUNT>
 __device__ __forceinline__ void cut_cell(const Mesh& m, const CutGrid& g,
                                          const double* __restrict__ src, int s0, int s1,
@@ -294,45 +347,19 @@ __device__ __forceinline__ void cut_cell(const Mesh& m, const CutGrid& g,
                                          unsigned long long& accepted)
 {
     if (s0 >= s1) return;
-    const double* sj = src + (size_t)s0 * 8;
-    double nx = sj[0], ny = sj[1], nz = sj[2], n1 = sj[3], n2 = sj[4], n3 = sj[5];
-    double nk1 = sj[6], nk2 = sj[7];
-    for (int j = s0; j < s1; ++j) {
+    const int last = s1 - 1;
+    SrcRec p0 = load_rec(src, s0), p1 = load_rec(src, s0 + 1 < s1 ? s0 + 1 : last);
+    for (int j = s0; j < s1; j += 2) {
 #pragma clang fp contract(off)
-        const double bx = nx, by = ny, bz = nz, g1 = n1, g2 = n2, g3 = n3;
-        const double k1 = nk1, k2 = nk2;
-        const double* sn = src + (size_t)(j + 1 < s1 ? j + 1 : j) * 8;   // same in every lane
-        nx = sn[0]; ny = sn[1]; nz = sn[2]; n1 = sn[3]; n2 = sn[4]; n3 = sn[5];
-        nk1 = sn[6]; nk2 = sn[7];
-        const double d1 = t.x - bx, d2 = t.y - by;
-        double r1, r2;
-        if (SHIFT == kShiftNone) {
-            r1 = d1;
-            r2 = d2;
-        } else if (SHIFT == kShiftUniform) {
-            r1 = d1 - SL1;
-            r2 = d2 - SL2;
-        } else {
-            const double S1 = t.Kx - k1, S2 = t.Ky - k2;
-            r1 = d1 - S1 * g.L1;
-            r2 = d2 - S2 * g.L2;
-        }
-        const double r3 = t.z - bz;
-        const double dd = r1 * r1 + r2 * r2 + r3 * r3;
-        const bool in = dd < g.rc2;
-        if (COUNT) {
-            tested += t.active ? 1 : 0;
-            accepted += (t.active && in) ? 1 : 0;
-        }
-        if ((__builtin_amdgcn_ballot_w64(in) & t.amask) == 0ull) continue;
-        const double wgt = in ? dev::inv_cube_sqrt(dd + m.eps2) : 0.0;
-        const double a1 = wgt * g1, a2 = wgt * g2, a3 = wgt * g3;
-        acc0 = fma(r2, a3, acc0);
-        acc0 = fma(-r3, a2, acc0);
-        acc1 = fma(r3, a1, acc1);
-        acc1 = fma(-r1, a3, acc1);
-        acc2 = fma(r1, a2, acc2);
-        acc2 = fma(-r2, a1, acc2);
+        const SrcRec c0 = p0, c1 = p1;
+        const double d1a = t.x - c0.x, d1b = t.x - c1.x;   // the pair has arrived
+        __builtin_amdgcn_sched_barrier(0);
+        p0 = load_rec(src, j + 2 < s1 ? j + 2 : last);
+        p1 = load_rec(src, j + 3 < s1 ? j + 3 : last);
+        __builtin_amdgcn_sched_barrier(0);
+        cut_pair<SHIFT, COUNT>(m, g, t, c0, d1a, SL1, SL2, acc0, acc1, acc2, tested, accepted);
+        if (j + 1 < s1)
+            cut_pair<SHIFT, COUNT>(m, g, t, c1, d1b, SL1, SL2, acc0, acc1, acc2, tested, accepted);
     }
 }
 
