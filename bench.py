@@ -384,8 +384,8 @@ def low_order_section(zm, torch, n: int = 4096, steps: int = 5):
     the largest power of two below it), per-kernel times, mesh points
     advanced per second, and the HBM rate of the FFT velocity against its
     algorithmic traffic: pack + row FFT (w in, complex out), transpose,
-    FFT-symbol-inverse-FFT rows, transpose, inverse row FFT + velocity
-    (complex, z, w in; u, V out)."""
+    FFT-symbol-inverse-FFT rows, transpose, inverse row FFT (complex in, S
+    out), point kernel (S, z, w in; u, V out)."""
     z, _ = rr.multi_mode(n, n, 8, seed=1)
     w = rr.synthetic_vorticity(n, n, seed=1)
     dev = torch.device("cuda:0")
@@ -405,9 +405,9 @@ def low_order_section(zm, torch, n: int = 4096, steps: int = 5):
     N = n * n
     # bytes of one FFT-velocity evaluation per point: pack + FFT rows (w 16
     # in, 16 out), two transposes and the symbol rows (16 in + 16 out each),
-    # inverse FFT + velocity (complex 16, z 24 with neighbours from cache,
-    # w 16 in; u 24, V 8 out)
-    fft_bytes = N * (32 + 3 * 32 + 88)
+    # inverse FFT rows (16 in, S 8 out), point kernel (S 8, z 24 with its
+    # stencil neighbours from cache, w 16 in; u 24, V 8 out)
+    fft_bytes = N * (32 + 3 * 32 + 24 + 80)
     return {"mesh": f"{n}x{n}", "steps": steps, "ms_per_step": wall / steps * 1e3,
             "points_per_s": N * steps / wall, "kernel_ms_per_eval": ms,
             "fft_velocity_bytes_per_eval": fft_bytes,
