@@ -13,7 +13,7 @@ import pytest
 
 import oracle
 import rocket_rig as rr
-from zm_testutil import relerr, to_dev, to_host
+from zm_testutil import fft_reference, relerr, to_dev, to_host
 
 pytestmark = pytest.mark.gpu
 
@@ -72,26 +72,6 @@ def test_fp32_refused_where_its_bound_fails(gpu):
     with pytest.raises(zm.ZMError) as e:
         zm.Context(zm.Params(8192, 8, eps=1e-3, precision=zm.ZM_FP32_PAIRS))
     assert e.value.status == zm.ZM_ERR_UNSUPPORTED
-
-
-def fft_reference(n1, n2, z, w, L1=2.0, L2=2.0):
-    """u = 1/2 (R1 w1 + R2 w2) n^ by numpy's FFT (the definition's symbols,
-    Nyquist modes zeroed along their own axis); n^ from the oracle's
-    tangents."""
-    W1 = np.fft.fft2(w[0].reshape(n2, n1))
-    W2 = np.fft.fft2(w[1].reshape(n2, n1))
-    K1 = 2 * np.pi * np.fft.fftfreq(n1, 1.0 / n1)[None, :] / L1 + 0 * np.arange(n2)[:, None]
-    K2 = 2 * np.pi * np.fft.fftfreq(n2, 1.0 / n2)[:, None] / L2 + 0 * np.arange(n1)[None, :]
-    KK = np.hypot(K1, K2)
-    with np.errstate(invalid="ignore", divide="ignore"):
-        c1 = np.where(KK > 0, K1 / KK, 0.0)
-        c2 = np.where(KK > 0, K2 / KK, 0.0)
-    c1[:, n1 // 2] = 0.0
-    c2[n2 // 2, :] = 0.0
-    S = np.real(np.fft.ifft2(0.5j * (c1 * W1 + c2 * W2))).ravel()
-    t1, t2 = oracle.tangents(oracle.Problem(n1, n2, eps=1.0 / n1, period1=L1, period2=L2), z)
-    nrm = np.cross(t1.T, t2.T).T
-    return S * (nrm / np.linalg.norm(nrm, axis=0))
 
 
 @pytest.mark.parametrize("n1,n2", [(4096, 8), (8, 4096), (4096, 16)])

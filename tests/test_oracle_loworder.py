@@ -138,3 +138,17 @@ def test_low_order_rejects_sampling_and_cutoff():
         oracle.br_velocity(prob(8), z, w, targets=[0, 1])
     with pytest.raises(ValueError):
         oracle.br_velocity(prob(8, cutoff=0.3), z, w)
+
+
+@pytest.mark.parametrize("n1,n2,L1,L2", [(16, 16, 2.0, 2.0), (32, 8, 2.0, 2.0), (8, 32, 3.0, 1.5)])
+def test_numpy_fft_reference_matches_oracle(n1, n2, L1, L2):
+    """The numpy-FFT evaluation the large GPU tests compare with agrees with
+    the oracle's direct DFT sums."""
+    from zm_testutil import fft_reference
+    z, w = rr.random_state(n1, n2, seed=n1 + n2, height=0.1)
+    z[0] *= L1 / 2.0
+    z[1] *= L2 / 2.0
+    P = oracle.Problem(n1, n2, eps=1.0 / n1, period1=L1, period2=L2, model=1)
+    u = oracle.br_velocity(P, z, w)
+    ref = fft_reference(n1, n2, z, w, L1, L2)
+    assert np.max(np.abs(ref - u)) < 1e-13 * np.max(np.abs(u))
