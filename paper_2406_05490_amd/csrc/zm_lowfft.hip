@@ -239,19 +239,54 @@ __global__ __launch_bounds__(kFftThreads) void k_lo_inv_rows(int logn, const dou
     for (int e = threadIdx.x; e < n; e += kFftThreads) S[row + e] = x[sw(e)].x;
 }
 
-// Per point: the velocity u = S n^ (not stored when u is null) and V.
-__global__ __launch_bounds__(kThreads) void k_lo_point(Mesh m, const double* __restrict__ S,
+// Per point: the velocity u = S n^ (not stored when u is null) and V.  A
+// 256-thread workgroup owns a tile of tx x ty points (tx = min(64, n1),
+// ty = min(256 / tx, n2)); the three position planes of the tile and a
+// 2-point halo are staged in LDS once, seam-corrected as they are loaded
+// (z1 + w L1 across the i1 seam, z2 + w L2 across the i2 seam, exactly as the
+// stencil helper adds them), so the 5-point tangents read LDS instead of
+// issuing 24 global loads per point.  Periodic meshes only (the FFT models
+// are periodic).
+constexpr int kTileMax = (64 + 4) * (4 + 4);   // largest (tx + 4)(ty + 4) over the tile shapes
+
+__global__ __launch_bounds__(kThreads) void k_lo_point(Mesh m, int tx, int ty,
+                                                       const double* __restrict__ S,
                                                        const double* __restrict__ z,
                                                        const double* __restrict__ w,
                                                        double* __restrict__ u,
                                                        double* __restrict__ V)
 {
-    const int N = m.N;
-    const int p = blockIdx.x * kThreads + threadIdx.x;
-    if (p >= N) return;
+    __shared__ double tz[3][kTileMax];
+    const int n1 = m.n1, n2 = m.n2, N = m.N;
+    const int W = tx + 4, H = ty + 4;
+    const int x0 = blockIdx.x * tx, y0 = blockIdx.y * ty;
+    for (int e = threadIdx.x; e < W * H; e += kThreads) {
+        const int ly = e / W, lx = e - ly * W;
+        int w1, w2;
+        const int j1 = dev::nbr(x0 - 2, lx, n1, w1);
+        const int j2 = dev::nbr(y0 - 2, ly, n2, w2);
+        const size_t q = (size_t)j2 * n1 + j1;
+        double a = z[q], b = z[N + q];
+        if (w1 != 0) a = a + (double)w1 * m.L1;
+        if (w2 != 0) b = b + (double)w2 * m.L2;
+        tz[0][e] = a;
+        tz[1][e] = b;
+        tz[2][e] = z[2 * (size_t)N + q];
+    }
+    __syncthreads();
+    const int ly = threadIdx.x / tx, lx = threadIdx.x - ly * tx;
+    const int i1 = x0 + lx, i2 = y0 + ly;
+    if (ly >= ty || i1 >= n1 || i2 >= n2) return;   // no barrier follows
+    const int p = i2 * n1 + i1;
+    const int c0 = (ly + 2) * W + (lx + 2);
+    double T1[3], T2[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const double* t = tz[c];
+        T1[c] = dev::d1_5pt(t[c0 - 2], t[c0 - 1], t[c0 + 1], t[c0 + 2], m.h1);
+        T2[c] = dev::d1_5pt(t[c0 - 2 * W], t[c0 - W], t[c0 + W], t[c0 + 2 * W], m.h2);
+    }
     {
-        double T1[3], T2[3];
-        dev::tangents_at<1>(m, p, z, T1, T2);
         const double nx = T1[1] * T2[2] - T1[2] * T2[1];
         const double ny = T1[2] * T2[0] - T1[0] * T2[2];
         const double nz = T1[0] * T2[1] - T1[1] * T2[0];
@@ -332,7 +367,10 @@ hipError_t launch_low_velocity(const Mesh& m, const double* z, const double* w,
     double* S = reinterpret_cast<double*>(b.b);   // B is spent after the second transpose
     hipLaunchKernelGGL(k_lo_inv_rows, dim3(n2), dim3(kFftThreads), sizeof(double2) * n1, s, l1, b.tw1,
                        b.a, S);
-    hipLaunchKernelGGL(k_lo_point, dim3(grid_for(N)), dim3(kThreads), 0, s, m, S, z, w, u, V);
+    const int tx = n1 < 64 ? n1 : 64;
+    const int ty = kThreads / tx < n2 ? kThreads / tx : n2;
+    hipLaunchKernelGGL(k_lo_point, dim3(n1 / tx, (n2 + ty - 1) / ty), dim3(kThreads), 0, s, m, tx, ty,
+                       S, z, w, u, V);
     return hipGetLastError();
 }
 
