@@ -243,7 +243,7 @@ constexpr double kF32NearExtents = 4.0;
 struct F32Tile {
     float4 a[2][kThreads];
     float4 b[2][kThreads];
-    float c[2][kThreads];
+    float2 c[2][kThreads];   // (c3, |b|^2 + eps^2)
 };
 
 // MODE 0: direct form; 1: direct form with the antipodal-band image
@@ -257,6 +257,16 @@ __device__ __forceinline__ void pair_segment_f32(const F32Tile& T, int buf, int 
                                                  const float* ay, const float* az, float eps2,
                                                  float (*G)[3], float (*C)[3])
 {
+    float mx[R], my[R], mz[R], aa[R];   // -2 a and |a|^2 (far-field form only)
+    if (MODE == 2) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            mx[r] = -2.f * ax[r];
+            my[r] = -2.f * ay[r];
+            mz[r] = -2.f * az[r];
+            aa[r] = fmaf(ax[r], ax[r], fmaf(ay[r], ay[r], az[r] * az[r]));
+        }
+    }
 #pragma unroll ZM_PAIR32_UNROLL
     for (int c = 0; c < cnt; ++c) {
         const float4 v0 = T.a[buf][k0 + c];
@@ -271,13 +281,14 @@ __device__ __forceinline__ void pair_segment_f32(const F32Tile& T, int buf, int 
         const float by = v0.y, bz = v0.z;
         const float g1 = v0.w, g2 = v1.x, g3 = v1.y;
         if (MODE == 2) {
-            const float c1 = v1.z, c2 = v1.w, c3 = T.c[buf][k0 + c];
+            const float2 cb = T.c[buf][k0 + c];
+            const float c1 = v1.z, c2 = v1.w, c3 = cb.x, bb = cb.y;
 #pragma unroll
             for (int r = 0; r < R; ++r) {
-                const float r1 = ax[r] - bx;
-                const float r2 = ay[r] - by;
-                const float r3 = az[r] - bz;
-                const float s = fmaf(r1, r1, fmaf(r2, r2, fmaf(r3, r3, eps2)));
+                // |a - b|^2 + eps^2 = |a|^2 + (|b|^2 + eps^2 - 2 a.b): outside the
+                // near box (|r| >= 4 half-extents beyond the patch) the
+                // expansion's rounding stays within (1 + 2/4)^2 ulp
+                const float s = fmaf(mz[r], bz, fmaf(my[r], by, fmaf(mx[r], bx, bb))) + aa[r];
                 const float y = __builtin_amdgcn_rsqf(s);
                 const float wgt = y * y * y;
                 G[r][0] = fmaf(wgt, g1, G[r][0]);
@@ -398,7 +409,7 @@ __device__ __forceinline__ void pairs_f32_block(const Mesh& m, const PairShape& 
 
     // ---- staging: source j relative to the centre, centre's image --------
     float4 st0, st1;
-    float st2;
+    float2 st2;
     auto load_tile = [&](int t) {
         const int tile = t % ntiles;
         const int j = src_begin + tile * kThreads + tid;
@@ -410,14 +421,17 @@ __device__ __forceinline__ void pairs_f32_block(const Mesh& m, const PairShape& 
             const double by = (z[N + j] + (double)sc2 * m.L2) - cy;
             const double bz = z[2 * N + j] - cz;
             const double g1 = gam[j], g2 = gam[N + j], g3 = gam[2 * N + j];
-            st0 = make_float4((float)bx, (float)by, (float)bz, (float)g1);
+            const float bxf = (float)bx, byf = (float)by, bzf = (float)bz;
+            st0 = make_float4(bxf, byf, bzf, (float)g1);
             st1 = make_float4((float)g2, (float)g3, (float)(by * g3 - bz * g2),
                               (float)(bz * g1 - bx * g3));
-            st2 = (float)(bx * g2 - by * g1);
+            // |b|^2 + eps^2 of the staged (rounded) offsets, rounded once
+            const double bbd = (double)bxf * bxf + (double)byf * byf + (double)bzf * bzf + (double)eps2f;
+            st2 = make_float2((float)(bx * g2 - by * g1), (float)bbd);
         } else {
             st0 = make_float4(0.f, 0.f, 0.f, 0.f);
             st1 = make_float4(0.f, 0.f, 0.f, 0.f);
-            st2 = 0.f;
+            st2 = make_float2(0.f, 1.f);
         }
     };
     auto store_tile = [&](int buf) {
@@ -545,11 +559,27 @@ __host__ __device__ inline bool factored_ok(const Mesh& m, int PX, int PY)
     return ex * ex + ey * ey <= lim * lim;
 }
 
-template <int R, bool BAND>
+enum { kF64Direct = 0, kF64FactNear = 1, kF64FactFar = 2 };
+
+// Near box half-width beyond the patch, in patch half-extents, for the
+// expanded |r|^2 of the FP64 factored form.  A source outside it lies at
+// least one half-extent beyond the patch, so |r| >= ext >= |a| and the
+// expansion's rounding, ulp * (|a| + |b|)^2 / |r|^2 with |b| <= |r| + |a|,
+// stays below 9 ulp (1 + 2 |a| / |r|)^2.
+#ifndef ZM_F64_NEAR_EXTENTS
+#define ZM_F64_NEAR_EXTENTS 1.0
+#endif
+constexpr double kF64NearExtents = ZM_F64_NEAR_EXTENTS;
+
+// MODE: kF64Direct (direct form, antipodal band), kF64FactNear (factored,
+// |r|^2 from r = a - b), kF64FactFar (factored, |r|^2 expanded as
+// |a|^2 + |b|^2 + eps^2 - 2 a.b: only for sources outside the near box,
+// where |r| >= |a| bounds its rounding by a few ulp).
+template <int R, int MODE>
 __device__ __forceinline__ void pair_segment_f64f(const double2 (*__restrict__ buf)[kThreads],
                                                   int k0, int cnt, int j1s, int b1, int s1lo,
                                                   int bc1, int sc1lo, double L1, const double* ax, const double* ay,
-                                                  const double* az, double eps2,
+                                                  const double* az, const double* aa, double eps2,
                                                   double (*A)[3], double (*B)[3])
 {
 #pragma unroll ZM_PAIR_UNROLL
@@ -557,19 +587,20 @@ __device__ __forceinline__ void pair_segment_f64f(const double2 (*__restrict__ b
         const double2 v0 = buf[0][k0 + c];
         const double2 v1 = buf[1][k0 + c];
         const double2 v2 = buf[2][k0 + c];
-        double bx = v0.x;
-        const double by = v0.y, bz = v1.x;
+        double mx = v0.x;   // m = -2 b (exact)
+        const double my = v0.y, mz = v1.x;
         const double g1 = v1.y, g2 = v2.x, g3 = v2.y;
-        if (BAND) {
+        if (MODE == kF64Direct) {
             const int jj = j1s + c;
             const int si = (jj < b1) ? s1lo : s1lo - 1;
             const int sc = (jj < bc1) ? sc1lo : sc1lo - 1;
-            bx = fma((double)(si - sc), L1, bx);
+            // -2 (b_x + d L1) rounded once: exactly -2 times the rounded b_x + d L1
+            mx = fma(-2.0 * (double)(si - sc), L1, mx);
 #pragma unroll
             for (int r = 0; r < R; ++r) {
-                const double r1 = ax[r] - bx;
-                const double r2 = ay[r] - by;
-                const double r3 = az[r] - bz;
+                const double r1 = fma(0.5, mx, ax[r]);   // a - b, rounded as the subtraction is
+                const double r2 = fma(0.5, my, ay[r]);
+                const double r3 = fma(0.5, mz, az[r]);
                 const double s = fma(r1, r1, fma(r2, r2, fma(r3, r3, eps2)));
                 const double wgt = inv_cube_sqrt(s);
                 const double a1 = wgt * g1, a2 = wgt * g2, a3 = wgt * g3;
@@ -583,13 +614,19 @@ __device__ __forceinline__ void pair_segment_f64f(const double2 (*__restrict__ b
         } else {
             const double2 v3 = buf[3][k0 + c];
             const double2 v4 = buf[4][k0 + c];
-            const double c1 = v3.x, c2 = v3.y, c3 = v4.x;
+            const double c1 = v3.x, c2 = v3.y, c3 = v4.x, bb = v4.y;   // bb = |b|^2 + eps^2
 #pragma unroll
             for (int r = 0; r < R; ++r) {
-                const double r1 = ax[r] - bx;
-                const double r2 = ay[r] - by;
-                const double r3 = az[r] - bz;
-                const double s = fma(r1, r1, fma(r2, r2, fma(r3, r3, eps2)));
+                double s;
+                if (MODE == kF64FactFar) {
+                    // |a - b|^2 + eps^2 = |a|^2 + (|b|^2 + eps^2 - 2 a.b): 4 operations instead of 6
+                    s = fma(az[r], mz, fma(ay[r], my, fma(ax[r], mx, bb))) + aa[r];
+                } else {
+                    const double r1 = fma(0.5, mx, ax[r]);
+                    const double r2 = fma(0.5, my, ay[r]);
+                    const double r3 = fma(0.5, mz, az[r]);
+                    s = fma(r1, r1, fma(r2, r2, fma(r3, r3, eps2)));
+                }
                 const double wgt = inv_cube_sqrt(s);
                 A[r][0] = fma(wgt, g1, A[r][0]);
                 A[r][1] = fma(wgt, g2, A[r][1]);
@@ -632,6 +669,14 @@ __device__ __forceinline__ void pairs_f64f_block(const Mesh& m, const PairShape&
     const int band_lo = axis_img_m(m, c0, n1).b;   // n1 (no band) on a free sheet
     const bool band_all = PX >= n1 || !factored_ok(m, PX, PY);
     const bool band_wraps = m.periodic && band_lo + PX > n1;
+    // near box: the patch widened by kF64NearExtents patch half-extents
+    const double ext = 0.5 * sqrt((double)(PX * PX) * m.h1 * m.h1 + (double)(PY * PY) * m.h2 * m.h2);
+    const int d1 = (int)ceil(kF64NearExtents * ext / m.h1);
+    const int d2 = (int)ceil(kF64NearExtents * ext / m.h2);
+    const int near1_len = PX + 2 * d1 >= n1 ? n1 : PX + 2 * d1;
+    const int near1_lo = ((c0 - d1) % n1 + n1) % n1;
+    const int near2_len = PY + 2 * d2 >= n2 ? n2 : PY + 2 * d2;
+    const int near2_lo = ((r0 - d2) % n2 + n2) % n2;
 
     // ---- targets of this lane --------------------------------------------
     const int col = c0 + (tid % PX);
@@ -639,7 +684,7 @@ __device__ __forceinline__ void pairs_f64f_block(const Mesh& m, const PairShape&
     const bool col_ok = col < n1;
     const int i1 = col_ok ? col : ci1;
     const AxisImg ax1 = axis_img_m(m, i1, n1);
-    double ax0[R], ay0[R], az[R], ax[R], ay[R];
+    double ax0[R], ay0[R], az[R], ax[R], ay[R], aa[R];
     int b2[R], s2lo[R], pidx[R];
     bool valid[R];
 #pragma unroll
@@ -677,14 +722,15 @@ __device__ __forceinline__ void pairs_f64f_block(const Mesh& m, const PairShape&
             const double by = (z[N + j] + (double)sc2 * m.L2) - cy;
             const double bz = z[2 * N + j] - cz;
             const double g1 = gam[j], g2 = gam[N + j], g3 = gam[2 * N + j];
-            st[0] = make_double2(bx, by);
-            st[1] = make_double2(bz, g1);
+            st[0] = make_double2(-2.0 * bx, -2.0 * by);
+            st[1] = make_double2(-2.0 * bz, g1);
             st[2] = make_double2(g2, g3);
             st[3] = make_double2(by * g3 - bz * g2, bz * g1 - bx * g3);
-            st[4] = make_double2(bx * g2 - by * g1, 0.0);
+            st[4] = make_double2(bx * g2 - by * g1, fma(bx, bx, fma(by, by, fma(bz, bz, m.eps2))));
         } else {
 #pragma unroll
             for (int q = 0; q < 5; ++q) st[q] = make_double2(0.0, 0.0);
+            st[4].y = 1.0;   // never read (segments stop at the last source); keeps s > 0 anyway
         }
     };
     auto store_tile = [&](int buf) {
@@ -719,7 +765,10 @@ __device__ __forceinline__ void pairs_f64f_block(const Mesh& m, const PairShape&
             for (int r = 0; r < R; ++r) {
                 const int s2 = (j2 < b2[r]) ? s2lo[r] : s2lo[r] - 1;
                 ay[r] = ay0[r] - (double)(s2 - sc2 + m2) * m.L2;
+                aa[r] = fma(ax[r], ax[r], fma(ay[r], ay[r], az[r] * az[r]));
             }
+            bool near_row;
+            interval_run(j2, near2_lo, near2_len, n2, near_row);
             int a = j1;
             const int e = j1 + seg;
             while (a < e) {
@@ -737,6 +786,13 @@ __device__ __forceinline__ void pairs_f64f_block(const Mesh& m, const PairShape&
                     else if (a < band_lo) { in_band = false; stop = min(e, band_lo); }
                     else { in_band = true; stop = e; }
                 }
+                bool in_near = true;
+                if (!in_band && near_row) {
+                    const int rn = interval_run(a, near1_lo, near1_len, n1, in_near);
+                    stop = min(stop, a + rn);
+                } else if (!in_band) {
+                    in_near = false;
+                }
                 const int kk = k + (a - j1);
                 double A[R][3], B[R][3];
 #pragma unroll
@@ -745,8 +801,9 @@ __device__ __forceinline__ void pairs_f64f_block(const Mesh& m, const PairShape&
                     B[r][0] = B[r][1] = B[r][2] = 0.0;
                 }
                 if (in_band) {
-                    pair_segment_f64f<R, true>(lds[buf], kk, stop - a, a, ax1.b, ax1.s_lo, cimg1.b,
-                                               cimg1.s_lo, m.L1, ax, ay, az, m.eps2, A, B);
+                    pair_segment_f64f<R, kF64Direct>(lds[buf], kk, stop - a, a, ax1.b, ax1.s_lo,
+                                                     cimg1.b, cimg1.s_lo, m.L1, ax, ay, az, aa,
+                                                     m.eps2, A, B);
                     // direct contributions
 #pragma unroll
                     for (int r = 0; r < R; ++r) {
@@ -755,8 +812,14 @@ __device__ __forceinline__ void pairs_f64f_block(const Mesh& m, const PairShape&
                         U[r][2] += A[r][2];
                     }
                 } else {
-                    pair_segment_f64f<R, false>(lds[buf], kk, stop - a, a, ax1.b, ax1.s_lo, cimg1.b,
-                                                cimg1.s_lo, m.L1, ax, ay, az, m.eps2, A, B);
+                    if (in_near)
+                        pair_segment_f64f<R, kF64FactNear>(lds[buf], kk, stop - a, a, ax1.b, ax1.s_lo,
+                                                           cimg1.b, cimg1.s_lo, m.L1, ax, ay, az, aa,
+                                                           m.eps2, A, B);
+                    else
+                        pair_segment_f64f<R, kF64FactFar>(lds[buf], kk, stop - a, a, ax1.b, ax1.s_lo,
+                                                          cimg1.b, cimg1.s_lo, m.L1, ax, ay, az, aa,
+                                                          m.eps2, A, B);
                     // a x A - B
 #pragma unroll
                     for (int r = 0; r < R; ++r) {
