@@ -264,6 +264,16 @@ __global__ __launch_bounds__(kThreads) void k_cut_gather(Mesh m, CutGrid g, cons
 // wave of a row outside the grid still writes its zero partial sums).
 constexpr int kCutThreads = 64;
 
+// Targets per lane of the pair kernel: every scalar-loaded source record
+// serves 64 TR targets.  TR = 2 halves the loads per pair but measured
+// slower (768^2, rc = 0.0667: 3.17 against 2.57 ms): a chunk of 128 targets
+// covers enough of its cell that far fewer sources are rejected by the
+// whole wave.
+#ifndef ZM_CUT_TARGETS_PER_LANE
+#define ZM_CUT_TARGETS_PER_LANE 1
+#endif
+constexpr int kCutTargetsPerLane = ZM_CUT_TARGETS_PER_LANE;
+
 // Image-shift handling of one (wave, neighbour cell) visit:
 //   kShiftNone     every target of the wave and every source of the cell has
 //                  wrap count 0 and the cell is not wrapped: S = 0, r = d
@@ -292,45 +302,55 @@ __device__ __forceinline__ SrcRec load_rec(const double* __restrict__ src, int j
     return SrcRec{s[0], s[1], s[2], s[3], s[4], s[5], s[6], s[7]};
 }
 
-// One (target, source) pair: d1 = x_i - x_j is formed by the caller.  A
-// source that no lane of the wave accepts skips the kernel evaluation (a
-// wave-uniform branch: the accepted set, and so every sum, is unchanged).
-template <int SHIFT, bool COUNT>
-__device__ __forceinline__ void cut_pair(const Mesh& m, const CutGrid& g, const CutTarget& t,
-                                         const SrcRec& b, double d1, double SL1, double SL2,
-                                         double& acc0, double& acc1, double& acc2,
+// One source against the lane's TR targets: d1 = x_i - x_j is formed by the
+// caller.  A source that no target of the wave accepts skips the kernel
+// evaluation (a wave-uniform branch: the accepted set, and so every sum, is
+// unchanged).
+template <int SHIFT, bool COUNT, int TR>
+__device__ __forceinline__ void cut_pair(const Mesh& m, const CutGrid& g, const CutTarget (&t)[TR],
+                                         const SrcRec& b, const double (&d1)[TR], double SL1,
+                                         double SL2, double (&acc)[TR][3],
                                          unsigned long long& tested, unsigned long long& accepted)
 {
 #pragma clang fp contract(off)
-    const double d2 = t.y - b.y;
-    double r1, r2;
-    if (SHIFT == kShiftNone) {
-        r1 = d1;
-        r2 = d2;
-    } else if (SHIFT == kShiftUniform) {
-        r1 = d1 - SL1;
-        r2 = d2 - SL2;
-    } else {
-        const double S1 = t.Kx - b.k1, S2 = t.Ky - b.k2;
-        r1 = d1 - S1 * g.L1;
-        r2 = d2 - S2 * g.L2;
+    double r1[TR], r2[TR], r3[TR], dd[TR];
+    bool in[TR];
+    uint64_t any = 0;
+#pragma unroll
+    for (int q = 0; q < TR; ++q) {
+        const double d2 = t[q].y - b.y;
+        if (SHIFT == kShiftNone) {
+            r1[q] = d1[q];
+            r2[q] = d2;
+        } else if (SHIFT == kShiftUniform) {
+            r1[q] = d1[q] - SL1;
+            r2[q] = d2 - SL2;
+        } else {
+            const double S1 = t[q].Kx - b.k1, S2 = t[q].Ky - b.k2;
+            r1[q] = d1[q] - S1 * g.L1;
+            r2[q] = d2 - S2 * g.L2;
+        }
+        r3[q] = t[q].z - b.z;
+        dd[q] = r1[q] * r1[q] + r2[q] * r2[q] + r3[q] * r3[q];
+        in[q] = dd[q] < g.rc2;
+        if (COUNT) {
+            tested += t[q].active ? 1 : 0;
+            accepted += (t[q].active && in[q]) ? 1 : 0;
+        }
+        any |= __builtin_amdgcn_ballot_w64(in[q]) & t[q].amask;
     }
-    const double r3 = t.z - b.z;
-    const double dd = r1 * r1 + r2 * r2 + r3 * r3;
-    const bool in = dd < g.rc2;
-    if (COUNT) {
-        tested += t.active ? 1 : 0;
-        accepted += (t.active && in) ? 1 : 0;
+    if (any == 0ull) return;
+#pragma unroll
+    for (int q = 0; q < TR; ++q) {
+        const double wgt = in[q] ? dev::inv_cube_sqrt(dd[q] + m.eps2) : 0.0;
+        const double a1 = wgt * b.g1, a2 = wgt * b.g2, a3 = wgt * b.g3;
+        acc[q][0] = fma(r2[q], a3, acc[q][0]);
+        acc[q][0] = fma(-r3[q], a2, acc[q][0]);
+        acc[q][1] = fma(r3[q], a1, acc[q][1]);
+        acc[q][1] = fma(-r1[q], a3, acc[q][1]);
+        acc[q][2] = fma(r1[q], a2, acc[q][2]);
+        acc[q][2] = fma(-r2[q], a1, acc[q][2]);
     }
-    if ((__builtin_amdgcn_ballot_w64(in) & t.amask) == 0ull) return;
-    const double wgt = in ? dev::inv_cube_sqrt(dd + m.eps2) : 0.0;
-    const double a1 = wgt * b.g1, a2 = wgt * b.g2, a3 = wgt * b.g3;
-    acc0 = fma(r2, a3, acc0);
-    acc0 = fma(-r3, a2, acc0);
-    acc1 = fma(r3, a1, acc1);
-    acc1 = fma(-r1, a3, acc1);
-    acc2 = fma(r1, a2, acc2);
-    acc2 = fma(-r2, a1, acc2);
 }
 
 // Sum the sources [s0, s1) of one cell into the lane's accumulators, two at
@@ -338,12 +358,11 @@ __device__ __forceinline__ void cut_pair(const Mesh& m, const CutGrid& g, const 
 // for every load in flight: the next pair is issued only after the current
 // pair has arrived (its first use sits before a scheduling barrier), which
 // leaves a whole pair of evaluations to hide the next pair's latency.
-template <int SHIFT, bool COUNT>
+template <int SHIFT, bool COUNT, int TR>
 __device__ __forceinline__ void cut_cell(const Mesh& m, const CutGrid& g,
                                          const double* __restrict__ src, int s0, int s1,
-                                         const CutTarget& t, double SL1, double SL2,
-                                         double& acc0, double& acc1, double& acc2,
-                                         unsigned long long& tested,
+                                         const CutTarget (&t)[TR], double SL1, double SL2,
+                                         double (&acc)[TR][3], unsigned long long& tested,
                                          unsigned long long& accepted)
 {
     if (s0 >= s1) return;
@@ -352,18 +371,23 @@ __device__ __forceinline__ void cut_cell(const Mesh& m, const CutGrid& g,
     for (int j = s0; j < s1; j += 2) {
 #pragma clang fp contract(off)
         const SrcRec c0 = p0, c1 = p1;
-        const double d1a = t.x - c0.x, d1b = t.x - c1.x;   // the pair has arrived
+        double d1a[TR], d1b[TR];
+#pragma unroll
+        for (int q = 0; q < TR; ++q) {
+            d1a[q] = t[q].x - c0.x;   // the pair has arrived
+            d1b[q] = t[q].x - c1.x;
+        }
         __builtin_amdgcn_sched_barrier(0);
         p0 = load_rec(src, j + 2 < s1 ? j + 2 : last);
         p1 = load_rec(src, j + 3 < s1 ? j + 3 : last);
         __builtin_amdgcn_sched_barrier(0);
-        cut_pair<SHIFT, COUNT>(m, g, t, c0, d1a, SL1, SL2, acc0, acc1, acc2, tested, accepted);
-        if (j + 1 < s1)
-            cut_pair<SHIFT, COUNT>(m, g, t, c1, d1b, SL1, SL2, acc0, acc1, acc2, tested, accepted);
+        cut_pair<SHIFT, COUNT, TR>(m, g, t, c0, d1a, SL1, SL2, acc, tested, accepted);
+        if (j + 1 < s1) cut_pair<SHIFT, COUNT, TR>(m, g, t, c1, d1b, SL1, SL2, acc, tested, accepted);
     }
 }
 
-template <bool COUNT>
+// Chunks of 64 TR targets: slot q of a chunk holds targets t0 + lane + 64 q.
+template <bool COUNT, int TR>
 __global__ __launch_bounds__(kCutThreads) void k_cut_pairs(Mesh m, CutGrid g,
                                                            const double* __restrict__ src,
                                                            const int* __restrict__ start,
@@ -375,9 +399,10 @@ __global__ __launch_bounds__(kCutThreads) void k_cut_pairs(Mesh m, CutGrid g,
                                                            double* __restrict__ part,
                                                            unsigned long long* __restrict__ counts)
 {
+    constexpr int CH = kCutThreads * TR;
     const int blk = blockIdx.x, row = blockIdx.y;
     const int T0 = bstart[blk], T1 = bend[blk];
-    if (T0 + (int)blockIdx.z * kCutThreads >= T1) return;   // nothing left: uniform
+    if (T0 + (int)blockIdx.z * CH >= T1) return;   // nothing left: uniform
     const int N = m.N;
     const int lane = threadIdx.x;
     const int bx = blk % g.nb1, by = blk / g.nb1;
@@ -386,20 +411,29 @@ __global__ __launch_bounds__(kCutThreads) void k_cut_pairs(Mesh m, CutGrid g,
     const bool row_in = g.periodic || wy == 0;
     unsigned long long tested = 0, accepted = 0;
 
-    // chunks of 64 targets, blockIdx.z, blockIdx.z + chunks, ...
-    for (int t0 = T0 + (int)blockIdx.z * kCutThreads; t0 < T1; t0 += g.chunks * kCutThreads) {
-        const int i = t0 + lane;
-        CutTarget t;
-        t.active = i < T1;
-        t.amask = __builtin_amdgcn_ballot_w64(t.active);
-        const double* ti = src + (size_t)(t.active ? i : T0) * 8;
-        t.x = ti[0];
-        t.y = ti[1];
-        t.z = ti[2];
-        const double kxi = ti[6], kyi = ti[7];
-        // every target of the wave unwrapped (inactive lanes hold a real target of the block)
-        const bool targets_k0 = __builtin_amdgcn_ballot_w64(kxi != 0.0 || kyi != 0.0) == 0ull;
-        double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0;
+    // chunks blockIdx.z, blockIdx.z + chunks, ...
+    for (int t0 = T0 + (int)blockIdx.z * CH; t0 < T1; t0 += g.chunks * CH) {
+        CutTarget t[TR];
+        double kxi[TR], kyi[TR];
+        bool any_k = false;
+#pragma unroll
+        for (int q = 0; q < TR; ++q) {
+            const int i = t0 + lane + kCutThreads * q;
+            t[q].active = i < T1;
+            t[q].amask = __builtin_amdgcn_ballot_w64(t[q].active);
+            const double* ti = src + (size_t)(t[q].active ? i : T0) * 8;
+            t[q].x = ti[0];
+            t[q].y = ti[1];
+            t[q].z = ti[2];
+            kxi[q] = ti[6];
+            kyi[q] = ti[7];
+            any_k = any_k || kxi[q] != 0.0 || kyi[q] != 0.0;
+        }
+        // every target of the wave unwrapped (inactive slots hold a real target of the block)
+        const bool targets_k0 = __builtin_amdgcn_ballot_w64(any_k) == 0ull;
+        double acc[TR][3];
+#pragma unroll
+        for (int q = 0; q < TR; ++q) acc[q][0] = acc[q][1] = acc[q][2] = 0.0;
         for (int col = 0; col < g.slots; ++col) {
             const int cx_raw = bx * g.B - g.m + col;
             const int wx = floordiv(cx_raw, g.nc1), cx = cx_raw - wx * g.nc1;
@@ -408,26 +442,32 @@ __global__ __launch_bounds__(kCutThreads) void k_cut_pairs(Mesh m, CutGrid g,
             const int s0 = start[key], s1 = end[key];
             if (targets_k0 && kflag[key] == 0) {
                 if (wx == 0 && wy == 0) {
-                    cut_cell<kShiftNone, COUNT>(m, g, src, s0, s1, t, 0.0, 0.0, acc0, acc1, acc2,
-                                                tested, accepted);
+                    cut_cell<kShiftNone, COUNT, TR>(m, g, src, s0, s1, t, 0.0, 0.0, acc, tested,
+                                                    accepted);
                 } else {
                     const double SL1 = (double)wx * g.L1, SL2 = (double)wy * g.L2;
-                    cut_cell<kShiftUniform, COUNT>(m, g, src, s0, s1, t, SL1, SL2, acc0, acc1,
-                                                   acc2, tested, accepted);
+                    cut_cell<kShiftUniform, COUNT, TR>(m, g, src, s0, s1, t, SL1, SL2, acc, tested,
+                                                       accepted);
                 }
             } else {
-                t.Kx = kxi + (double)wx;
-                t.Ky = kyi + (double)wy;
-                cut_cell<kShiftPerLane, COUNT>(m, g, src, s0, s1, t, 0.0, 0.0, acc0, acc1, acc2,
-                                               tested, accepted);
+#pragma unroll
+                for (int q = 0; q < TR; ++q) {
+                    t[q].Kx = kxi[q] + (double)wx;
+                    t[q].Ky = kyi[q] + (double)wy;
+                }
+                cut_cell<kShiftPerLane, COUNT, TR>(m, g, src, s0, s1, t, 0.0, 0.0, acc, tested,
+                                                   accepted);
             }
         }
-        if (t.active) {
-            const int p = (int)order[i];
-            double* out = part + (size_t)row * 3 * N;
-            out[p] = acc0;
-            out[N + p] = acc1;
-            out[2 * N + p] = acc2;
+        double* out = part + (size_t)row * 3 * N;
+#pragma unroll
+        for (int q = 0; q < TR; ++q) {
+            if (t[q].active) {
+                const int p = (int)order[t0 + lane + kCutThreads * q];
+                out[p] = acc[q][0];
+                out[N + p] = acc[q][1];
+                out[2 * N + p] = acc[q][2];
+            }
         }
     }
     if (COUNT) {
@@ -471,7 +511,8 @@ CutGrid make_cut_grid(int n1, int n2, double L1, double L2, double rc, bool peri
     g.slots = g.B + 2 * g.m;
     const long N = (long)n1 * n2;
     const long per_block = (N + (long)g.nb1 * g.nb2 - 1) / ((long)g.nb1 * g.nb2);
-    g.chunks = (int)std::max(1L, std::min(65535L, (per_block + 63) / 64));
+    g.tr = kCutTargetsPerLane;
+    g.chunks = (int)std::max(1L, std::min(65535L, (per_block + 64L * g.tr - 1) / (64L * g.tr)));
     g.sort_blocks = (int)std::max(1L, std::min(1024L, (N + 1023) / 1024));
     g.x0 = -0.5 * L1;
     g.y0 = -0.5 * L2;
@@ -517,11 +558,13 @@ hipError_t launch_cut_pairs(const Mesh& m, const CutGrid& g, const CutBuffers& b
     const dim3 grid(g.nb1 * g.nb2, g.slots, g.chunks);
     const unsigned* order = b.vals[sorted_half];
     if (count)
-        hipLaunchKernelGGL(k_cut_pairs<true>, grid, dim3(kCutThreads), 0, s, m, g, b.src, b.start,
-                           b.end, b.bstart, b.bend, b.kflag, order, part, b.counts);
+        hipLaunchKernelGGL((k_cut_pairs<true, kCutTargetsPerLane>), grid, dim3(kCutThreads), 0, s, m,
+                           g, b.src, b.start, b.end, b.bstart, b.bend, b.kflag, order, part,
+                           b.counts);
     else
-        hipLaunchKernelGGL(k_cut_pairs<false>, grid, dim3(kCutThreads), 0, s, m, g, b.src, b.start,
-                           b.end, b.bstart, b.bend, b.kflag, order, part, b.counts);
+        hipLaunchKernelGGL((k_cut_pairs<false, kCutTargetsPerLane>), grid, dim3(kCutThreads), 0, s,
+                           m, g, b.src, b.start, b.end, b.bstart, b.bend, b.kflag, order, part,
+                           b.counts);
     return hipGetLastError();
 }
 

@@ -88,7 +88,8 @@ struct CutGrid {
     int nkeys;           // nb1 nb2 B^2
     int key_bits;        // bits of the sort key
     int slots;           // B + 2m
-    int chunks;          // waves per (target block, row): ~ mean 64-target chunks per block
+    int chunks;          // waves per (target block, row): ~ mean chunks of 64 tr targets per block
+    int tr;              // targets per lane of the pair kernel
     int sort_blocks;     // workgroups of the radix-sort passes
     int periodic;        // 1: cells wrap with the period; 0 (free sheet): cells clamp to the box
     int pad_;
