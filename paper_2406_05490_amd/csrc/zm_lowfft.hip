@@ -40,6 +40,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 namespace zm {
 namespace {
 
@@ -160,7 +162,7 @@ __device__ __forceinline__ void fft_pass(double2* x, int n, int Ns, const double
 
 // Unnormalised DFT (INV: conjugate twiddles) of the LDS row x, n = 2^logn.
 template <bool INV>
-__device__ void fft_row(double2* x, int logn, const double2* __restrict__ tw)
+__device__ __forceinline__ void fft_row(double2* x, int logn, const double2* __restrict__ tw)
 {
     const int n = 1 << logn;
     int Ns = 1, rem = logn;
@@ -174,20 +176,48 @@ __device__ void fft_row(double2* x, int logn, const double2* __restrict__ tw)
     else if (rem == 1) fft_pass<2, INV>(x, n, Ns, tw);
 }
 
+// Persistent row kernels: workgroup b takes rows b, b + G, b + 2G, ... (G =
+// the grid, sized to the workgroups that fit on the CUs at once).  Each
+// thread holds its n / 256 elements of the next row in registers: their
+// global loads are issued before the current row's FFT passes and land
+// while those run, so a row's load no longer waits behind its own compute.
+constexpr int kRowRegs = 16;   // elements per thread at n = 4096
+
 // Row i2: c = w1 + i w2 over i1, forward FFT -> A[i2][m1].
-__global__ __launch_bounds__(kFftThreads) void k_lo_pack_rows(int logn, int N,
+__global__ __launch_bounds__(kFftThreads) void k_lo_pack_rows(int logn, int rows, int N,
                                                               const double* __restrict__ w,
                                                               const double2* __restrict__ tw,
                                                               double2* __restrict__ A)
 {
     extern __shared__ double2 x[];
     const int n = 1 << logn;
-    const size_t row = (size_t)blockIdx.x * n;
-    for (int e = threadIdx.x; e < n; e += kFftThreads)
-        x[sw(e)] = make_double2(w[row + e], w[N + row + e]);
-    __syncthreads();
-    fft_row<false>(x, logn, tw);
-    for (int e = threadIdx.x; e < n; e += kFftThreads) A[row + e] = x[sw(e)];
+    const int tid = threadIdx.x;
+    double2 pre[kRowRegs];
+#define ZM_FETCH_PACK(r)                                                                     \
+    do {                                                                                     \
+        const size_t fb = (size_t)(r) * n;                                                   \
+        _Pragma("unroll") for (int k = 0; k < kRowRegs; ++k) {                               \
+            const int e = tid + k * kFftThreads;                                             \
+            if (e < n) pre[k] = make_double2(w[fb + e], w[N + fb + e]);                      \
+        }                                                                                    \
+    } while (0)
+    int row = blockIdx.x;
+    if (row < rows) ZM_FETCH_PACK(row);
+    for (; row < rows; row += gridDim.x) {
+#pragma unroll
+        for (int k = 0; k < kRowRegs; ++k) {
+            const int e = tid + k * kFftThreads;
+            if (e < n) x[sw(e)] = pre[k];
+        }
+        __syncthreads();
+        const int next = row + gridDim.x;
+        if (next < rows) ZM_FETCH_PACK(next);
+        fft_row<false>(x, logn, tw);
+        const size_t base = (size_t)row * n;
+        for (int e = tid; e < n; e += kFftThreads) A[base + e] = x[sw(e)];
+        __syncthreads();   // the row is out of LDS before the next one is written
+    }
+#undef ZM_FETCH_PACK
 }
 
 // Row m1 of B (length n2 over i2): forward FFT over i2, times the symbol
@@ -199,45 +229,80 @@ __global__ __launch_bounds__(kFftThreads) void k_lo_symbol_rows(int n1, int logn
 {
     extern __shared__ double2 x[];
     const int n2 = 1 << logn2;
-    const int m1 = blockIdx.x;
-    double2* row = B + (size_t)m1 * n2;
-    for (int e = threadIdx.x; e < n2; e += kFftThreads) x[sw(e)] = row[e];
-    __syncthreads();
-    fft_row<false>(x, logn2, tw);
-    const int s1 = 2 * m1 < n1 ? m1 : m1 - n1;
-    const double k1 = 2.0 * M_PI * s1 / L1;
+    const int tid = threadIdx.x;
+    double2 pre[kRowRegs];
+#define ZM_FETCH_ROW(src, r, len)                                                            \
+    do {                                                                                     \
+        const double2* fr = (src) + (size_t)(r) * (len);                                     \
+        _Pragma("unroll") for (int k = 0; k < kRowRegs; ++k) {                               \
+            const int e = tid + k * kFftThreads;                                             \
+            if (e < (len)) pre[k] = make_double2(fr[e].x, fr[e].y);                           \
+        }                                                                                    \
+    } while (0)
     const double h = 0.5 / ((double)n1 * (double)n2);
-    for (int m2 = threadIdx.x; m2 < n2; m2 += kFftThreads) {
-        const int s2 = 2 * m2 < n2 ? m2 : m2 - n2;
-        const double k2 = 2.0 * M_PI * s2 / L2;
-        const double kk = sqrt(k1 * k1 + k2 * k2);
-        double c1 = 0.0, c2 = 0.0;
-        if (kk > 0.0) {
-            c1 = (2 * m1 == n1) ? 0.0 : k1 / kk;
-            c2 = (2 * m2 == n2) ? 0.0 : k2 / kk;
+    int m1 = blockIdx.x;
+    if (m1 < n1) ZM_FETCH_ROW(B, m1, n2);
+    for (; m1 < n1; m1 += gridDim.x) {
+#pragma unroll
+        for (int k = 0; k < kRowRegs; ++k) {
+            const int e = tid + k * kFftThreads;
+            if (e < n2) x[sw(e)] = pre[k];
         }
-        const double2 v = x[sw(m2)];
-        const double mx = c2 * h, my = c1 * h;   // (c2 + i c1) / (2N)
-        x[sw(m2)] = make_double2(v.x * mx - v.y * my, v.x * my + v.y * mx);
+        __syncthreads();
+        const int next = m1 + gridDim.x;
+        if (next < n1) ZM_FETCH_ROW(B, next, n2);
+        fft_row<false>(x, logn2, tw);
+        const int s1 = 2 * m1 < n1 ? m1 : m1 - n1;
+        const double k1 = 2.0 * M_PI * s1 / L1;
+        for (int m2 = tid; m2 < n2; m2 += kFftThreads) {
+            const int s2 = 2 * m2 < n2 ? m2 : m2 - n2;
+            const double k2 = 2.0 * M_PI * s2 / L2;
+            const double kk = sqrt(k1 * k1 + k2 * k2);
+            double c1 = 0.0, c2 = 0.0;
+            if (kk > 0.0) {
+                c1 = (2 * m1 == n1) ? 0.0 : k1 / kk;
+                c2 = (2 * m2 == n2) ? 0.0 : k2 / kk;
+            }
+            const double2 v = x[sw(m2)];
+            const double mx = c2 * h, my = c1 * h;   // (c2 + i c1) / (2N)
+            x[sw(m2)] = make_double2(v.x * mx - v.y * my, v.x * my + v.y * mx);
+        }
+        __syncthreads();
+        fft_row<true>(x, logn2, tw);
+        double2* row = B + (size_t)m1 * n2;
+        for (int e = tid; e < n2; e += kFftThreads) row[e] = x[sw(e)];
+        __syncthreads();
     }
-    __syncthreads();
-    fft_row<true>(x, logn2, tw);
-    for (int e = threadIdx.x; e < n2; e += kFftThreads) row[e] = x[sw(e)];
 }
 
 // Row i2 of A (over m1): inverse FFT over m1, S = Re -> S[i2][i1].
-__global__ __launch_bounds__(kFftThreads) void k_lo_inv_rows(int logn, const double2* __restrict__ tw,
+__global__ __launch_bounds__(kFftThreads) void k_lo_inv_rows(int logn, int rows,
+                                                             const double2* __restrict__ tw,
                                                              const double2* __restrict__ A,
                                                              double* __restrict__ S)
 {
     extern __shared__ double2 x[];
     const int n = 1 << logn;
-    const size_t row = (size_t)blockIdx.x * n;
-    for (int e = threadIdx.x; e < n; e += kFftThreads) x[sw(e)] = A[row + e];
-    __syncthreads();
-    fft_row<true>(x, logn, tw);
-    for (int e = threadIdx.x; e < n; e += kFftThreads) S[row + e] = x[sw(e)].x;
+    const int tid = threadIdx.x;
+    double2 pre[kRowRegs];
+    int row = blockIdx.x;
+    if (row < rows) ZM_FETCH_ROW(A, row, n);
+    for (; row < rows; row += gridDim.x) {
+#pragma unroll
+        for (int k = 0; k < kRowRegs; ++k) {
+            const int e = tid + k * kFftThreads;
+            if (e < n) x[sw(e)] = pre[k];
+        }
+        __syncthreads();
+        const int next = row + gridDim.x;
+        if (next < rows) ZM_FETCH_ROW(A, next, n);
+        fft_row<true>(x, logn, tw);
+        const size_t base = (size_t)row * n;
+        for (int e = tid; e < n; e += kFftThreads) S[base + e] = x[sw(e)].x;
+        __syncthreads();
+    }
 }
+#undef ZM_FETCH_ROW
 
 // Per point: the velocity u = S n^ (not stored when u is null) and V.  A
 // 256-thread workgroup owns a tile of tx x ty points (tx = min(64, n1),
@@ -339,6 +404,15 @@ int log2i(int n)
     return l;
 }
 
+// Workgroups of the persistent row kernels for rows of n complex doubles:
+// as many as the CUs hold at once (LDS-bound: 160 KiB per CU, 256 CUs),
+// at most one per row.
+unsigned row_grid(int n, int rows)
+{
+    const int per_cu = std::max(1, std::min(8, (160 * 1024) / (int)(sizeof(double2) * n)));
+    return (unsigned)std::min(rows, 256 * per_cu);
+}
+
 hipError_t transpose(const double2* in, double2* out, int rows, int cols, hipStream_t s)
 {
     hipLaunchKernelGGL(k_transpose, dim3((cols + 31) / 32, (rows + 31) / 32), dim3(kThreads), 0, s,
@@ -358,15 +432,15 @@ hipError_t launch_low_velocity(const Mesh& m, const double* z, const double* w,
     hipError_t e;
     hipLaunchKernelGGL(k_twiddle, dim3(grid_for(n1 > n2 ? n1 : n2)), dim3(kThreads), 0, s, n1,
                        b.tw1, n2, b.tw2);
-    hipLaunchKernelGGL(k_lo_pack_rows, dim3(n2), dim3(kFftThreads), sizeof(double2) * n1, s, l1, N,
-                       w, b.tw1, b.a);                                        // A[i2][m1]
+    hipLaunchKernelGGL(k_lo_pack_rows, dim3(row_grid(n1, n2)), dim3(kFftThreads),
+                       sizeof(double2) * n1, s, l1, n2, N, w, b.tw1, b.a);   // A[i2][m1]
     if ((e = transpose(b.a, b.b, n2, n1, s)) != hipSuccess) return e;       // B[m1][i2]
-    hipLaunchKernelGGL(k_lo_symbol_rows, dim3(n1), dim3(kFftThreads), sizeof(double2) * n2, s, n1,
-                       l2, m.L1, m.L2, b.tw2, b.b);                           // B[m1][i2]: S^ filtered
+    hipLaunchKernelGGL(k_lo_symbol_rows, dim3(row_grid(n2, n1)), dim3(kFftThreads),
+                       sizeof(double2) * n2, s, n1, l2, m.L1, m.L2, b.tw2, b.b);   // B[m1][i2]
     if ((e = transpose(b.b, b.a, n1, n2, s)) != hipSuccess) return e;       // A[i2][m1]
     double* S = reinterpret_cast<double*>(b.b);   // B is spent after the second transpose
-    hipLaunchKernelGGL(k_lo_inv_rows, dim3(n2), dim3(kFftThreads), sizeof(double2) * n1, s, l1, b.tw1,
-                       b.a, S);
+    hipLaunchKernelGGL(k_lo_inv_rows, dim3(row_grid(n1, n2)), dim3(kFftThreads),
+                       sizeof(double2) * n1, s, l1, n2, b.tw1, b.a, S);
     const int tx = n1 < 64 ? n1 : 64;
     const int ty = kThreads / tx < n2 ? kThreads / tx : n2;
     hipLaunchKernelGGL(k_lo_point, dim3(n1 / tx, (n2 + ty - 1) / ty), dim3(kThreads), 0, s, m, tx, ty,
