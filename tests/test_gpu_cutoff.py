@@ -206,3 +206,12 @@ def test_cutoff_not_in_batches(gpu):
     with pytest.raises(zm.ZMError) as e:
         zm.Batch([params(32, 32, 0.3)])
     assert e.value.status in (zm.ZM_ERR_UNSUPPORTED, zm.ZM_ERR_INVALID_ARG)
+
+
+def test_cutoff_below_the_spacing_is_exactly_zero(gpu):
+    """Only the self pair is within rc; it contributes exactly zero."""
+    n = 48
+    p = params(n, n, 0.01)
+    z, w = drifted_state(n, n, 14)
+    u, ctx = gpu_br(p, z, w, gpu)
+    assert np.all(u == 0.0)

@@ -151,3 +151,12 @@ def test_cutoff_rejects_bad_arguments():
     for kw in ({"cutoff": 0.95}, {"cutoff": -0.1}, {"cutoff": 0.3, "images": 1}):
         with pytest.raises(ValueError):
             oracle.br_velocity(prob(8, **kw), z, w)
+
+
+def test_cutoff_below_the_spacing_leaves_only_the_self_pair():
+    """rc below every pair distance: only the self pair is inside, and it
+    contributes exactly zero (r = 0), so u = 0 bit for bit."""
+    n = 16
+    z, w = rr.random_state(n, n, seed=21, height=0.05)
+    P = oracle.Problem(n, n, eps=1.0 / n, cutoff=0.01)
+    assert np.all(oracle.br_velocity(P, z, w) == 0.0)
