@@ -618,6 +618,30 @@ def cpu_baseline(wl, ctx_factory, z0, w0, target_seconds: float):
     }
 
 
+def cpu_oracle_detail(threads: int):
+    """The oracle's own rates on the other workloads (about a second of host
+    time in all): one full BR evaluation of the 64 x 64 workload, 256 seeded
+    targets of the 1024 x 1024 workload, and the 64 x 64 evaluation on one
+    thread."""
+    import oracle
+    out = {"threads": threads}
+    for name, key, targets, nthreads in (
+            ("periodic64_full_br", "periodic64_single_fp64", None, threads),
+            ("periodic1024_sampled_br", "periodic1024_multimode16_fp32", 256, threads),
+            ("periodic64_full_br_1thread", "periodic64_single_fp64", None, 1)):
+        wl = rr.WORKLOADS[key]
+        z, _ = wl.state()
+        w = rr.synthetic_vorticity(wl.n1, wl.n2, seed=wl.seed)
+        P = oracle.Problem(wl.n1, wl.n2, eps=wl.eps)
+        tg = rr.sample_targets(wl.n, targets, seed=7) if targets else None
+        t0 = time.perf_counter()
+        oracle.br_velocity(P, z, w, targets=tg, threads=nthreads)
+        dt = time.perf_counter() - t0
+        pairs = (tg.size if targets else wl.n) * wl.n
+        out[name] = {"pairs": pairs, "seconds": dt, "pairs_per_s": pairs / dt, "threads": nthreads}
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -732,6 +756,7 @@ def main():
         out["serving"] = serving(zm, torch, window_s=args.serve_seconds)
     if args.cpu_seconds > 0:
         out["cpu_baseline"] = cpu_baseline(wl, lambda: zm.Context(p), z0, w0, args.cpu_seconds)
+        out["cpu_oracle_detail"] = cpu_oracle_detail(out["cpu_baseline"]["cores"])
     print(json.dumps(out), flush=True)
 
 
