@@ -141,7 +141,7 @@ def br_sweep_1m(zm, torch, reps: int = 2):
     res["fp32_over_fp64_speedup"] = res["fp32_pairs"]["pairs_per_s"] / res["fp64"]["pairs_per_s"]
     res["fp32_vs_fp64_max_rel_err"] = err
     res["workload"] = f"{wl.name}: one BR evaluation, synthetic vorticity, {wl.n} points"
-    return res
+    return res, us
 
 
 def ensemble64(zm, torch, steps: int = 20):
@@ -618,16 +618,17 @@ def cpu_baseline(wl, ctx_factory, z0, w0, target_seconds: float):
     }
 
 
-def cpu_oracle_detail(threads: int):
-    """The oracle's own rates on the other workloads (about a second of host
-    time in all): one full BR evaluation of the 64 x 64 workload, 256 seeded
+def cpu_oracle_detail(threads: int, sweep_u=None):
+    """The oracle's own rates on the other workloads (a few seconds of host
+    time in all): one full BR evaluation of the 64 x 64 workload, 1024 seeded
     targets of the 1024 x 1024 workload, and the 64 x 64 evaluation on one
-    thread."""
+    thread.  With the 1M-point sweep's GPU velocities (FP64 and FP32 forms,
+    same state and vorticity) their error on those 1024 targets as well."""
     import oracle
     out = {"threads": threads}
     for name, key, targets, nthreads in (
             ("periodic64_full_br", "periodic64_single_fp64", None, threads),
-            ("periodic1024_sampled_br", "periodic1024_multimode16_fp32", 256, threads),
+            ("periodic1024_sampled_br", "periodic1024_multimode16_fp32", 1024, threads),
             ("periodic64_full_br_1thread", "periodic64_single_fp64", None, 1)):
         wl = rr.WORKLOADS[key]
         z, _ = wl.state()
@@ -635,10 +636,15 @@ def cpu_oracle_detail(threads: int):
         P = oracle.Problem(wl.n1, wl.n2, eps=wl.eps)
         tg = rr.sample_targets(wl.n, targets, seed=7) if targets else None
         t0 = time.perf_counter()
-        oracle.br_velocity(P, z, w, targets=tg, threads=nthreads)
+        ref = oracle.br_velocity(P, z, w, targets=tg, threads=nthreads)
         dt = time.perf_counter() - t0
         pairs = (tg.size if targets else wl.n) * wl.n
         out[name] = {"pairs": pairs, "seconds": dt, "pairs_per_s": pairs / dt, "threads": nthreads}
+        if targets and sweep_u is not None:
+            scale = float(np.max(np.abs(ref)))
+            for form, u in sweep_u.items():
+                ug = u.reshape(3, -1)[:, tg]
+                out[name][f"{form}_vs_oracle_max_rel_err"] = float(np.max(np.abs(ug - ref)) / scale)
     return out
 
 
@@ -671,6 +677,7 @@ def main():
         print(json.dumps({"tune_report": tune_report(zm, torch)}), flush=True)
         return
 
+    sweep_u = None
     wl = rr.WORKLOADS[args.workload]
     prec = zm.ZM_FP32_PAIRS if wl.precision == "fp32_pairs" else zm.ZM_FP64
     steps = wl.steps if args.steps is None else args.steps
@@ -745,7 +752,7 @@ def main():
     }
 
     if not args.no_sweep:
-        out["br_sweep_1m"] = br_sweep_1m(zm, torch)
+        out["br_sweep_1m"], sweep_u = br_sweep_1m(zm, torch)
         out["ensemble64_fp32_graph"] = ensemble64(zm, torch)
         out["periodic64_latency"] = small_mesh_latency(zm, torch)
         out["cutoff"] = cutoff_section(zm, torch)
@@ -756,7 +763,7 @@ def main():
         out["serving"] = serving(zm, torch, window_s=args.serve_seconds)
     if args.cpu_seconds > 0:
         out["cpu_baseline"] = cpu_baseline(wl, lambda: zm.Context(p), z0, w0, args.cpu_seconds)
-        out["cpu_oracle_detail"] = cpu_oracle_detail(out["cpu_baseline"]["cores"])
+        out["cpu_oracle_detail"] = cpu_oracle_detail(out["cpu_baseline"]["cores"], sweep_u)
     print(json.dumps(out), flush=True)
 
 
