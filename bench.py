@@ -65,16 +65,43 @@ def parse():
 PAIR_KERNEL_SOURCES = ("zm_device.h", "zm_internal.h", "zm_kernels.hip")
 
 
+def code_only(text: str) -> str:
+    """C/C++ source with comments removed and whitespace runs collapsed, so
+    that comment and layout edits leave it unchanged (string and character
+    literals are kept as written)."""
+    out, i, n = [], 0, len(text)
+    while i < n:
+        c = text[i]
+        if text.startswith("//", i):
+            j = text.find("\n", i)
+            i = n if j < 0 else j
+        elif text.startswith("/*", i):
+            j = text.find("*/", i + 2)
+            i = n if j < 0 else j + 2
+            out.append(" ")
+        elif c in "\"'":
+            j = i + 1
+            while j < n and text[j] != c:
+                j += 2 if text[j] == "\\" else 1
+            out.append(text[i:j + 1])
+            i = j + 1
+        else:
+            out.append(c)
+            i += 1
+    return " ".join("".join(out).split())
+
+
 def library_source_hash() -> str:
-    """SHA-256 over the sources that define the single-instance pair kernels
-    (name, then bytes, in this order)."""
+    """SHA-256 over the code (comments and whitespace runs removed) of the
+    sources that define the single-instance pair kernels (name, then code,
+    in this order)."""
     import hashlib
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2406_05490_amd", "csrc")
     for f in PAIR_KERNEL_SOURCES:
         h.update(f.encode())
-        with open(os.path.join(csrc, f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(csrc, f), encoding="utf-8") as fh:
+            h.update(code_only(fh.read()).encode())
     return h.hexdigest()
 
 

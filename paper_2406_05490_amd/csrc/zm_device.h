@@ -221,13 +221,16 @@ __device__ __forceinline__ AxisImg axis_img(int i, int n)
 // is added into FP64 per-target accumulators.
 
 // Away from the patch the same factored sum as the FP64 kernel is used
-// (a x sum w g - sum w c with c = b x g formed once per staged source): for a
-// source at distance |r| the rounding of the two terms is amplified by
-// about |a| / |r|, which is below 1/4 outside a near box of four patch
-// half-extents around the patch, so there it is no worse than the direct
-// form and takes 15 instead of 18 VALU operations per pair.  Inside the near
-// box, in the antipodal band and for extra image layers the direct form is
-// used.
+// (a x sum w g - sum w c with c = b x g formed once per staged source), and
+// |a - b|^2 + eps^2 is expanded as |a|^2 + (|b|^2 + eps^2 - 2 a.b) with -2b
+// and |b|^2 + eps^2 staged per source: 12 VALU operations and the rsqrt per
+// pair instead of 17.  Outside a near box of one patch half-extent around
+// the patch |r| >= |a|, so the expansion's rounding stays below
+// (1 + 2|a|/|r|)^2 <= 9 ulp of |r|^2 + eps^2, and the factored terms, at most
+// about twice the direct term, add at most about twice its rounding: a few
+// 1e-7 relative per far pair, against the 1e-5 the FP32 form is held to.
+// Inside the near box, in the antipodal band and for extra image layers the
+// direct form is used.
 
 #ifndef ZM_PAIR32_UNROLL
 #define ZM_PAIR32_UNROLL 2
@@ -237,7 +240,10 @@ __device__ __forceinline__ AxisImg axis_img(int i, int n)
 #endif
 
 // Near box half-width beyond the patch, in patch half-extents.
-constexpr double kF32NearExtents = 4.0;
+#ifndef ZM_F32_NEAR_EXTENTS
+#define ZM_F32_NEAR_EXTENTS 1.0
+#endif
+constexpr double kF32NearExtents = ZM_F32_NEAR_EXTENTS;
 
 // Staged FP32 sources, double buffered: (bx, by, bz, g1), (g2, g3, c1, c2), c3.
 struct F32Tile {
@@ -286,8 +292,8 @@ __device__ __forceinline__ void pair_segment_f32(const F32Tile& T, int buf, int 
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 // |a - b|^2 + eps^2 = |a|^2 + (|b|^2 + eps^2 - 2 a.b): outside the
-                // near box (|r| >= 4 half-extents beyond the patch) the
-                // expansion's rounding stays within (1 + 2/4)^2 ulp
+                // near box (|r| >= |a|) the expansion's rounding stays within
+                // (1 + 2|a|/|r|)^2 <= 9 ulp
                 const float s = fmaf(mz[r], bz, fmaf(my[r], by, fmaf(mx[r], bx, bb))) + aa[r];
                 const float y = __builtin_amdgcn_rsqf(s);
                 const float wgt = y * y * y;

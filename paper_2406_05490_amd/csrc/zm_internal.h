@@ -35,8 +35,11 @@ struct PairShape {
 // default of >= 2048 workgroups).  Supported R: 1, 2, 4.
 PairShape make_pair_shape(int n1, int n2, int precision, int R, int splits);
 
+// The untuned default shape for (n1, n2, precision).
+PairShape default_pair_shape(int n1, int n2, int precision);
+
 // Shape a new context or batch member uses: the process-wide tuning entry
-// for (n1, n2, precision) if one is set, else an untuned default.
+// for (n1, n2, precision) if one is set, else the untuned default.
 PairShape choose_pair_shape(int n1, int n2, int precision);
 
 // Process-wide tuning table (zm_tune.hip).  Returns true and fills R and

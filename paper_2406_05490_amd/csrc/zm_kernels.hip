@@ -5,6 +5,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 namespace zm {
 namespace {
 
@@ -123,20 +125,36 @@ PairShape make_pair_shape(int n1, int n2, int precision, int R, int splits)
     return sh;
 }
 
+PairShape default_pair_shape(int n1, int n2, int precision)
+{
+    // From autotuner runs on MI355X (32^2 .. 1024^2): fewer targets per lane
+    // on small meshes (more waves in flight); FP32 prefers 2 targets per lane
+    // from 64^2 up, FP64 4 from 128^2 up; twice the default source splits
+    // helps FP32 from 64^2 up and FP64 on mid-size meshes.
+    const long N = (long)n1 * n2;
+    int R;
+    if (precision == 1) R = N >= 4096 ? 2 : 1;
+    else R = N >= 16384 ? 4 : (N >= 9216 ? 2 : 1);
+    const PairShape d = make_pair_shape(n1, n2, precision, R, 0);
+    if (precision == 1 && N >= (1L << 20)) {
+        // FP32 from 2^20 points up: about 32768 workgroups (at 1024^2, 16
+        // source ranges of 64 rows).  Each workgroup then runs for a few
+        // milliseconds instead of tens of them, which shortens the tail of
+        // the launch: 3-4% faster at 1024^2 than 2 ranges.  The partial sums
+        // take splits x N x 24 B, about 400 MB at any size.
+        const int patches = d.px * d.py;
+        const int s = std::min((32768 + patches - 1) / patches, std::max(1, n2 / 2));
+        return make_pair_shape(n1, n2, precision, R, std::max(s, 2 * d.splits));
+    }
+    const bool mid = precision == 1 ? (N >= 4096) : (N >= 9216);
+    return mid ? make_pair_shape(n1, n2, precision, R, 2 * d.splits) : d;
+}
+
 PairShape choose_pair_shape(int n1, int n2, int precision)
 {
     int R = 0, splits = 0;
     if (lookup_tuning(n1, n2, precision, &R, &splits)) return make_pair_shape(n1, n2, precision, R, splits);
-    // Untuned default, from autotuner runs on MI355X (32^2 .. 1024^2): fewer
-    // targets per lane on small meshes (more waves in flight); FP32 prefers 2
-    // targets per lane from 64^2 up, FP64 4 from 128^2 up; twice the default
-    // source splits helps FP32 from 64^2 up and FP64 on mid-size meshes.
-    const long N = (long)n1 * n2;
-    if (precision == 1) R = N >= 4096 ? 2 : 1;
-    else R = N >= 16384 ? 4 : (N >= 9216 ? 2 : 1);
-    const PairShape d = make_pair_shape(n1, n2, precision, R, 0);
-    const bool mid = precision == 1 ? (N >= 4096) : (N >= 9216);
-    return mid ? make_pair_shape(n1, n2, precision, R, 2 * d.splits) : d;
+    return default_pair_shape(n1, n2, precision);
 }
 
 hipError_t launch_tune_init(const Mesh& m, double* z, double* gam, hipStream_t s)

@@ -24,22 +24,27 @@ bool valid_tuning(const zm_pair_tuning& t)
 }
 
 // Candidate shapes: R in {1, 2, 4} x splits in {s0/4, s0/2, s0, 2 s0} where s0
-// is the default split count for that R, clamped to [1, n2], deduplicated;
-// for the FP32 form only the R whose patches keep its error bound.
+// is the split count giving >= 2048 workgroups for that R, clamped to
+// [1, n2], plus the untuned default shape, deduplicated; for the FP32 form
+// only the R whose patches keep its error bound.
 std::vector<zm::PairShape> candidates(const zm_params& p)
 {
     std::vector<zm::PairShape> out;
+    auto add = [&](const zm::PairShape& sh) {
+        bool dup = false;
+        for (const auto& o : out) dup |= (o.R == sh.R && o.splits == sh.splits);
+        if (!dup) out.push_back(sh);
+    };
     for (int R : {1, 2, 4}) {
         const zm::PairShape d = zm::make_pair_shape(p.n1, p.n2, p.precision, R, 0);
         if (zm::fp32_shape_problem(p, d)) continue;
         for (int f : {-2, -1, 0, 1}) {
             int s = f < 0 ? d.splits >> (-f) : d.splits << f;
-            const zm::PairShape sh = zm::make_pair_shape(p.n1, p.n2, p.precision, R, std::max(1, s));
-            bool dup = false;
-            for (const auto& o : out) dup |= (o.R == sh.R && o.splits == sh.splits);
-            if (!dup) out.push_back(sh);
+            add(zm::make_pair_shape(p.n1, p.n2, p.precision, R, std::max(1, s)));
         }
     }
+    const zm::PairShape d = zm::default_pair_shape(p.n1, p.n2, p.precision);
+    if (!zm::fp32_shape_problem(p, d)) add(d);
     return out;
 }
 

@@ -202,6 +202,21 @@ def test_tuning_table_host_side():
     assert lib.zm_autotune_workspace_bytes(ctypes.byref(zm.Params(64, 64, eps=1 / 64).c())) > 0
 
 
+def test_default_shapes_large_fp32_meshes():
+    """Untuned defaults: FP32 from 2^20 points up takes about 32768
+    workgroups (source splits), so partial sums stay near 400 MB; smaller
+    FP32 meshes (batch and serving sizes) and FP64 keep the >= 2048-workgroup
+    rule with twice its splits."""
+    assert zm.tuning_get(1024, 1024, zm.ZM_FP32_PAIRS) == (2, 16)     # 2048 patches
+    assert zm.tuning_get(2048, 2048, zm.ZM_FP32_PAIRS) == (2, 4)      # 8192 patches
+    assert zm.tuning_get(512, 512, zm.ZM_FP32_PAIRS) == (2, 8)
+    assert zm.tuning_get(1024, 1024, zm.ZM_FP64) == (4, 4)
+    p = zm.Params(1024, 1024, eps=1 / 1024, precision=zm.ZM_FP32_PAIRS)
+    assert zm.workspace_bytes(p) > 16 * 3 * 1024 * 1024 * 8
+    # the autotuner's candidates include the default, so its workspace holds it
+    assert zm.load().zm_autotune_workspace_bytes(ctypes.byref(p.c())) >= 16 * 3 * 1024 * 1024 * 8
+
+
 def test_pool_host_side_validation():
     p = zm.Params(64, 64, eps=1 / 64)
     rb = zm.pool_request_bytes(p)
