@@ -546,8 +546,13 @@ __device__ __forceinline__ void pairs_f32_block(const Mesh& m, const PairShape& 
 // that leaves the distance, the weight and two 3-vector accumulations (17
 // VALU operations instead of 21).  The cancellation between the two terms is
 // bounded by |a| / |r| ~ the patch extent over the spacing for near pairs.
-// In the antipodal band, where a lane's image differs from the centre's, the
-// direct form is used with a per-source image correction.  On meshes where a
+// In the antipodal band a lane's image of a source differs from the
+// centre's by d = 0 or +-L1 along x.  Outside the near box the lane shifts
+// the staged record to its own image (b_x + d: -2b_x, |b|^2 + eps^2 and the
+// two components of c that involve b_x; a select and five FP64 operations
+// per source and lane, shared by its R targets) and takes the factored far
+// form; inside the near box the direct form is used with the same
+// per-source correction.  On meshes where a
 // patch is wide compared with the finest spacing (strongly anisotropic
 // spacings, or a patch that spans a short axis), that cancellation could
 // reach the FP64 tolerance, so there every source takes the direct form.
@@ -565,7 +570,14 @@ __host__ __device__ inline bool factored_ok(const Mesh& m, int PX, int PY)
     return ex * ex + ey * ey <= lim * lim;
 }
 
-enum { kF64Direct = 0, kF64FactNear = 1, kF64FactFar = 2 };
+enum { kF64Direct = 0, kF64FactNear = 1, kF64FactFar = 2, kF64BandFar = 3 };
+
+// Antipodal-band sources outside the near box take the factored far form on
+// the lane's own image (1) or the direct form (0).
+#ifndef ZM_BAND_FACTORED
+#define ZM_BAND_FACTORED 1
+#endif
+
 
 // Near box half-width beyond the patch, in patch half-extents, for the
 // expanded |r|^2 of the FP64 factored form.  A source outside it lies at
@@ -580,7 +592,9 @@ constexpr double kF64NearExtents = ZM_F64_NEAR_EXTENTS;
 // MODE: kF64Direct (direct form, antipodal band), kF64FactNear (factored,
 // |r|^2 from r = a - b), kF64FactFar (factored, |r|^2 expanded as
 // |a|^2 + |b|^2 + eps^2 - 2 a.b: only for sources outside the near box,
-// where |r| >= |a| bounds its rounding by a few ulp).
+// where |r| >= |a| bounds its rounding by a few ulp), kF64BandFar (the far
+// form on the lane's own image of an antipodal-band source outside the near
+// box; the segment must not cross the centre's breakpoint bc1).
 template <int R, int MODE>
 __device__ __forceinline__ void pair_segment_f64f(const double2 (*__restrict__ buf)[kThreads],
                                                   int k0, int cnt, int j1s, int b1, int s1lo,
@@ -588,6 +602,11 @@ __device__ __forceinline__ void pair_segment_f64f(const double2 (*__restrict__ b
                                                   const double* az, const double* aa, double eps2,
                                                   double (*A)[3], double (*B)[3])
 {
+    // kF64BandFar: the lane's image shift d = (s_lane - s_centre) L1 is dA
+    // before the lane's breakpoint b1 and dA - L1 from it on (the centre's
+    // image is constant over the segment); both are exact
+    const int scb = (j1s < bc1) ? sc1lo : sc1lo - 1;
+    const double dA = (double)(s1lo - scb) * L1, dB = dA - L1;
 #pragma unroll ZM_PAIR_UNROLL
     for (int c = 0; c < cnt; ++c) {
         const double2 v0 = buf[0][k0 + c];
@@ -596,7 +615,27 @@ __device__ __forceinline__ void pair_segment_f64f(const double2 (*__restrict__ b
         double mx = v0.x;   // m = -2 b (exact)
         const double my = v0.y, mz = v1.x;
         const double g1 = v1.y, g2 = v2.x, g3 = v2.y;
-        if (MODE == kF64Direct) {
+        if (MODE == kF64BandFar) {
+            const double d = (j1s + c < b1) ? dA : dB;   // 0 or +-L1
+            const double2 v3 = buf[3][k0 + c];
+            const double2 v4 = buf[4][k0 + c];
+            // the record of b + d e1: m_x = -2 (b_x + d) rounded once,
+            // |b + d e1|^2 + eps^2 = bb + d (d + 2 b_x), c_2 - d g_3, c_3 + d g_2
+            const double mxs = fma(-2.0, d, mx);
+            const double bbs = fma(d, d - mx, v4.y);
+            const double c1 = v3.x, c2 = fma(-d, g3, v3.y), c3 = fma(d, g2, v4.x);
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const double s = fma(az[r], mz, fma(ay[r], my, fma(ax[r], mxs, bbs))) + aa[r];
+                const double wgt = inv_cube_sqrt(s);
+                A[r][0] = fma(wgt, g1, A[r][0]);
+                A[r][1] = fma(wgt, g2, A[r][1]);
+                A[r][2] = fma(wgt, g3, A[r][2]);
+                B[r][0] = fma(wgt, c1, B[r][0]);
+                B[r][1] = fma(wgt, c2, B[r][1]);
+                B[r][2] = fma(wgt, c3, B[r][2]);
+            }
+        } else if (MODE == kF64Direct) {
             const int jj = j1s + c;
             const int si = (jj < b1) ? s1lo : s1lo - 1;
             const int sc = (jj < bc1) ? sc1lo : sc1lo - 1;
@@ -793,12 +832,16 @@ __device__ __forceinline__ void pairs_f64f_block(const Mesh& m, const PairShape&
                     else { in_band = true; stop = e; }
                 }
                 bool in_near = true;
-                if (!in_band && near_row) {
+                if (near_row && !(in_band && (band_all || !ZM_BAND_FACTORED))) {
                     const int rn = interval_run(a, near1_lo, near1_len, n1, in_near);
                     stop = min(stop, a + rn);
                 } else if (!in_band) {
                     in_near = false;
+                } else if (!band_all && ZM_BAND_FACTORED) {
+                    in_near = false;
                 }
+                // a band segment of the far form keeps the centre's image fixed
+                if (in_band && !in_near && a < cimg1.b && stop > cimg1.b) stop = cimg1.b;
                 const int kk = k + (a - j1);
                 double A[R][3], B[R][3];
 #pragma unroll
@@ -806,7 +849,7 @@ __device__ __forceinline__ void pairs_f64f_block(const Mesh& m, const PairShape&
                     A[r][0] = A[r][1] = A[r][2] = 0.0;
                     B[r][0] = B[r][1] = B[r][2] = 0.0;
                 }
-                if (in_band) {
+                if (in_band && in_near) {
                     pair_segment_f64f<R, kF64Direct>(lds[buf], kk, stop - a, a, ax1.b, ax1.s_lo,
                                                      cimg1.b, cimg1.s_lo, m.L1, ax, ay, az, aa,
                                                      m.eps2, A, B);
@@ -818,7 +861,11 @@ __device__ __forceinline__ void pairs_f64f_block(const Mesh& m, const PairShape&
                         U[r][2] += A[r][2];
                     }
                 } else {
-                    if (in_near)
+                    if (in_band)
+                        pair_segment_f64f<R, kF64BandFar>(lds[buf], kk, stop - a, a, ax1.b, ax1.s_lo,
+                                                          cimg1.b, cimg1.s_lo, m.L1, ax, ay, az, aa,
+                                                          m.eps2, A, B);
+                    else if (in_near)
                         pair_segment_f64f<R, kF64FactNear>(lds[buf], kk, stop - a, a, ax1.b, ax1.s_lo,
                                                            cimg1.b, cimg1.s_lo, m.L1, ax, ay, az, aa,
                                                            m.eps2, A, B);
