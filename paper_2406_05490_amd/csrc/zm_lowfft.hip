@@ -34,7 +34,9 @@
 // (j - k) R + k + r Ns.  The LDS index is XOR-swizzled within groups of 16
 // (e ^ ((e >> 4) & 15)) so that the stride-R stores of the first pass do not
 // fall into one bank.  Twiddle tables exp(-2 pi i t / n), t < n, are built by
-// k_twiddle in each evaluation.
+// k_twiddle in each evaluation.  For n = 4096 the symbol rows keep the row in
+// registers between the forward and the inverse transform (fft4096_regs):
+// two LDS exchanges per transform instead of four.
 #include "zm_device.h"
 #include "zm_internal.h"
 
@@ -176,6 +178,49 @@ __device__ __forceinline__ void fft_row(double2* x, int logn, const double2* __r
     else if (rem == 1) fft_pass<2, INV>(x, n, Ns, tw);
 }
 
+// n = 4096 = 16^3 on 256 threads: the first radix-16 pass reads, and the last
+// writes, element j + 256 r in thread j (r < 16), which is also the
+// coalesced row layout.  So a row enters in registers, goes through LDS only
+// for the two exchanges between the three passes, and leaves in registers in
+// natural order: v[r] = X[j + 256 r].  Same operations in the same order as
+// fft_row (bitwise the same result), half its LDS traffic and barriers.  The
+// caller must not touch x between calls except through this function: its
+// first barrier orders the previous call's last LDS reads before this call's
+// first writes.
+template <bool INV>
+__device__ __forceinline__ void fft4096_regs(double2 (&v)[16], double2* x,
+                                             const double2* __restrict__ tw)
+{
+    const int j = threadIdx.x;
+    // pass 1 (Ns = 1, no twiddles): output 16 j + r
+    dft<16, INV>(v);
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < 16; ++r) x[sw(16 * j + r)] = v[brev<16>(r)];
+    __syncthreads();
+    // pass 2 (Ns = 16), in place in LDS
+    fft_pass<16, INV>(x, 4096, 16, tw);
+    // pass 3 (Ns = 256, k = j): output j + 256 r, kept in registers
+#pragma unroll
+    for (int r = 0; r < 16; ++r) v[r] = x[sw(j + r * 256)];
+    if (j != 0) {
+        double2 w1 = tw[j];
+        if (INV) w1.y = -w1.y;
+        double2 w = w1;
+#pragma unroll
+        for (int r = 1; r < 16; ++r) {
+            v[r] = cmul(v[r], w);
+            if (r + 1 < 16) w = cmul(w, w1);
+        }
+    }
+    dft<16, INV>(v);
+    double2 o[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) o[r] = v[brev<16>(r)];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) v[r] = o[r];
+}
+
 // Persistent row kernels: workgroup b takes rows b, b + G, b + 2G, ... (G =
 // the grid, sized to the workgroups that fit on the CUs at once).  Each
 // thread holds its n / 256 elements of the next row in registers: their
@@ -242,6 +287,38 @@ __global__ __launch_bounds__(kFftThreads) void k_lo_symbol_rows(int n1, int logn
     const double h = 0.5 / ((double)n1 * (double)n2);
     int m1 = blockIdx.x;
     if (m1 < n1) ZM_FETCH_ROW(B, m1, n2);
+    if (logn2 == 12) {
+        for (; m1 < n1; m1 += gridDim.x) {
+            double2 v[16];
+#pragma unroll
+            for (int k = 0; k < 16; ++k) v[k] = pre[k];
+            const int next = m1 + gridDim.x;
+            if (next < n1) ZM_FETCH_ROW(B, next, n2);
+            fft4096_regs<false>(v, x, tw);
+            const int s1 = 2 * m1 < n1 ? m1 : m1 - n1;
+            const double k1 = 2.0 * M_PI * s1 / L1;
+#pragma unroll
+            for (int k = 0; k < 16; ++k) {
+                const int m2 = tid + k * kFftThreads;
+                const int s2 = 2 * m2 < n2 ? m2 : m2 - n2;
+                const double k2 = 2.0 * M_PI * s2 / L2;
+                // h / |k| from the hardware rsqrt (relative error <= 2^-24) and one
+                // correction y0 (1 + e / 2), e = 1 - q y0^2: error ~ 1.5 e^2 < 1e-14
+                const double q = k1 * k1 + k2 * k2;
+                const double y0 = __builtin_amdgcn_rsq(q);
+                const double y = fma(0.5 * y0, fma(-q, y0 * y0, 1.0), y0);
+                const double ih = q > 0.0 ? h * y : 0.0;   // 1 / (2N |k|)
+                const double mx = (2 * m2 == n2) ? 0.0 : k2 * ih;  // (c2 + i c1) / (2N)
+                const double my = (2 * m1 == n1) ? 0.0 : k1 * ih;
+                v[k] = make_double2(v[k].x * mx - v[k].y * my, v[k].x * my + v[k].y * mx);
+            }
+            fft4096_regs<true>(v, x, tw);
+            double2* row = B + (size_t)m1 * n2;
+#pragma unroll
+            for (int k = 0; k < 16; ++k) row[tid + k * kFftThreads] = v[k];
+        }
+        return;
+    }
     for (; m1 < n1; m1 += gridDim.x) {
 #pragma unroll
         for (int k = 0; k < kRowRegs; ++k) {
