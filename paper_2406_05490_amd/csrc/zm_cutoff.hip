@@ -265,10 +265,12 @@ __global__ __launch_bounds__(kThreads) void k_cut_gather(Mesh m, CutGrid g, cons
 constexpr int kCutThreads = 64;
 
 // Targets per lane of the pair kernel: every scalar-loaded source record
-// serves 64 TR targets.  TR = 2 halves the loads per pair but measured
-// slower (768^2, rc = 0.0667: 3.17 against 2.57 ms): a chunk of 128 targets
-// covers enough of its cell that far fewer sources are rejected by the
-// whole wave.
+// serves 64 TR targets, each slot of 64 skipping on its own.  TR = 2, 3, 4
+// cut the loads per pair but measured no faster overall (768^2, rc =
+// 0.0667: 2.72, 2.46, 2.72 against 2.55 ms; 512^2, rc = 1/6: 2.94, 3.10,
+// 3.07 against 2.97 ms): the kernel is bound by the per-pair VALU work of
+// the accepted slots more than by its loads, and more targets per lane
+// lower the occupancy (165 VGPRs at TR = 3 against 45).
 #ifndef ZM_CUT_TARGETS_PER_LANE
 #define ZM_CUT_TARGETS_PER_LANE 1
 #endif
@@ -303,9 +305,9 @@ __device__ __forceinline__ SrcRec load_rec(const double* __restrict__ src, int j
 }
 
 // One source against the lane's TR targets: d1 = x_i - x_j is formed by the
-// caller.  A source that no target of the wave accepts skips the kernel
-// evaluation (a wave-uniform branch: the accepted set, and so every sum, is
-// unchanged).
+// caller.  Slot q of the wave (64 consecutive targets of the block) skips the
+// kernel evaluation of a source none of its targets accepts (a wave-uniform
+// branch: the accepted set, and so every sum, is unchanged).
 template <int SHIFT, bool COUNT, int TR>
 __device__ __forceinline__ void cut_pair(const Mesh& m, const CutGrid& g, const CutTarget (&t)[TR],
                                          const SrcRec& b, const double (&d1)[TR], double SL1,
@@ -315,7 +317,7 @@ __device__ __forceinline__ void cut_pair(const Mesh& m, const CutGrid& g, const 
 #pragma clang fp contract(off)
     double r1[TR], r2[TR], r3[TR], dd[TR];
     bool in[TR];
-    uint64_t any = 0;
+    uint64_t any[TR];
 #pragma unroll
     for (int q = 0; q < TR; ++q) {
         const double d2 = t[q].y - b.y;
@@ -337,11 +339,11 @@ __device__ __forceinline__ void cut_pair(const Mesh& m, const CutGrid& g, const 
             tested += t[q].active ? 1 : 0;
             accepted += (t[q].active && in[q]) ? 1 : 0;
         }
-        any |= __builtin_amdgcn_ballot_w64(in[q]) & t[q].amask;
+        any[q] = __builtin_amdgcn_ballot_w64(in[q]) & t[q].amask;
     }
-    if (any == 0ull) return;
 #pragma unroll
     for (int q = 0; q < TR; ++q) {
+        if (any[q] == 0ull) continue;
         const double wgt = in[q] ? dev::inv_cube_sqrt(dd[q] + m.eps2) : 0.0;
         const double a1 = wgt * b.g1, a2 = wgt * b.g2, a3 = wgt * b.g3;
         acc[q][0] = fma(r2[q], a3, acc[q][0]);
