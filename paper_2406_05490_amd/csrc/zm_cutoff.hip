@@ -402,9 +402,13 @@ __global__ __launch_bounds__(kCutThreads) void k_cut_pairs(Mesh m, CutGrid g,
                                                            unsigned long long* __restrict__ counts)
 {
     constexpr int CH = kCutThreads * TR;
-    const int blk = blockIdx.x, row = blockIdx.y;
+    // Grid order as launched (block fastest), so that the 8 XCDs, which
+    // take workgroups round robin, share every region of the mesh.  Giving
+    // each XCD a contiguous range of blocks instead (neighbouring blocks read
+    // mostly the same cells) measured 7% slower at 768^2 and 15% at 512^2.
+    const int blk = blockIdx.x, row = blockIdx.y, zc = blockIdx.z;
     const int T0 = bstart[blk], T1 = bend[blk];
-    if (T0 + (int)blockIdx.z * CH >= T1) return;   // nothing left: uniform
+    if (T0 + zc * CH >= T1) return;   // nothing left: uniform
     const int N = m.N;
     const int lane = threadIdx.x;
     const int bx = blk % g.nb1, by = blk / g.nb1;
@@ -413,8 +417,8 @@ __global__ __launch_bounds__(kCutThreads) void k_cut_pairs(Mesh m, CutGrid g,
     const bool row_in = g.periodic || wy == 0;
     unsigned long long tested = 0, accepted = 0;
 
-    // chunks blockIdx.z, blockIdx.z + chunks, ...
-    for (int t0 = T0 + (int)blockIdx.z * CH; t0 < T1; t0 += g.chunks * CH) {
+    // chunks zc, zc + chunks, ...
+    for (int t0 = T0 + zc * CH; t0 < T1; t0 += g.chunks * CH) {
         CutTarget t[TR];
         double kxi[TR], kyi[TR];
         bool any_k = false;

@@ -13,7 +13,7 @@ import pytest
 
 import oracle
 import rocket_rig as rr
-from zm_testutil import relerr, to_dev, to_host
+from zm_testutil import fft_reference, relerr, to_dev, to_host
 
 pytestmark = pytest.mark.gpu
 
@@ -131,3 +131,18 @@ def test_low_order_1024_against_numpy_fft(gpu):
     nrm = np.cross(t1.T, t2.T).T
     ref = S * (nrm / np.linalg.norm(nrm, axis=0))
     assert relerr(u, ref) < TOL64
+
+
+@pytest.mark.parametrize("n1,n2,L1,L2", [(64, 4096, 0.5, 2.0), (4096, 64, 2.0, 0.5)])
+def test_low_order_4096_side_against_numpy_fft(gpu, n1, n2, L1, L2):
+    """A side of 4096: the symbol rows of a 4096-point column transform keep
+    the row in registers between the forward FFT, the symbol and the inverse
+    FFT (64 x 4096); the pack and inverse rows take 4096-point row transforms
+    in LDS (4096 x 64).  Both against numpy's FFT of the definition."""
+    p = params(n1, n2, period1=L1, period2=L2)
+    z, _ = rr.multi_mode(n1, n2, 8, seed=5)
+    z[0] *= L1 / 2.0
+    z[1] *= L2 / 2.0
+    w = rr.synthetic_vorticity(n1, n2, seed=5)
+    u = gpu_u(p, z, w, gpu)
+    assert relerr(u, fft_reference(n1, n2, z, w, L1, L2)) < TOL64
