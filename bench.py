@@ -173,7 +173,10 @@ def br_sweep_1m(zm, torch, reps: int = 2):
 
 def ensemble64(zm, torch, steps: int = 20):
     """The 64-member uneven ensemble (sides 32..256, FP32 form) advanced by
-    one batch with graph-captured RK3 steps: aggregate pair-interactions/s."""
+    one batch with graph-captured RK3 steps: aggregate pair-interactions/s,
+    one member of each side checked bit for bit against a solo run, and the
+    autotuner's choice per side (default and tuned shape, pair-kernel ms;
+    measured after the timed run, entries removed afterwards)."""
     ms = rr.ensemble(64, seed=3)
     ps = [zm.Params(m.n, m.n, eps=m.eps, atwood=m.atwood, gravity=1.0, dt=1e-3,
                     precision=zm.ZM_FP32_PAIRS) for m in ms]
@@ -189,8 +192,35 @@ def ensemble64(zm, torch, steps: int = 20):
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     info = b.info()
+    # one member of each side rerun alone for the same 1 + steps steps: its
+    # state must be bitwise equal to the batch's
+    firsts = {}
+    for i, m in enumerate(ms):
+        firsts.setdefault(m.n, i)
+    equal = 0
+    for i in sorted(firsts.values()):
+        m = ms[i]
+        zb = torch.empty(3 * m.n * m.n, dtype=torch.float64, device=dev)
+        wb = torch.empty(2 * m.n * m.n, dtype=torch.float64, device=dev)
+        b.get_state(i, zb, wb)
+        z, w = m.state()
+        ctx = zm.Context(ps[i])
+        ctx.init_state(torch.from_numpy(z.ravel()).to(dev), torch.from_numpy(w.ravel()).to(dev))
+        ctx.step(1 + steps)
+        zs = torch.empty_like(zb); ws = torch.empty_like(wb)
+        ctx.get_state(zs, ws)
+        torch.cuda.synchronize()
+        equal += int(torch.equal(zs, zb) and torch.equal(ws, wb))
+        del ctx
     b.destroy()
-    return {"members": 64, "sides": sorted({m.n for m in ms}), "steps": steps,
+    sides = sorted({m.n for m in ms})
+    tuned = tune_report(zm, torch, sides=tuple(sides), precisions=("fp32_pairs",))
+    return {"members": 64, "sides": sides, "steps": steps,
+            "solo_vs_batch": {"members_checked": len(firsts), "bitwise_equal": equal},
+            "autotune_fp32": [{"side": r["side"], "default": [r["default"]["R"], r["default"]["splits"]],
+                               "tuned": [r["tuned"]["R"], r["tuned"]["splits"]],
+                               "default_ms": r["default"]["pair_ms"], "tuned_ms": r["tuned"]["pair_ms"]}
+                              for r in tuned],
             "pairs_per_step": info.pairs_per_step, "work_items": info.work_items[1],
             "persistent_groups": info.persistent_groups, "seconds": dt,
             "pairs_per_s": info.pairs_per_step * steps / dt,
@@ -460,11 +490,15 @@ def pair_kernel_ms(zm, torch, n: int, prec: int, reps: int = 3) -> float:
     return ms / n_
 
 
-def tune_report(zm, torch, sides=(32, 48, 64, 96, 128, 192, 256, 512, 1024)):
+def tune_report(zm, torch, sides=(32, 48, 64, 96, 128, 192, 256, 512, 1024),
+                precisions=("fp64", "fp32_pairs")):
     """Autotune the pair kernel per (side, precision); report the default and
-    tuned shapes with their measured pair-kernel times."""
+    tuned shapes with their measured pair-kernel times.  The process-wide
+    tuning entries are removed again afterwards."""
     rows = []
     for prec, name in ((zm.ZM_FP64, "fp64"), (zm.ZM_FP32_PAIRS, "fp32_pairs")):
+        if name not in precisions:
+            continue
         for n in sides:
             zm.tuning_set(n, n, prec)
             d = zm.tuning_get(n, n, prec)
@@ -482,7 +516,7 @@ def tune_report(zm, torch, sides=(32, 48, 64, 96, 128, 192, 256, 512, 1024)):
 
 
 def serving(zm, torch, window_s: float = 30.0, budget: int = 1 << 30, count: int = 200,
-            step_scale: int = 10):
+            step_scale: int = 10, solo_checks: int = 8):
     """Poisson request stream (sides log-uniform 64..512, A ~ U[0.1, 0.9],
     100..1000 RK3 steps, FP32 form) served by one pool with a 1 GiB budget.
     Capacity is measured first on a saturated pool; the arrival rate is then
@@ -492,7 +526,9 @@ def serving(zm, torch, window_s: float = 30.0, budget: int = 1 << 30, count: int
     (10..100 steps) and the rate multiplied by it.  The mean number of live
     requests (rate x residence time) and hence the per-step latency
     distribution of the steady state are unchanged, while a bounded window
-    sees step_scale times more arrivals and completions."""
+    sees step_scale times more arrivals and completions.  The first
+    solo_checks requests to finish are rerun alone afterwards and compared
+    bit for bit with their pooled result."""
     import numpy as np
     dev = torch.device("cuda:0")
 
@@ -525,6 +561,7 @@ def serving(zm, torch, window_s: float = 30.0, budget: int = 1 << 30, count: int
     pool = zm.Pool(budget)
     lat, queue_delay, admitted_at = [], [], {}
     ids = {}
+    checked = []   # (stream index, final z, final w) of the first finished requests
     nxt = 0
     start = time.perf_counter()
     p0 = pool.stats().pairs_done
@@ -547,6 +584,12 @@ def serving(zm, torch, window_s: float = 30.0, budget: int = 1 << 30, count: int
                 admitted_at[rid] = t_now
                 queue_delay.append(t_now - stream[ids[rid]].arrival)
             if state == zm.ZM_REQ_FINISHED:
+                if len(checked) < solo_checks:
+                    m = stream[ids[rid]]
+                    zf = torch.empty(3 * m.n * m.n, dtype=torch.float64, device=dev)
+                    wf = torch.empty(2 * m.n * m.n, dtype=torch.float64, device=dev)
+                    pool.fetch(rid, zf, wf)
+                    checked.append((ids[rid], zf, wf))
                 pool.release(rid)
         if not recs:
             if nxt >= len(stream):
@@ -554,6 +597,20 @@ def serving(zm, torch, window_s: float = 30.0, budget: int = 1 << 30, count: int
             time.sleep(min(0.01, max(0.0, stream[nxt].arrival - t_now)))
     wall = time.perf_counter() - start
     st = pool.stats()
+    # solo vs mix: each checked request rerun alone in its own context from
+    # the same state must end bitwise equal to its run inside the pool
+    equal = 0
+    for k, zf, wf in checked:
+        m = stream[k]
+        z, w = m.state()
+        ctx = zm.Context(params(m))
+        ctx.init_state(torch.from_numpy(z.ravel()).to(dev), torch.from_numpy(w.ravel()).to(dev))
+        ctx.step(m.steps)
+        zs = torch.empty_like(zf); ws = torch.empty_like(wf)
+        ctx.get_state(zs, ws)
+        torch.cuda.synchronize()
+        equal += int(torch.equal(zs, zf) and torch.equal(ws, wf))
+        del ctx
     out = {
         "requests_total": count, "steps_per_request": [100 // step_scale, 1000 // step_scale],
         "time_compression": step_scale, "arrived": nxt, "admitted": len(admitted_at),
@@ -569,6 +626,8 @@ def serving(zm, torch, window_s: float = 30.0, budget: int = 1 << 30, count: int
         "pairs_per_s": (st.pairs_done - p0) / wall,
         "saturated_pairs_per_s": cap_pairs,
         "live_at_end": st.live, "queued_at_end": st.queued,
+        "solo_vs_mix": {"requests_checked": len(checked), "bitwise_equal": equal,
+                        "sides": [stream[k].n for k, _, _ in checked]},
     }
     pool.destroy()
     return out
