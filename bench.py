@@ -230,11 +230,23 @@ def ensemble64(zm, torch, steps: int = 20):
 
 def small_mesh_latency(zm, torch, steps: int = 50):
     """64 x 64 FP64 (launch-latency bound): ms per RK3 step with direct
-    launches and with the captured graph."""
+    launches and with the captured graph; also returns the state after the
+    workload's own trajectory (its step count from its initial state), which
+    the oracle leg compares."""
     wl = rr.WORKLOADS["periodic64_single_fp64"]
     z, w = wl.state()
     dev = torch.device("cuda:0")
     out = {}
+    p = zm.Params(wl.n1, wl.n2, eps=wl.eps, atwood=wl.atwood, gravity=wl.gravity, dt=wl.dt)
+    ctx = zm.Context(p)
+    zd = torch.from_numpy(z.ravel()).to(dev); wd = torch.from_numpy(w.ravel()).to(dev)
+    ctx.init_state(zd, wd)
+    ctx.step(wl.steps)
+    z1 = torch.empty_like(zd); w1 = torch.empty_like(wd)
+    ctx.get_state(z1, w1)
+    torch.cuda.synchronize()
+    traj = (z1.cpu().numpy().reshape(3, -1), w1.cpu().numpy().reshape(2, -1))
+    del ctx
     for name, flags in (("direct", 0), ("graph", zm.ZM_FLAG_GRAPH)):
         p = zm.Params(wl.n1, wl.n2, eps=wl.eps, atwood=wl.atwood, gravity=wl.gravity, dt=wl.dt,
                       flags=flags)
@@ -248,7 +260,7 @@ def small_mesh_latency(zm, torch, steps: int = 50):
         out[name + "_ms_per_step"] = (time.perf_counter() - t0) / steps * 1e3
         del ctx
     out["pairs_per_s_graph"] = 3 * wl.n * wl.n / (out["graph_ms_per_step"] / 1e3)
-    return out
+    return out, traj
 
 
 def cutoff_eval(zm, torch, p, z, w, reps: int = 3):
@@ -704,12 +716,14 @@ def cpu_baseline(wl, ctx_factory, z0, w0, target_seconds: float):
     }
 
 
-def cpu_oracle_detail(threads: int, sweep_u=None):
+def cpu_oracle_detail(threads: int, sweep_u=None, traj64=None):
     """The oracle's own rates on the other workloads (a few seconds of host
     time in all): one full BR evaluation of the 64 x 64 workload, 1024 seeded
     targets of the 1024 x 1024 workload, and the 64 x 64 evaluation on one
     thread.  With the 1M-point sweep's GPU velocities (FP64 and FP32 forms,
-    same state and vorticity) their error on those 1024 targets as well."""
+    same state and vorticity) their error on those 1024 targets as well.
+    With the GPU's 64 x 64 trajectory, the oracle's own trajectory of the
+    workload (its step count from its initial state), timed and compared."""
     import oracle
     out = {"threads": threads}
     for name, key, targets, nthreads in (
@@ -731,6 +745,21 @@ def cpu_oracle_detail(threads: int, sweep_u=None):
             for form, u in sweep_u.items():
                 ug = u.reshape(3, -1)[:, tg]
                 out[name][f"{form}_vs_oracle_max_rel_err"] = float(np.max(np.abs(ug - ref)) / scale)
+    if traj64 is not None:
+        wl = rr.WORKLOADS["periodic64_single_fp64"]
+        z0, w0 = wl.state()
+        P = oracle.Problem(wl.n1, wl.n2, eps=wl.eps, atwood=wl.atwood, gravity=wl.gravity, dt=wl.dt)
+        t0 = time.perf_counter()
+        zr, wr = oracle.rk3(P, z0, w0, wl.steps, threads=threads)
+        dt = time.perf_counter() - t0
+        zg, wg = traj64
+        out["periodic64_trajectory"] = {
+            "steps": wl.steps, "pairs": 3.0 * wl.steps * wl.n * wl.n, "seconds": dt,
+            "pairs_per_s": 3.0 * wl.steps * wl.n * wl.n / dt, "threads": threads,
+            "gpu_vs_oracle_max_rel_err": {
+                "z": float(np.max(np.abs(zg - zr)) / np.max(np.abs(zr))),
+                "w": float(np.max(np.abs(wg - wr)) / np.max(np.abs(wr))),
+                "z_motion": float(np.max(np.abs((zg - z0) - (zr - z0))) / np.max(np.abs(zr - z0)))}}
     return out
 
 
@@ -763,7 +792,7 @@ def main():
         print(json.dumps({"tune_report": tune_report(zm, torch)}), flush=True)
         return
 
-    sweep_u = None
+    sweep_u = traj64 = None
     wl = rr.WORKLOADS[args.workload]
     prec = zm.ZM_FP32_PAIRS if wl.precision == "fp32_pairs" else zm.ZM_FP64
     steps = wl.steps if args.steps is None else args.steps
@@ -840,7 +869,7 @@ def main():
     if not args.no_sweep:
         out["br_sweep_1m"], sweep_u = br_sweep_1m(zm, torch)
         out["ensemble64_fp32_graph"] = ensemble64(zm, torch)
-        out["periodic64_latency"] = small_mesh_latency(zm, torch)
+        out["periodic64_latency"], traj64 = small_mesh_latency(zm, torch)
         out["cutoff"] = cutoff_section(zm, torch)
         out["low_order_4096"] = low_order_section(zm, torch)
         out["free_single_mode"] = free_section(zm, torch)
@@ -849,7 +878,8 @@ def main():
         out["serving"] = serving(zm, torch, window_s=args.serve_seconds)
     if args.cpu_seconds > 0:
         out["cpu_baseline"] = cpu_baseline(wl, lambda: zm.Context(p), z0, w0, args.cpu_seconds)
-        out["cpu_oracle_detail"] = cpu_oracle_detail(out["cpu_baseline"]["cores"], sweep_u)
+        out["cpu_baseline"]["gpu_speedup"] = value / out["cpu_baseline"]["value"]
+        out["cpu_oracle_detail"] = cpu_oracle_detail(out["cpu_baseline"]["cores"], sweep_u, traj64)
     print(json.dumps(out), flush=True)
 
 
