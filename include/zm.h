@@ -295,8 +295,9 @@ zm_status zm_tuning_get(int32_t n1, int32_t n2, int32_t precision, zm_pair_tunin
 size_t zm_autotune_workspace_bytes(const zm_params *params);
 
 /* Time the pair kernel on synthetic data of this mesh size for every
- * candidate shape (targets per lane 1, 2, 4 x source splits around the
- * default; for FP32 only the shapes the FP32 form accepts on this mesh,
+ * candidate shape (targets per lane 1, 2, 4 x source splits from a quarter
+ * to eight times the count that gives >= 2048 workgroups, plus the default
+ * shape; for FP32 only the shapes the FP32 form accepts on this mesh,
  * ZM_ERR_UNSUPPORTED if none), store the fastest in the table and return it (best, and its
  * time per launch in best_ms; either may be NULL).  Synchronous: waits for
  * its own work on hip_stream.  Uses only the caller's workspace. */

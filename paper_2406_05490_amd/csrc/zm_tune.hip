@@ -23,10 +23,11 @@ bool valid_tuning(const zm_pair_tuning& t)
            t.source_splits >= 1;
 }
 
-// Candidate shapes: R in {1, 2, 4} x splits in {s0/4, s0/2, s0, 2 s0} where s0
-// is the split count giving >= 2048 workgroups for that R, clamped to
-// [1, n2], plus the untuned default shape, deduplicated; for the FP32 form
-// only the R whose patches keep its error bound.
+// Candidate shapes: R in {1, 2, 4} x splits in {s0/4, s0/2, s0, 2 s0, 4 s0,
+// 8 s0} where s0 is the split count giving >= 2048 workgroups for that R,
+// clamped to [1, n2], plus the untuned default shape, deduplicated; for the
+// FP32 form only the R whose patches keep its error bound.  (Finer splits
+// pay in FP32: 8 s0 at 256 x 256.)
 std::vector<zm::PairShape> candidates(const zm_params& p)
 {
     std::vector<zm::PairShape> out;
@@ -38,7 +39,7 @@ std::vector<zm::PairShape> candidates(const zm_params& p)
     for (int R : {1, 2, 4}) {
         const zm::PairShape d = zm::make_pair_shape(p.n1, p.n2, p.precision, R, 0);
         if (zm::fp32_shape_problem(p, d)) continue;
-        for (int f : {-2, -1, 0, 1}) {
+        for (int f : {-2, -1, 0, 1, 2, 3}) {
             int s = f < 0 ? d.splits >> (-f) : d.splits << f;
             add(zm::make_pair_shape(p.n1, p.n2, p.precision, R, std::max(1, s)));
         }
