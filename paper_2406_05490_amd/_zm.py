@@ -474,6 +474,7 @@ class Pool:
         self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=dev)
         self.stream = torch.cuda.current_stream(dev) if stream is None else stream
         self._inputs = {}          # id -> (z, w) kept alive until admitted
+        self._points = {}          # id -> mesh points of the request (checks fetch buffers)
         h = ctypes.c_void_p()
         with torch.cuda.device(dev):
             st = self.lib.zm_pool_create(ctypes.byref(h), int(budget_bytes), int(flags),
@@ -493,6 +494,7 @@ class Pool:
         self._raise(self.lib.zm_pool_submit(self.handle, ctypes.byref(p.c()), _ptr(z), _ptr(w),
                                             int(steps), ctypes.byref(rid)))
         self._inputs[rid.value] = (z, w)
+        self._points[rid.value] = p.n
         return rid.value
 
     def iterate(self):
@@ -511,14 +513,21 @@ class Pool:
         return st.value, done.value
 
     def fetch(self, rid: int, z, w):
+        n = self._points.get(int(rid))
+        if n is None:
+            raise ZMError(ZM_ERR_INVALID_ARG, f"request {rid} was not submitted through this pool "
+                                               "or was already released")
+        _check_f64_planes(z, 3, n, "z"); _check_f64_planes(w, 2, n, "w")
         self._raise(self.lib.zm_pool_fetch(self.handle, int(rid), _ptr(z), _ptr(w)))
 
     def release(self, rid: int):
         self._raise(self.lib.zm_pool_release(self.handle, int(rid)))
+        self._points.pop(int(rid), None)
 
     def cancel(self, rid: int):
         self._raise(self.lib.zm_pool_cancel(self.handle, int(rid)))
         self._inputs.pop(rid, None)
+        self._points.pop(int(rid), None)
 
     def stats(self) -> zm_pool_stats:
         out = zm_pool_stats()
