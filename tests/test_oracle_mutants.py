@@ -38,6 +38,10 @@ MUTANTS = {
                               "return (-fp2 + 16.0 * fp1 - 32.0 * f0 + 16.0 * fm1 - fm2) / (12.0 * h * h);"),
     "q_no_metric": ("q[p] = (g1 * g1 + g2 * g2 + g3 * g3) / (n1 * n1 + n2 * n2 + n3 * n3);",
                     "q[p] = (g1 * g1 + g2 * g2 + g3 * g3);"),
+    "v_q_coefficient": ("return P->atwood * ((uu - 0.25 * q) - (2.0 * P->gravity) * z3);",
+                        "return P->atwood * ((uu - 0.5 * q) - (2.0 * P->gravity) * z3);"),
+    "v_velocity_squared_dropped": ("double uu = u1 * u1 + u2 * u2 + u3 * u3;",
+                                   "double uu = 0.0 * (u1 * u1 + u2 * u2 + u3 * u3);"),
     "gravity_sign": ("return P->atwood * ((uu - 0.25 * q) - (2.0 * P->gravity) * z3);",
                      "return P->atwood * ((uu - 0.25 * q) + (2.0 * P->gravity) * z3);"),
     "rk3_stage2_weights": ("y2[k] = 0.75 * y0[k] + 0.25 * (y1[k] + dt * F[k]);",
@@ -89,6 +93,7 @@ def test_mutant_is_caught(name, source, tmp_path):
                         os.path.join(ROOT, "tests", "test_oracle_cutoff.py"),
                         os.path.join(ROOT, "tests", "test_oracle_loworder.py"),
                         os.path.join(ROOT, "tests", "test_oracle_free.py"),
-                        os.path.join(ROOT, "tests", "test_oracle_medium.py")],
+                        os.path.join(ROOT, "tests", "test_oracle_medium.py"),
+                        os.path.join(ROOT, "tests", "test_oracle_vterms.py")],
                        cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
     assert r.returncode == 1, f"mutant {name} passed every pin:\n{r.stdout[-2000:]}"
