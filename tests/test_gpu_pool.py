@@ -149,3 +149,51 @@ def test_pool_evicts_failing_request_alone(gpu):
     assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1])
     pool.release(b)
     assert pool.query(b)[0] == zm.ZM_REQ_UNKNOWN
+
+
+def test_pool_results_match_the_oracle(gpu):
+    """Served results against the CPU oracle, not only against solo runs:
+    a mix of four requests (even, odd and non-square sides, one of 64; FP64
+    and FP32 pair forms; a budget that makes one wait) is served to the end,
+    and every fetched state is compared with the oracle's own RK3
+    trajectory: FP64 requests within 1e-12 (state) and 1e-9 (motion
+    z - z0 and w), FP32 requests within 1e-5 on the motion and w."""
+    import oracle
+    import paper_2406_05490_amd as zm
+    from zm_testutil import relerr
+    reqs = []
+    for (n1, n2), a, prec, steps, seed in (((64, 64), 0.6, zm.ZM_FP64, 3, 11),
+                                           ((45, 45), 0.4, zm.ZM_FP32_PAIRS, 4, 12),
+                                           ((40, 56), 0.8, zm.ZM_FP64, 2, 13),
+                                           ((33, 30), 0.3, zm.ZM_FP32_PAIRS, 3, 14)):
+        p = zm.Params(n1, n2, eps=1.0 / n1, atwood=a, gravity=1.0, dt=2e-3, precision=prec)
+        z, w = rr.random_state(n1, n2, seed=seed, height=0.05)
+        reqs.append((p, z, w, steps))
+    sizes = sorted(zm.pool_request_bytes(p) for p, *_ in reqs)
+    pool = zm.Pool(sizes[-1] + sizes[-2] + sizes[0])
+    ids = [pool.submit(p, to_dev(z, gpu), to_dev(w, gpu), steps) for p, z, w, steps in reqs]
+    index = {rid: i for i, rid in enumerate(ids)}
+    results, live = {}, []
+    for _ in range(50):
+        recs = pool.iterate()
+        if not recs and pool.stats().queued == 0:
+            break
+        live.append(len(recs))
+        for rid, done, state, _ in recs:
+            if state == zm.ZM_REQ_FINISHED:
+                results[rid] = fetch(pool, rid, reqs[index[rid]][0], gpu)
+                pool.release(rid)
+    assert max(live) >= 2 and sorted(results) == sorted(ids)
+    for rid, (p, z, w, steps) in zip(ids, reqs):
+        P = oracle.Problem(p.n1, p.n2, eps=p.eps, atwood=p.atwood, gravity=p.gravity, dt=p.dt)
+        zr, wr = oracle.rk3(P, z, w, steps)
+        zg = results[rid][0].reshape(3, -1)
+        wg = results[rid][1].reshape(2, -1)
+        e_motion = relerr(zg - z, zr - z)
+        e_w = relerr(wg - w, wr - w)
+        if p.precision == zm.ZM_FP64:
+            assert relerr(zg, zr) < 1e-12, (p.n1, p.n2)
+            assert e_motion < 1e-9 and e_w < 1e-9, (p.n1, p.n2, e_motion, e_w)
+        else:
+            assert e_motion < 1e-5 and e_w < 1e-5, (p.n1, p.n2, e_motion, e_w)
+    assert pool.stats().used_bytes == 0
