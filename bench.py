@@ -5,16 +5,25 @@
 
 A step is one SSP-RK3 step: three evaluations of (surface derivatives ->
 all-pairs Birkhoff-Rott sweep -> tie correction -> reduction -> RK3 stage),
-each evaluation doing N^2 pair interactions.  Inputs are seeded synthetic
-rocket-rig interfaces resident in HBM before the timed region.  Prints one
-JSON line with the throughput, the pair kernel's place on its VALU roofline
-(timed with HIP events inside the library, on the stream it launches on) and
-the CPU oracle timed on a bounded sample of the same workload.
+each evaluation doing N^2 pair interactions.  The default workload is the
+1024 x 1024 (1,048,576-point) sixteen-mode interface with FP32 pair
+interactions and FP64 state, sums and RK3.  Inputs are seeded synthetic
+rocket-rig interfaces resident in HBM before the timed region.
+
+The last stdout line is one JSON object: the throughput, the pair kernel's
+place on its VALU roofline (timed with HIP events inside the library, on the
+stream it launches on) with the FP64 form of the same 1M-point sweep beside
+it, the CPU oracle timed on a bounded sample of the same workload, and short
+summaries of the other measurements (the five-step trajectory against the
+FP64 path and the oracle, the 256 x 256 FP64 run, the 64 x 64 trajectory,
+the 64-member ensemble, the served request stream).  Progress lines come
+before it; --detail-out writes every measured figure to a JSON file.
 """
 from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -28,9 +37,19 @@ import numpy as np  # noqa: E402
 import rocket_rig as rr  # noqa: E402
 
 METRIC = "BR pair-interactions/s & % VALU peak (FP32 vs FP64); served p50/p99 step ms"
-FLOPS_PER_PAIR = 27          # 3 sub, 3 fma, 1 rsqrt, 2 mul, 3 mul, 6 fma (fma = 2)
+# Algorithmic work of one pair in the direct form (the roofline unit): r (3
+# sub), |r|^2 + eps^2 (3 FMA), rsqrt (1), cube (2 mul), w gamma (3 mul),
+# r x (w gamma) accumulated (6 FMA), an FMA counted as 2 flop.  The kernels'
+# factored far form executes fewer operations per pair; the flop they do
+# execute is read from the committed VALU counters (executed_flops_per_pair).
+FLOPS_PER_PAIR = 27
 PEAK_TFLOPS = {"fp64": 78.6, "fp32_pairs": 157.3}   # MI355X vector peaks
-DEFAULT_WORKLOAD = "periodic256_multimode8_fp64"
+DEFAULT_WORKLOAD = "periodic1024_multimode16_fp32"
+
+
+def log(msg: str):
+    """Progress line on stdout (the JSON result is always the last line)."""
+    print(f"[bench] {msg}", flush=True)
 
 
 def parse():
@@ -42,9 +61,16 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target CPU time of the oracle sample (0 = skip)")
     ap.add_argument("--no-sweep", action="store_true",
-                    help="skip the 1M-point BR sweep (FP64 and FP32 forms)")
-    ap.add_argument("--serve-seconds", type=float, default=30.0,
-                    help="length of the real-time serving window (0 = skip)")
+                    help="time the workload's RK3 steps only (no precision sweep, trajectory "
+                         "checks, ensemble or model sections)")
+    ap.add_argument("--no-sections", action="store_true",
+                    help="skip the cutoff, low-order, medium-order and free-sheet sections")
+    ap.add_argument("--serve-requests", type=int, default=200,
+                    help="requests of the served stream (0 = skip serving)")
+    ap.add_argument("--serve-max-seconds", type=float, default=420.0,
+                    help="stop serving after this long even if requests remain")
+    ap.add_argument("--detail-out", default=None, metavar="PATH",
+                    help="also write every measured figure to this JSON file")
     ap.add_argument("--tune-report", action="store_true",
                     help="only autotune the pair kernel for a range of mesh sides and print "
                          "the choice table (default shape vs tuned)")
@@ -57,9 +83,33 @@ def parse():
     ap.add_argument("--free-only", action="store_true",
                     help="only measure the non-periodic single-mode case (exact, cutoff, "
                          "far-field check)")
+    ap.add_argument("--ensemble-only", action="store_true",
+                    help="only measure the 64-member ensemble")
+    ap.add_argument("--serve-only", action="store_true",
+                    help="only serve the request stream")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of this many MiB (counter calibration)")
     return ap.parse_args()
+
+
+def sig(x, digits: int = 4):
+    """Floats rounded to a few significant digits, recursively (for the
+    one-line summary)."""
+    if isinstance(x, float):
+        if x == 0.0 or not math.isfinite(x):
+            return x
+        return float(f"{x:.{digits}g}")
+    if isinstance(x, dict):
+        return {k: sig(v, digits) for k, v in x.items()}
+    if isinstance(x, (list, tuple)):
+        return [sig(v, digits) for v in x]
+    return x
+
+
+def rel(a, b):
+    """Normwise relative error max |a - b| / max |b|."""
+    den = float(np.max(np.abs(b)))
+    return float(np.max(np.abs(a - b)) / den) if den > 0 else float(np.max(np.abs(a)))
 
 
 PAIR_KERNEL_SOURCES = ("zm_device.h", "zm_internal.h", "zm_kernels.hip")
@@ -105,11 +155,13 @@ def library_source_hash() -> str:
     return h.hexdigest()
 
 
-def measured_traffic(kernel: str, workload: str):
-    """HBM bytes per launch from the committed counter summary of this kernel
-    and workload (FETCH_SIZE and WRITE_SIZE scaled by a plain copy's reading),
-    or None when there is none or the sources changed since it was taken."""
-    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}.traffic.json")
+def measured_counters(kernel: str, workload: str):
+    """The committed counter record of this kernel and workload
+    (profiles/<kernel>_<workload>.counters.json: HBM bytes per launch from
+    FETCH_SIZE / WRITE_SIZE scaled by a plain copy's reading, and VALU
+    instructions per 64 pairs by kind), or None when there is none or the
+    pair-kernel sources changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}.counters.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
@@ -118,7 +170,26 @@ def measured_traffic(kernel: str, workload: str):
         return None
     if rec.get("source_sha256") != library_source_hash():
         return None
+    return rec
+
+
+def measured_traffic(kernel: str, workload: str):
+    """HBM bytes per launch from the committed counter record, or None."""
+    rec = measured_counters(kernel, workload)
+    if rec is None or "read_bytes_per_launch" not in rec:
+        return None
     return rec["read_bytes_per_launch"] + rec["write_bytes_per_launch"]
+
+
+def executed_flops_per_pair(kernel: str, workload: str):
+    """Flop the kernel executes per pair by the committed VALU counters:
+    (2 FMA + MUL + ADD + TRANS) wave instructions per 64 pairs (each wave
+    instruction is 64 lane operations), or None."""
+    rec = measured_counters(kernel, workload)
+    if rec is None or "valu_per_64_pairs" not in rec:
+        return None
+    v = rec["valu_per_64_pairs"]
+    return 2.0 * v["fma"] + v["mul"] + v["add"] + v["trans"]
 
 
 def copy_calibration(mib: int):
@@ -132,21 +203,64 @@ def copy_calibration(mib: int):
     print(json.dumps({"copy_calibration_bytes_read": n * 8, "bytes_written": n * 8, "launches": 3}))
 
 
-def br_sweep_1m(zm, torch, reps: int = 2):
-    """One BR evaluation on the 1024 x 1024 precision workload (synthetic
-    vorticity) in the FP64 and FP32 forms: pair-kernel time from HIP events,
-    roofline fraction against each form's vector peak, speedup and error."""
-    wl = rr.WORKLOADS["periodic1024_multimode16_fp32"]
+def to_dev(torch, a, dev):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64).ravel()).to(dev)
+
+
+def params_of(zm, wl, precision=None, flags=0):
+    prec = precision if precision is not None else (
+        zm.ZM_FP32_PAIRS if wl.precision == "fp32_pairs" else zm.ZM_FP64)
+    return zm.Params(wl.n1, wl.n2, eps=wl.eps, atwood=wl.atwood, gravity=wl.gravity, dt=wl.dt,
+                     precision=prec, flags=flags)
+
+
+def trajectory_run(zm, torch, wl, steps: int, warmup: int):
+    """The workload's RK3 steps from its initial state: warmup steps, then
+    `steps` timed steps with per-kernel HIP events on the context stream."""
+    dev = torch.device("cuda:0")
+    p = params_of(zm, wl)
+    z0, w0 = wl.state()
+    zd, wd = to_dev(torch, z0, dev), to_dev(torch, w0, dev)
+    ctx = zm.Context(p)
+    ctx.init_state(zd, wd)
+    info = ctx.launch_info()
+    stream = ctx.stream
+    ctx.step(warmup)
+    torch.cuda.synchronize()
+    ctx.profile_read()                      # discard warm-up timings
+    ctx.profile_enable(True)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    ctx.step(steps)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    gpu_s = ev0.elapsed_time(ev1) / 1e3
+    stats = ctx.profile_read()
+    ctx.profile_enable(False)
+    del ctx
+    elapsed = max(wall, gpu_s)
+    launches, pair_ms = stats["pairs"]
+    return {"info": info, "elapsed": elapsed, "steps": steps, "stats": stats,
+            "pair_launches": launches, "avg_pair_s": pair_ms / 1e3 / max(launches, 1),
+            "pairs_per_step": 3 * info.pairs_per_eval}
+
+
+def br_sweep(zm, torch, wl, reps: int = 2):
+    """One BR evaluation of the workload's state with the synthetic
+    vorticity in the FP64 and FP32 forms: pair-kernel time from HIP events,
+    roofline fraction against each form's vector peak, speedup and the
+    difference between the forms on every target."""
     z, _ = wl.state()
     w = rr.synthetic_vorticity(wl.n1, wl.n2, seed=wl.seed)
     dev = torch.device("cuda:0")
-    zd = torch.from_numpy(z.ravel()).to(dev)
-    wd = torch.from_numpy(w.ravel()).to(dev)
+    zd, wd = to_dev(torch, z, dev), to_dev(torch, w, dev)
     res, us = {}, {}
     for name, prec in (("fp64", zm.ZM_FP64), ("fp32_pairs", zm.ZM_FP32_PAIRS)):
-        p = zm.Params(wl.n1, wl.n2, eps=wl.eps, atwood=wl.atwood, gravity=wl.gravity,
-                      dt=wl.dt, precision=prec)
-        ctx = zm.Context(p)
+        ctx = zm.Context(params_of(zm, wl, precision=prec))
         ud = torch.empty_like(zd)
         ctx.br_velocity(zd, wd, ud)          # warm-up
         torch.cuda.synchronize()
@@ -160,72 +274,67 @@ def br_sweep_1m(zm, torch, reps: int = 2):
         pairs = ctx.launch_info().pairs_per_eval
         sec = ms / 1e3 / n
         tf = FLOPS_PER_PAIR * pairs / sec / 1e12
-        res[name] = {"pair_kernel_ms": sec * 1e3, "pairs_per_s": pairs / sec, "tflops": tf,
-                     "peak_tflops": PEAK_TFLOPS[name], "frac": tf / PEAK_TFLOPS[name]}
-        us[name] = ud.cpu().numpy()
+        res[name] = {"kernel": "k_pairs_f64f" if prec == zm.ZM_FP64 else "k_pairs_f32",
+                     "pair_kernel_ms": sec * 1e3, "pairs_per_s": pairs / sec, "tflops": tf,
+                     "peak_tflops": PEAK_TFLOPS[name], "frac": tf / PEAK_TFLOPS[name],
+                     "eval_ms": sum(v[1] / max(v[0], 1) for v in st.values() if v[0])}
+        us[name] = ud.cpu().numpy().reshape(3, -1)
         del ctx
-    err = float(np.max(np.abs(us["fp32_pairs"] - us["fp64"])) / np.max(np.abs(us["fp64"])))
     res["fp32_over_fp64_speedup"] = res["fp32_pairs"]["pairs_per_s"] / res["fp64"]["pairs_per_s"]
-    res["fp32_vs_fp64_max_rel_err"] = err
+    res["fp32_vs_fp64_max_rel_err"] = rel(us["fp32_pairs"], us["fp64"])
     res["workload"] = f"{wl.name}: one BR evaluation, synthetic vorticity, {wl.n} points"
-    return res, us
+    return res, (z, w), us
 
 
-def ensemble64(zm, torch, steps: int = 20):
-    """The 64-member uneven ensemble (sides 32..256, FP32 form) advanced by
-    one batch with graph-captured RK3 steps: aggregate pair-interactions/s,
-    one member of each side checked bit for bit against a solo run, and the
-    autotuner's choice per side (default and tuned shape, pair-kernel ms;
-    measured after the timed run, entries removed afterwards)."""
-    ms = rr.ensemble(64, seed=3)
-    ps = [zm.Params(m.n, m.n, eps=m.eps, atwood=m.atwood, gravity=1.0, dt=1e-3,
-                    precision=zm.ZM_FP32_PAIRS) for m in ms]
-    b = zm.Batch(ps, flags=zm.ZM_FLAG_GRAPH)
+def precision_trajectory(zm, torch, wl, oracle_targets: int = 256, threads: int = 0):
+    """The workload's own RK3 trajectory (its step count from its initial
+    state) in the FP32 pair form and in FP64: the two final states compared
+    (motion z - z0 and w), then F at the FP32 final state in both forms
+    against the oracle's F at seeded targets (the oracle also evaluates the
+    BR velocity at their stencil neighbours).  With oracle_targets = 0 the
+    oracle leg is skipped."""
     dev = torch.device("cuda:0")
-    for i, m in enumerate(ms):
-        z, w = m.state()
-        b.init_state(i, torch.from_numpy(z.ravel()).to(dev), torch.from_numpy(w.ravel()).to(dev))
-    b.step(1)                                   # capture + warm-up
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    b.step(steps)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    info = b.info()
-    # one member of each side rerun alone for the same 1 + steps steps: its
-    # state must be bitwise equal to the batch's
-    firsts = {}
-    for i, m in enumerate(ms):
-        firsts.setdefault(m.n, i)
-    equal = 0
-    for i in sorted(firsts.values()):
-        m = ms[i]
-        zb = torch.empty(3 * m.n * m.n, dtype=torch.float64, device=dev)
-        wb = torch.empty(2 * m.n * m.n, dtype=torch.float64, device=dev)
-        b.get_state(i, zb, wb)
-        z, w = m.state()
-        ctx = zm.Context(ps[i])
-        ctx.init_state(torch.from_numpy(z.ravel()).to(dev), torch.from_numpy(w.ravel()).to(dev))
-        ctx.step(1 + steps)
-        zs = torch.empty_like(zb); ws = torch.empty_like(wb)
-        ctx.get_state(zs, ws)
+    z0, w0 = wl.state()
+    out, final, ctxs = {}, {}, {}
+    for name, prec in (("fp32_pairs", zm.ZM_FP32_PAIRS), ("fp64", zm.ZM_FP64)):
+        ctx = zm.Context(params_of(zm, wl, precision=prec))
+        zd, wd = to_dev(torch, z0, dev), to_dev(torch, w0, dev)
+        ctx.init_state(zd, wd)
         torch.cuda.synchronize()
-        equal += int(torch.equal(zs, zb) and torch.equal(ws, wb))
+        t0 = time.perf_counter()
+        ctx.step(wl.steps)
+        torch.cuda.synchronize()
+        out[f"{name}_ms_per_step"] = (time.perf_counter() - t0) / wl.steps * 1e3
+        z1, w1 = torch.empty_like(zd), torch.empty_like(wd)
+        ctx.get_state(z1, w1)
+        torch.cuda.synchronize()
+        final[name] = (z1.cpu().numpy().reshape(3, -1), w1.cpu().numpy().reshape(2, -1))
+        ctxs[name] = ctx
+    (z32, w32), (z64, w64) = final["fp32_pairs"], final["fp64"]
+    out["steps"] = wl.steps
+    out["pairs"] = 3.0 * wl.steps * wl.n * wl.n
+    out["fp32_vs_fp64_state"] = {"z_motion": rel(z32 - z0, z64 - z0), "w": rel(w32, w64)}
+    if oracle_targets > 0:
+        import oracle
+        zs, ws = to_dev(torch, z32, dev), to_dev(torch, w32, dev)
+        g = {}
+        for name, ctx in ctxs.items():
+            zt, wt = torch.empty_like(zs), torch.empty_like(ws)
+            ctx.rhs(zs, ws, zt, wt)
+            torch.cuda.synchronize()
+            g[name] = (zt.cpu().numpy().reshape(3, -1), wt.cpu().numpy().reshape(2, -1))
+        tg = rr.sample_targets(wl.n, oracle_targets, seed=wl.seed + 11)
+        P = oracle.Problem(wl.n1, wl.n2, eps=wl.eps, atwood=wl.atwood, gravity=wl.gravity,
+                           dt=wl.dt)
+        t0 = time.perf_counter()
+        zr, wr = oracle.rhs_sampled(P, z32, w32, tg, threads=threads)
+        dt = time.perf_counter() - t0
+        out["F_vs_oracle"] = {"targets": int(tg.size), "oracle_seconds": dt}
+        for name, (zt, wt) in g.items():
+            out["F_vs_oracle"][name] = {"z_t": rel(zt[:, tg], zr), "w_t": rel(wt[:, tg], wr)}
+    for ctx in ctxs.values():
         del ctx
-    b.destroy()
-    sides = sorted({m.n for m in ms})
-    tuned = tune_report(zm, torch, sides=tuple(sides), precisions=("fp32_pairs",))
-    return {"members": 64, "sides": sides, "steps": steps,
-            "solo_vs_batch": {"members_checked": len(firsts), "bitwise_equal": equal},
-            "autotune_fp32": [{"side": r["side"], "default": [r["default"]["R"], r["default"]["splits"]],
-                               "tuned": [r["tuned"]["R"], r["tuned"]["splits"]],
-                               "default_ms": r["default"]["pair_ms"], "tuned_ms": r["tuned"]["pair_ms"]}
-                              for r in tuned],
-            "pairs_per_step": info.pairs_per_step, "work_items": info.work_items[1],
-            "persistent_groups": info.persistent_groups, "seconds": dt,
-            "pairs_per_s": info.pairs_per_step * steps / dt,
-            "tflops": FLOPS_PER_PAIR * info.pairs_per_step * steps / dt / 1e12,
-            "frac_of_fp32_peak": FLOPS_PER_PAIR * info.pairs_per_step * steps / dt / 1e12 / 157.3}
+    return out
 
 
 def small_mesh_latency(zm, torch, steps: int = 50):
@@ -523,40 +632,114 @@ def tune_report(zm, torch, sides=(32, 48, 64, 96, 128, 192, 256, 512, 1024),
                          "tuned": {"R": R, "splits": S, "pair_ms": ms_t},
                          "tuned_pairs_per_s": float(n) ** 4 / (ms_t / 1e3),
                          "tuned_tflops": FLOPS_PER_PAIR * float(n) ** 4 / (ms_t / 1e3) / 1e12})
-            print(json.dumps(rows[-1]), file=sys.stderr, flush=True)
     return rows
 
 
-def serving(zm, torch, window_s: float = 30.0, budget: int = 1 << 30, count: int = 200,
-            step_scale: int = 10, solo_checks: int = 8):
+def ensemble64(zm, torch, steps: int = 20):
+    """The 64-member uneven ensemble (sides 32..256, FP32 form) advanced by
+    one batch with graph-captured RK3 steps.  The autotuner first picks the
+    pair-kernel shape of every side (entries kept for the timed run); the
+    same batch with the untuned default shapes is timed beside it.  One
+    member of each side is rerun alone and compared bit for bit with the
+    tuned batch (the solo context takes the same tuned shape)."""
+    ms = rr.ensemble(64, seed=3)
+    ps = [zm.Params(m.n, m.n, eps=m.eps, atwood=m.atwood, gravity=1.0, dt=1e-3,
+                    precision=zm.ZM_FP32_PAIRS) for m in ms]
+    dev = torch.device("cuda:0")
+    sides = sorted({m.n for m in ms})
+    prec = zm.ZM_FP32_PAIRS
+
+    def timed_batch():
+        b = zm.Batch(ps, flags=zm.ZM_FLAG_GRAPH)
+        for i, m in enumerate(ms):
+            z, w = m.state()
+            b.init_state(i, to_dev(torch, z, dev), to_dev(torch, w, dev))
+        b.step(1)                                   # capture + warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        b.step(steps)
+        torch.cuda.synchronize()
+        return b, time.perf_counter() - t0
+
+    for n in sides:
+        zm.tuning_set(n, n, prec)                  # defaults
+    defaults = {n: zm.tuning_get(n, n, prec) for n in sides}
+    b, dt_default = timed_batch()
+    info = b.info()
+    b.destroy()
+    tuned = {}
+    for n in sides:
+        R, S, tms = zm.autotune(zm.Params(n, n, eps=1.0 / n, precision=prec))
+        tuned[n] = (R, S, tms)
+    b, dt = timed_batch()
+    info_t = b.info()
+    # one member of each side rerun alone for the same 1 + steps steps: its
+    # state must be bitwise equal to the batch's
+    firsts = {}
+    for i, m in enumerate(ms):
+        firsts.setdefault(m.n, i)
+    equal = 0
+    for i in sorted(firsts.values()):
+        m = ms[i]
+        zb = torch.empty(3 * m.n * m.n, dtype=torch.float64, device=dev)
+        wb = torch.empty(2 * m.n * m.n, dtype=torch.float64, device=dev)
+        b.get_state(i, zb, wb)
+        z, w = m.state()
+        ctx = zm.Context(ps[i])
+        ctx.init_state(to_dev(torch, z, dev), to_dev(torch, w, dev))
+        ctx.step(1 + steps)
+        zs, ws = torch.empty_like(zb), torch.empty_like(wb)
+        ctx.get_state(zs, ws)
+        torch.cuda.synchronize()
+        equal += int(torch.equal(zs, zb) and torch.equal(ws, wb))
+        del ctx
+    b.destroy()
+    for n in sides:
+        zm.tuning_set(n, n, prec)                  # leave the table as found
+    pps = info_t.pairs_per_step
+    tf = FLOPS_PER_PAIR * pps * steps / dt / 1e12
+    return {"members": 64, "sides": sides, "steps": steps,
+            "solo_vs_batch": {"members_checked": len(firsts), "bitwise_equal": equal},
+            "shapes": [{"side": n, "default": list(defaults[n]), "tuned": list(tuned[n][:2]),
+                        "tuned_solo_pair_ms": tuned[n][2]} for n in sides],
+            "pairs_per_step": pps, "work_items": info_t.work_items[1],
+            "work_items_default": info.work_items[1],
+            "persistent_groups": info_t.persistent_groups, "seconds": dt,
+            "pairs_per_s": pps * steps / dt, "tflops": tf, "frac_of_fp32_peak": tf / 157.3,
+            "default_shapes_pairs_per_s": pps * steps / dt_default,
+            "tuned_over_default": dt_default / dt}
+
+
+def serving(zm, torch, count: int = 200, budget: int = 1 << 30, step_scale: int = 10,
+            solo_checks: int = 8, max_seconds: float = 420.0):
     """Poisson request stream (sides log-uniform 64..512, A ~ U[0.1, 0.9],
-    100..1000 RK3 steps, FP32 form) served by one pool with a 1 GiB budget.
+    100..1000 RK3 steps, FP32 form) served by one pool with a 1 GiB budget
+    until every request has arrived and finished (or max_seconds pass).
     Capacity is measured first on a saturated pool; the arrival rate is then
-    0.8 x capacity and the stream is replayed in real time for window_s.
+    0.8 x capacity.
 
     Time compression: every request's step count is divided by step_scale
     (10..100 steps) and the rate multiplied by it.  The mean number of live
     requests (rate x residence time) and hence the per-step latency
-    distribution of the steady state are unchanged, while a bounded window
-    sees step_scale times more arrivals and completions.  The first
-    solo_checks requests to finish are rerun alone afterwards and compared
-    bit for bit with their pooled result."""
-    import numpy as np
+    distribution of the steady state are unchanged, while the whole stream
+    is served in step_scale times less wall time.  The first solo_checks
+    requests to finish are rerun alone afterwards and compared bit for bit
+    with their pooled result."""
     dev = torch.device("cuda:0")
 
     def params(m):
         return zm.Params(m.n, m.n, eps=m.eps, atwood=m.atwood, gravity=1.0, dt=1e-3,
                          precision=zm.ZM_FP32_PAIRS)
 
-    probe = rr.request_stream(count, rate=1.0, seed=4, steps_min=100 // step_scale,
-                              steps_max=1000 // step_scale)
+    smin, smax = 100 // step_scale, 1000 // step_scale
+    probe = rr.request_stream(count, rate=1.0, seed=4, steps_min=smin, steps_max=smax)
     mean_pairs = float(np.mean([3.0 * m.n ** 4 * m.steps for m in probe]))
     # capacity: a saturated pool (requests waiting), pairs/s over 40 iterations
     pool = zm.Pool(budget)
     keep = []
     for m in probe[:40]:
         z, w = m.state()
-        zt = torch.from_numpy(z.ravel()).to(dev); wt = torch.from_numpy(w.ravel()).to(dev)
+        zt, wt = to_dev(torch, z, dev), to_dev(torch, w, dev)
         keep.append((zt, wt))
         pool.submit(params(m), zt, wt, m.steps)
     pool.iterate()
@@ -566,26 +749,29 @@ def serving(zm, torch, window_s: float = 30.0, budget: int = 1 << 30, count: int
         pool.iterate()
     dt = time.perf_counter() - t0
     cap_pairs = (pool.stats().pairs_done - s0) / dt
-    pool.destroy(); del keep
+    pool.destroy()
+    del keep
     rate = 0.8 * cap_pairs / mean_pairs
-    stream = rr.request_stream(count, rate=rate, seed=4, steps_min=100 // step_scale,
-                               steps_max=1000 // step_scale)
+    stream = rr.request_stream(count, rate=rate, seed=4, steps_min=smin, steps_max=smax)
+    log(f"serving {count} requests at {rate:.2f}/s (0.8 x capacity), steps / {step_scale}")
     pool = zm.Pool(budget)
-    lat, queue_delay, admitted_at = [], [], {}
+    lat, queue_delay, admitted_at, finished = [], [], {}, 0
     ids = {}
     checked = []   # (stream index, final z, final w) of the first finished requests
     nxt = 0
     start = time.perf_counter()
+    last_log = start
     p0 = pool.stats().pairs_done
+    timed_out = False
     while True:
         now = time.perf_counter() - start
-        if now >= window_s:
+        if now >= max_seconds:
+            timed_out = True
             break
         while nxt < len(stream) and stream[nxt].arrival <= now:
             m = stream[nxt]
             z, w = m.state()
-            rid = pool.submit(params(m), torch.from_numpy(z.ravel()).to(dev),
-                              torch.from_numpy(w.ravel()).to(dev), m.steps)
+            rid = pool.submit(params(m), to_dev(torch, z, dev), to_dev(torch, w, dev), m.steps)
             ids[rid] = nxt
             nxt += 1
         recs = pool.iterate()
@@ -596,6 +782,7 @@ def serving(zm, torch, window_s: float = 30.0, budget: int = 1 << 30, count: int
                 admitted_at[rid] = t_now
                 queue_delay.append(t_now - stream[ids[rid]].arrival)
             if state == zm.ZM_REQ_FINISHED:
+                finished += 1
                 if len(checked) < solo_checks:
                     m = stream[ids[rid]]
                     zf = torch.empty(3 * m.n * m.n, dtype=torch.float64, device=dev)
@@ -603,6 +790,9 @@ def serving(zm, torch, window_s: float = 30.0, budget: int = 1 << 30, count: int
                     pool.fetch(rid, zf, wf)
                     checked.append((ids[rid], zf, wf))
                 pool.release(rid)
+        if time.perf_counter() - last_log > 20.0:
+            last_log = time.perf_counter()
+            log(f"serving: {t_now:.0f} s, arrived {nxt}, finished {finished}")
         if not recs:
             if nxt >= len(stream):
                 break
@@ -616,18 +806,18 @@ def serving(zm, torch, window_s: float = 30.0, budget: int = 1 << 30, count: int
         m = stream[k]
         z, w = m.state()
         ctx = zm.Context(params(m))
-        ctx.init_state(torch.from_numpy(z.ravel()).to(dev), torch.from_numpy(w.ravel()).to(dev))
+        ctx.init_state(to_dev(torch, z, dev), to_dev(torch, w, dev))
         ctx.step(m.steps)
-        zs = torch.empty_like(zf); ws = torch.empty_like(wf)
+        zs, ws = torch.empty_like(zf), torch.empty_like(wf)
         ctx.get_state(zs, ws)
         torch.cuda.synchronize()
         equal += int(torch.equal(zs, zf) and torch.equal(ws, wf))
         del ctx
     out = {
-        "requests_total": count, "steps_per_request": [100 // step_scale, 1000 // step_scale],
+        "requests_total": count, "steps_per_request": [smin, smax],
         "time_compression": step_scale, "arrived": nxt, "admitted": len(admitted_at),
-        "finished_in_window": sum(1 for r in ids if pool.query(r)[0] == zm.ZM_REQ_UNKNOWN),
-        "window_s": wall, "budget_bytes": budget,
+        "finished": finished, "stopped_at_time_limit": timed_out,
+        "makespan_s": wall, "budget_bytes": budget,
         "capacity_requests_per_s": cap_pairs / mean_pairs, "rate_requests_per_s": rate,
         "step_samples": len(lat), "iterations": st.iterations,
         "p50_step_ms": float(np.percentile(lat, 50)) if lat else None,
@@ -649,39 +839,39 @@ def oracle_threads() -> int:
     return int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or os.cpu_count()
 
 
-def cpu_baseline(wl, ctx_factory, z0, w0, target_seconds: float):
+def cpu_baseline(zm, torch, wl, target_seconds: float, sweep=None):
     """The CPU oracle on a bounded sample of the same workload.
 
     If one full oracle RK3 step (3 N^2 pairs) fits in about 3x target_seconds
     of host time, time exactly that from the workload's initial state and
     compare the GPU's step from the same state with it, element by element.
     Otherwise time the BR velocity of seeded targets (against all sources)
-    sized to target_seconds and compare those targets.
+    sized to target_seconds, on the workload's state with the synthetic
+    vorticity, and compare the GPU's velocity at those targets: in both pair
+    forms when the precision sweep's velocities are given (sweep =
+    ((z, w), {form: u})), else in the workload's own form.
     """
     import oracle
-    import torch
     threads = oracle_threads()
     P = oracle.Problem(wl.n1, wl.n2, eps=wl.eps, atwood=wl.atwood, gravity=wl.gravity, dt=wl.dt)
-    w_probe = rr.synthetic_vorticity(wl.n1, wl.n2, seed=wl.seed)
+    z0, w0 = wl.state()
+    w_syn = rr.synthetic_vorticity(wl.n1, wl.n2, seed=wl.seed)
     probe = rr.sample_targets(wl.n, 256, seed=99)
     t0 = time.perf_counter()
-    oracle.br_velocity(P, z0, w_probe, targets=probe, threads=threads)
+    oracle.br_velocity(P, z0, w_syn, targets=probe, threads=threads)
     rate = probe.size * wl.n / (time.perf_counter() - t0)        # pairs/s
     full_step = 3.0 * wl.n * wl.n / rate
-
-    def rel(a, b):
-        return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+    dev = torch.device("cuda:0")
 
     if full_step <= 3.0 * target_seconds:
         t0 = time.perf_counter()
         zr, wr = oracle.rk3(P, z0, w0, 1, threads=threads)
         dt = time.perf_counter() - t0
-        ctx = ctx_factory()
-        dev = ctx.workspace.device
-        zd = torch.from_numpy(z0.ravel()).to(dev); wd = torch.from_numpy(w0.ravel()).to(dev)
+        ctx = zm.Context(params_of(zm, wl))
+        zd, wd = to_dev(torch, z0, dev), to_dev(torch, w0, dev)
         ctx.init_state(zd, wd)
         ctx.step(1)
-        z1 = torch.empty_like(zd); w1 = torch.empty_like(wd)
+        z1, w1 = torch.empty_like(zd), torch.empty_like(wd)
         ctx.get_state(z1, w1)
         torch.cuda.synchronize()
         zg = z1.cpu().numpy().reshape(3, -1); wg = w1.cpu().numpy().reshape(2, -1)
@@ -697,70 +887,71 @@ def cpu_baseline(wl, ctx_factory, z0, w0, target_seconds: float):
 
     count = int(min(wl.n, max(64, target_seconds * rate / wl.n)))
     tg = rr.sample_targets(wl.n, count, seed=wl.seed)
-    ctx = ctx_factory()
-    dev = ctx.workspace.device
-    zd = torch.from_numpy(z0.ravel()).to(dev); wd = torch.from_numpy(w_probe.ravel()).to(dev)
-    ud = torch.empty_like(zd)
-    ctx.br_velocity(zd, wd, ud)
-    torch.cuda.synchronize()
+    if sweep is not None:
+        us = sweep[1]
+    else:
+        ctx = zm.Context(params_of(zm, wl))
+        zd, wd = to_dev(torch, z0, dev), to_dev(torch, w_syn, dev)
+        ud = torch.empty_like(zd)
+        ctx.br_velocity(zd, wd, ud)
+        torch.cuda.synchronize()
+        us = {wl.precision: ud.cpu().numpy().reshape(3, -1)}
+        del ctx
     t0 = time.perf_counter()
-    ref = oracle.br_velocity(P, z0, w_probe, targets=tg, threads=threads)
+    ref = oracle.br_velocity(P, z0, w_syn, targets=tg, threads=threads)
     dt = time.perf_counter() - t0
     return {
         "value": tg.size * wl.n / dt, "unit": "pair-interactions/s", "cores": threads,
         "kind": "oracle",
-        "sample": f"BR velocity of {tg.size} seeded targets x {wl.n} sources "
-                  f"({tg.size * wl.n:.3e} pairs, {dt:.1f} s), synthetic vorticity",
+        "sample": f"BR of {tg.size} seeded targets x all {wl.n} sources, workload state, "
+                  f"synthetic vorticity ({tg.size * wl.n:.2e} pairs)",
         "seconds": dt,
-        "gpu_vs_oracle_max_rel_err": {"u": rel(ud.cpu().numpy().reshape(3, -1)[:, tg], ref)},
+        "gpu_vs_oracle_max_rel_err": {form: rel(u[:, tg], ref) for form, u in us.items()},
     }
 
 
-def cpu_oracle_detail(threads: int, sweep_u=None, traj64=None):
-    """The oracle's own rates on the other workloads (a few seconds of host
-    time in all): one full BR evaluation of the 64 x 64 workload, 1024 seeded
-    targets of the 1024 x 1024 workload, and the 64 x 64 evaluation on one
-    thread.  With the 1M-point sweep's GPU velocities (FP64 and FP32 forms,
-    same state and vorticity) their error on those 1024 targets as well.
-    With the GPU's 64 x 64 trajectory, the oracle's own trajectory of the
-    workload (its step count from its initial state), timed and compared."""
+def small_mesh_oracle(threads: int, traj64):
+    """The oracle's own runs on the 64 x 64 workload (a few seconds of host
+    time): one full BR evaluation with all threads and with one, and the
+    workload's trajectory (its step count from its initial state), timed
+    and compared with the GPU's."""
     import oracle
     out = {"threads": threads}
-    for name, key, targets, nthreads in (
-            ("periodic64_full_br", "periodic64_single_fp64", None, threads),
-            ("periodic1024_sampled_br", "periodic1024_multimode16_fp32", 1024, threads),
-            ("periodic64_full_br_1thread", "periodic64_single_fp64", None, 1)):
-        wl = rr.WORKLOADS[key]
-        z, _ = wl.state()
-        w = rr.synthetic_vorticity(wl.n1, wl.n2, seed=wl.seed)
-        P = oracle.Problem(wl.n1, wl.n2, eps=wl.eps)
-        tg = rr.sample_targets(wl.n, targets, seed=7) if targets else None
+    wl = rr.WORKLOADS["periodic64_single_fp64"]
+    z, _ = wl.state()
+    w = rr.synthetic_vorticity(wl.n1, wl.n2, seed=wl.seed)
+    P = oracle.Problem(wl.n1, wl.n2, eps=wl.eps)
+    for name, nt in (("full_br", threads), ("full_br_1thread", 1)):
         t0 = time.perf_counter()
-        ref = oracle.br_velocity(P, z, w, targets=tg, threads=nthreads)
+        oracle.br_velocity(P, z, w, threads=nt)
         dt = time.perf_counter() - t0
-        pairs = (tg.size if targets else wl.n) * wl.n
-        out[name] = {"pairs": pairs, "seconds": dt, "pairs_per_s": pairs / dt, "threads": nthreads}
-        if targets and sweep_u is not None:
-            scale = float(np.max(np.abs(ref)))
-            for form, u in sweep_u.items():
-                ug = u.reshape(3, -1)[:, tg]
-                out[name][f"{form}_vs_oracle_max_rel_err"] = float(np.max(np.abs(ug - ref)) / scale)
-    if traj64 is not None:
-        wl = rr.WORKLOADS["periodic64_single_fp64"]
-        z0, w0 = wl.state()
-        P = oracle.Problem(wl.n1, wl.n2, eps=wl.eps, atwood=wl.atwood, gravity=wl.gravity, dt=wl.dt)
-        t0 = time.perf_counter()
-        zr, wr = oracle.rk3(P, z0, w0, wl.steps, threads=threads)
-        dt = time.perf_counter() - t0
-        zg, wg = traj64
-        out["periodic64_trajectory"] = {
-            "steps": wl.steps, "pairs": 3.0 * wl.steps * wl.n * wl.n, "seconds": dt,
-            "pairs_per_s": 3.0 * wl.steps * wl.n * wl.n / dt, "threads": threads,
-            "gpu_vs_oracle_max_rel_err": {
-                "z": float(np.max(np.abs(zg - zr)) / np.max(np.abs(zr))),
-                "w": float(np.max(np.abs(wg - wr)) / np.max(np.abs(wr))),
-                "z_motion": float(np.max(np.abs((zg - z0) - (zr - z0))) / np.max(np.abs(zr - z0)))}}
+        out[name] = {"pairs": wl.n * wl.n, "seconds": dt, "pairs_per_s": wl.n * wl.n / dt,
+                     "threads": nt}
+    z0, w0 = wl.state()
+    P = oracle.Problem(wl.n1, wl.n2, eps=wl.eps, atwood=wl.atwood, gravity=wl.gravity, dt=wl.dt)
+    t0 = time.perf_counter()
+    zr, wr = oracle.rk3(P, z0, w0, wl.steps, threads=threads)
+    dt = time.perf_counter() - t0
+    zg, wg = traj64
+    out["trajectory"] = {
+        "steps": wl.steps, "pairs": 3.0 * wl.steps * wl.n * wl.n, "seconds": dt,
+        "pairs_per_s": 3.0 * wl.steps * wl.n * wl.n / dt, "threads": threads,
+        "gpu_vs_oracle_max_rel_err": {"z": rel(zg, zr), "w": rel(wg, wr),
+                                      "z_motion": rel(zg - z0, zr - z0)}}
     return out
+
+
+def fp64_256(zm, torch, steps: int = 50, warmup: int = 2):
+    """The 256 x 256 eight-mode FP64 workload: its RK3 steps timed, the
+    FP64 pair kernel on its roofline."""
+    wl = rr.WORKLOADS["periodic256_multimode8_fp64"]
+    r = trajectory_run(zm, torch, wl, steps, warmup)
+    ach = FLOPS_PER_PAIR * r["info"].pairs_per_eval / r["avg_pair_s"] / 1e12
+    return {"workload": wl.name, "steps": steps, "ms_per_step": r["elapsed"] / steps * 1e3,
+            "pairs_per_s": r["pairs_per_step"] * steps / r["elapsed"],
+            "pair_kernel_ms": r["avg_pair_s"] * 1e3, "pair_kernel_tflops": ach,
+            "frac_of_fp64_peak": ach / PEAK_TFLOPS["fp64"],
+            "pair_share_of_step": r["avg_pair_s"] * 3 * steps / r["elapsed"]}
 
 
 def main():
@@ -776,64 +967,60 @@ def main():
     import torch
     import paper_2406_05490_amd as zm
 
-    if args.cutoff_only:
-        print(json.dumps({"cutoff": cutoff_section(zm, torch)}), flush=True)
-        return
-    if args.low_order_only:
-        print(json.dumps({"low_order_4096": low_order_section(zm, torch)}), flush=True)
-        return
-    if args.medium_only:
-        print(json.dumps({"medium_order": medium_section(zm, torch)}), flush=True)
-        return
-    if args.free_only:
-        print(json.dumps({"free_single_mode": free_section(zm, torch)}), flush=True)
-        return
-    if args.tune_report:
-        print(json.dumps({"tune_report": tune_report(zm, torch)}), flush=True)
+    only = {"cutoff": args.cutoff_only, "low_order_4096": args.low_order_only,
+            "medium_order": args.medium_only, "free_single_mode": args.free_only,
+            "tune_report": args.tune_report, "ensemble64": args.ensemble_only}
+    runners = {"cutoff": cutoff_section, "low_order_4096": low_order_section,
+               "medium_order": medium_section, "free_single_mode": free_section,
+               "tune_report": tune_report, "ensemble64": ensemble64}
+    for key, on in only.items():
+        if on:
+            print(json.dumps({key: runners[key](zm, torch)}), flush=True)
+            return
+    if args.serve_only:
+        print(json.dumps({"serving": serving(zm, torch, count=args.serve_requests,
+                                             max_seconds=args.serve_max_seconds)}), flush=True)
         return
 
-    sweep_u = traj64 = None
     wl = rr.WORKLOADS[args.workload]
-    prec = zm.ZM_FP32_PAIRS if wl.precision == "fp32_pairs" else zm.ZM_FP64
     steps = wl.steps if args.steps is None else args.steps
-    dev = torch.device("cuda:0")
-    torch.cuda.set_device(dev)
-    p = zm.Params(wl.n1, wl.n2, eps=wl.eps, atwood=wl.atwood, gravity=wl.gravity, dt=wl.dt,
-                  precision=prec)
-    z0, w0 = wl.state()
-    zd = torch.from_numpy(z0.ravel()).to(dev)
-    wd = torch.from_numpy(w0.ravel()).to(dev)
-    ctx = zm.Context(p)
-    ctx.init_state(zd, wd)
-    info = ctx.launch_info()
-    stream = ctx.stream
+    torch.cuda.set_device(torch.device("cuda:0"))
+    threads = oracle_threads()
+    detail = {}
 
-    ctx.step(args.warmup)
-    torch.cuda.synchronize()
-    ctx.profile_read()                      # discard warm-up timings
-    ctx.profile_enable(True)
-
-    torch.cuda.synchronize()
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    t0 = time.perf_counter()
-    ev0.record(stream)
-    ctx.step(steps)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    gpu_s = ev0.elapsed_time(ev1) / 1e3
-    stats = ctx.profile_read()
-    ctx.profile_enable(False)
-
-    pairs_per_step = 3 * info.pairs_per_eval
-    elapsed = max(wall, gpu_s)
-    value = pairs_per_step * steps / elapsed
-    launches, pair_ms = stats["pairs"]
-    avg_pair_s = pair_ms / 1e3 / max(launches, 1)
-    achieved = FLOPS_PER_PAIR * info.pairs_per_eval / avg_pair_s / 1e12
+    log(f"{wl.name}: {args.warmup} warm-up + {steps} timed RK3 steps")
+    r = trajectory_run(zm, torch, wl, steps, args.warmup)
+    info = r["info"]
+    prec32 = wl.precision == "fp32_pairs"
+    kernel = "k_pairs_f32" if prec32 else "k_pairs_f64f"
     peak = PEAK_TFLOPS[wl.precision]
-    kernel = "k_pairs_f64f" if prec == zm.ZM_FP64 else "k_pairs_f32"
+    value = r["pairs_per_step"] * steps / r["elapsed"]
+    achieved = FLOPS_PER_PAIR * info.pairs_per_eval / r["avg_pair_s"] / 1e12
+    roof = {"kernel": kernel, "bound": "alu", "achieved": achieved, "peak": peak,
+            "unit": "TFLOP/s", "frac": achieved / peak,
+            "traffic": measured_traffic(kernel, wl.name), "traffic_unit": "B",
+            "flops_per_pair": FLOPS_PER_PAIR, "avg_launch_ms": r["avg_pair_s"] * 1e3,
+            "launches": r["pair_launches"]}
+    xf = executed_flops_per_pair(kernel, wl.name)
+    if xf is not None:
+        roof["executed_flops_per_pair"] = xf
+        roof["frac_executed"] = xf / FLOPS_PER_PAIR * achieved / peak
+    detail["kernel_ms"] = {k: {"launches": n, "total_ms": ms} for k, (n, ms) in r["stats"].items()}
+    detail["pair_kernel_share"] = r["avg_pair_s"] * r["pair_launches"] / r["elapsed"]
+
+    sweep = None
+    extras = {}
+    if not args.no_sweep and wl.n1 * wl.n2 >= 1 << 20:
+        log("one BR evaluation in each pair form")
+        sw, zw, us = br_sweep(zm, torch, wl)
+        detail["br_sweep"] = sw
+        sweep = (zw, us)
+        f64 = sw["fp64"]
+        roof["fp64_form"] = {"kernel": f64["kernel"], "avg_launch_ms": f64["pair_kernel_ms"],
+                             "achieved": f64["tflops"], "peak": PEAK_TFLOPS["fp64"],
+                             "frac": f64["frac"]}
+        roof["fp32_over_fp64_speedup"] = sw["fp32_over_fp64_speedup"]
+        roof["fp32_vs_fp64_max_rel_err"] = sw["fp32_vs_fp64_max_rel_err"]
 
     out = {
         "metric": METRIC,
@@ -842,45 +1029,80 @@ def main():
         "n_gpus": 1,
         "steps": steps,
         "warmup": args.warmup,
-        "ms_per_step": elapsed / steps * 1e3,
+        "ms_per_step": r["elapsed"] / steps * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if prec == zm.ZM_FP64 else "f32",
+        "dtype": "f32" if prec32 else "f64",
         "data": "synthetic",
         "config": {
             "workload": wl.name, "mesh": f"{wl.n1}x{wl.n2}", "points": wl.n,
-            "eps_over_h": wl.eps_over_h, "atwood": wl.atwood, "dt": wl.dt,
-            "precision": wl.precision, "image_layers": 0,
-            "pairs_per_step": pairs_per_step, "pair_kernel_workgroups": info.workgroups,
-            "source_splits": info.source_splits, "targets_per_lane": info.targets_per_lane,
+            "modes": wl.modes, "eps_over_h": wl.eps_over_h, "atwood": wl.atwood, "dt": wl.dt,
+            "precision": wl.precision, "pairs_per_step": r["pairs_per_step"],
+            "pair_shape": f"R{info.targets_per_lane} S{info.source_splits} WG{info.workgroups}",
         },
-        "roofline": {
-            "kernel": kernel, "bound": "alu", "achieved": achieved, "peak": peak,
-            "unit": "TFLOP/s", "frac": achieved / peak,
-            "traffic": measured_traffic(kernel, wl.name), "traffic_unit": "bytes/launch",
-            "flops_per_pair": FLOPS_PER_PAIR, "pairs_per_launch": info.pairs_per_eval,
-            "avg_launch_ms": avg_pair_s * 1e3, "launches": launches,
-        },
-        "kernel_ms": {k: {"launches": n, "total_ms": ms} for k, (n, ms) in stats.items()},
-        "pair_kernel_share": pair_ms / 1e3 / elapsed,
+        "roofline": roof,
     }
 
-    if not args.no_sweep:
-        out["br_sweep_1m"], sweep_u = br_sweep_1m(zm, torch)
-        out["ensemble64_fp32_graph"] = ensemble64(zm, torch)
-        out["periodic64_latency"], traj64 = small_mesh_latency(zm, torch)
-        out["cutoff"] = cutoff_section(zm, torch)
-        out["low_order_4096"] = low_order_section(zm, torch)
-        out["free_single_mode"] = free_section(zm, torch)
-        out["medium_order"] = medium_section(zm, torch)
-    if args.serve_seconds > 0:
-        out["serving"] = serving(zm, torch, window_s=args.serve_seconds)
     if args.cpu_seconds > 0:
-        out["cpu_baseline"] = cpu_baseline(wl, lambda: zm.Context(p), z0, w0, args.cpu_seconds)
-        out["cpu_baseline"]["gpu_speedup"] = value / out["cpu_baseline"]["value"]
-        out["cpu_oracle_detail"] = cpu_oracle_detail(out["cpu_baseline"]["cores"], sweep_u, traj64)
-    print(json.dumps(out), flush=True)
+        log("CPU oracle sample")
+        cb = cpu_baseline(zm, torch, wl, args.cpu_seconds, sweep=sweep)
+        cb["gpu_speedup"] = value / cb["value"]
+        out["cpu_baseline"] = cb
+
+    if not args.no_sweep:
+        if wl.n1 * wl.n2 >= 1 << 20:
+            log(f"{wl.steps}-step trajectory in both forms, F against the oracle")
+            pt = precision_trajectory(zm, torch, wl, threads=threads,
+                                      oracle_targets=256 if args.cpu_seconds > 0 else 0)
+            detail["precision_trajectory"] = pt
+            extras["traj5"] = {"fp32_vs_fp64_state": pt["fp32_vs_fp64_state"]}
+            if "F_vs_oracle" in pt:
+                f = pt["F_vs_oracle"]
+                extras["traj5"]["F_vs_oracle"] = {
+                    "targets": f["targets"],
+                    "fp32": max(f["fp32_pairs"].values()), "fp64": max(f["fp64"].values())}
+        log("256 x 256 FP64 workload")
+        detail["fp64_256"] = fp64_256(zm, torch)
+        extras["fp64_256"] = {k: detail["fp64_256"][k] for k in
+                              ("pairs_per_s", "pair_kernel_ms", "frac_of_fp64_peak")}
+        log("64 x 64 workload")
+        lat, traj64 = small_mesh_latency(zm, torch)
+        detail["periodic64_latency"] = lat
+        if args.cpu_seconds > 0:
+            so = small_mesh_oracle(threads, traj64)
+            detail["periodic64_oracle"] = so
+            extras["c64"] = {"graph_ms_per_step": lat["graph_ms_per_step"],
+                             "traj_vs_oracle": max(so["trajectory"]["gpu_vs_oracle_max_rel_err"]
+                                                   [k] for k in ("z", "w"))}
+        log("64-member ensemble")
+        en = ensemble64(zm, torch)
+        detail["ensemble64"] = en
+        extras["ensemble64"] = {"pairs_per_s": en["pairs_per_s"],
+                                "frac_of_fp32_peak": en["frac_of_fp32_peak"],
+                                "default_shapes_pairs_per_s": en["default_shapes_pairs_per_s"],
+                                "solo_bitwise": f"{en['solo_vs_batch']['bitwise_equal']}/"
+                                                f"{en['solo_vs_batch']['members_checked']}"}
+        if not args.no_sections:
+            for key, fn in (("cutoff", cutoff_section), ("low_order_4096", low_order_section),
+                            ("free_single_mode", free_section), ("medium_order", medium_section)):
+                log(f"section {key}")
+                detail[key] = fn(zm, torch)
+    if args.serve_requests > 0:
+        sv = serving(zm, torch, count=args.serve_requests, max_seconds=args.serve_max_seconds)
+        detail["serving"] = sv
+        extras["serving"] = {k: sv[k] for k in ("p50_step_ms", "p99_step_ms", "queue_delay_p99_s",
+                                                "pairs_per_s", "arrived", "finished",
+                                                "time_compression")}
+        extras["serving"]["solo_bitwise"] = (f"{sv['solo_vs_mix']['bitwise_equal']}/"
+                                             f"{sv['solo_vs_mix']['requests_checked']}")
+    if args.detail_out:
+        full = dict(out, **detail)
+        os.makedirs(os.path.dirname(os.path.abspath(args.detail_out)), exist_ok=True)
+        with open(args.detail_out, "w") as fh:
+            json.dump(full, fh, indent=1)
+    out.update(sig(extras, 3))
+    print(json.dumps(sig(out), separators=(",", ":")), flush=True)
 
 
 if __name__ == "__main__":
