@@ -72,7 +72,8 @@
  *     structure-of-arrays planes: z is 3 planes of N = n1*n2 doubles
  *     (z1 plane, z2 plane, z3 plane), w is 2 planes, u is 3 planes.
  *   - The library never allocates device memory.  All scratch lives in the
- *     caller's workspace of zm_workspace_bytes() bytes.
+ *     caller's workspace of zm_workspace_bytes() bytes, except that of
+ *     zm_br_velocity_noalloc, which lives in a static device array.
  *   - Work is enqueued asynchronously on the stream given to zm_create (a
  *     hipStream_t, or NULL for the null stream).  Results are visible after
  *     that stream is synchronised.
@@ -198,7 +199,7 @@ zm_status zm_destroy(zm_ctx *ctx);
 const char *zm_status_string(zm_status status);
 
 /* Message of the last error on this context ("" if none; NULL ctx: the last
- * error of a failed zm_create on this thread). */
+ * error of a failed zm_create or zm_br_velocity_noalloc on this thread). */
 const char *zm_last_error(const zm_ctx *ctx);
 
 /* ---- launch configuration and per-kernel timing ------------------------- */
@@ -439,6 +440,41 @@ zm_status zm_pool_get_stats(const zm_pool *pool, zm_pool_stats *out);
 zm_status zm_pool_destroy(zm_pool *pool);
 
 const char *zm_pool_last_error(const zm_pool *pool);
+
+/* ---- allocation-free evaluation ------------------------------------------ */
+/*
+ * For callers that cannot allocate device memory at all: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation.
+ *
+ * zm_br_velocity_noalloc computes what zm_br_velocity computes on a context
+ * created with *params -- d_u (3 planes) = u(d_z, d_w) -- without a context
+ * or a workspace: its scratch (source strengths, q, tie corrections and
+ * per-source-range partial sums) lives in one static device array of
+ * ZM_NOALLOC_SCRATCH_BYTES that the library holds on every device it runs
+ * on until the process ends.  The call allocates nothing (no device or host
+ * allocation); the caller passes the inputs and the output, all as for
+ * zm_br_velocity (float64 planes, 256-byte aligned, d_u not overlapping an
+ * input), and the stream the kernels are enqueued on (a hipStream_t, NULL =
+ * null stream; asynchronous like every other call).
+ *
+ * Scope: exact BR sums (cutoff = 0) of the high- or medium-order model,
+ * either pair form, any image_layers and boundary.  The pair kernel takes
+ * the shape a context of this size would use when its partial sums fit the
+ * scratch (then the result is bitwise that of zm_br_velocity); otherwise as
+ * many source ranges as fit (the same sums in another order).  Meshes whose
+ * scratch exceeds the array even with one source range -- about 645,000
+ * points with an even side, 1.19 million with both sides odd or on a free
+ * sheet -- are refused with ZM_ERR_CAPACITY.  Other errors as for zm_create
+ * and zm_br_velocity; zm_last_error(NULL) gives the message.
+ *
+ * Every call on one device shares that device's array and leaves it holding
+ * its scratch.  Calls that may overlap on one device (different streams,
+ * different host threads) race on it: order them, e.g. on one stream.
+ */
+#define ZM_NOALLOC_SCRATCH_BYTES (64u * 1024u * 1024u)
+
+zm_status zm_br_velocity_noalloc(const zm_params *params, const double *d_z, const double *d_w,
+                                 double *d_u, void *hip_stream);
 
 /* Interface version (incremented on any ABI change). */
 int32_t zm_abi_version(void);

@@ -12,7 +12,8 @@ from ._zm import (  # noqa: F401
     ZM_ERR_CAPACITY, ZM_ERR_HIP, ZM_ERR_INVALID_ARG, ZM_ERR_NONFINITE,
     ZM_ERR_UNSUPPORTED, ZM_ERR_WORKSPACE, ZM_FLAG_CHECK_FINITE, ZM_FP32_PAIRS,
     ZM_FP64, ZM_OK, ZM_MODEL_HIGH, ZM_MODEL_LOW, ZM_MODEL_MEDIUM, ZM_BOUNDARY_PERIODIC,
-    ZM_BOUNDARY_FREE, load, status_string, workspace_bytes,
+    ZM_BOUNDARY_FREE, load, status_string, workspace_bytes, br_velocity_noalloc,
+    NOALLOC_SCRATCH_BYTES,
 )
 
 load()

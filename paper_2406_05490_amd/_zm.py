@@ -30,6 +30,7 @@ ZM_BOUNDARY_PERIODIC = 0
 ZM_BOUNDARY_FREE = 1
 ZM_FLAG_CHECK_FINITE = 0x1
 ZM_FLAG_GRAPH = 0x2
+NOALLOC_SCRATCH_BYTES = 64 * 1024 * 1024   # ZM_NOALLOC_SCRATCH_BYTES
 
 KERNELS = ("surface", "pairs", "ties", "reduce", "update", "cells", "fft")
 
@@ -111,7 +112,7 @@ EXPORTS = (
     "zm_pool_workspace_bytes", "zm_pool_request_bytes", "zm_pool_create", "zm_pool_submit",
     "zm_pool_iterate", "zm_pool_query", "zm_pool_fetch", "zm_pool_release", "zm_pool_cancel",
     "zm_pool_get_stats", "zm_pool_destroy", "zm_pool_last_error",
-    "zm_abi_version",
+    "zm_br_velocity_noalloc", "zm_abi_version",
 )
 
 _lib = None
@@ -214,6 +215,8 @@ def load(path: str = LIB_PATH):
     lib.zm_pool_destroy.restype = ctypes.c_int32
     lib.zm_pool_last_error.argtypes = [vp]
     lib.zm_pool_last_error.restype = ctypes.c_char_p
+    lib.zm_br_velocity_noalloc.argtypes = [P, vp, vp, vp, vp]
+    lib.zm_br_velocity_noalloc.restype = ctypes.c_int32
     lib.zm_abi_version.argtypes = []
     lib.zm_abi_version.restype = ctypes.c_int32
     _lib = lib
@@ -457,6 +460,23 @@ class Batch:
             self.destroy()
         except Exception:
             pass
+
+
+def br_velocity_noalloc(p: Params, z, w, u, stream=None):
+    """u = BR velocity of (z, w) through zm_br_velocity_noalloc: no context,
+    no workspace, scratch in the library's static device array (calls that
+    may overlap on one device race on it).  Enqueued on `stream` (default:
+    the current torch stream)."""
+    import torch
+    lib = load()
+    _check_f64_planes(z, 3, p.n, "z"); _check_f64_planes(w, 2, p.n, "w")
+    _check_f64_planes(u, 3, p.n, "u")
+    s = torch.cuda.current_stream(z.device) if stream is None else stream
+    with torch.cuda.device(z.device):
+        st = lib.zm_br_velocity_noalloc(ctypes.byref(p.c()), _ptr(z), _ptr(w), _ptr(u),
+                                        s.cuda_stream)
+    if st != ZM_OK:
+        raise ZMError(st, lib.zm_last_error(None).decode())
 
 
 def pool_request_bytes(p: Params) -> int:

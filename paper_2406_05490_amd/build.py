@@ -20,7 +20,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libzm.so")
 SOURCES = [os.path.join(CSRC, f) for f in
            ("zm_kernels.hip", "zm_batch.hip", "zm_api.hip", "zm_batch_api.hip", "zm_tune.hip",
-            "zm_pool_api.hip", "zm_cutoff.hip", "zm_lowfft.hip")]
+            "zm_pool_api.hip", "zm_cutoff.hip", "zm_lowfft.hip", "zm_noalloc.hip")]
 ARCH = "gfx950"
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -40,6 +40,8 @@ struct Timed {
 
 }  // namespace
 
+void zm::set_create_error(const std::string& msg) { g_create_error = msg; }
+
 struct zm_ctx {
     zm_params prm;
     zm::Mesh mesh;
@@ -571,6 +573,6 @@ zm_status zm_profile_read(zm_ctx* c, zm_kernel_stats* out)
     return st;
 }
 
-int32_t zm_abi_version(void) { return 4; }
+int32_t zm_abi_version(void) { return 5; }
 
 }  // extern "C"

@@ -9,8 +9,13 @@
 #include <cmath>
 #include <cstddef>
 #include <cstdint>
+#include <string>
 
 namespace zm {
+
+// Message zm_last_error(NULL) returns on this thread (zm_create and the
+// allocation-free evaluation record why they refused a call).
+void set_create_error(const std::string& msg);
 
 constexpr size_t kAlign = 256;
 constexpr int kMaxSide = 8192;

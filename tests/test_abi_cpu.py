@@ -32,7 +32,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_abi_version_and_status_strings():
     lib = zm.load()
-    assert lib.zm_abi_version() == 4
+    assert lib.zm_abi_version() == 5
     assert zm.status_string(zm.ZM_OK) == "ok"
     for st in (zm.ZM_ERR_INVALID_ARG, zm.ZM_ERR_UNSUPPORTED, zm.ZM_ERR_WORKSPACE,
                zm.ZM_ERR_HIP, zm.ZM_ERR_NONFINITE, zm.ZM_ERR_CAPACITY):
@@ -230,3 +230,30 @@ def test_pool_host_side_validation():
     assert h.value is None
     assert lib.zm_pool_create(ctypes.byref(h), 1 << 20, 0, 4096, 1 << 10, None) == zm.ZM_ERR_WORKSPACE
     assert lib.zm_pool_create(ctypes.byref(h), 1 << 20, 0x40, 4096, 1 << 40, None) == zm.ZM_ERR_INVALID_ARG
+
+
+def test_noalloc_host_side_validation():
+    """zm_br_velocity_noalloc checks its arguments and its scratch limit on
+    the host before any HIP call (fake, far-apart aligned addresses; nothing
+    is launched)."""
+    lib = zm.load()
+    z, w, u = 1 << 40, 2 << 40, 3 << 40
+
+    def call(p, zz=z, ww=w, uu=u):
+        st = lib.zm_br_velocity_noalloc(ctypes.byref(p.c()), zz, ww, uu, None)
+        return st, lib.zm_last_error(None).decode()
+
+    st, msg = call(zm.Params(4, 16, eps=0.1))
+    assert st == zm.ZM_ERR_INVALID_ARG and "n1" in msg
+    st, msg = call(zm.Params(64, 64, eps=1 / 64, cutoff=0.2))
+    assert st == zm.ZM_ERR_UNSUPPORTED and "exact" in msg
+    st, msg = call(zm.Params(64, 64, eps=1 / 64, model=zm.ZM_MODEL_LOW))
+    assert st == zm.ZM_ERR_UNSUPPORTED
+    st, msg = call(zm.Params(64, 64, eps=1 / 64), zz=None)
+    assert st == zm.ZM_ERR_INVALID_ARG and "aligned" in msg
+    st, msg = call(zm.Params(64, 64, eps=1 / 64), uu=z + 8 * 256)
+    assert st == zm.ZM_ERR_INVALID_ARG and "overlaps" in msg
+    # even sides: 80 B per point before any partial sums -> 1024^2 cannot fit
+    st, msg = call(zm.Params(1024, 1024, eps=1 / 1024))
+    assert st == zm.ZM_ERR_CAPACITY and "scratch" in msg
+    assert zm.NOALLOC_SCRATCH_BYTES == 64 * 1024 * 1024
