@@ -97,9 +97,12 @@ __device__ __forceinline__ double d2_5pt(double fm2, double fm1, double f0, doub
 }
 
 // w = (|r|^2 + eps^2)^(-3/2) from s = |r|^2 + eps^2.  The hardware reciprocal
-// square root y0 has relative error below 2^-24 on gfx950; with
-// e = 1 - s y0^2 the exact value is y0^3 (1 - e)^(-3/2) and the first-order
-// correction w = y0^3 (1 + 3e/2) leaves 15 e^2 / 8 < 2e-14 (always low).
+// square root y0 = s^(-1/2) (1 + d) had |d| <= 2^-24 in a probe over every
+// binade on gfx950 (a measurement; no bound is documented).  With
+// e = 1 - s y0^2 = -(2d + d^2), |e| <= 2^-23, the exact value is
+// y0^3 (1 - e)^(-3/2) = y0^3 (1 + 3e/2 + 15e^2/8 + ...), so the first-order
+// correction w = y0^3 (1 + 3e/2) is low by 15 e^2 / 8 <= 2.7e-14 relative
+// (plus a few ulp of rounding), a one-signed bias per pair.
 __device__ __forceinline__ double inv_cube_sqrt(double s)
 {
     const double y0 = __builtin_amdgcn_rsq(s);
@@ -672,7 +675,12 @@ __device__ __forceinline__ void pair_segment_f64f(const double2 (*__restrict__ b
                     const double r3 = fma(0.5, mz, az[r]);
                     s = fma(r1, r1, fma(r2, r2, fma(r3, r3, eps2)));
                 }
-                const double wgt = inv_cube_sqrt(s);
+                // A pair with r = 0 (the self pair, or a coincident point)
+                // contributes exactly 0.  In the factored sum its two terms
+                // a x w g and w (b x g) cancel only to rounding, and w =
+                // eps^-3 would blow that residue up for small eps; r = 0 is
+                // exactly s == eps^2 here (r is formed exactly above).
+                const double wgt = (MODE == kF64FactNear && s == eps2) ? 0.0 : inv_cube_sqrt(s);
                 A[r][0] = fma(wgt, g1, A[r][0]);
                 A[r][1] = fma(wgt, g2, A[r][1]);
                 A[r][2] = fma(wgt, g3, A[r][2]);
