@@ -11,7 +11,9 @@ import os
 from dataclasses import dataclass, field
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libzm.so")
+# ZM_LIBRARY selects another build of the same library (the host-sanitizer
+# test loads one); by default the in-tree build is used.
+LIB_PATH = os.environ.get("ZM_LIBRARY", os.path.join(HERE, "libzm.so"))
 
 ZM_OK = 0
 ZM_ERR_INVALID_ARG = -1

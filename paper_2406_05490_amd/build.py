@@ -32,14 +32,18 @@ FLAGS = [
 ]
 
 
-def build(verbose: bool = False, asm_dir: str | None = None, defines=(), out: str = LIB) -> str:
+def build(verbose: bool = False, asm_dir: str | None = None, defines=(), out: str = LIB,
+          extra_flags=(), obj_dir: str | None = None) -> str:
     """Compile and link; `defines` are extra -D macros (tuning builds), `out`
-    the library path."""
+    the library path, `extra_flags` more compile and link flags (e.g. host-only
+    sanitizers), `obj_dir` where the objects go (default: next to the
+    sources)."""
     objs = []
-    extra = [f"-D{d}" for d in defines]
+    extra = [f"-D{d}" for d in defines] + list(extra_flags)
     tag = "_".join(d.replace("=", "") for d in defines)
     for src in SOURCES:
-        obj = os.path.join(CSRC, os.path.basename(src) + (f".{tag}" if tag else "") + ".o")
+        obj = os.path.join(obj_dir or CSRC,
+                           os.path.basename(src) + (f".{tag}" if tag else "") + ".o")
         cmd = [HIPCC, *FLAGS, *extra, "-c", src, "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
@@ -51,7 +55,7 @@ def build(verbose: bool = False, asm_dir: str | None = None, defines=(), out: st
                     os.path.join(asm_dir, os.path.basename(src) + ".s")]
             subprocess.run(acmd, check=True)
     tmp = out + ".tmp"
-    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp]
+    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", *extra_flags, *objs, "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
