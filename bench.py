@@ -637,11 +637,11 @@ def tune_report(zm, torch, sides=(32, 48, 64, 96, 128, 192, 256, 512, 1024),
 
 def ensemble64(zm, torch, steps: int = 20):
     """The 64-member uneven ensemble (sides 32..256, FP32 form) advanced by
-    one batch with graph-captured RK3 steps.  The autotuner first picks the
-    pair-kernel shape of every side (entries kept for the timed run); the
-    same batch with the untuned default shapes is timed beside it.  One
-    member of each side is rerun alone and compared bit for bit with the
-    tuned batch (the solo context takes the same tuned shape)."""
+    one batch with graph-captured RK3 steps.  The same batch is timed with
+    the untuned default shapes, then the batch tuner picks the pair-kernel
+    shape of every side by timing the batched sweep itself (entries kept for
+    the timed run).  One member of each side is rerun alone and compared bit
+    for bit with the tuned batch (the solo context takes the same shape)."""
     ms = rr.ensemble(64, seed=3)
     ps = [zm.Params(m.n, m.n, eps=m.eps, atwood=m.atwood, gravity=1.0, dt=1e-3,
                     precision=zm.ZM_FP32_PAIRS) for m in ms]
@@ -667,10 +667,8 @@ def ensemble64(zm, torch, steps: int = 20):
     b, dt_default = timed_batch()
     info = b.info()
     b.destroy()
-    tuned = {}
-    for n in sides:
-        R, S, tms = zm.autotune(zm.Params(n, n, eps=1.0 / n, precision=prec))
-        tuned[n] = (R, S, tms)
+    shapes, sweep_ms = zm.batch_autotune(ps)
+    tuned = {m.n: shapes[i] for i, m in enumerate(ms)}
     b, dt = timed_batch()
     info_t = b.info()
     # one member of each side rerun alone for the same 1 + steps steps: its
@@ -700,8 +698,9 @@ def ensemble64(zm, torch, steps: int = 20):
     tf = FLOPS_PER_PAIR * pps * steps / dt / 1e12
     return {"members": 64, "sides": sides, "steps": steps,
             "solo_vs_batch": {"members_checked": len(firsts), "bitwise_equal": equal},
-            "shapes": [{"side": n, "default": list(defaults[n]), "tuned": list(tuned[n][:2]),
-                        "tuned_solo_pair_ms": tuned[n][2]} for n in sides],
+            "shapes": [{"side": n, "default": list(defaults[n]), "tuned": list(tuned[n])}
+                       for n in sides],
+            "tuned_batch_pair_sweep_ms": sweep_ms,
             "pairs_per_step": pps, "work_items": info_t.work_items[1],
             "work_items_default": info.work_items[1],
             "persistent_groups": info_t.persistent_groups, "seconds": dt,

@@ -305,6 +305,27 @@ size_t zm_autotune_workspace_bytes(const zm_params *params);
 zm_status zm_autotune(const zm_params *params, void *d_workspace, size_t workspace_bytes,
                       void *hip_stream, zm_pair_tuning *best, double *best_ms);
 
+/* Workspace bytes zm_batch_autotune needs for this set of members (0 if an
+ * entry is invalid, or one a batch refuses: see zm_batch_create). */
+size_t zm_batch_autotune_workspace_bytes(const zm_params *params, int32_t count);
+
+/* Choose the pair-kernel shape of every mesh size in a batch by timing the
+ * batched persistent pair sweep itself (zm_batch_create below), not solo
+ * launches: inside a batch the other members keep the device busy, so a
+ * size's best split count can differ from its solo one.  On synthetic data
+ * of the members' sizes, starting from the shapes new contexts would take,
+ * every size (largest total pair work first) tries each candidate (targets
+ * per lane 1, 2, 4 x source splits 1, 2, 4, ... up to n2 and the solo
+ * candidates; for FP32 only shapes the form accepts) with the other sizes
+ * fixed, keeping the fastest.  The chosen shapes go into the process-wide
+ * table, so batches, pools and contexts created afterwards use them (and
+ * stay bitwise identical to each other).  best: `count` entries (one per
+ * member) or NULL; best_ms: time of one batched pair sweep with the chosen
+ * shapes, or NULL.  Synchronous; uses only the caller's workspace. */
+zm_status zm_batch_autotune(const zm_params *params, int32_t count, void *d_workspace,
+                            size_t workspace_bytes, void *hip_stream, zm_pair_tuning *best,
+                            double *best_ms);
+
 /* ---- batched ensemble ---------------------------------------------------- */
 /*
  * A batch advances `count` independent instances (each with its own mesh

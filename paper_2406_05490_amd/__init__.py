@@ -7,7 +7,7 @@ built -- there is no CPU fallback.
 """
 from ._zm import (  # noqa: F401
     EXPORTS, KERNELS, LIB_PATH, Batch, Context, Params, ZMError, batch_workspace_bytes,
-    ZM_FLAG_GRAPH, autotune, tuning_get, tuning_set, Pool, pool_request_bytes,
+    ZM_FLAG_GRAPH, autotune, batch_autotune, tuning_get, tuning_set, Pool, pool_request_bytes,
     ZM_REQ_UNKNOWN, ZM_REQ_QUEUED, ZM_REQ_LIVE, ZM_REQ_FINISHED, ZM_REQ_FAILED,
     ZM_ERR_CAPACITY, ZM_ERR_HIP, ZM_ERR_INVALID_ARG, ZM_ERR_NONFINITE,
     ZM_ERR_UNSUPPORTED, ZM_ERR_WORKSPACE, ZM_FLAG_CHECK_FINITE, ZM_FP32_PAIRS,

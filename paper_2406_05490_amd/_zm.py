@@ -109,6 +109,7 @@ EXPORTS = (
     "zm_step", "zm_get_state", "zm_destroy", "zm_status_string", "zm_last_error",
     "zm_get_launch_info", "zm_profile_enable", "zm_profile_read", "zm_cutoff_info_get",
     "zm_tuning_set", "zm_tuning_get", "zm_autotune_workspace_bytes", "zm_autotune",
+    "zm_batch_autotune_workspace_bytes", "zm_batch_autotune",
     "zm_batch_workspace_bytes", "zm_batch_create", "zm_batch_init_state", "zm_batch_get_state",
     "zm_batch_step", "zm_batch_get_info", "zm_batch_destroy", "zm_batch_last_error",
     "zm_pool_workspace_bytes", "zm_pool_request_bytes", "zm_pool_create", "zm_pool_submit",
@@ -173,6 +174,11 @@ def load(path: str = LIB_PATH):
     lib.zm_autotune_workspace_bytes.restype = ctypes.c_size_t
     lib.zm_autotune.argtypes = [P, vp, ctypes.c_size_t, vp, T, ctypes.POINTER(ctypes.c_double)]
     lib.zm_autotune.restype = ctypes.c_int32
+    lib.zm_batch_autotune_workspace_bytes.argtypes = [P, ctypes.c_int32]
+    lib.zm_batch_autotune_workspace_bytes.restype = ctypes.c_size_t
+    lib.zm_batch_autotune.argtypes = [P, ctypes.c_int32, vp, ctypes.c_size_t, vp, T,
+                                      ctypes.POINTER(ctypes.c_double)]
+    lib.zm_batch_autotune.restype = ctypes.c_int32
     lib.zm_batch_workspace_bytes.argtypes = [P, ctypes.c_int32]
     lib.zm_batch_workspace_bytes.restype = ctypes.c_size_t
     lib.zm_batch_create.argtypes = [ctypes.POINTER(vp), P, ctypes.c_int32, ctypes.c_uint32, vp,
@@ -399,6 +405,28 @@ def _params_array(ps):
     for i, p in enumerate(ps):
         arr[i] = p.c()
     return arr
+
+
+def batch_autotune(ps, stream=None):
+    """Choose the pair-kernel shape of every mesh size of a batch by timing
+    the batched persistent sweep itself (zm_batch_autotune); the choices go
+    into the process-wide table.  Returns ([(targets_per_lane, splits)] per
+    member, ms of one batched pair sweep with them)."""
+    import torch
+    lib = load()
+    arr = _params_array(ps)
+    nbytes = int(lib.zm_batch_autotune_workspace_bytes(arr, len(ps)))
+    if nbytes == 0:
+        raise ZMError(ZM_ERR_INVALID_ARG, "invalid batch parameters")
+    ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    stream = torch.cuda.current_stream() if stream is None else stream
+    best = (zm_pair_tuning * len(ps))()
+    ms = ctypes.c_double()
+    st = lib.zm_batch_autotune(arr, len(ps), ws.data_ptr(), nbytes, stream.cuda_stream, best,
+                               ctypes.byref(ms))
+    if st != ZM_OK:
+        raise ZMError(st, "batch autotune")
+    return [(int(b.targets_per_lane), int(b.source_splits)) for b in best], float(ms.value)
 
 
 def batch_workspace_bytes(ps) -> int:

@@ -170,11 +170,9 @@ __global__ __launch_bounds__(kThreads) void kb_pairs_f32(const InstDesc* __restr
 int dev_tie_blocks(int n1, int n2) { return dev::tie_blocks(n1, n2); }
 int dev_reduce_lanes(int N, int splits) { return dev::reduce_lanes(N, splits); }
 
-hipError_t launch_batch_stage(const BatchLaunch& b, int stage, hipStream_t s)
+hipError_t launch_batch_pairs(const BatchLaunch& b, int stage, hipStream_t s)
 {
-    if (b.count <= 0) return hipSuccess;
     const dim3 blk(kThreads);
-    hipLaunchKernelGGL(kb_surface, dim3(b.total_blocks), blk, 0, s, b.table, b.count, stage);
     for (int g = 0; g < b.ngroups; ++g) {
         const PairGroup& G = b.groups[g];
         if (G.nitems == 0) continue;
@@ -194,6 +192,16 @@ hipError_t launch_batch_stage(const BatchLaunch& b, int stage, hipStream_t s)
             else hipLaunchKernelGGL((kb_pairs_f32<4>), dim3(grid), blk, 0, s, b.table, items, n, ctr, stage);
         }
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_stage(const BatchLaunch& b, int stage, hipStream_t s)
+{
+    if (b.count <= 0) return hipSuccess;
+    const dim3 blk(kThreads);
+    hipLaunchKernelGGL(kb_surface, dim3(b.total_blocks), blk, 0, s, b.table, b.count, stage);
+    hipError_t e = launch_batch_pairs(b, stage, s);
+    if (e != hipSuccess) return e;
     if (b.any_even)
         hipLaunchKernelGGL(kb_ties, dim3(b.total_tie_blocks, 2), blk, 0, s, b.table, b.count, stage);
     hipLaunchKernelGGL(kb_reduce, dim3(b.total_reduce_blocks), blk, 0, s, b.table, b.count, stage);

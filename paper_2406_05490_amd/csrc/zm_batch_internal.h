@@ -76,6 +76,10 @@ int dev_reduce_lanes(int N, int splits);
 // through InstDesc::flag.
 hipError_t launch_batch_stage(const BatchLaunch& b, int stage, hipStream_t s);
 
+// Enqueue only the persistent pair launches of one stage (one per group),
+// each preceded by its work-counter reset.
+hipError_t launch_batch_pairs(const BatchLaunch& b, int stage, hipStream_t s);
+
 // Host-side tables for a set of instances: descriptors, pair work items
 // grouped by (precision, targets per lane) and ordered longest first within a
 // group, block offsets of the point kernels.

@@ -68,3 +68,51 @@ def test_autotune_then_solo_equals_batch(gpu):
         assert torch.equal(zs, zb) and torch.equal(ws, wb)
     finally:
         zm.tuning_set(n, n, zm.ZM_FP32_PAIRS)
+
+
+def test_batch_autotune_sets_shapes_the_batch_and_solo_runs_share(gpu):
+    """The batch tuner times the batched sweep itself and stores one shape per
+    mesh size; members of one size share it, the table holds it, and a batch
+    built afterwards equals solo contexts bitwise and the oracle at the
+    parity bar."""
+    import paper_2406_05490_amd as zm
+    import torch
+    sizes = [(32, zm.ZM_FP32_PAIRS), (48, zm.ZM_FP64), (32, zm.ZM_FP32_PAIRS), (64, zm.ZM_FP32_PAIRS),
+             (40, zm.ZM_FP64)]
+    ps = [zm.Params(n, n, eps=1 / n, precision=pr, atwood=0.3 + 0.1 * i)
+          for i, (n, pr) in enumerate(sizes)]
+    keys = {(p.n1, p.n2, p.precision) for p in ps}
+    try:
+        shapes, ms = zm.batch_autotune(ps)
+        assert ms > 0 and len(shapes) == len(ps)
+        for p, (R, S) in zip(ps, shapes):
+            assert R in (1, 2, 4) and 1 <= S <= p.n2
+            assert zm.tuning_get(p.n1, p.n2, p.precision) == (R, S)
+        assert shapes[0] == shapes[2]                 # one shape per size
+        b = zm.Batch(ps)
+        states = []
+        for i, p in enumerate(ps):
+            z, w = rr.random_state(p.n1, p.n2, seed=60 + i, height=0.05)
+            states.append((z, w))
+            b.init_state(i, to_dev(z, gpu), to_dev(w, gpu))
+        b.step(2)
+        for i, p in enumerate(ps):
+            z, w = states[i]
+            zb = torch.empty(3 * p.n, dtype=torch.float64, device=gpu)
+            wb = torch.empty(2 * p.n, dtype=torch.float64, device=gpu)
+            b.get_state(i, zb, wb)
+            ctx = zm.Context(p)
+            ctx.init_state(to_dev(z, gpu), to_dev(w, gpu))
+            ctx.step(2)
+            zs, ws = torch.empty_like(zb), torch.empty_like(wb)
+            ctx.get_state(zs, ws)
+            torch.cuda.synchronize()
+            assert torch.equal(zs, zb) and torch.equal(ws, wb), i
+            assert ctx.launch_info().source_splits == shapes[i][1]
+            P = oracle.Problem(p.n1, p.n2, eps=p.eps, atwood=p.atwood, gravity=p.gravity, dt=p.dt)
+            zr, wr = oracle.rk3(P, z, w, 2)
+            tol = 1e-9 if p.precision == zm.ZM_FP64 else 1e-5
+            assert relerr(to_host(zb).reshape(3, -1) - z, zr - z) < tol, i
+    finally:
+        for (n1, n2, pr) in keys:
+            zm.tuning_set(n1, n2, pr)
