@@ -134,6 +134,7 @@ zm_status eval_velocity(zm_ctx* c, const double* z, const double* w, double* u, 
     double* q = c->at(c->layout.q);
     double* part = c->at(c->layout.part);
     double* tie = c->at(c->layout.tie);
+    int* fold = reinterpret_cast<int*>(c->ws + c->layout.fold);
     hipError_t e;
     if (c->low) {   // the FFT velocity needs no source strengths
         e = timed(c, ZM_KERNEL_FFT,
@@ -141,7 +142,8 @@ zm_status eval_velocity(zm_ctx* c, const double* z, const double* w, double* u, 
         if (e != hipSuccess) return hip_fail(c, e, "FFT velocity launch");
         return ZM_OK;
     }
-    e = timed(c, ZM_KERNEL_SURFACE, [&] { return zm::launch_surface(m, z, w, gam, q, stream); });
+    e = timed(c, ZM_KERNEL_SURFACE,
+              [&] { return zm::launch_surface(m, z, w, gam, q, fold, stream); });
     if (e != hipSuccess) return hip_fail(c, e, "surface kernel launch");
     if (c->cutoff) {
         int half = 0;
@@ -161,8 +163,8 @@ zm_status eval_velocity(zm_ctx* c, const double* z, const double* w, double* u, 
     }
     e = timed(c, ZM_KERNEL_PAIRS, [&] {
         return c->prm.precision == ZM_FP32_PAIRS
-                   ? zm::launch_pairs_f32(m, c->shape, z, gam, part, stream)
-                   : zm::launch_pairs_f64(m, c->shape, z, gam, part, stream);
+                   ? zm::launch_pairs_f32(m, c->shape, z, gam, part, fold, stream)
+                   : zm::launch_pairs_f64(m, c->shape, z, gam, part, fold, stream);
     });
     if (e != hipSuccess) return hip_fail(c, e, "pair kernel launch");
     const bool ties = m.periodic && ((m.n1 % 2) == 0 || (m.n2 % 2) == 0);
@@ -277,6 +279,14 @@ zm_status zm_create(zm_ctx** out, const zm_params* params, void* d_workspace,
         c->cb.src = reinterpret_cast<double*>(ws + L.cut_src);
         c->cb.counts = reinterpret_cast<unsigned long long*>(ws + L.cut_counts);
         c->cb.kflag = reinterpret_cast<int*>(ws + L.cut_kflag);
+    }
+    // the surface kernel's fold statistics start cleared (each evaluation's
+    // last surface workgroup clears them again for the next one)
+    e = hipMemsetAsync(c->ws + L.fold, 0, 8 * sizeof(int), c->stream);
+    if (e != hipSuccess) {
+        g_create_error = std::string("workspace clear: ") + hipGetErrorString(e);
+        delete c;
+        return ZM_ERR_HIP;
     }
     *out = c;
     return ZM_OK;

@@ -50,7 +50,9 @@ __global__ __launch_bounds__(kThreads) void kb_surface(const InstDesc* __restric
     const InstDesc& d = T[i];
     const int p = (blockIdx.x - d.block_begin) * kThreads + threadIdx.x;
     const double* ys = d.Y[stage];
-    dev::surface_point(d.m, p, ys, ys + 3 * (size_t)d.m.N, d.gam, d.q);
+    const dev::FoldStat st = dev::surface_point(d.m, p, ys, ys + 3 * (size_t)d.m.N, d.gam, d.q);
+    // every workgroup belongs to one instance: gather over that instance's
+    dev::fold_gather(st, d.fold, d.blocks);
 }
 
 __global__ __launch_bounds__(kThreads) void kb_ties(const InstDesc* __restrict__ T, int count,
@@ -109,59 +111,54 @@ __global__ void kb_reset(int* __restrict__ counter)
     if (threadIdx.x == 0) counter[0] = 0;
 }
 
-// Persistent pair sweep over the FP64 items.  Exit: a workgroup leaves once
+// Persistent pair sweep over the items of one group (FP64 pair form, R
+// targets per lane, patches PX columns wide).  Exit: a workgroup leaves once
 // the counter passes nitems, which every workgroup reaches.
-template <int R>
+template <int R, int PX>
 __global__ __launch_bounds__(kThreads) void kb_pairs_f64(const InstDesc* __restrict__ T,
                                                          const WorkItem* __restrict__ items,
                                                          int nitems, int* __restrict__ counter,
                                                          int stage)
 {
-    __shared__ double2 lds[2][5][kThreads];
+    __shared__ dev::F64Tile lds;
     __shared__ int next;
     for (;;) {
         if (threadIdx.x == 0) next = atomicAdd(counter, 1);
         __syncthreads();
-        const int it = next;
+        // the same item in every lane: read it into a scalar register so the
+        // item and its descriptor are scalar loads (and scalar registers)
+        const int it = __builtin_amdgcn_readfirstlane(next);
         __syncthreads();
         if (it >= nitems) break;
         const WorkItem w = items[it];
         const InstDesc& d = T[w.inst];
-        if (d.sh.cx == 32)
-            dev::pairs_f64f_block<R, 32>(d.m, d.sh, d.Y[stage], d.gam, d.part, w.patch, w.split, lds);
-        else if (d.sh.cx == 16)
-            dev::pairs_f64f_block<R, 16>(d.m, d.sh, d.Y[stage], d.gam, d.part, w.patch, w.split, lds);
-        else
-            dev::pairs_f64f_block<R, 8>(d.m, d.sh, d.Y[stage], d.gam, d.part, w.patch, w.split, lds);
+        dev::pairs_f64f_block<R, PX>(d.m, d.sh, d.Y[stage], d.gam, d.part, w.patch, w.split, d.fold,
+                                     lds);
         // the body ends with a barrier, so `next` and the LDS tiles are free
     }
 }
 
-template <int R>
-__global__ __launch_bounds__(kThreads) void kb_pairs_f32(const InstDesc* __restrict__ T,
-                                                         const WorkItem* __restrict__ items,
-                                                         int nitems, int* __restrict__ counter,
-                                                         int stage)
+// The same over FP32-form items; up to two targets per lane it keeps four
+// waves per SIMD, as the single-instance kernel does.
+template <int R, int PX>
+__global__ __launch_bounds__(kThreads, R <= 2 ? 4 : 1) void kb_pairs_f32(
+    const InstDesc* __restrict__ T, const WorkItem* __restrict__ items, int nitems,
+    int* __restrict__ counter, int stage)
 {
     __shared__ dev::F32Tile tile;
     __shared__ int next;
     for (;;) {
         if (threadIdx.x == 0) next = atomicAdd(counter, 1);
         __syncthreads();
-        const int it = next;
+        // the same item in every lane: read it into a scalar register so the
+        // item and its descriptor are scalar loads (and scalar registers)
+        const int it = __builtin_amdgcn_readfirstlane(next);
         __syncthreads();
         if (it >= nitems) break;
         const WorkItem w = items[it];
         const InstDesc& d = T[w.inst];
-        if (d.sh.cx == 32)
-            dev::pairs_f32_block<R, 32>(d.m, d.sh, d.Y[stage], d.gam, d.part, w.patch, w.split,
-                                        tile);
-        else if (d.sh.cx == 16)
-            dev::pairs_f32_block<R, 16>(d.m, d.sh, d.Y[stage], d.gam, d.part, w.patch, w.split,
-                                        tile);
-        else
-            dev::pairs_f32_block<R, 8>(d.m, d.sh, d.Y[stage], d.gam, d.part, w.patch, w.split,
-                                       tile);
+        dev::pairs_f32_block<R, PX>(d.m, d.sh, d.Y[stage], d.gam, d.part, w.patch, w.split, d.fold,
+                                    tile);
     }
 }
 
@@ -182,15 +179,22 @@ hipError_t launch_batch_pairs(const BatchLaunch& b, int stage, hipStream_t s)
         const WorkItem* items = b.items + G.item_begin;
         int* ctr = b.counters + g;
         const int n = G.nitems;
-        if (G.precision == 0) {
-            if (G.R == 1) hipLaunchKernelGGL((kb_pairs_f64<1>), dim3(grid), blk, 0, s, b.table, items, n, ctr, stage);
-            else if (G.R == 2) hipLaunchKernelGGL((kb_pairs_f64<2>), dim3(grid), blk, 0, s, b.table, items, n, ctr, stage);
-            else hipLaunchKernelGGL((kb_pairs_f64<4>), dim3(grid), blk, 0, s, b.table, items, n, ctr, stage);
-        } else {
-            if (G.R == 1) hipLaunchKernelGGL((kb_pairs_f32<1>), dim3(grid), blk, 0, s, b.table, items, n, ctr, stage);
-            else if (G.R == 2) hipLaunchKernelGGL((kb_pairs_f32<2>), dim3(grid), blk, 0, s, b.table, items, n, ctr, stage);
-            else hipLaunchKernelGGL((kb_pairs_f32<4>), dim3(grid), blk, 0, s, b.table, items, n, ctr, stage);
-        }
+#define ZM_KB_CASE(PREC, KER, RR, CC)                                                             \
+        else if (G.precision == PREC && G.R == RR && G.px == CC)                                  \
+            hipLaunchKernelGGL((KER<RR, CC>), dim3(grid), blk, 0, s, b.table, items, n, ctr, stage);
+        if (false) {}
+        ZM_KB_CASE(0, kb_pairs_f64, 1, 32) ZM_KB_CASE(0, kb_pairs_f64, 1, 16)
+        ZM_KB_CASE(0, kb_pairs_f64, 1, 8) ZM_KB_CASE(0, kb_pairs_f64, 2, 32)
+        ZM_KB_CASE(0, kb_pairs_f64, 2, 16) ZM_KB_CASE(0, kb_pairs_f64, 2, 8)
+        ZM_KB_CASE(0, kb_pairs_f64, 4, 32) ZM_KB_CASE(0, kb_pairs_f64, 4, 16)
+        ZM_KB_CASE(0, kb_pairs_f64, 4, 8)
+        ZM_KB_CASE(1, kb_pairs_f32, 1, 32) ZM_KB_CASE(1, kb_pairs_f32, 1, 16)
+        ZM_KB_CASE(1, kb_pairs_f32, 1, 8) ZM_KB_CASE(1, kb_pairs_f32, 2, 32)
+        ZM_KB_CASE(1, kb_pairs_f32, 2, 16) ZM_KB_CASE(1, kb_pairs_f32, 2, 8)
+        ZM_KB_CASE(1, kb_pairs_f32, 4, 32) ZM_KB_CASE(1, kb_pairs_f32, 4, 16)
+        ZM_KB_CASE(1, kb_pairs_f32, 4, 8)
+        else return hipErrorInvalidConfiguration;
+#undef ZM_KB_CASE
     }
     return hipGetLastError();
 }

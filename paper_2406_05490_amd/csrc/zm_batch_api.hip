@@ -163,11 +163,13 @@ void build_tables(const zm_params* params, const PairShape* shapes, const Layout
         d.tie = reinterpret_cast<double*>(base + L.tie);
         d.u = reinterpret_cast<double*>(base + L.u);
         d.V = reinterpret_cast<double*>(base + L.V);
+        d.fold = reinterpret_cast<int*>(base + L.fold);
         d.flag = flags ? flags[i] : nullptr;
         if (params[i].n1 % 2 == 0 || params[i].n2 % 2 == 0) out.any_even = true;
         const PairShape& sh = shapes[i];
-        const int g = (params[i].precision == ZM_FP32_PAIRS ? 3 : 0) +
-                      (sh.R == 1 ? 0 : (sh.R == 2 ? 1 : 2));
+        const int g = (params[i].precision == ZM_FP32_PAIRS ? 9 : 0) +
+                      3 * (sh.R == 1 ? 0 : (sh.R == 2 ? 1 : 2)) +
+                      (sh.cx == 32 ? 0 : (sh.cx == 16 ? 1 : 2));
         const int side = 2 * params[i].image_layers + 1;
         for (int pt = 0; pt < sh.px * sh.py; ++pt) {
             for (int sp = 0; sp < sh.splits; ++sp) {
@@ -182,11 +184,13 @@ void build_tables(const zm_params* params, const PairShape* shapes, const Layout
     out.total_tie_blocks = tie_block;
     out.total_reduce_blocks = reduce_block;
     static const int kR[3] = {1, 2, 4};
+    static const int kPX[3] = {32, 16, 8};
     for (int g = 0; g < kMaxPairGroups; ++g) {
         if (keyed[g].empty()) continue;
         std::stable_sort(keyed[g].begin(), keyed[g].end(),
                          [](const auto& a, const auto& b) { return a.first > b.first; });
-        out.groups.push_back(PairGroup{g / 3, kR[g % 3], (int)out.items.size(), (int)keyed[g].size()});
+        out.groups.push_back(PairGroup{g / 9, kR[(g / 3) % 3], kPX[g % 3], (int)out.items.size(),
+                                       (int)keyed[g].size()});
         for (auto& k : keyed[g]) out.items.push_back(k.second);
     }
 }
@@ -264,6 +268,9 @@ zm_status zm_batch_create(zm_batch** out, const zm_params* params, int32_t count
     if (e == hipSuccess && !tb.items.empty())
         e = hipMemcpyAsync(ditems, tb.items.data(), sizeof(zm::WorkItem) * tb.items.size(),
                            hipMemcpyHostToDevice, b->stream);
+    // every instance's fold statistics start cleared
+    for (int i = 0; e == hipSuccess && i < count; ++i)
+        e = hipMemsetAsync(bases[i] + P.layouts[i].fold, 0, 8 * sizeof(int), b->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
     if (e != hipSuccess) {
         g_batch_create_error = std::string("table upload: ") + hipGetErrorString(e);

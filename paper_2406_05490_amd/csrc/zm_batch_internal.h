@@ -27,6 +27,7 @@ struct InstDesc {
     double* tie;         // 2 x 3 planes
     double* u;           // 3 planes
     double* V;           // 1 plane
+    int* fold;           // tangent-map statistics and far-form flag (5 ints)
     int* flag;           // set to 1 by the update if this instance's state is not finite (may be NULL)
 };
 
@@ -38,15 +39,18 @@ struct WorkItem {
     int pad_;
 };
 
-// Items of one persistent pair launch: same precision and targets per lane.
+// Items of one persistent pair launch: same precision, targets per lane and
+// patch width (one kernel body per launch, so each keeps the register count,
+// and with it the occupancy, of the single-instance kernel of that shape).
 struct PairGroup {
     int precision;
     int R;
+    int px;
     int item_begin;
     int nitems;
 };
 
-constexpr int kMaxPairGroups = 6;   // 2 precisions x R in {1, 2, 4}
+constexpr int kMaxPairGroups = 18;   // 2 precisions x R in {1, 2, 4} x patch width in {32, 16, 8}
 
 // Everything one batched RK3 stage needs (device pointers + host counts).
 struct BatchLaunch {
@@ -81,8 +85,8 @@ hipError_t launch_batch_stage(const BatchLaunch& b, int stage, hipStream_t s);
 hipError_t launch_batch_pairs(const BatchLaunch& b, int stage, hipStream_t s);
 
 // Host-side tables for a set of instances: descriptors, pair work items
-// grouped by (precision, targets per lane) and ordered longest first within a
-// group, block offsets of the point kernels.
+// grouped by (precision, targets per lane, patch width) and ordered longest
+// first within a group, block offsets of the point kernels.
 struct TableBuild {
     std::vector<InstDesc> table;
     std::vector<WorkItem> items;

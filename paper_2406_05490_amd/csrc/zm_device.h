@@ -145,11 +145,113 @@ __device__ __forceinline__ void tangents_at(const Mesh& m, int p, const double* 
     }
 }
 
-__device__ __forceinline__ void surface_point(const Mesh& m, int p, const double* __restrict__ z,
-                                              const double* __restrict__ w,
-                                              double* __restrict__ gam, double* __restrict__ q)
+// ---- fold statistics of the sheet -------------------------------------------
+//
+// The pair kernels' far forms expand |r|^2 + eps^2 as |a|^2 + (|b|^2 + eps^2 -
+// 2 a.b), whose rounding is about ((|a| + |b|) / |r|)^2 ulp, and pick the
+// sources that take it by their index distance from the target patch: every
+// source at least one patch half-extent e beyond the patch.  That bounds the
+// ratio only while index distance bounds physical distance.  With the
+// tangent map J3 = (T1, T2) and its horizontal part J2 (the x, y rows):
+// while det J2 keeps one sign (and is not 0) at every point the horizontal
+// map alpha -> (x, y) is a covering of the period cell of degree +-1, i.e.
+// one-to-one, so
+// the horizontal distance of two points is at least sigma_min(J2) times their
+// index distance (the straight horizontal segment between them pulls back
+// to a path at least that long); and a target lies within sigma_max(J3) e of
+// the patch centre.  So |r| >= sigma_min e, |a| <= sigma_max e and
+// (|a| + |b|) / |r| <= 1 + 2 sigma_max / sigma_min: with sigma_max <= 4
+// sigma_min everywhere the far forms stay within 81 ulp.  A sheet that
+// folds (det J2 changes sign or vanishes: overturned, rolled up) or stretches beyond
+// that ratio takes exact r for every pair instead (the same sums with more
+// operations per pair).  The surface kernel gathers min sigma_min(J2)^2,
+// max sigma_max(J3)^2 and the signs det J2 takes over the mesh; its last workgroup
+// turns them into the flag the pair kernels read and clears the gathered
+// values for the next evaluation.
+//
+// fold[0]: max of (bits(+inf) - bits(min sigma_min^2)) (0 = nothing seen)
+// fold[1]: max of bits(max sigma_max^2)
+// fold[2]: signs of det J2 seen (bits as in fold_stat)
+// fold[3]: workgroups done
+// fold[4]: 1 = the far forms are off for this evaluation (read by the pair kernels)
+constexpr int kFoldWords = 5;
+constexpr float kFoldMaxStretch2 = 16.f;   // (sigma_max / sigma_min)^2 allowed
+
+struct FoldStat {
+    float smin2, smax2;
+    int folded;
+};
+
+// Called by every thread of a workgroup (256 threads); the workgroup's
+// points' statistics are combined into fold[], and the last workgroup of
+// the launch (of `groups` in all) writes the flag and clears the rest.
+__device__ __forceinline__ void fold_gather(FoldStat st, int* __restrict__ fold, int groups)
 {
-    if (p >= m.N) return;
+    __shared__ float smin_w[kThreads / 64], smax_w[kThreads / 64];
+    __shared__ int fold_w[kThreads / 64];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        st.smin2 = fminf(st.smin2, __shfl_xor(st.smin2, off, 64));
+        st.smax2 = fmaxf(st.smax2, __shfl_xor(st.smax2, off, 64));
+        st.folded |= __shfl_xor(st.folded, off, 64);
+    }
+    const int wv = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        smin_w[wv] = st.smin2;
+        smax_w[wv] = st.smax2;
+        fold_w[wv] = st.folded;
+    }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    float a = smin_w[0], b = smax_w[0];
+    int f = fold_w[0];
+#pragma unroll
+    for (int k = 1; k < kThreads / 64; ++k) {
+        a = fminf(a, smin_w[k]);
+        b = fmaxf(b, smax_w[k]);
+        f |= fold_w[k];
+    }
+    const int inf_bits = __float_as_int(__builtin_inff());
+    atomicMax(&fold[0], inf_bits - __float_as_int(a));   // a, b >= 0: bit order = value order
+    atomicMax(&fold[1], __float_as_int(b));
+    if (f) atomicOr(&fold[2], f);
+    __threadfence();
+    if (atomicAdd(&fold[3], 1) != groups - 1) return;
+    // last workgroup: every other one has added its values (fenced above)
+    const float smin2 = __int_as_float(inf_bits - atomicAdd(&fold[0], 0));
+    const float smax2 = __int_as_float(atomicAdd(&fold[1], 0));
+    const int sg = atomicAdd(&fold[2], 0);
+    const bool off = (sg & 3) == 3 || (sg & 4) != 0 || !(smax2 <= kFoldMaxStretch2 * smin2);
+    atomicExch(&fold[4], off ? 1 : 0);
+    atomicExch(&fold[0], 0);
+    atomicExch(&fold[1], 0);
+    atomicExch(&fold[2], 0);
+    atomicExch(&fold[3], 0);
+}
+
+// Tangent-map statistics of one point (identity values for p >= N).
+// folded: bit 0 det J2 > 0, bit 1 det J2 < 0, bit 2 neither (0 or NaN).
+__device__ __forceinline__ FoldStat fold_stat(const double T1[3], const double T2[3], double det2)
+{
+    const float x1 = (float)T1[0], y1 = (float)T1[1], z1 = (float)T1[2];
+    const float x2 = (float)T2[0], y2 = (float)T2[1], z2 = (float)T2[2];
+    const float det = (float)det2;
+    const float s2 = x1 * x1 + x2 * x2 + y1 * y1 + y2 * y2;
+    const float s3 = s2 + z1 * z1 + z2 * z2;
+    const float n1 = y1 * z2 - z1 * y2, n2 = z1 * x2 - x1 * z2;
+    const float nn = n1 * n1 + n2 * n2 + det * det;   // |T1 x T2|^2
+    FoldStat st;
+    st.smin2 = 0.5f * (s2 - __builtin_amdgcn_sqrtf(fmaxf(s2 * s2 - 4.f * det * det, 0.f)));
+    st.smax2 = 0.5f * (s3 + __builtin_amdgcn_sqrtf(fmaxf(s3 * s3 - 4.f * nn, 0.f)));
+    st.folded = det2 > 0.0 ? 1 : (det2 < 0.0 ? 2 : 4);
+    return st;
+}
+
+__device__ __forceinline__ FoldStat surface_point(const Mesh& m, int p, const double* __restrict__ z,
+                                                  const double* __restrict__ w,
+                                                  double* __restrict__ gam, double* __restrict__ q)
+{
+    if (p >= m.N) return FoldStat{__builtin_inff(), 0.f, 0};
     const int N = m.N;
     double T1[3], T2[3];
     tangents_at(m, p, z, T1, T2);
@@ -164,6 +266,7 @@ __device__ __forceinline__ void surface_point(const Mesh& m, int p, const double
     const double c2 = T1[2] * T2[0] - T1[0] * T2[2];
     const double c3 = T1[0] * T2[1] - T1[1] * T2[0];
     q[p] = (g1 * g1 + g2 * g2 + g3 * g3) / (c1 * c1 + c2 * c2 + c3 * c3);
+    return fold_stat(T1, T2, c3);
 }
 
 // ---------------------------------------------------------------------------
@@ -347,7 +450,7 @@ __device__ __forceinline__ void pairs_f32_block(const Mesh& m, const PairShape& 
                                                 const double* __restrict__ z,
                                                 const double* __restrict__ gam,
                                                 double* __restrict__ part, int patch, int split,
-                                                F32Tile& T)
+                                                const int* __restrict__ fold, F32Tile& T)
 {
     constexpr int RY = kThreads / PX;
     constexpr int PY = RY * R;
@@ -415,6 +518,9 @@ __device__ __forceinline__ void pairs_f32_block(const Mesh& m, const PairShape& 
     const int total = ntiles * side * side;
     const float L1f = (float)m.L1;
     const float eps2f = (float)m.eps2;
+    // the sheet's tangent map keeps index distance a bound on distance (see
+    // fold_gather): the far forms may be used this evaluation
+    const bool far_ok = fold == nullptr || fold[4] == 0;
 
     // ---- staging: source j relative to the centre, centre's image --------
     float4 st0, st1;
@@ -480,7 +586,7 @@ __device__ __forceinline__ void pairs_f32_block(const Mesh& m, const PairShape& 
             }
             bool near_row;
             interval_run(j2, near2_lo, near2_len, n2, near_row);
-            const bool fact_row = ZM_F32_FACTORED && layer0;
+            const bool fact_row = ZM_F32_FACTORED && layer0 && far_ok;
             float G[R][3], C[R][3];
 #pragma unroll
             for (int r = 0; r < R; ++r) {
@@ -692,7 +798,12 @@ __device__ __forceinline__ void pair_segment_f64f(const double2 (*__restrict__ b
     }
 }
 
-// lds: [buffer][(bx,by) (bz,g1) (g2,g3) (c1,c2) (c3,-)][source].
+// Staged FP64 sources, double buffered: v[buffer][(bx,by) (bz,g1) (g2,g3)
+// (c1,c2) (c3, |b|^2 + eps^2)][source].
+struct F64Tile {
+    double2 v[2][5][kThreads];
+};
+
 // Workgroup = target patch of PX columns x (256/PX)*R rows (lane = one
 // column, R rows 256/PX apart) x one range of source rows.
 template <int R, int PX>
@@ -700,7 +811,7 @@ __device__ __forceinline__ void pairs_f64f_block(const Mesh& m, const PairShape&
                                                  const double* __restrict__ z,
                                                  const double* __restrict__ gam,
                                                  double* __restrict__ part, int patch, int split,
-                                                 double2 (*lds)[5][kThreads])
+                                                 const int* __restrict__ fold, F64Tile& T)
 {
     constexpr int RY = kThreads / PX;
     constexpr int PY = RY * R;
@@ -762,6 +873,9 @@ __device__ __forceinline__ void pairs_f64f_block(const Mesh& m, const PairShape&
     const int ntiles = (src_end - src_begin + kThreads - 1) / kThreads;
     const int side = 2 * m.K + 1;
     const int total = ntiles * side * side;
+    // the sheet's tangent map keeps index distance a bound on distance (see
+    // fold_gather): the expanded far forms may be used this evaluation
+    const bool far_ok = fold == nullptr || fold[4] == 0;
 
     double2 st[5];
     auto load_tile = [&](int t) {
@@ -788,7 +902,7 @@ __device__ __forceinline__ void pairs_f64f_block(const Mesh& m, const PairShape&
     };
     auto store_tile = [&](int buf) {
 #pragma unroll
-        for (int q = 0; q < 5; ++q) lds[buf][q][tid] = st[q];
+        for (int q = 0; q < 5; ++q) T.v[buf][q][tid] = st[q];
     };
 
     load_tile(0);
@@ -848,6 +962,8 @@ __device__ __forceinline__ void pairs_f64f_block(const Mesh& m, const PairShape&
                 } else if (!band_all && ZM_BAND_FACTORED) {
                     in_near = false;
                 }
+                // a folded or strongly stretched sheet: exact r everywhere
+                if (!far_ok) in_near = true;
                 // a band segment of the far form keeps the centre's image fixed
                 if (in_band && !in_near && a < cimg1.b && stop > cimg1.b) stop = cimg1.b;
                 const int kk = k + (a - j1);
@@ -858,7 +974,7 @@ __device__ __forceinline__ void pairs_f64f_block(const Mesh& m, const PairShape&
                     B[r][0] = B[r][1] = B[r][2] = 0.0;
                 }
                 if (in_band && in_near) {
-                    pair_segment_f64f<R, kF64Direct>(lds[buf], kk, stop - a, a, ax1.b, ax1.s_lo,
+                    pair_segment_f64f<R, kF64Direct>(T.v[buf], kk, stop - a, a, ax1.b, ax1.s_lo,
                                                      cimg1.b, cimg1.s_lo, m.L1, ax, ay, az, aa,
                                                      m.eps2, A, B);
                     // direct contributions
@@ -870,15 +986,15 @@ __device__ __forceinline__ void pairs_f64f_block(const Mesh& m, const PairShape&
                     }
                 } else {
                     if (in_band)
-                        pair_segment_f64f<R, kF64BandFar>(lds[buf], kk, stop - a, a, ax1.b, ax1.s_lo,
+                        pair_segment_f64f<R, kF64BandFar>(T.v[buf], kk, stop - a, a, ax1.b, ax1.s_lo,
                                                           cimg1.b, cimg1.s_lo, m.L1, ax, ay, az, aa,
                                                           m.eps2, A, B);
                     else if (in_near)
-                        pair_segment_f64f<R, kF64FactNear>(lds[buf], kk, stop - a, a, ax1.b, ax1.s_lo,
+                        pair_segment_f64f<R, kF64FactNear>(T.v[buf], kk, stop - a, a, ax1.b, ax1.s_lo,
                                                            cimg1.b, cimg1.s_lo, m.L1, ax, ay, az, aa,
                                                            m.eps2, A, B);
                     else
-                        pair_segment_f64f<R, kF64FactFar>(lds[buf], kk, stop - a, a, ax1.b, ax1.s_lo,
+                        pair_segment_f64f<R, kF64FactFar>(T.v[buf], kk, stop - a, a, ax1.b, ax1.s_lo,
                                                           cimg1.b, cimg1.s_lo, m.L1, ax, ay, az, aa,
                                                           m.eps2, A, B);
                     // a x A - B

@@ -31,6 +31,7 @@ struct Layout {
     size_t tie;          // 6N
     size_t u, V;         // 3N, N
     size_t flag;         // one int
+    size_t fold;         // kFoldWords ints: tangent-map statistics, far-form flag
     // cutoff solver only (size 0 otherwise)
     size_t cut_keys[2], cut_vals[2];   // N unsigned each
     size_t cut_hist;                   // 256 * sort_blocks unsigned
@@ -73,6 +74,7 @@ inline Layout make_layout(const zm_params& p, const zm::PairShape& sh)
     L.u = take(3 * N * d);
     L.V = take(N * d);
     L.flag = take(sizeof(int));
+    L.fold = take(8 * sizeof(int));
     const size_t u4 = sizeof(unsigned);
     L.cut_keys[0] = take(cut ? N * u4 : 0);
     L.cut_keys[1] = take(cut ? N * u4 : 0);

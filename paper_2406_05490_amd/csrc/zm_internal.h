@@ -50,19 +50,23 @@ bool lookup_tuning(int n1, int n2, int precision, int* R, int* splits);
 
 // Synthetic positions (3 planes) and source strengths (3 planes) for tuning.
 hipError_t launch_tune_init(const Mesh& m, double* z, double* gam, hipStream_t s);
+// fold (5 ints, zero before the first use; may be NULL): the sheet's
+// tangent-map statistics, turned by the launch's last workgroup into the
+// flag fold[4] the pair kernels read (1: use exact r for every pair).
 hipError_t launch_surface(const Mesh& m, const double* z, const double* w,
-                          double* gam, double* q, hipStream_t s);
+                          double* gam, double* q, int* fold, hipStream_t s);
 
 // part[split][3][N] = unscaled sums over the split's sources of
 // (r x gamma) / (|r|^2 + eps^2)^(3/2), images handled as described in zm.h
 // with ties counted once at the image of offset -n_a/2.
+// fold: the flag launch_surface left (NULL: the far forms are allowed).
 hipError_t launch_pairs_f64(const Mesh& m, const PairShape& sh, const double* z,
-                            const double* gam, double* part, hipStream_t s);
+                            const double* gam, double* part, const int* fold, hipStream_t s);
 
 // Same contract, pair terms in FP32 with tile-relative coordinates and FP64
 // per-target sums.
 hipError_t launch_pairs_f32(const Mesh& m, const PairShape& sh, const double* z,
-                            const double* gam, double* part, hipStream_t s);
+                            const double* gam, double* part, const int* fold, hipStream_t s);
 
 // tie[pass][3][N]: pass 0 (n1 even) corrects the tie column, pass 1 (n2 even)
 // the tie row, so that tied sources end with weight 1/2 per end image.

@@ -15,29 +15,33 @@ using dev::kThreads;
 __global__ __launch_bounds__(kThreads) void k_surface(Mesh m, const double* __restrict__ z,
                                                       const double* __restrict__ w,
                                                       double* __restrict__ gam,
-                                                      double* __restrict__ q)
+                                                      double* __restrict__ q,
+                                                      int* __restrict__ fold)
 {
-    dev::surface_point(m, blockIdx.x * kThreads + threadIdx.x, z, w, gam, q);
+    const dev::FoldStat st = dev::surface_point(m, blockIdx.x * kThreads + threadIdx.x, z, w, gam, q);
+    if (fold) dev::fold_gather(st, fold, gridDim.x);
 }
 
 template <int R, int PX>
 __global__ __launch_bounds__(kThreads) void k_pairs_f64f(Mesh m, PairShape sh,
                                                          const double* __restrict__ z,
                                                          const double* __restrict__ gam,
-                                                         double* __restrict__ part)
+                                                         double* __restrict__ part,
+                                                         const int* __restrict__ fold)
 {
-    __shared__ double2 lds[2][5][kThreads];
-    dev::pairs_f64f_block<R, PX>(m, sh, z, gam, part, blockIdx.x, blockIdx.y, lds);
+    __shared__ dev::F64Tile lds;
+    dev::pairs_f64f_block<R, PX>(m, sh, z, gam, part, blockIdx.x, blockIdx.y, fold, lds);
 }
 
 template <int R, int PX>
 __global__ __launch_bounds__(kThreads) void k_pairs_f32(Mesh m, PairShape sh,
                                                         const double* __restrict__ z,
                                                         const double* __restrict__ gam,
-                                                        double* __restrict__ part)
+                                                        double* __restrict__ part,
+                                                        const int* __restrict__ fold)
 {
     __shared__ dev::F32Tile tile;
-    dev::pairs_f32_block<R, PX>(m, sh, z, gam, part, blockIdx.x, blockIdx.y, tile);
+    dev::pairs_f32_block<R, PX>(m, sh, z, gam, part, blockIdx.x, blockIdx.y, fold, tile);
 }
 
 // blockIdx.y = pass (0: tie column, 1: tie row); L threads per target
@@ -164,20 +168,20 @@ hipError_t launch_tune_init(const Mesh& m, double* z, double* gam, hipStream_t s
 }
 
 hipError_t launch_surface(const Mesh& m, const double* z, const double* w, double* gam, double* q,
-                          hipStream_t s)
+                          int* fold, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_surface, dim3(blocks_for(m.N)), dim3(kThreads), 0, s, m, z, w, gam, q);
+    hipLaunchKernelGGL(k_surface, dim3(blocks_for(m.N)), dim3(kThreads), 0, s, m, z, w, gam, q, fold);
     return hipGetLastError();
 }
 
 hipError_t launch_pairs_f64(const Mesh& m, const PairShape& sh, const double* z,
-                            const double* gam, double* part, hipStream_t s)
+                            const double* gam, double* part, const int* fold, hipStream_t s)
 {
     const dim3 grid((unsigned)(sh.px * sh.py), (unsigned)sh.splits);
     const dim3 blk(kThreads);
 #define ZM_F64_CASE(RR, CC)                                                                       \
     else if (sh.R == RR && sh.cx == CC)                                                           \
-        hipLaunchKernelGGL((k_pairs_f64f<RR, CC>), grid, blk, 0, s, m, sh, z, gam, part);
+        hipLaunchKernelGGL((k_pairs_f64f<RR, CC>), grid, blk, 0, s, m, sh, z, gam, part, fold);
     if (false) {}
     ZM_F64_CASE(1, 32) ZM_F64_CASE(1, 16) ZM_F64_CASE(1, 8) ZM_F64_CASE(2, 32)
     ZM_F64_CASE(2, 16) ZM_F64_CASE(2, 8) ZM_F64_CASE(4, 32) ZM_F64_CASE(4, 16)
@@ -188,13 +192,13 @@ hipError_t launch_pairs_f64(const Mesh& m, const PairShape& sh, const double* z,
 }
 
 hipError_t launch_pairs_f32(const Mesh& m, const PairShape& sh, const double* z,
-                            const double* gam, double* part, hipStream_t s)
+                            const double* gam, double* part, const int* fold, hipStream_t s)
 {
     const dim3 grid((unsigned)(sh.px * sh.py), (unsigned)sh.splits);
     const dim3 blk(kThreads);
 #define ZM_F32_CASE(RR, CC)                                                                       \
     else if (sh.R == RR && sh.cx == CC)                                                           \
-        hipLaunchKernelGGL((k_pairs_f32<RR, CC>), grid, blk, 0, s, m, sh, z, gam, part);
+        hipLaunchKernelGGL((k_pairs_f32<RR, CC>), grid, blk, 0, s, m, sh, z, gam, part, fold);
     if (false) {}
     ZM_F32_CASE(1, 32) ZM_F32_CASE(1, 16) ZM_F32_CASE(1, 8) ZM_F32_CASE(2, 32)
     ZM_F32_CASE(2, 16) ZM_F32_CASE(2, 8) ZM_F32_CASE(4, 32) ZM_F32_CASE(4, 16)

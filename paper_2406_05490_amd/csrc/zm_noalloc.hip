@@ -47,7 +47,7 @@ hipError_t scratch_of(int dev, char** out)
 }
 
 struct NoallocLayout {
-    size_t gam, q, tie, part, total;
+    size_t fold, gam, q, tie, part, total;
 };
 
 NoallocLayout noalloc_layout(size_t N, bool ties, int splits)
@@ -56,6 +56,9 @@ NoallocLayout noalloc_layout(size_t N, bool ties, int splits)
     NoallocLayout L;
     size_t o = 0;
     auto take = [&](size_t bytes) { size_t at = o; o = zm::align_up(o + bytes); return at; };
+    // fold statistics: zero when the array is loaded, and cleared again by
+    // the last surface workgroup of every call
+    L.fold = take(8 * sizeof(int));
     L.gam = take(3 * N * d);
     L.q = take(N * d);
     L.tie = take(ties ? 6 * N * d : 0);
@@ -129,10 +132,12 @@ extern "C" zm_status zm_br_velocity_noalloc(const zm_params* params, const doubl
     double* q = reinterpret_cast<double*>(base + L.q);
     double* tie = reinterpret_cast<double*>(base + L.tie);
     double* part = reinterpret_cast<double*>(base + L.part);
-    e = zm::launch_surface(m, d_z, d_w, gam, q, s);
+    int* fold = reinterpret_cast<int*>(base + L.fold);
+    e = zm::launch_surface(m, d_z, d_w, gam, q, fold, s);
     if (e == hipSuccess)
-        e = params->precision == ZM_FP32_PAIRS ? zm::launch_pairs_f32(m, sh, d_z, gam, part, s)
-                                               : zm::launch_pairs_f64(m, sh, d_z, gam, part, s);
+        e = params->precision == ZM_FP32_PAIRS
+                ? zm::launch_pairs_f32(m, sh, d_z, gam, part, fold, s)
+                : zm::launch_pairs_f64(m, sh, d_z, gam, part, fold, s);
     if (e == hipSuccess && ties) e = zm::launch_ties(m, d_z, gam, tie, s);
     if (e == hipSuccess)
         e = zm::launch_reduce(m, sh.splits, part, tie, q, d_z, d_u, nullptr, s, m.periodic != 0);

@@ -184,6 +184,9 @@ zm_status admit(zm_pool* P)
         if (e == hipSuccess)
             e = hipMemcpyAsync(y0 + 3 * N, r.src_w, 2 * N * sizeof(double),
                                hipMemcpyDeviceToDevice, P->stream);
+        // its fold statistics start cleared (the arena slot held another request)
+        if (e == hipSuccess)
+            e = hipMemsetAsync(P->ws + off + r.layout.fold, 0, 8 * sizeof(int), P->stream);
         if (e != hipSuccess) {
             P->arena.release(off, r.bytes);
             return phip(P, e, "admission copy");

@@ -106,7 +106,7 @@ std::vector<zm::PairShape> batch_candidates(const zm_params& p)
 // count of its size; then the descriptor table, the longest work list any
 // candidate set can produce, and the work counters.
 struct BatchTuneLayout {
-    std::vector<size_t> z, gam, part;
+    std::vector<size_t> z, gam, part, fold;
     size_t table = 0, items = 0, counters = 0, total = 0;
     size_t max_items = 0;
 };
@@ -128,6 +128,7 @@ BatchTuneLayout batch_tune_layout(const zm_params* params, int count)
         L.z.push_back(take(3 * N * d));
         L.gam.push_back(take(3 * N * d));
         L.part.push_back(take((size_t)max_splits * 3 * N * d));
+        L.fold.push_back(take(8 * sizeof(int)));
         L.max_items += max_items;
     }
     L.table = take(sizeof(zm::InstDesc) * count);
@@ -223,8 +224,8 @@ zm_status zm_autotune(const zm_params* params, void* d_workspace, size_t workspa
         for (const zm::PairShape& sh : candidates(*params)) {
             auto launch = [&] {
                 return params->precision == ZM_FP32_PAIRS
-                           ? zm::launch_pairs_f32(m, sh, z, gam, part, s)
-                           : zm::launch_pairs_f64(m, sh, z, gam, part, s);
+                           ? zm::launch_pairs_f32(m, sh, z, gam, part, nullptr, s)
+                           : zm::launch_pairs_f64(m, sh, z, gam, part, nullptr, s);
             };
             if (launch() != hipSuccess) { st = ZM_ERR_HIP; break; }   // warm-up
             float times[3];
@@ -303,9 +304,11 @@ zm_status zm_batch_autotune(const zm_params* params, int32_t count, void* d_work
         l.gam = L.gam[i];
         l.part = L.part[i];
         l.q = l.tie = l.u = l.V = L.z[i];   // not touched by the pair sweep
+        l.fold = L.fold[i];                 // cleared: the far forms are allowed
         const zm::Mesh m = zm::make_mesh(params[i]);
         if (zm::launch_tune_init(m, reinterpret_cast<double*>(ws + L.z[i]),
-                                 reinterpret_cast<double*>(ws + L.gam[i]), s) != hipSuccess)
+                                 reinterpret_cast<double*>(ws + L.gam[i]), s) != hipSuccess ||
+            hipMemsetAsync(ws + L.fold[i], 0, 8 * sizeof(int), s) != hipSuccess)
             return ZM_ERR_HIP;
     }
     hipEvent_t e0 = nullptr, e1 = nullptr;
