@@ -39,10 +39,14 @@
  *                                  high-precision brute force).
  *   zmo_rhs (linear part)       : pinned by the linear growth rate.
  *   zmo_rhs (|u|^2 and q/4 terms of the Bernoulli potential): the identity
- *                                  q = g^{ab} w_a w_b is pinned; the choice
- *                                  to keep |u|^2 and drop the mean-potential
- *                                  time derivative is a reading of the
- *                                  model -- parity unpinned.
+ *                                  q = g^{ab} w_a w_b is pinned, and so is the
+ *                                  formula as implemented (high-order
+ *                                  flat-sheet closed form of w_t, which a
+ *                                  dropped |u|^2 or a wrong q coefficient
+ *                                  fails); the choice to keep |u|^2 and drop
+ *                                  the mean-potential time derivative is a
+ *                                  reading of the model that no value from
+ *                                  the paper fixes -- parity unpinned.
  *   zmo_rk3_step                : pinned (amplification factor, order 3).
  *   cutoff BR (cutoff > 0)      : pinned (flat-sheet lattice-sum eigenvalue
  *                                  over the disc |rho| < rc, brute force,
