@@ -148,10 +148,10 @@ zm_status eval_velocity(zm_ctx* c, const double* z, const double* w, double* u, 
     if (c->cutoff) {
         int half = 0;
         e = timed(c, ZM_KERNEL_CELLS,
-                  [&] { return zm::launch_cut_cells(m, c->cut, z, gam, c->cb, &half, stream); });
+                  [&] { return zm::launch_cut_cells(m, c->cut, z, gam, c->cb, fold, &half, stream); });
         if (e != hipSuccess) return hip_fail(c, e, "cell binning launch");
         e = timed(c, ZM_KERNEL_PAIRS, [&] {
-            return zm::launch_cut_pairs(m, c->cut, c->cb, half, part, c->profiling, stream);
+            return zm::launch_cut_pairs(m, c->cut, c->cb, half, part, c->profiling, fold, stream);
         });
         if (e != hipSuccess) return hip_fail(c, e, "cutoff pair kernel launch");
         e = timed(c, ZM_KERNEL_REDUCE, [&] {
@@ -282,7 +282,7 @@ zm_status zm_create(zm_ctx** out, const zm_params* params, void* d_workspace,
     }
     // the surface kernel's fold statistics start cleared (each evaluation's
     // last surface workgroup clears them again for the next one)
-    e = hipMemsetAsync(c->ws + L.fold, 0, 8 * sizeof(int), c->stream);
+    e = hipMemsetAsync(c->ws + L.fold, 0, zm::kFoldWords * sizeof(int), c->stream);
     if (e != hipSuccess) {
         g_create_error = std::string("workspace clear: ") + hipGetErrorString(e);
         delete c;

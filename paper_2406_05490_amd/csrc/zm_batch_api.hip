@@ -270,7 +270,8 @@ zm_status zm_batch_create(zm_batch** out, const zm_params* params, int32_t count
                            hipMemcpyHostToDevice, b->stream);
     // every instance's fold statistics start cleared
     for (int i = 0; e == hipSuccess && i < count; ++i)
-        e = hipMemsetAsync(bases[i] + P.layouts[i].fold, 0, 8 * sizeof(int), b->stream);
+        e = hipMemsetAsync(bases[i] + P.layouts[i].fold, 0, zm::kFoldWords * sizeof(int),
+                           b->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
     if (e != hipSuccess) {
         g_batch_create_error = std::string("table upload: ") + hipGetErrorString(e);

@@ -27,7 +27,7 @@ struct InstDesc {
     double* tie;         // 2 x 3 planes
     double* u;           // 3 planes
     double* V;           // 1 plane
-    int* fold;           // tangent-map statistics and far-form flag (5 ints)
+    int* fold;           // tangent-map statistics and far-form flag (kFoldWords ints)
     int* flag;           // set to 1 by the update if this instance's state is not finite (may be NULL)
 };
 

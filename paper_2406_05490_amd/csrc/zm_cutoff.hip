@@ -23,6 +23,14 @@
 //                   count is involved, and a source no lane accepts skips
 //                   the kernel evaluation
 //
+// On a periodic sheet whose horizontal map alpha -> (x, y) is one-to-one
+// (the surface kernel's fold statistics: det J2 of one sign at every point)
+// the binning is skipped: every source a target can accept lies within
+// rc / sigma_min(J2) of it in the index torus, so each wave takes an 8 x 8
+// patch of targets and walks that index window of sources in index order
+// (k_cut_records, k_cut_win); the cell kernels then leave at once, and the
+// other way round on folded or free sheets.
+//
 // The inclusion test is evaluated exactly as the definition writes it
 // (r_a = (z_i,a - z_j,a) - S_a L_a, then r1*r1 + r2*r2 + r3*r3 < rc*rc, no
 // contraction), so every include / exclude decision is the same bit for bit
@@ -51,6 +59,18 @@ __host__ __device__ inline int cell_key(const CutGrid& g, int cx, int cy)
     return ((by * g.nb1 + bx) * g.B + ly) * g.B + lx;
 }
 
+// Whether this evaluation takes the index-window path: a periodic sheet whose
+// tangent map keeps one orientation everywhere (fold[7]: the signs det J2
+// took, bit 0 positive, bit 1 negative, bit 2 zero or not a number) and has
+// a positive sigma_min(J2)^2 (fold[5]).  Every kernel of either path reads
+// it and the other path's kernels leave at once.
+__device__ __forceinline__ bool window_path(const int* __restrict__ fold, int periodic)
+{
+    if (!periodic || fold == nullptr) return false;
+    const int sg = fold[7];
+    return (sg == 1 || sg == 2) && __int_as_float(fold[5]) > 0.f;
+}
+
 // Periodic grid: wrap count k (x - k L lies in the period cell [x0, x0 + L))
 // and the cell of the wrapped coordinate, clamped against rounding at the
 // cell edges.  Free sheet: k = 0 and the cell of x itself, clamped to the
@@ -77,8 +97,10 @@ __device__ inline void wrap_cell(bool periodic, double x, double x0, double L, d
 
 __global__ __launch_bounds__(kThreads) void k_cut_keys(Mesh m, CutGrid g, const double* __restrict__ z,
                                                        unsigned* __restrict__ keys,
-                                                       unsigned* __restrict__ vals)
+                                                       unsigned* __restrict__ vals,
+                                                       const int* __restrict__ fold)
 {
+    if (window_path(fold, g.periodic)) return;
     const int p = blockIdx.x * kThreads + threadIdx.x;
     if (p >= m.N) return;
     int kx, ky, cx, cy;
@@ -95,8 +117,10 @@ __global__ __launch_bounds__(kThreads) void k_cut_keys(Mesh m, CutGrid g, const 
 
 __global__ __launch_bounds__(kThreads) void k_sort_hist(const unsigned* __restrict__ keys, int n,
                                                         int shift, int seg,
-                                                        unsigned* __restrict__ hist)
+                                                        unsigned* __restrict__ hist,
+                                                        const int* __restrict__ fold, int periodic)
 {
+    if (window_path(fold, periodic)) return;
     __shared__ unsigned h[256];
     h[threadIdx.x] = 0;
     __syncthreads();
@@ -116,8 +140,11 @@ __global__ __launch_bounds__(kThreads) void k_sort_hist(const unsigned* __restri
 constexpr int kScanThreads = 1024;
 constexpr int kScanPer = 8;
 
-__global__ __launch_bounds__(kScanThreads) void k_sort_scan(unsigned* __restrict__ a, int total)
+__global__ __launch_bounds__(kScanThreads) void k_sort_scan(unsigned* __restrict__ a, int total,
+                                                            const int* __restrict__ fold,
+                                                            int periodic)
 {
+    if (window_path(fold, periodic)) return;
     __shared__ unsigned tile[kScanThreads * kScanPer];
     __shared__ unsigned s[kScanThreads];
     __shared__ unsigned carry;
@@ -156,8 +183,11 @@ __global__ __launch_bounds__(kThreads) void k_sort_scatter(const unsigned* __res
                                                            unsigned* __restrict__ kout,
                                                            unsigned* __restrict__ vout, int n,
                                                            int shift, int seg,
-                                                           const unsigned* __restrict__ offs)
+                                                           const unsigned* __restrict__ offs,
+                                                           const int* __restrict__ fold,
+                                                           int periodic)
 {
+    if (window_path(fold, periodic)) return;
     __shared__ unsigned base[256];
     __shared__ unsigned wcnt[kThreads / 64][256];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -196,8 +226,10 @@ __global__ __launch_bounds__(kThreads) void k_sort_scatter(const unsigned* __res
     }
 }
 
-__global__ __launch_bounds__(kThreads) void k_fill_int(int* __restrict__ a, int n, int v)
+__global__ __launch_bounds__(kThreads) void k_fill_int(int* __restrict__ a, int n, int v,
+                                                       const int* __restrict__ fold, int periodic)
 {
+    if (window_path(fold, periodic)) return;
     const int i = blockIdx.x * kThreads + threadIdx.x;
     if (i < n) a[i] = v;
 }
@@ -210,8 +242,10 @@ __global__ void k_fill_u64(unsigned long long* __restrict__ a, int n)
 __global__ __launch_bounds__(kThreads) void k_cut_bounds(CutGrid g, int n,
                                                          const unsigned* __restrict__ ks,
                                                          int* __restrict__ start, int* __restrict__ end,
-                                                         int* __restrict__ bstart, int* __restrict__ bend)
+                                                         int* __restrict__ bstart, int* __restrict__ bend,
+                                                         const int* __restrict__ fold)
 {
+    if (window_path(fold, g.periodic)) return;
     const int i = blockIdx.x * kThreads + threadIdx.x;
     if (i >= n) return;
     const unsigned bb = (unsigned)(g.B * g.B);
@@ -226,8 +260,10 @@ __global__ __launch_bounds__(kThreads) void k_cut_gather(Mesh m, CutGrid g, cons
                                                          const double* __restrict__ gam,
                                                          const unsigned* __restrict__ order,
                                                          double* __restrict__ src,
-                                                         int* __restrict__ kflag)
+                                                         int* __restrict__ kflag,
+                                                         const int* __restrict__ fold)
 {
+    if (window_path(fold, g.periodic)) return;
     const int i = blockIdx.x * kThreads + threadIdx.x;
     const int N = m.N;
     if (i >= N) return;
@@ -282,9 +318,14 @@ constexpr int kCutTargetsPerLane = ZM_CUT_TARGETS_PER_LANE;
 //                  (d - 0 L is d bit for bit);
 //   kShiftUniform  wrap counts all 0 but the cell is wrapped: S = (wx, wy)
 //                  for every pair, S_a L_a formed once;
-//   kShiftPerLane  S = k_i + w - k_j per pair.
-// All three give the same r as the definition's r_a = d_a - S_a L_a.
-enum { kShiftNone = 0, kShiftUniform = 1, kShiftPerLane = 2 };
+//   kShiftPerLane  S = k_i + w - k_j per pair;
+//   kShiftExact    S = the integer nearest to d / L per pair (the definition
+//                  itself; d * (1 / L) in place of d / L can only change S
+//                  where d / L is within rounding of a half-integer, and
+//                  then both images lie about L/2 > rc away and are
+//                  rejected).
+// All give the same r as the definition's r_a = d_a - S_a L_a.
+enum { kShiftNone = 0, kShiftUniform = 1, kShiftPerLane = 2, kShiftExact = 3 };
 
 struct CutTarget {
     double x, y, z;     // target position
@@ -327,6 +368,10 @@ __device__ __forceinline__ void cut_pair(const Mesh& m, const CutGrid& g, const 
         } else if (SHIFT == kShiftUniform) {
             r1[q] = d1[q] - SL1;
             r2[q] = d2 - SL2;
+        } else if (SHIFT == kShiftExact) {
+            const double S1 = rint(d1[q] * g.iL1), S2 = rint(d2 * g.iL2);
+            r1[q] = d1[q] - S1 * g.L1;
+            r2[q] = d2 - S2 * g.L2;
         } else {
             const double S1 = t[q].Kx - b.k1, S2 = t[q].Ky - b.k2;
             r1[q] = d1[q] - S1 * g.L1;
@@ -399,8 +444,10 @@ __global__ __launch_bounds__(kCutThreads) void k_cut_pairs(Mesh m, CutGrid g,
                                                            const int* __restrict__ kflag,
                                                            const unsigned* __restrict__ order,
                                                            double* __restrict__ part,
-                                                           unsigned long long* __restrict__ counts)
+                                                           unsigned long long* __restrict__ counts,
+                                                           const int* __restrict__ fold)
 {
+    if (window_path(fold, g.periodic)) return;   // uniform: the index-window path runs instead
     constexpr int CH = kCutThreads * TR;
     // Grid order as launched (block fastest), so that the 8 XCDs, which
     // take workgroups round robin, share every region of the mesh.  Giving
@@ -488,6 +535,134 @@ __global__ __launch_bounds__(kCutThreads) void k_cut_pairs(Mesh m, CutGrid g,
     }
 }
 
+// ---- index-window path ----------------------------------------------------
+
+// Records (x, y, z, g1, g2, g3, 0, 0) in index order.
+__global__ __launch_bounds__(kThreads) void k_cut_records(Mesh m, CutGrid g,
+                                                          const double* __restrict__ z,
+                                                          const double* __restrict__ gam,
+                                                          double* __restrict__ src,
+                                                          const int* __restrict__ fold)
+{
+    if (!window_path(fold, g.periodic)) return;
+    const int p = blockIdx.x * kThreads + threadIdx.x;
+    const int N = m.N;
+    if (p >= N) return;
+    double* r = src + (size_t)p * 8;
+    r[0] = z[p];
+    r[1] = z[N + p];
+    r[2] = z[2 * N + p];
+    r[3] = gam[p];
+    r[4] = gam[N + p];
+    r[5] = gam[2 * N + p];
+    r[6] = 0.0;
+    r[7] = 0.0;
+}
+
+// One wave per (8 x 8 patch of targets, row group).  Lane = one target
+// (t1, t2) = (c0 + lane % 8, r0 + lane / 8).  With sigma_min = min
+// sigma_min(J2) over the sheet (fold[5]), a source whose nearest image lies
+// within rc of a target is less than Ra = rc / sigma_min from it in alpha
+// (the index torus scaled by h); the window is every source whose alpha
+// distance to the patch's rectangle is at most Ra (plus a margin of 2% and
+// one spacing for the discrete tangents), rows of it split over the slots.
+// Along a window row the sources of one period copy (unwrapped column ju1 =
+// j1 + w1 n1, row ju2 = j2 + w2 n2) have image shift S = (w1, w2) whenever
+// sigma_max(J3) (fold[6]) times the largest alpha offset between a target
+// and a window source stays below 0.45 min(L1, L2): |z_i - z_j - w L| is at
+// most that; otherwise S is formed per pair from its definition.
+template <bool COUNT>
+__global__ __launch_bounds__(kCutThreads) void k_cut_win(Mesh m, CutGrid g,
+                                                         const double* __restrict__ src,
+                                                         double* __restrict__ part,
+                                                         unsigned long long* __restrict__ counts,
+                                                         const int* __restrict__ fold)
+{
+    if (!window_path(fold, g.periodic)) return;   // uniform: the cell path runs instead
+    const int n1 = m.n1, n2 = m.n2, N = m.N;
+    const int pc = (n1 + 7) / 8;
+    const int c0 = (int)(blockIdx.x % pc) * 8, r0 = (int)(blockIdx.x / pc) * 8;
+    const int slot = blockIdx.y;
+    const int lane = threadIdx.x;
+    const int t1 = c0 + (lane & 7), t2 = r0 + (lane >> 3);
+
+    CutTarget t[1];
+    t[0].active = t1 < n1 && t2 < n2;
+    t[0].amask = __builtin_amdgcn_ballot_w64(t[0].active);
+    const int p = t[0].active ? t2 * n1 + t1 : r0 * n1 + c0;   // idle lanes hold a real target
+    const double* tr = src + (size_t)p * 8;
+    t[0].x = tr[0];
+    t[0].y = tr[1];
+    t[0].z = tr[2];
+    t[0].Kx = t[0].Ky = 0.0;
+
+    // window radii (index units) and the image-shift bound
+    const double smin = sqrt((double)__int_as_float(fold[5]));
+    const double smax = sqrt((double)__int_as_float(fold[6]));
+    const double Ra = sqrt(g.rc2) * 1.02 / smin;
+    const int W2 = (int)ceil(Ra / m.h2) + 1;
+    const int W1 = (int)ceil(Ra / m.h1) + 1;
+    const double dmax = sqrt((double)(W1 + 8) * (W1 + 8) * m.h1 * m.h1 +
+                             (double)(W2 + 8) * (W2 + 8) * m.h2 * m.h2);
+    const bool by_seams = smax * dmax < 0.45 * fmin(g.L1, g.L2);
+    int rlo = r0 - W2, nrows = 8 + 2 * W2;
+    // a window taller than the period takes every row once; a row's
+    // distance from the patch is then its distance in the torus
+    const bool all_rows = nrows >= n2;
+    if (all_rows) nrows = n2;
+    const int per = (nrows + g.slots - 1) / g.slots;
+    const int ra = rlo + slot * per, rb = min(rlo + nrows, ra + per);
+    const double Ra2 = Ra * Ra;
+    auto row_gap = [&](int ju) { return ju < r0 ? r0 - ju : (ju > r0 + 7 ? ju - (r0 + 7) : 0); };
+
+    unsigned long long tested = 0, accepted = 0;
+    double acc[1][3] = {{0.0, 0.0, 0.0}};
+    for (int ju2 = ra; ju2 < rb; ++ju2) {
+        const int w2 = floordiv(ju2, n2), j2 = ju2 - w2 * n2;
+        int dy = row_gap(ju2);
+        if (all_rows) dy = min(dy, min(row_gap(ju2 + n2), row_gap(ju2 - n2)));
+        const double ry = dy * m.h2;
+        const double half = Ra2 > ry * ry ? sqrt(Ra2 - ry * ry) : 0.0;
+        const int dxm = (int)ceil(half / m.h1) + 1;
+        int clo = c0 - dxm, ncols = 8 + 2 * dxm;
+        if (ncols > n1) ncols = n1;               // every column once
+        // the row's columns [clo, clo + ncols) in pieces of one period copy
+        int a = clo;
+        const int e = clo + ncols;
+        while (a < e) {
+            const int w1 = floordiv(a, n1);
+            const int b = min(e, (w1 + 1) * n1);
+            const int s0 = j2 * n1 + (a - w1 * n1), s1 = s0 + (b - a);
+            if (!by_seams)
+                cut_cell<kShiftExact, COUNT, 1>(m, g, src, s0, s1, t, 0.0, 0.0, acc, tested,
+                                                accepted);
+            else if (w1 == 0 && w2 == 0)
+                cut_cell<kShiftNone, COUNT, 1>(m, g, src, s0, s1, t, 0.0, 0.0, acc, tested,
+                                               accepted);
+            else
+                cut_cell<kShiftUniform, COUNT, 1>(m, g, src, s0, s1, t, (double)w1 * g.L1,
+                                                  (double)w2 * g.L2, acc, tested, accepted);
+            a = b;
+        }
+    }
+    if (t[0].active) {
+        double* out = part + (size_t)slot * 3 * N;
+        out[p] = acc[0][0];
+        out[N + p] = acc[0][1];
+        out[2 * N + p] = acc[0][2];
+    }
+    if (COUNT) {
+        for (int off = 32; off > 0; off >>= 1) {
+            tested += __shfl_xor(tested, off, 64);
+            accepted += __shfl_xor(accepted, off, 64);
+        }
+        if (lane == 0) {
+            atomicAdd(&counts[0], tested);
+            atomicAdd(&counts[1], accepted);
+        }
+    }
+}
+
 inline unsigned grid_for(long n) { return (unsigned)((n + kThreads - 1) / kThreads); }
 
 }  // namespace
@@ -525,52 +700,66 @@ CutGrid make_cut_grid(int n1, int n2, double L1, double L2, double rc, bool peri
     g.L1 = L1;
     g.L2 = L2;
     g.rc2 = rc * rc;
+    g.iL1 = 1.0 / L1;
+    g.iL2 = 1.0 / L2;
     return g;
 }
 
 hipError_t launch_cut_cells(const Mesh& m, const CutGrid& g, const double* z, const double* gam,
-                            const CutBuffers& b, int* sorted_half, hipStream_t s)
+                            const CutBuffers& b, const int* fold, int* sorted_half, hipStream_t s)
 {
     const int N = m.N;
     const dim3 blk(kThreads);
-    hipLaunchKernelGGL(k_cut_keys, dim3(grid_for(N)), blk, 0, s, m, g, z, b.keys[0], b.vals[0]);
+    const int per = g.periodic;
+    hipLaunchKernelGGL(k_cut_records, dim3(grid_for(N)), blk, 0, s, m, g, z, gam, b.src, fold);
+    hipLaunchKernelGGL(k_cut_keys, dim3(grid_for(N)), blk, 0, s, m, g, z, b.keys[0], b.vals[0], fold);
     const int G = g.sort_blocks;
     const int seg = ((N + G - 1) / G + kThreads - 1) / kThreads * kThreads;
     int cur = 0;
     for (int shift = 0; shift < g.key_bits; shift += 8) {
-        hipLaunchKernelGGL(k_sort_hist, dim3(G), blk, 0, s, b.keys[cur], N, shift, seg, b.hist);
-        hipLaunchKernelGGL(k_sort_scan, dim3(1), dim3(kScanThreads), 0, s, b.hist, 256 * G);
+        hipLaunchKernelGGL(k_sort_hist, dim3(G), blk, 0, s, b.keys[cur], N, shift, seg, b.hist, fold,
+                           per);
+        hipLaunchKernelGGL(k_sort_scan, dim3(1), dim3(kScanThreads), 0, s, b.hist, 256 * G, fold, per);
         hipLaunchKernelGGL(k_sort_scatter, dim3(G), blk, 0, s, b.keys[cur], b.vals[cur],
-                           b.keys[cur ^ 1], b.vals[cur ^ 1], N, shift, seg, b.hist);
+                           b.keys[cur ^ 1], b.vals[cur ^ 1], N, shift, seg, b.hist, fold, per);
         cur ^= 1;
     }
     const int nblk = g.nb1 * g.nb2;
-    hipLaunchKernelGGL(k_fill_int, dim3(grid_for(g.nkeys)), blk, 0, s, b.start, g.nkeys, 0);
-    hipLaunchKernelGGL(k_fill_int, dim3(grid_for(g.nkeys)), blk, 0, s, b.end, g.nkeys, 0);
-    hipLaunchKernelGGL(k_fill_int, dim3(grid_for(nblk)), blk, 0, s, b.bstart, nblk, 0);
-    hipLaunchKernelGGL(k_fill_int, dim3(grid_for(nblk)), blk, 0, s, b.bend, nblk, 0);
-    hipLaunchKernelGGL(k_fill_int, dim3(grid_for(g.nkeys)), blk, 0, s, b.kflag, g.nkeys, 0);
+    hipLaunchKernelGGL(k_fill_int, dim3(grid_for(g.nkeys)), blk, 0, s, b.start, g.nkeys, 0, fold, per);
+    hipLaunchKernelGGL(k_fill_int, dim3(grid_for(g.nkeys)), blk, 0, s, b.end, g.nkeys, 0, fold, per);
+    hipLaunchKernelGGL(k_fill_int, dim3(grid_for(nblk)), blk, 0, s, b.bstart, nblk, 0, fold, per);
+    hipLaunchKernelGGL(k_fill_int, dim3(grid_for(nblk)), blk, 0, s, b.bend, nblk, 0, fold, per);
+    hipLaunchKernelGGL(k_fill_int, dim3(grid_for(g.nkeys)), blk, 0, s, b.kflag, g.nkeys, 0, fold, per);
     hipLaunchKernelGGL(k_cut_bounds, dim3(grid_for(N)), blk, 0, s, g, N, b.keys[cur], b.start,
-                       b.end, b.bstart, b.bend);
+                       b.end, b.bstart, b.bend, fold);
     hipLaunchKernelGGL(k_cut_gather, dim3(grid_for(N)), blk, 0, s, m, g, z, gam, b.vals[cur], b.src,
-                       b.kflag);
+                       b.kflag, fold);
     *sorted_half = cur;
     return hipGetLastError();
 }
 
 hipError_t launch_cut_pairs(const Mesh& m, const CutGrid& g, const CutBuffers& b,
-                            int sorted_half, double* part, bool count, hipStream_t s)
+                            int sorted_half, double* part, bool count, const int* fold,
+                            hipStream_t s)
 {
     const dim3 grid(g.nb1 * g.nb2, g.slots, g.chunks);
     const unsigned* order = b.vals[sorted_half];
     if (count)
         hipLaunchKernelGGL((k_cut_pairs<true, kCutTargetsPerLane>), grid, dim3(kCutThreads), 0, s, m,
                            g, b.src, b.start, b.end, b.bstart, b.bend, b.kflag, order, part,
-                           b.counts);
+                           b.counts, fold);
     else
         hipLaunchKernelGGL((k_cut_pairs<false, kCutTargetsPerLane>), grid, dim3(kCutThreads), 0, s,
                            m, g, b.src, b.start, b.end, b.bstart, b.bend, b.kflag, order, part,
-                           b.counts);
+                           b.counts, fold);
+    // the index-window path (its workgroups leave at once on the cell path)
+    const dim3 wgrid((unsigned)(((m.n1 + 7) / 8) * ((m.n2 + 7) / 8)), (unsigned)g.slots);
+    if (count)
+        hipLaunchKernelGGL((k_cut_win<true>), wgrid, dim3(kCutThreads), 0, s, m, g, b.src, part,
+                           b.counts, fold);
+    else
+        hipLaunchKernelGGL((k_cut_win<false>), wgrid, dim3(kCutThreads), 0, s, m, g, b.src, part,
+                           b.counts, fold);
     return hipGetLastError();
 }
 

@@ -174,7 +174,10 @@ __device__ __forceinline__ void tangents_at(const Mesh& m, int p, const double* 
 // fold[2]: signs of det J2 seen (bits as in fold_stat)
 // fold[3]: workgroups done
 // fold[4]: 1 = the far forms are off for this evaluation (read by the pair kernels)
-constexpr int kFoldWords = 5;
+// fold[5], fold[6], fold[7]: this evaluation's min sigma_min(J2)^2 and max
+//          sigma_max(J3)^2 (float bits) and det J2 signs, kept for the cutoff
+//          solver's index windows
+// (kFoldWords = 8 ints in all, zm_internal.h)
 constexpr float kFoldMaxStretch2 = 16.f;   // (sigma_max / sigma_min)^2 allowed
 
 struct FoldStat {
@@ -223,6 +226,9 @@ __device__ __forceinline__ void fold_gather(FoldStat st, int* __restrict__ fold,
     const int sg = atomicAdd(&fold[2], 0);
     const bool off = (sg & 3) == 3 || (sg & 4) != 0 || !(smax2 <= kFoldMaxStretch2 * smin2);
     atomicExch(&fold[4], off ? 1 : 0);
+    atomicExch(&fold[5], __float_as_int(smin2));
+    atomicExch(&fold[6], __float_as_int(smax2));
+    atomicExch(&fold[7], sg);
     atomicExch(&fold[0], 0);
     atomicExch(&fold[1], 0);
     atomicExch(&fold[2], 0);

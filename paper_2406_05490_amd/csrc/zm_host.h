@@ -74,7 +74,7 @@ inline Layout make_layout(const zm_params& p, const zm::PairShape& sh)
     L.u = take(3 * N * d);
     L.V = take(N * d);
     L.flag = take(sizeof(int));
-    L.fold = take(8 * sizeof(int));
+    L.fold = take(kFoldWords * sizeof(int));
     const size_t u4 = sizeof(unsigned);
     L.cut_keys[0] = take(cut ? N * u4 : 0);
     L.cut_keys[1] = take(cut ? N * u4 : 0);

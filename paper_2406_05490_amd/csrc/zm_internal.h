@@ -7,6 +7,10 @@
 
 namespace zm {
 
+// Ints of the sheet's fold statistics (tangent-map bounds gathered by the
+// surface kernel, read by the pair kernels and the cutoff solver).
+constexpr int kFoldWords = 8;
+
 // Mesh geometry and model constants, passed by value to every kernel.
 struct Mesh {
     int n1, n2;          // points per axis
@@ -104,6 +108,7 @@ struct CutGrid {
     double L1, L2;
     double cw1, cw2;     // cell sides
     double rc2;          // rc * rc
+    double iL1, iL2;     // 1 / L1, 1 / L2
 };
 
 CutGrid make_cut_grid(int n1, int n2, double L1, double L2, double rc, bool periodic);
@@ -125,8 +130,12 @@ struct CutBuffers {
 // Bin every point into its cell and sort the points by cell (stable), then
 // gather positions, source strengths and wrap counts in sorted order.
 // Returns the index of the buffer pair holding the sorted (key, point).
+// fold: the sheet statistics of this evaluation (launch_surface); when they
+// allow the index-window path (a periodic sheet whose horizontal map is
+// one-to-one) these kernels leave at once and the records are written in
+// index order instead.
 hipError_t launch_cut_cells(const Mesh& m, const CutGrid& g, const double* z, const double* gam,
-                            const CutBuffers& b, int* sorted_half, hipStream_t s);
+                            const CutBuffers& b, const int* fold, int* sorted_half, hipStream_t s);
 
 // ---- low-order model (zm_lowfft.hip) ----------------------------------------
 
@@ -150,10 +159,12 @@ hipError_t launch_low_velocity(const Mesh& m, const double* z, const double* w,
 // Zero the two pair counters (a kernel, so it may sit in a captured graph).
 hipError_t launch_cut_count_reset(unsigned long long* counts, hipStream_t s);
 
-// part[slot][3][N] = unscaled cutoff sums per target and neighbour row.
+// part[slot][3][N] = unscaled cutoff sums per target and slot (neighbour row
+// of the cell path, or row group of the index-window path).
 // count != 0: also add the tested / accepted pair counts to b.counts.
 hipError_t launch_cut_pairs(const Mesh& m, const CutGrid& g, const CutBuffers& b,
-                            int sorted_half, double* part, bool count, hipStream_t s);
+                            int sorted_half, double* part, bool count, const int* fold,
+                            hipStream_t s);
 
 // F = (u, D V + nu Lap w) at state ys, then
 //   stage 0: out = ys + dt F

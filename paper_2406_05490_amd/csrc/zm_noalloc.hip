@@ -58,7 +58,7 @@ NoallocLayout noalloc_layout(size_t N, bool ties, int splits)
     auto take = [&](size_t bytes) { size_t at = o; o = zm::align_up(o + bytes); return at; };
     // fold statistics: zero when the array is loaded, and cleared again by
     // the last surface workgroup of every call
-    L.fold = take(8 * sizeof(int));
+    L.fold = take(zm::kFoldWords * sizeof(int));
     L.gam = take(3 * N * d);
     L.q = take(N * d);
     L.tie = take(ties ? 6 * N * d : 0);

@@ -186,7 +186,8 @@ zm_status admit(zm_pool* P)
                                hipMemcpyDeviceToDevice, P->stream);
         // its fold statistics start cleared (the arena slot held another request)
         if (e == hipSuccess)
-            e = hipMemsetAsync(P->ws + off + r.layout.fold, 0, 8 * sizeof(int), P->stream);
+            e = hipMemsetAsync(P->ws + off + r.layout.fold, 0, zm::kFoldWords * sizeof(int),
+                               P->stream);
         if (e != hipSuccess) {
             P->arena.release(off, r.bytes);
             return phip(P, e, "admission copy");

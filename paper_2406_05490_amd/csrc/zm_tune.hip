@@ -128,7 +128,7 @@ BatchTuneLayout batch_tune_layout(const zm_params* params, int count)
         L.z.push_back(take(3 * N * d));
         L.gam.push_back(take(3 * N * d));
         L.part.push_back(take((size_t)max_splits * 3 * N * d));
-        L.fold.push_back(take(8 * sizeof(int)));
+        L.fold.push_back(take(zm::kFoldWords * sizeof(int)));
         L.max_items += max_items;
     }
     L.table = take(sizeof(zm::InstDesc) * count);
@@ -308,7 +308,7 @@ zm_status zm_batch_autotune(const zm_params* params, int32_t count, void* d_work
         const zm::Mesh m = zm::make_mesh(params[i]);
         if (zm::launch_tune_init(m, reinterpret_cast<double*>(ws + L.z[i]),
                                  reinterpret_cast<double*>(ws + L.gam[i]), s) != hipSuccess ||
-            hipMemsetAsync(ws + L.fold[i], 0, 8 * sizeof(int), s) != hipSuccess)
+            hipMemsetAsync(ws + L.fold[i], 0, zm::kFoldWords * sizeof(int), s) != hipSuccess)
             return ZM_ERR_HIP;
     }
     hipEvent_t e0 = nullptr, e1 = nullptr;

@@ -215,3 +215,31 @@ def test_cutoff_below_the_spacing_is_exactly_zero(gpu):
     z, w = drifted_state(n, n, 14)
     u, ctx = gpu_br(p, z, w, gpu)
     assert np.all(u == 0.0)
+
+
+@pytest.mark.parametrize("kind,n1,n2,rc", [
+    ("smooth", 64, 48, 0.3),      # index window, seam counts as image shifts
+    ("sheared", 40, 40, 0.4),     # strong horizontal shear: larger window, per-pair images
+    ("folded", 48, 64, 0.3),      # overturned rows: cell grid
+])
+def test_cutoff_window_and_cell_paths_match_oracle(gpu, kind, n1, n2, rc):
+    """A periodic sheet whose horizontal map stays one-to-one takes the
+    index-window path (no binning), a folded one the cell grid; either way the
+    velocity meets the FP64 bar and the accepted-pair count is the
+    definition's exactly."""
+    A1, A2 = rr.grid(n1, n2)
+    if kind == "folded":
+        z = np.stack([A1, A2 + (1.5 / math.pi) * np.sin(math.pi * A2),
+                      0.02 * np.cos(math.pi * A2)]).reshape(3, -1)
+    elif kind == "sheared":
+        z = np.stack([A1 + 0.6 * np.sin(math.pi * A2) + 0.3, A2 - 0.2,
+                      0.1 * np.cos(math.pi * A1)]).reshape(3, -1)
+    else:
+        z, _ = drifted_state(n1, n2, 11)
+    w = rr.synthetic_vorticity(n1, n2, seed=12)
+    p = params(n1, n2, rc)
+    u, ctx = gpu_br(p, z, w, gpu, count=True)
+    assert relerr(u, oracle.br_velocity(oparams(p), z, w)) < TOL64, kind
+    info = ctx.cutoff_info()
+    assert info.pairs_accepted == accepted_pairs(z, rc), kind
+    assert info.pairs_tested >= info.pairs_accepted
