@@ -151,11 +151,12 @@ zm_status eval_velocity(zm_ctx* c, const double* z, const double* w, double* u, 
                   [&] { return zm::launch_cut_cells(m, c->cut, z, gam, c->cb, fold, &half, stream); });
         if (e != hipSuccess) return hip_fail(c, e, "cell binning launch");
         e = timed(c, ZM_KERNEL_PAIRS, [&] {
-            return zm::launch_cut_pairs(m, c->cut, c->cb, half, part, c->profiling, fold, stream);
+            return zm::launch_cut_pairs(m, c->cut, z, gam, c->cb, half, part, c->profiling, fold,
+                                        stream);
         });
         if (e != hipSuccess) return hip_fail(c, e, "cutoff pair kernel launch");
         e = timed(c, ZM_KERNEL_REDUCE, [&] {
-            return zm::launch_reduce(m, c->cut.slots, part, tie, q, z, u, c->medium ? nullptr : V,
+            return zm::launch_reduce(m, c->cut.planes, part, tie, q, z, u, c->medium ? nullptr : V,
                                      stream, false);
         });
         if (e != hipSuccess) return hip_fail(c, e, "reduce kernel launch");
@@ -505,7 +506,7 @@ zm_status zm_get_launch_info(const zm_ctx* c, zm_launch_info* out)
         out->targets_per_lane = 1;
         out->patch_cols = g.B;   // in cells
         out->patch_rows = g.B;
-        out->source_splits = g.slots;
+        out->source_splits = g.planes;
         out->workgroups = g.nb1 * g.nb2 * g.slots;
         out->threads_per_group = 256;
         out->pairs_per_eval = (int64_t)c->mesh.N * (int64_t)c->mesh.N;
@@ -551,7 +552,7 @@ zm_status zm_cutoff_info_get(zm_ctx* c, zm_cutoff_info* out)
     out->cells2 = c->cut.nc2;
     out->cells_per_cutoff = c->cut.m;
     out->block_cells = c->cut.B;
-    out->slots = c->cut.slots;
+    out->slots = c->cut.planes;
     out->reserved = 0;
     out->pairs_tested = (int64_t)h[0];
     out->pairs_accepted = (int64_t)h[1];

@@ -26,10 +26,14 @@
 // On a periodic sheet whose horizontal map alpha -> (x, y) is one-to-one
 // (the surface kernel's fold statistics: det J2 of one sign at every point)
 // the binning is skipped: every source a target can accept lies within
-// rc / sigma_min(J2) of it in the index torus, so each wave takes an 8 x 8
-// patch of targets and walks that index window of sources in index order
-// (k_cut_records, k_cut_win); the cell kernels then leave at once, and the
-// other way round on folded or free sheets.
+// rc / sigma_min(J2) of it in the index torus.  Where that window fits the
+// period, k_cut_sten walks it per target: offsets shared by all lanes, each
+// lane's source read from a band of the mesh staged in LDS, so a target
+// tests about its own window (1.1 - 1.2 times the pairs it accepts on the
+// paper's workloads).  A larger window falls back to the patch window
+// (k_cut_records, k_cut_win: one 8 x 8 patch of targets per wave,
+// sources read with scalar loads).  The kernels of the paths not taken
+// leave at once; their launches are capped at a few thousand workgroups.
 //
 // The inclusion test is evaluated exactly as the definition writes it
 // (r_a = (z_i,a - z_j,a) - S_a L_a, then r1*r1 + r2*r2 + r3*r3 < rc*rc, no
@@ -299,6 +303,7 @@ __global__ __launch_bounds__(kThreads) void k_cut_gather(Mesh m, CutGrid g, cons
 // skipped, every wrap count is 0 and S = 0, so r = z_i - z_j exactly (the
 // wave of a row outside the grid still writes its zero partial sums).
 constexpr int kCutThreads = 64;
+constexpr long kCutMaxGroups = 16384;   // workgroups of a cell-path or patch-window launch at most
 
 // Targets per lane of the pair kernel: every scalar-loaded source record
 // serves 64 TR targets, each slot of 64 skipping on its own.  TR = 2, 3, 4
@@ -380,11 +385,11 @@ __device__ __forceinline__ void cut_pair(const Mesh& m, const CutGrid& g, const 
         r3[q] = t[q].z - b.z;
         dd[q] = r1[q] * r1[q] + r2[q] * r2[q] + r3[q] * r3[q];
         in[q] = dd[q] < g.rc2;
-        if (COUNT) {
-            tested += t[q].active ? 1 : 0;
-            accepted += (t[q].active && in[q]) ? 1 : 0;
-        }
         any[q] = __builtin_amdgcn_ballot_w64(in[q]) & t[q].amask;
+        if (COUNT) {   // whole-wave counts (scalar work, the same in every lane)
+            tested += (unsigned long long)__popcll(t[q].amask);
+            accepted += (unsigned long long)__popcll(any[q]);
+        }
     }
 #pragma unroll
     for (int q = 0; q < TR; ++q) {
@@ -453,81 +458,83 @@ __global__ __launch_bounds__(kCutThreads) void k_cut_pairs(Mesh m, CutGrid g,
     // take workgroups round robin, share every region of the mesh.  Giving
     // each XCD a contiguous range of blocks instead (neighbouring blocks read
     // mostly the same cells) measured 7% slower at 768^2 and 15% at 512^2.
-    const int blk = blockIdx.x, row = blockIdx.y, zc = blockIdx.z;
-    const int T0 = bstart[blk], T1 = bend[blk];
-    if (T0 + zc * CH >= T1) return;   // nothing left: uniform
     const int N = m.N;
     const int lane = threadIdx.x;
-    const int bx = blk % g.nb1, by = blk / g.nb1;
-    const int cy_raw = by * g.B - g.m + row;
-    const int wy = floordiv(cy_raw, g.nc2), cy = cy_raw - wy * g.nc2;
-    const bool row_in = g.periodic || wy == 0;
+    const int nblk = g.nb1 * g.nb2;
+    const long items = (long)nblk * g.slots * g.chunks;
     unsigned long long tested = 0, accepted = 0;
+    // items (block, row, chunk), block fastest, strided over a capped grid
+    for (long it = blockIdx.x; it < items; it += gridDim.x) {
+        const int blk = (int)(it % nblk), row = (int)(it / nblk % g.slots);
+        const int zc = (int)(it / ((long)nblk * g.slots));
+        const int T0 = bstart[blk], T1 = bend[blk];
+        if (T0 + zc * CH >= T1) continue;   // nothing left: uniform
+        const int bx = blk % g.nb1, by = blk / g.nb1;
+        const int cy_raw = by * g.B - g.m + row;
+        const int wy = floordiv(cy_raw, g.nc2), cy = cy_raw - wy * g.nc2;
+        const bool row_in = g.periodic || wy == 0;
 
-    // chunks zc, zc + chunks, ...
-    for (int t0 = T0 + zc * CH; t0 < T1; t0 += g.chunks * CH) {
-        CutTarget t[TR];
-        double kxi[TR], kyi[TR];
-        bool any_k = false;
+        // chunks zc, zc + chunks, ...
+        for (int t0 = T0 + zc * CH; t0 < T1; t0 += g.chunks * CH) {
+            CutTarget t[TR];
+            double kxi[TR], kyi[TR];
+            bool any_k = false;
 #pragma unroll
-        for (int q = 0; q < TR; ++q) {
-            const int i = t0 + lane + kCutThreads * q;
-            t[q].active = i < T1;
-            t[q].amask = __builtin_amdgcn_ballot_w64(t[q].active);
-            const double* ti = src + (size_t)(t[q].active ? i : T0) * 8;
-            t[q].x = ti[0];
-            t[q].y = ti[1];
-            t[q].z = ti[2];
-            kxi[q] = ti[6];
-            kyi[q] = ti[7];
-            any_k = any_k || kxi[q] != 0.0 || kyi[q] != 0.0;
-        }
-        // every target of the wave unwrapped (inactive slots hold a real target of the block)
-        const bool targets_k0 = __builtin_amdgcn_ballot_w64(any_k) == 0ull;
-        double acc[TR][3];
+            for (int q = 0; q < TR; ++q) {
+                const int i = t0 + lane + kCutThreads * q;
+                t[q].active = i < T1;
+                t[q].amask = __builtin_amdgcn_ballot_w64(t[q].active);
+                const double* ti = src + (size_t)(t[q].active ? i : T0) * 8;
+                t[q].x = ti[0];
+                t[q].y = ti[1];
+                t[q].z = ti[2];
+                kxi[q] = ti[6];
+                kyi[q] = ti[7];
+                any_k = any_k || kxi[q] != 0.0 || kyi[q] != 0.0;
+            }
+            // every target of the wave unwrapped (inactive slots hold a real target of the block)
+            const bool targets_k0 = __builtin_amdgcn_ballot_w64(any_k) == 0ull;
+            double acc[TR][3];
 #pragma unroll
-        for (int q = 0; q < TR; ++q) acc[q][0] = acc[q][1] = acc[q][2] = 0.0;
-        for (int col = 0; col < g.slots; ++col) {
-            const int cx_raw = bx * g.B - g.m + col;
-            const int wx = floordiv(cx_raw, g.nc1), cx = cx_raw - wx * g.nc1;
-            if (!row_in || (!g.periodic && wx != 0)) continue;   // wave-uniform
-            const int key = cell_key(g, cx, cy);
-            const int s0 = start[key], s1 = end[key];
-            if (targets_k0 && kflag[key] == 0) {
-                if (wx == 0 && wy == 0) {
-                    cut_cell<kShiftNone, COUNT, TR>(m, g, src, s0, s1, t, 0.0, 0.0, acc, tested,
-                                                    accepted);
+            for (int q = 0; q < TR; ++q) acc[q][0] = acc[q][1] = acc[q][2] = 0.0;
+            for (int col = 0; col < g.slots; ++col) {
+                const int cx_raw = bx * g.B - g.m + col;
+                const int wx = floordiv(cx_raw, g.nc1), cx = cx_raw - wx * g.nc1;
+                if (!row_in || (!g.periodic && wx != 0)) continue;   // wave-uniform
+                const int key = cell_key(g, cx, cy);
+                const int s0 = start[key], s1 = end[key];
+                if (targets_k0 && kflag[key] == 0) {
+                    if (wx == 0 && wy == 0) {
+                        cut_cell<kShiftNone, COUNT, TR>(m, g, src, s0, s1, t, 0.0, 0.0, acc, tested,
+                                                        accepted);
+                    } else {
+                        const double SL1 = (double)wx * g.L1, SL2 = (double)wy * g.L2;
+                        cut_cell<kShiftUniform, COUNT, TR>(m, g, src, s0, s1, t, SL1, SL2, acc, tested,
+                                                           accepted);
+                    }
                 } else {
-                    const double SL1 = (double)wx * g.L1, SL2 = (double)wy * g.L2;
-                    cut_cell<kShiftUniform, COUNT, TR>(m, g, src, s0, s1, t, SL1, SL2, acc, tested,
+#pragma unroll
+                    for (int q = 0; q < TR; ++q) {
+                        t[q].Kx = kxi[q] + (double)wx;
+                        t[q].Ky = kyi[q] + (double)wy;
+                    }
+                    cut_cell<kShiftPerLane, COUNT, TR>(m, g, src, s0, s1, t, 0.0, 0.0, acc, tested,
                                                        accepted);
                 }
-            } else {
-#pragma unroll
-                for (int q = 0; q < TR; ++q) {
-                    t[q].Kx = kxi[q] + (double)wx;
-                    t[q].Ky = kyi[q] + (double)wy;
-                }
-                cut_cell<kShiftPerLane, COUNT, TR>(m, g, src, s0, s1, t, 0.0, 0.0, acc, tested,
-                                                   accepted);
             }
-        }
-        double* out = part + (size_t)row * 3 * N;
+            double* out = part + (size_t)row * 3 * N;
 #pragma unroll
-        for (int q = 0; q < TR; ++q) {
-            if (t[q].active) {
-                const int p = (int)order[t0 + lane + kCutThreads * q];
-                out[p] = acc[q][0];
-                out[N + p] = acc[q][1];
-                out[2 * N + p] = acc[q][2];
+            for (int q = 0; q < TR; ++q) {
+                if (t[q].active) {
+                    const int p = (int)order[t0 + lane + kCutThreads * q];
+                    out[p] = acc[q][0];
+                    out[N + p] = acc[q][1];
+                    out[2 * N + p] = acc[q][2];
+                }
             }
         }
     }
     if (COUNT) {
-        for (int off = 32; off > 0; off >>= 1) {
-            tested += __shfl_xor(tested, off, 64);
-            accepted += __shfl_xor(accepted, off, 64);
-        }
         if (lane == 0) {
             atomicAdd(&counts[0], tested);
             atomicAdd(&counts[1], accepted);
@@ -537,6 +544,73 @@ __global__ __launch_bounds__(kCutThreads) void k_cut_pairs(Mesh m, CutGrid g,
 
 // ---- index-window path ----------------------------------------------------
 
+constexpr int kStThreads = 256;
+constexpr int kXcds = 8;                               // XCDs the workgroups are dealt over
+constexpr int kStBlk = 4;                              // tiles per side of a block of the work order
+constexpr int kCUs = 256;                              // compute units of the device
+constexpr int kMaxPlanes = 16;                         // partial sums per target at most
+constexpr int kStTX = 32, kStTY = 16;                  // target tile (columns, rows)
+constexpr int kStBh = 8, kStBw = 16;                   // offsets per band (rows, columns)
+constexpr int kStRows = kStTY + kStBh - 1;             // staged source rows
+constexpr int kStCols = kStTX - 2 + kStBw;             // staged source columns
+constexpr int kStHalf = kStCols / 2;                   // entries per parity and row
+constexpr int kStPad = kStHalf + 1;
+constexpr int kStPer = (kStRows * kStCols + kStThreads - 1) / kStThreads;   // staged per lane
+static_assert(kStTX == 32 && kStTY * 16 == kStThreads, "lane layout");
+static_assert(kStBw % 2 == 0, "a band starts both parities");
+
+// Index window of one evaluation (the same in every workgroup): alpha radius
+// Ra (squared), row and column reach W2, W1 in spacings, and whether the
+// seam counts give the image shifts.  A source whose nearest image lies
+// within rc of a target is less than Ra = rc / sigma_min from it in alpha
+// (sigma_min = min sigma_min(J2) over the sheet, fold[5]; plus a margin of 2%
+// and one spacing for the discrete tangents).  Along the window the sources
+// of one period copy (unwrapped column ju1 = j1 + w1 n1, row ju2 = j2 + w2 n2)
+// have image shift S = (w1, w2) whenever sigma_max(J2) (fold[9]) times the
+// largest alpha offset between a target and a window source stays below
+// 0.45 min(L1, L2): the horizontal part of z_i - z_j - w L, the only part the
+// shift depends on, is at most that long, so the nearest integer to d_a / L_a
+// is w_a.
+struct WinGeom {
+    double Ra2;
+    int W1, W2;
+    bool by_seams;
+};
+
+__device__ inline WinGeom win_geom(const Mesh& m, const CutGrid& g, const int* __restrict__ fold)
+{
+    WinGeom w;
+    const double smin = sqrt((double)__int_as_float(fold[5]));
+    const double hmax = sqrt((double)__int_as_float(fold[9]));
+    const double Ra = sqrt(g.rc2) * 1.02 / smin;
+    w.Ra2 = Ra * Ra;
+    w.W2 = (int)ceil(Ra / m.h2) + 1;
+    w.W1 = (int)ceil(Ra / m.h1) + 1;
+    const double dmax = sqrt((double)(w.W1 + 8) * (w.W1 + 8) * m.h1 * m.h1 +
+                             (double)(w.W2 + 8) * (w.W2 + 8) * m.h2 * m.h2);
+    w.by_seams = hmax * dmax < 0.45 * fmin(g.L1, g.L2);
+    return w;
+}
+
+// Columns either side of a target that the window takes in the row dy
+// spacings away (the chord of the radius-Ra disc, plus one spacing).
+__device__ inline int win_chord(const Mesh& m, const WinGeom& w, int dy)
+{
+    const double ry = (double)dy * m.h2;
+    const double half = w.Ra2 > ry * ry ? sqrt(w.Ra2 - ry * ry) : 0.0;
+    return (int)ceil(half / m.h1) + 1;
+}
+
+// Whether the per-target stencil (k_cut_sten) takes the evaluation: the
+// seam counts give the shifts and no target's window holds a source twice
+// (its 2 W1 + 2 columns and 2 W2 + 1 rows fit the period).  Otherwise the
+// patch-window kernel (k_cut_win) does.
+__device__ inline bool sten_fits(const Mesh& m, const WinGeom& w)
+{
+    return w.by_seams && 2 * w.W1 + 2 <= m.n1 && 2 * w.W2 + 1 <= m.n2 && m.n1 >= kStCols &&
+           m.n2 >= kStRows;
+}
+
 // Records (x, y, z, g1, g2, g3, 0, 0) in index order.
 __global__ __launch_bounds__(kThreads) void k_cut_records(Mesh m, CutGrid g,
                                                           const double* __restrict__ z,
@@ -545,6 +619,7 @@ __global__ __launch_bounds__(kThreads) void k_cut_records(Mesh m, CutGrid g,
                                                           const int* __restrict__ fold)
 {
     if (!window_path(fold, g.periodic)) return;
+    if (sten_fits(m, win_geom(m, g, fold))) return;   // the stencil reads the planes
     const int p = blockIdx.x * kThreads + threadIdx.x;
     const int N = m.N;
     if (p >= N) return;
@@ -559,18 +634,13 @@ __global__ __launch_bounds__(kThreads) void k_cut_records(Mesh m, CutGrid g,
     r[7] = 0.0;
 }
 
-// One wave per (8 x 8 patch of targets, row group).  Lane = one target
-// (t1, t2) = (c0 + lane % 8, r0 + lane / 8).  With sigma_min = min
-// sigma_min(J2) over the sheet (fold[5]), a source whose nearest image lies
-// within rc of a target is less than Ra = rc / sigma_min from it in alpha
-// (the index torus scaled by h); the window is every source whose alpha
-// distance to the patch's rectangle is at most Ra (plus a margin of 2% and
-// one spacing for the discrete tangents), rows of it split over the slots.
-// Along a window row the sources of one period copy (unwrapped column ju1 =
-// j1 + w1 n1, row ju2 = j2 + w2 n2) have image shift S = (w1, w2) whenever
-// sigma_max(J3) (fold[6]) times the largest alpha offset between a target
-// and a window source stays below 0.45 min(L1, L2): |z_i - z_j - w L| is at
-// most that; otherwise S is formed per pair from its definition.
+// Patch window, for windows too large for the stencil: one wave per (8 x 8
+// patch of targets, row group).  Lane = one target (t1, t2) = (c0 + lane % 8,
+// r0 + lane / 8); the window is every source whose alpha distance to the
+// patch's rectangle is at most Ra, rows of it split over the slots, each
+// source read once for all 64 lanes.  Without the seam-count rule S is
+// formed per pair from its definition; a window wider than the period takes
+// every column (row) once.
 template <bool COUNT>
 __global__ __launch_bounds__(kCutThreads) void k_cut_win(Mesh m, CutGrid g,
                                                          const double* __restrict__ src,
@@ -579,88 +649,330 @@ __global__ __launch_bounds__(kCutThreads) void k_cut_win(Mesh m, CutGrid g,
                                                          const int* __restrict__ fold)
 {
     if (!window_path(fold, g.periodic)) return;   // uniform: the cell path runs instead
+    const WinGeom wg = win_geom(m, g, fold);
+    if (sten_fits(m, wg)) return;                 // uniform: the stencil runs instead
     const int n1 = m.n1, n2 = m.n2, N = m.N;
-    const int pc = (n1 + 7) / 8;
-    const int c0 = (int)(blockIdx.x % pc) * 8, r0 = (int)(blockIdx.x / pc) * 8;
-    const int slot = blockIdx.y;
     const int lane = threadIdx.x;
-    const int t1 = c0 + (lane & 7), t2 = r0 + (lane >> 3);
-
-    CutTarget t[1];
-    t[0].active = t1 < n1 && t2 < n2;
-    t[0].amask = __builtin_amdgcn_ballot_w64(t[0].active);
-    const int p = t[0].active ? t2 * n1 + t1 : r0 * n1 + c0;   // idle lanes hold a real target
-    const double* tr = src + (size_t)p * 8;
-    t[0].x = tr[0];
-    t[0].y = tr[1];
-    t[0].z = tr[2];
-    t[0].Kx = t[0].Ky = 0.0;
-
-    // window radii (index units) and the image-shift bound
-    const double smin = sqrt((double)__int_as_float(fold[5]));
-    const double smax = sqrt((double)__int_as_float(fold[6]));
-    const double Ra = sqrt(g.rc2) * 1.02 / smin;
-    const int W2 = (int)ceil(Ra / m.h2) + 1;
-    const int W1 = (int)ceil(Ra / m.h1) + 1;
-    const double dmax = sqrt((double)(W1 + 8) * (W1 + 8) * m.h1 * m.h1 +
-                             (double)(W2 + 8) * (W2 + 8) * m.h2 * m.h2);
-    const bool by_seams = smax * dmax < 0.45 * fmin(g.L1, g.L2);
-    int rlo = r0 - W2, nrows = 8 + 2 * W2;
-    // a window taller than the period takes every row once; a row's
-    // distance from the patch is then its distance in the torus
-    const bool all_rows = nrows >= n2;
-    if (all_rows) nrows = n2;
-    const int per = (nrows + g.slots - 1) / g.slots;
-    const int ra = rlo + slot * per, rb = min(rlo + nrows, ra + per);
-    const double Ra2 = Ra * Ra;
-    auto row_gap = [&](int ju) { return ju < r0 ? r0 - ju : (ju > r0 + 7 ? ju - (r0 + 7) : 0); };
-
+    const int pc = (n1 + 7) / 8, npatch = pc * ((n2 + 7) / 8);
+    const long items = (long)npatch * g.planes;
     unsigned long long tested = 0, accepted = 0;
-    double acc[1][3] = {{0.0, 0.0, 0.0}};
-    for (int ju2 = ra; ju2 < rb; ++ju2) {
-        const int w2 = floordiv(ju2, n2), j2 = ju2 - w2 * n2;
-        int dy = row_gap(ju2);
-        if (all_rows) dy = min(dy, min(row_gap(ju2 + n2), row_gap(ju2 - n2)));
-        const double ry = dy * m.h2;
-        const double half = Ra2 > ry * ry ? sqrt(Ra2 - ry * ry) : 0.0;
-        const int dxm = (int)ceil(half / m.h1) + 1;
-        int clo = c0 - dxm, ncols = 8 + 2 * dxm;
-        if (ncols > n1) ncols = n1;               // every column once
-        // the row's columns [clo, clo + ncols) in pieces of one period copy
-        int a = clo;
-        const int e = clo + ncols;
-        while (a < e) {
-            const int w1 = floordiv(a, n1);
-            const int b = min(e, (w1 + 1) * n1);
-            const int s0 = j2 * n1 + (a - w1 * n1), s1 = s0 + (b - a);
-            if (!by_seams)
-                cut_cell<kShiftExact, COUNT, 1>(m, g, src, s0, s1, t, 0.0, 0.0, acc, tested,
-                                                accepted);
-            else if (w1 == 0 && w2 == 0)
-                cut_cell<kShiftNone, COUNT, 1>(m, g, src, s0, s1, t, 0.0, 0.0, acc, tested,
-                                               accepted);
-            else
-                cut_cell<kShiftUniform, COUNT, 1>(m, g, src, s0, s1, t, (double)w1 * g.L1,
-                                                  (double)w2 * g.L2, acc, tested, accepted);
-            a = b;
+    // items (patch, slot), patch fastest, strided over a capped grid
+    for (long it = blockIdx.x; it < items; it += gridDim.x) {
+        const int patch = (int)(it % npatch), slot = (int)(it / npatch);
+        const int c0 = (patch % pc) * 8, r0 = (patch / pc) * 8;
+        const int t1 = c0 + (lane & 7), t2 = r0 + (lane >> 3);
+
+        CutTarget t[1];
+        t[0].active = t1 < n1 && t2 < n2;
+        t[0].amask = __builtin_amdgcn_ballot_w64(t[0].active);
+        const int p = t[0].active ? t2 * n1 + t1 : r0 * n1 + c0;   // idle lanes hold a real target
+        const double* tr = src + (size_t)p * 8;
+        t[0].x = tr[0];
+        t[0].y = tr[1];
+        t[0].z = tr[2];
+        t[0].Kx = t[0].Ky = 0.0;
+
+        const int W2 = wg.W2;
+        const bool by_seams = wg.by_seams;
+        int rlo = r0 - W2, nrows = 8 + 2 * W2;
+        // a window taller than the period takes every row once; a row's
+        // distance from the patch is then its distance in the torus
+        const bool all_rows = nrows >= n2;
+        if (all_rows) nrows = n2;
+        const int per = (nrows + g.planes - 1) / g.planes;
+        const int ra = rlo + slot * per, rb = min(rlo + nrows, ra + per);
+        const double Ra2 = wg.Ra2;
+        auto row_gap = [&](int ju) { return ju < r0 ? r0 - ju : (ju > r0 + 7 ? ju - (r0 + 7) : 0); };
+
+        double acc[1][3] = {{0.0, 0.0, 0.0}};
+        for (int ju2 = ra; ju2 < rb; ++ju2) {
+            const int w2 = floordiv(ju2, n2), j2 = ju2 - w2 * n2;
+            int dy = row_gap(ju2);
+            if (all_rows) dy = min(dy, min(row_gap(ju2 + n2), row_gap(ju2 - n2)));
+            const double ry = dy * m.h2;
+            const double half = Ra2 > ry * ry ? sqrt(Ra2 - ry * ry) : 0.0;
+            const int dxm = (int)ceil(half / m.h1) + 1;
+            int clo = c0 - dxm, ncols = 8 + 2 * dxm;
+            if (ncols > n1) ncols = n1;               // every column once
+            // the row's columns [clo, clo + ncols) in pieces of one period copy
+            int a = clo;
+            const int e = clo + ncols;
+            while (a < e) {
+                const int w1 = floordiv(a, n1);
+                const int b = min(e, (w1 + 1) * n1);
+                const int s0 = j2 * n1 + (a - w1 * n1), s1 = s0 + (b - a);
+                if (!by_seams)
+                    cut_cell<kShiftExact, COUNT, 1>(m, g, src, s0, s1, t, 0.0, 0.0, acc, tested,
+                                                    accepted);
+                else if (w1 == 0 && w2 == 0)
+                    cut_cell<kShiftNone, COUNT, 1>(m, g, src, s0, s1, t, 0.0, 0.0, acc, tested,
+                                                   accepted);
+                else
+                    cut_cell<kShiftUniform, COUNT, 1>(m, g, src, s0, s1, t, (double)w1 * g.L1,
+                                                      (double)w2 * g.L2, acc, tested, accepted);
+                a = b;
+            }
         }
-    }
-    if (t[0].active) {
-        double* out = part + (size_t)slot * 3 * N;
-        out[p] = acc[0][0];
-        out[N + p] = acc[0][1];
-        out[2 * N + p] = acc[0][2];
+        if (t[0].active) {
+            double* out = part + (size_t)slot * 3 * N;
+            out[p] = acc[0][0];
+            out[N + p] = acc[0][1];
+            out[2 * N + p] = acc[0][2];
+        }
     }
     if (COUNT) {
-        for (int off = 32; off > 0; off >>= 1) {
-            tested += __shfl_xor(tested, off, 64);
-            accepted += __shfl_xor(accepted, off, 64);
-        }
         if (lane == 0) {
             atomicAdd(&counts[0], tested);
             atomicAdd(&counts[1], accepted);
         }
     }
+}
+
+// Per-target stencil: a workgroup of 256 lanes takes a 32 x 16 tile of
+// targets, two horizontally adjacent targets per lane ((C0 + 2a + k, R0 + b),
+// a = lane % 16, b = lane / 16, k = 0, 1), and walks offsets (dy, sx) that
+// are the same in every lane: the lane's source is the point at (C0 + 2a +
+// sx, R0 + b + dy), its first target's offset is (sx, dy), its second's
+// (sx - 1, dy).  Offsets run over every row |dy| <= W2 and, in row dy, the
+// columns -chord(dy) .. chord(dy) + 1, so each target meets every source of
+// its own window and no other: the tests per target are about the disc of
+// radius Ra rather than its union over a patch.  The sources of a band of
+// kStBh x kStBw offsets are staged in LDS (the band's 23 rows x 46 columns,
+// split by column parity so that consecutive lanes read consecutive
+// entries); bands no row of the disc reaches are skipped and the others are
+// dealt round-robin to the slots.  Every source is one period copy away from
+// its wrapped index (w1, w2 in -1 .. 1), which is its image shift; bands that
+// cross no seam skip the shift arithmetic (S = 0, r = d bit for bit).
+// Two doubles as one native vector (staged records stay in registers; the
+// HIP vector wrapper type keeps them in private memory when copied through
+// an array).
+typedef double dv2 __attribute__((ext_vector_type(2)));
+
+struct StTile {
+    dv2 xy[2][kStRows][kStPad];
+    dv2 zg[2][kStRows][kStPad];   // (z, g1)
+    dv2 gg[2][kStRows][kStPad];   // (g2, g3)
+};
+
+// One source against the lane's two targets (cut_pair's sums): a target
+// slot no lane accepts skips its evaluation, and one that every active lane
+// accepts takes the kernel weight without the accept select.
+template <bool SEAM, bool COUNT>
+__device__ __forceinline__ void sten_pair(const Mesh& m, const CutGrid& g, const CutTarget (&t)[2],
+                                          const SrcRec& b, const double (&d1)[2], double SL1,
+                                          double SL2, double (&acc)[2][3],
+                                          unsigned long long& tested, unsigned long long& accepted)
+{
+#pragma clang fp contract(off)
+    double r1[2], r2[2], r3[2], dd[2];
+    bool in[2];
+    uint64_t any[2];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const double d2 = t[q].y - b.y;
+        r1[q] = SEAM ? d1[q] - SL1 : d1[q];
+        r2[q] = SEAM ? d2 - SL2 : d2;
+        r3[q] = t[q].z - b.z;
+        dd[q] = r1[q] * r1[q] + r2[q] * r2[q] + r3[q] * r3[q];
+        in[q] = dd[q] < g.rc2;
+        any[q] = __builtin_amdgcn_ballot_w64(in[q]) & t[q].amask;
+        if (COUNT) {   // whole-wave counts (scalar work, the same in every lane)
+            tested += (unsigned long long)__popcll(t[q].amask);
+            accepted += (unsigned long long)__popcll(any[q]);
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        if (any[q] == 0ull) continue;
+        double wgt = dev::inv_cube_sqrt(dd[q] + m.eps2);
+        if (any[q] != t[q].amask) wgt = in[q] ? wgt : 0.0;
+        const double a1 = wgt * b.g1, a2 = wgt * b.g2, a3 = wgt * b.g3;
+        acc[q][0] = fma(r2[q], a3, acc[q][0]);
+        acc[q][0] = fma(-r3[q], a2, acc[q][0]);
+        acc[q][1] = fma(r3[q], a1, acc[q][1]);
+        acc[q][1] = fma(-r1[q], a3, acc[q][1]);
+        acc[q][2] = fma(r1[q], a2, acc[q][2]);
+        acc[q][2] = fma(-r2[q], a1, acc[q][2]);
+    }
+}
+
+template <bool SEAM, bool COUNT>
+__device__ __forceinline__ void sten_band(const Mesh& m, const CutGrid& g, const WinGeom& wg,
+                                          const StTile& T, int C0, int R0, int a, int b, int dy0,
+                                          int dx0, const CutTarget (&t)[2], double (&acc)[2][3],
+                                          unsigned long long& tested, unsigned long long& accepted)
+{
+    const int dyhi = min(dy0 + kStBh, wg.W2 + 1);
+    for (int dy = dy0; dy < dyhi; ++dy) {
+        const int dm = win_chord(m, wg, dy);
+        const int slo = max(dx0, -dm), shi = min(dx0 + kStBw, dm + 2);
+        if (slo >= shi) continue;
+        const int rr = b + dy - dy0;
+        // an active target's source lies less than one period outside the
+        // mesh, so its wrap count is -1, 0 or 1 and S L is -L, 0 or L exactly
+        // (idle lanes' shifts are never used)
+        double SL2 = 0.0;
+        if (SEAM) {
+            const int r = R0 + b + dy;
+            SL2 = r < 0 ? -g.L2 : (r >= m.n2 ? g.L2 : 0.0);
+        }
+        // offsets o = sx - dx0 in even / odd pairs: both read entry a + o / 2
+        // of the two parity planes (one address, immediate offsets)
+        auto step = [&](int sx, int par, int hc) {
+#pragma clang fp contract(off)
+            const dv2 xy = T.xy[par][rr][hc];
+            const dv2 zg = T.zg[par][rr][hc];
+            const dv2 gg = T.gg[par][rr][hc];
+            const SrcRec rec{xy.x, xy.y, zg.x, zg.y, gg.x, gg.y, 0.0, 0.0};
+            double SL1 = 0.0;
+            if (SEAM) {
+                const int c = C0 + 2 * a + sx;
+                SL1 = c < 0 ? -g.L1 : (c >= m.n1 ? g.L1 : 0.0);
+            }
+            double d1[2];
+            d1[0] = t[0].x - rec.x;
+            d1[1] = t[1].x - rec.x;
+            sten_pair<SEAM, COUNT>(m, g, t, rec, d1, SL1, SL2, acc, tested, accepted);
+        };
+        int sx = slo;
+        if ((sx - dx0) & 1) {
+            step(sx, 1, a + ((sx - dx0) >> 1));
+            ++sx;
+        }
+        for (; sx + 1 < shi; sx += 2) {
+            const int hc = a + ((sx - dx0) >> 1);
+            step(sx, 0, hc);
+            step(sx + 1, 1, hc);
+        }
+        if (sx < shi) step(sx, 0, a + ((sx - dx0) >> 1));
+    }
+}
+
+template <bool COUNT>
+__global__ __launch_bounds__(kStThreads) void k_cut_sten(Mesh m, CutGrid g,
+                                                         const double* __restrict__ z,
+                                                         const double* __restrict__ gam,
+                                                         double* __restrict__ part,
+                                                         unsigned long long* __restrict__ counts,
+                                                         const int* __restrict__ fold)
+{
+    if (!window_path(fold, g.periodic)) return;   // uniform: the cell path runs instead
+    const WinGeom wg = win_geom(m, g, fold);
+    if (!sten_fits(m, wg)) return;                // uniform: the patch window runs instead
+    __shared__ StTile T;
+    const int n1 = m.n1, n2 = m.n2, N = m.N;
+    const int tiles1 = (n1 + kStTX - 1) / kStTX;
+    // workgroups are dealt round-robin to the XCDs: give each XCD one
+    // contiguous run of (tile, slot) items so that the windows of the tiles it
+    // works on at one time overlap in its L2; items run over blocks of
+    // kStBlk x kStBlk tiles, the tiles of a block, then the slots
+    const int tiles2 = (n2 + kStTY - 1) / kStTY;
+    const int blocks1 = (tiles1 + kStBlk - 1) / kStBlk;
+    const int total = (int)gridDim.x;
+    const int L = (int)blockIdx.x;
+    const int xcd = L % kXcds, per = total / kXcds, rem = total % kXcds;
+    const int item = xcd * per + min(xcd, rem) + L / kXcds;
+    const int slot = item % g.planes, bt = item / g.planes;
+    const int blk = bt / (kStBlk * kStBlk), in = bt - blk * (kStBlk * kStBlk);
+    const int tx = (blk % blocks1) * kStBlk + in % kStBlk, ty = (blk / blocks1) * kStBlk + in / kStBlk;
+    if (tx >= tiles1 || ty >= tiles2) return;     // the ragged edge of the block grid
+    const int C0 = tx * kStTX, R0 = ty * kStTY;
+    const int tid = threadIdx.x, a = tid & 15, b = tid >> 4;
+
+    CutTarget t[2];
+    int tp[2];
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        const int c = C0 + 2 * a + k, r = R0 + b;
+        t[k].active = c < n1 && r < n2;
+        t[k].amask = __builtin_amdgcn_ballot_w64(t[k].active);
+        tp[k] = t[k].active ? r * n1 + c : 0;   // idle lanes hold a real target
+        t[k].x = z[tp[k]];
+        t[k].y = z[N + tp[k]];
+        t[k].z = z[2 * N + tp[k]];
+        t[k].Kx = t[k].Ky = 0.0;
+    }
+
+    unsigned long long tested = 0, accepted = 0;
+    double acc[2][3] = {{0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}};
+    int band = 0;
+    for (int dy0 = -wg.W2; dy0 <= wg.W2; dy0 += kStBh) {
+        // the band's row nearest dy = 0 has the longest chord
+        const int dyn = dy0 > 0 ? dy0 : min(dy0 + kStBh - 1, 0);
+        const int dm = win_chord(m, wg, dyn);
+        for (int dx0 = -wg.W1; dx0 <= wg.W1 + 1; dx0 += kStBw) {
+            if (max(dx0, -dm) >= min(dx0 + kStBw, dm + 2)) continue;   // outside the disc
+            if (band++ % g.planes != slot) continue;
+            // stage the band's sources: every load is issued before the
+            // first LDS write (one round trip per band); the band's first
+            // row and column are wrapped once, the rest by subtraction
+            int rb = R0 + dy0, cb = C0 + dx0;
+            rb -= floordiv(rb, n2) * n2;
+            cb -= floordiv(cb, n1) * n1;
+            dv2 v[kStPer][3];
+#pragma unroll
+            for (int i = 0; i < kStPer; ++i) {
+                const int e = tid + i * kStThreads;
+                const int ee = e < kStRows * kStCols ? e : 0;
+                const int rr = ee / kStCols, cr = ee - rr * kStCols;
+                int r = rb + rr, c = cb + cr;
+                r = r >= n2 ? r - n2 : r;   // one period at most: n2 >= kStRows, n1 >= kStCols
+                c = c >= n1 ? c - n1 : c;
+                const int j = r * n1 + c;
+                v[i][0] = dv2{z[j], z[N + j]};
+                v[i][1] = dv2{z[2 * N + j], gam[j]};
+                v[i][2] = dv2{gam[N + j], gam[2 * N + j]};
+            }
+            __syncthreads();   // the previous band's reads are done
+#pragma unroll
+            for (int i = 0; i < kStPer; ++i) {
+                const int e = tid + i * kStThreads;
+                if (e < kStRows * kStCols) {
+                    const int rr = e / kStCols, cr = e - rr * kStCols;
+                    const int par = cr & 1, hc = cr >> 1;
+                    T.xy[par][rr][hc] = v[i][0];
+                    T.zg[par][rr][hc] = v[i][1];
+                    T.gg[par][rr][hc] = v[i][2];
+                }
+            }
+            __syncthreads();
+            const bool seam = C0 + dx0 < 0 || C0 + dx0 + kStCols > n1 || R0 + dy0 < 0 ||
+                              R0 + dy0 + kStRows > n2;
+            if (seam)
+                sten_band<true, COUNT>(m, g, wg, T, C0, R0, a, b, dy0, dx0, t, acc, tested,
+                                       accepted);
+            else
+                sten_band<false, COUNT>(m, g, wg, T, C0, R0, a, b, dy0, dx0, t, acc, tested,
+                                        accepted);
+        }
+    }
+    double* out = part + (size_t)slot * 3 * N;
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        if (!t[k].active) continue;
+        out[tp[k]] = acc[k][0];
+        out[N + tp[k]] = acc[k][1];
+        out[2 * N + tp[k]] = acc[k][2];
+    }
+    if (COUNT) {
+        if ((tid & 63) == 0) {
+            atomicAdd(&counts[0], tested);
+            atomicAdd(&counts[1], accepted);
+        }
+    }
+}
+
+// The cell path writes partial sums [0, slots); the reduction sums
+// [0, planes): zero the rest (the window kernels write every plane).
+__global__ __launch_bounds__(kThreads) void k_cut_zero_planes(Mesh m, CutGrid g,
+                                                              double* __restrict__ part,
+                                                              const int* __restrict__ fold)
+{
+    if (window_path(fold, g.periodic)) return;
+    const long n = (long)(g.planes - g.slots) * 3 * m.N;
+    double* p = part + (long)g.slots * 3 * m.N;
+    for (long i = (long)blockIdx.x * kThreads + threadIdx.x; i < n; i += (long)gridDim.x * kThreads)
+        p[i] = 0.0;
 }
 
 inline unsigned grid_for(long n) { return (unsigned)((n + kThreads - 1) / kThreads); }
@@ -690,6 +1002,15 @@ CutGrid make_cut_grid(int n1, int n2, double L1, double L2, double rc, bool peri
     g.key_bits = 1;
     while ((1L << g.key_bits) < (long)g.nkeys) ++g.key_bits;
     g.slots = g.B + 2 * g.m;
+    // the index-window kernels split each target's sources over more
+    // partial sums when the mesh has few stencil tiles, so that a launch
+    // holds about eight rounds of resident workgroups (three per CU)
+    g.planes = g.slots;
+    if (periodic) {
+        const long tiles = (long)((n1 + kStTX - 1) / kStTX) * ((n2 + kStTY - 1) / kStTY);
+        const long want = (8L * 3L * kCUs + tiles - 1) / tiles;
+        g.planes = (int)std::max<long>(g.slots, std::min<long>(want, kMaxPlanes));
+    }
     const long N = (long)n1 * n2;
     const long per_block = (N + (long)g.nb1 * g.nb2 - 1) / ((long)g.nb1 * g.nb2);
     g.tr = kCutTargetsPerLane;
@@ -738,11 +1059,13 @@ hipError_t launch_cut_cells(const Mesh& m, const CutGrid& g, const double* z, co
     return hipGetLastError();
 }
 
-hipError_t launch_cut_pairs(const Mesh& m, const CutGrid& g, const CutBuffers& b,
-                            int sorted_half, double* part, bool count, const int* fold,
-                            hipStream_t s)
+hipError_t launch_cut_pairs(const Mesh& m, const CutGrid& g, const double* z, const double* gam,
+                            const CutBuffers& b, int sorted_half, double* part, bool count,
+                            const int* fold, hipStream_t s)
 {
-    const dim3 grid(g.nb1 * g.nb2, g.slots, g.chunks);
+    // capped grids: the kernels of the path not taken launch few workgroups
+    const long cell_items = (long)g.nb1 * g.nb2 * g.slots * g.chunks;
+    const dim3 grid((unsigned)std::min<long>(cell_items, kCutMaxGroups));
     const unsigned* order = b.vals[sorted_half];
     if (count)
         hipLaunchKernelGGL((k_cut_pairs<true, kCutTargetsPerLane>), grid, dim3(kCutThreads), 0, s, m,
@@ -752,13 +1075,26 @@ hipError_t launch_cut_pairs(const Mesh& m, const CutGrid& g, const CutBuffers& b
         hipLaunchKernelGGL((k_cut_pairs<false, kCutTargetsPerLane>), grid, dim3(kCutThreads), 0, s,
                            m, g, b.src, b.start, b.end, b.bstart, b.bend, b.kflag, order, part,
                            b.counts, fold);
-    // the index-window path (its workgroups leave at once on the cell path)
-    const dim3 wgrid((unsigned)(((m.n1 + 7) / 8) * ((m.n2 + 7) / 8)), (unsigned)g.slots);
+    if (g.planes > g.slots)
+        hipLaunchKernelGGL(k_cut_zero_planes, dim3(1024), dim3(kThreads), 0, s, m, g, part, fold);
+    // the index-window path: patch window or per-target stencil (the
+    // workgroups of the kernels not taking the evaluation leave at once)
+    const long win_items = (long)((m.n1 + 7) / 8) * ((m.n2 + 7) / 8) * g.planes;
+    const dim3 wgrid((unsigned)std::min<long>(win_items, kCutMaxGroups));
     if (count)
         hipLaunchKernelGGL((k_cut_win<true>), wgrid, dim3(kCutThreads), 0, s, m, g, b.src, part,
                            b.counts, fold);
     else
         hipLaunchKernelGGL((k_cut_win<false>), wgrid, dim3(kCutThreads), 0, s, m, g, b.src, part,
+                           b.counts, fold);
+    const int bl1 = ((m.n1 + kStTX - 1) / kStTX + kStBlk - 1) / kStBlk;
+    const int bl2 = ((m.n2 + kStTY - 1) / kStTY + kStBlk - 1) / kStBlk;
+    const dim3 sgrid((unsigned)(bl1 * bl2 * kStBlk * kStBlk * g.planes));
+    if (count)
+        hipLaunchKernelGGL((k_cut_sten<true>), sgrid, dim3(kStThreads), 0, s, m, g, z, gam, part,
+                           b.counts, fold);
+    else
+        hipLaunchKernelGGL((k_cut_sten<false>), sgrid, dim3(kStThreads), 0, s, m, g, z, gam, part,
                            b.counts, fold);
     return hipGetLastError();
 }

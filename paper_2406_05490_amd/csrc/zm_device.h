@@ -165,9 +165,9 @@ __device__ __forceinline__ void tangents_at(const Mesh& m, int p, const double* 
 // folds (det J2 changes sign or vanishes: overturned, rolled up) or stretches beyond
 // that ratio takes exact r for every pair instead (the same sums with more
 // operations per pair).  The surface kernel gathers min sigma_min(J2)^2,
-// max sigma_max(J3)^2 and the signs det J2 takes over the mesh; its last workgroup
-// turns them into the flag the pair kernels read and clears the gathered
-// values for the next evaluation.
+// max sigma_max(J3)^2, max sigma_max(J2)^2 and the signs det J2 takes over
+// the mesh; its last workgroup turns them into the flag the pair kernels read
+// and clears the gathered values for the next evaluation.
 //
 // fold[0]: max of (bits(+inf) - bits(min sigma_min^2)) (0 = nothing seen)
 // fold[1]: max of bits(max sigma_max^2)
@@ -177,11 +177,14 @@ __device__ __forceinline__ void tangents_at(const Mesh& m, int p, const double* 
 // fold[5], fold[6], fold[7]: this evaluation's min sigma_min(J2)^2 and max
 //          sigma_max(J3)^2 (float bits) and det J2 signs, kept for the cutoff
 //          solver's index windows
-// (kFoldWords = 8 ints in all, zm_internal.h)
+// fold[8]: max of bits(max sigma_max(J2)^2)
+// fold[9]: this evaluation's max sigma_max(J2)^2 (float bits), kept for the
+//          cutoff solver's image-shift rule
+// (kFoldWords = 10 ints in all, zm_internal.h)
 constexpr float kFoldMaxStretch2 = 16.f;   // (sigma_max / sigma_min)^2 allowed
 
 struct FoldStat {
-    float smin2, smax2;
+    float smin2, smax2, hmax2;   // sigma_min(J2)^2, sigma_max(J3)^2, sigma_max(J2)^2
     int folded;
 };
 
@@ -190,49 +193,67 @@ struct FoldStat {
 // the launch (of `groups` in all) writes the flag and clears the rest.
 __device__ __forceinline__ void fold_gather(FoldStat st, int* __restrict__ fold, int groups)
 {
-    __shared__ float smin_w[kThreads / 64], smax_w[kThreads / 64];
+    __shared__ float smin_w[kThreads / 64], smax_w[kThreads / 64], hmax_w[kThreads / 64];
     __shared__ int fold_w[kThreads / 64];
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {
         st.smin2 = fminf(st.smin2, __shfl_xor(st.smin2, off, 64));
         st.smax2 = fmaxf(st.smax2, __shfl_xor(st.smax2, off, 64));
+        st.hmax2 = fmaxf(st.hmax2, __shfl_xor(st.hmax2, off, 64));
         st.folded |= __shfl_xor(st.folded, off, 64);
     }
     const int wv = threadIdx.x >> 6;
     if ((threadIdx.x & 63) == 0) {
         smin_w[wv] = st.smin2;
         smax_w[wv] = st.smax2;
+        hmax_w[wv] = st.hmax2;
         fold_w[wv] = st.folded;
     }
     __syncthreads();
     if (threadIdx.x != 0) return;
-    float a = smin_w[0], b = smax_w[0];
+    float a = smin_w[0], b = smax_w[0], c = hmax_w[0];
     int f = fold_w[0];
 #pragma unroll
     for (int k = 1; k < kThreads / 64; ++k) {
         a = fminf(a, smin_w[k]);
         b = fmaxf(b, smax_w[k]);
+        c = fmaxf(c, hmax_w[k]);
         f |= fold_w[k];
     }
     const int inf_bits = __float_as_int(__builtin_inff());
-    atomicMax(&fold[0], inf_bits - __float_as_int(a));   // a, b >= 0: bit order = value order
-    atomicMax(&fold[1], __float_as_int(b));
-    if (f) atomicOr(&fold[2], f);
+    // every workgroup adds to the same words: an atomic only where it would
+    // change the word (within an evaluation the words only grow, so a value
+    // read here is a lower bound of the final one)
+    auto peek = [&](int i) { return __hip_atomic_load(&fold[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); };
+    const int v0 = inf_bits - __float_as_int(a), v1 = __float_as_int(b), v8 = __float_as_int(c);
+    if (v0 > peek(0)) atomicMax(&fold[0], v0);   // a, b, c >= 0: bit order = value order
+    if (v1 > peek(1)) atomicMax(&fold[1], v1);
+    if (v8 > peek(8)) atomicMax(&fold[8], v8);
+    if (f & ~peek(2)) atomicOr(&fold[2], f);
     __threadfence();
     if (atomicAdd(&fold[3], 1) != groups - 1) return;
     // last workgroup: every other one has added its values (fenced above)
     const float smin2 = __int_as_float(inf_bits - atomicAdd(&fold[0], 0));
     const float smax2 = __int_as_float(atomicAdd(&fold[1], 0));
+    const float hmax2 = __int_as_float(atomicAdd(&fold[8], 0));
     const int sg = atomicAdd(&fold[2], 0);
     const bool off = (sg & 3) == 3 || (sg & 4) != 0 || !(smax2 <= kFoldMaxStretch2 * smin2);
     atomicExch(&fold[4], off ? 1 : 0);
     atomicExch(&fold[5], __float_as_int(smin2));
     atomicExch(&fold[6], __float_as_int(smax2));
     atomicExch(&fold[7], sg);
+    atomicExch(&fold[9], __float_as_int(hmax2));
     atomicExch(&fold[0], 0);
     atomicExch(&fold[1], 0);
     atomicExch(&fold[2], 0);
     atomicExch(&fold[3], 0);
+    atomicExch(&fold[8], 0);
+}
+
+__device__ __forceinline__ FoldStat fold_merge(FoldStat a, FoldStat b)
+{
+    return FoldStat{fminf(a.smin2, b.smin2), fmaxf(a.smax2, b.smax2), fmaxf(a.hmax2, b.hmax2),
+                    a.folded | b.folded};
 }
 
 // Tangent-map statistics of one point (identity values for p >= N).
@@ -249,6 +270,7 @@ __device__ __forceinline__ FoldStat fold_stat(const double T1[3], const double T
     FoldStat st;
     st.smin2 = 0.5f * (s2 - __builtin_amdgcn_sqrtf(fmaxf(s2 * s2 - 4.f * det * det, 0.f)));
     st.smax2 = 0.5f * (s3 + __builtin_amdgcn_sqrtf(fmaxf(s3 * s3 - 4.f * nn, 0.f)));
+    st.hmax2 = 0.5f * (s2 + __builtin_amdgcn_sqrtf(fmaxf(s2 * s2 - 4.f * det * det, 0.f)));
     st.folded = det2 > 0.0 ? 1 : (det2 < 0.0 ? 2 : 4);
     return st;
 }
@@ -257,7 +279,7 @@ __device__ __forceinline__ FoldStat surface_point(const Mesh& m, int p, const do
                                                   const double* __restrict__ w,
                                                   double* __restrict__ gam, double* __restrict__ q)
 {
-    if (p >= m.N) return FoldStat{__builtin_inff(), 0.f, 0};
+    if (p >= m.N) return FoldStat{__builtin_inff(), 0.f, 0.f, 0};
     const int N = m.N;
     double T1[3], T2[3];
     tangents_at(m, p, z, T1, T2);

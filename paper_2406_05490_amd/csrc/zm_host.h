@@ -60,7 +60,7 @@ inline Layout make_layout(const zm_params& p, const zm::PairShape& sh)
     const size_t d = sizeof(double);
     const bool cut = has_cutoff(p);
     const CutGrid g = cut ? cut_grid_of(p) : CutGrid();
-    const int slots = cut ? (g.slots > sh.splits ? g.slots : sh.splits) : sh.splits;
+    const int slots = cut ? (g.planes > sh.splits ? g.planes : sh.splits) : sh.splits;
     Layout L;
     size_t o = 0;
     auto take = [&](size_t bytes) { size_t at = o; o = align_up(o + bytes); return at; };

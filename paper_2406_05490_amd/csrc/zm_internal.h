@@ -9,7 +9,7 @@ namespace zm {
 
 // Ints of the sheet's fold statistics (tangent-map bounds gathered by the
 // surface kernel, read by the pair kernels and the cutoff solver).
-constexpr int kFoldWords = 8;
+constexpr int kFoldWords = 10;
 
 // Mesh geometry and model constants, passed by value to every kernel.
 struct Mesh {
@@ -98,7 +98,8 @@ struct CutGrid {
     int nb1, nb2;        // target blocks per axis
     int nkeys;           // nb1 nb2 B^2
     int key_bits;        // bits of the sort key
-    int slots;           // B + 2m
+    int slots;           // B + 2m (neighbour rows and columns of the cell path)
+    int planes;          // partial sums per target: slots, or more for the index-window path
     int chunks;          // waves per (target block, row): ~ mean chunks of 64 tr targets per block
     int tr;              // targets per lane of the pair kernel
     int sort_blocks;     // workgroups of the radix-sort passes
@@ -160,11 +161,12 @@ hipError_t launch_low_velocity(const Mesh& m, const double* z, const double* w,
 hipError_t launch_cut_count_reset(unsigned long long* counts, hipStream_t s);
 
 // part[slot][3][N] = unscaled cutoff sums per target and slot (neighbour row
-// of the cell path, or row group of the index-window path).
+// of the cell path, row group of the patch window, band group of the
+// per-target stencil, which reads the z and gam planes directly).
 // count != 0: also add the tested / accepted pair counts to b.counts.
-hipError_t launch_cut_pairs(const Mesh& m, const CutGrid& g, const CutBuffers& b,
-                            int sorted_half, double* part, bool count, const int* fold,
-                            hipStream_t s);
+hipError_t launch_cut_pairs(const Mesh& m, const CutGrid& g, const double* z, const double* gam,
+                            const CutBuffers& b, int sorted_half, double* part, bool count,
+                            const int* fold, hipStream_t s);
 
 // F = (u, D V + nu Lap w) at state ys, then
 //   stage 0: out = ys + dt F

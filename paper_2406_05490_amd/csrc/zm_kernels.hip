@@ -18,7 +18,12 @@ __global__ __launch_bounds__(kThreads) void k_surface(Mesh m, const double* __re
                                                       double* __restrict__ q,
                                                       int* __restrict__ fold)
 {
-    const dev::FoldStat st = dev::surface_point(m, blockIdx.x * kThreads + threadIdx.x, z, w, gam, q);
+    // a few hundred workgroups stride over the mesh, so that the tangent-map
+    // statistics meet in few atomics (every workgroup adds its values to the
+    // same words)
+    dev::FoldStat st{__builtin_inff(), 0.f, 0.f, 0};
+    for (int p = blockIdx.x * kThreads + threadIdx.x; p < m.N; p += gridDim.x * kThreads)
+        st = dev::fold_merge(st, dev::surface_point(m, p, z, w, gam, q));
     if (fold) dev::fold_gather(st, fold, gridDim.x);
 }
 
@@ -100,6 +105,9 @@ __global__ __launch_bounds__(kThreads) void k_tune_init(Mesh m, double* __restri
 
 inline unsigned blocks_for(int n) { return (unsigned)((n + kThreads - 1) / kThreads); }
 
+// Workgroups of the surface kernel at most (two per CU of a 256-CU device).
+constexpr unsigned kSurfaceGroups = 512;
+
 }  // namespace
 
 
@@ -170,7 +178,8 @@ hipError_t launch_tune_init(const Mesh& m, double* z, double* gam, hipStream_t s
 hipError_t launch_surface(const Mesh& m, const double* z, const double* w, double* gam, double* q,
                           int* fold, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_surface, dim3(blocks_for(m.N)), dim3(kThreads), 0, s, m, z, w, gam, q, fold);
+    const int groups = std::min(blocks_for(m.N), kSurfaceGroups);
+    hipLaunchKernelGGL(k_surface, dim3(groups), dim3(kThreads), 0, s, m, z, w, gam, q, fold);
     return hipGetLastError();
 }
 
