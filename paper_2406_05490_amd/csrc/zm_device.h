@@ -175,8 +175,9 @@ __device__ __forceinline__ void tangents_at(const Mesh& m, int p, const double* 
 // fold[3]: workgroups done
 // fold[4]: 1 = the far forms are off for this evaluation (read by the pair kernels)
 // fold[5], fold[6], fold[7]: this evaluation's min sigma_min(J2)^2 and max
-//          sigma_max(J3)^2 (float bits) and det J2 signs, kept for the cutoff
-//          solver's index windows
+//          sigma_max(J3)^2 (float bits) and det J2 signs, kept after the
+//          gathered values are cleared (the cutoff solver's index windows read
+//          fold[5] and fold[7])
 // fold[8]: max of bits(max sigma_max(J2)^2)
 // fold[9]: this evaluation's max sigma_max(J2)^2 (float bits), kept for the
 //          cutoff solver's image-shift rule
