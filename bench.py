@@ -902,8 +902,7 @@ def cpu_baseline(zm, torch, wl, target_seconds: float, sweep=None):
     return {
         "value": tg.size * wl.n / dt, "unit": "pair-interactions/s", "cores": threads,
         "kind": "oracle",
-        "sample": f"BR of {tg.size} seeded targets x all {wl.n} sources, workload state, "
-                  f"synthetic vorticity ({tg.size * wl.n:.2e} pairs)",
+        "sample": f"BR at {tg.size} seeded targets x {wl.n} sources ({tg.size * wl.n:.2e} pairs)",
         "seconds": dt,
         "gpu_vs_oracle_max_rel_err": {form: rel(u[:, tg], ref) for form, u in us.items()},
     }
@@ -1087,6 +1086,12 @@ def main():
                             ("free_single_mode", free_section), ("medium_order", medium_section)):
                 log(f"section {key}")
                 detail[key] = fn(zm, torch)
+            cut = detail["cutoff"]
+            extras["cutoff"] = {
+                side: {"acc_per_s": c["accepted_pairs_per_s"],
+                       "tested_per_acc": c["pairs_tested_per_eval"] / c["pairs_accepted_per_eval"],
+                       "pair_ms": c["kernel_ms"]["pairs"]}
+                for side, c in (("768", cut["multimode768"]), ("512", cut["singlemode512"]))}
     if args.serve_requests > 0:
         sv = serving(zm, torch, count=args.serve_requests, max_seconds=args.serve_max_seconds)
         detail["serving"] = sv
