@@ -27,6 +27,23 @@ __global__ __launch_bounds__(kThreads) void k_surface(Mesh m, const double* __re
     if (fold) dev::fold_gather(st, fold, gridDim.x);
 }
 
+// Workgroups are dealt round-robin to the 8 XCDs.  The pair kernels give
+// each XCD one contiguous run of the split-major (patch, split) work list, so
+// that the workgroups an XCD runs at one time share a split and its sources
+// stay in that XCD's L2 (dealt round-robin, every XCD would run patches of
+// every split and read every split's sources).  A bijection of the grid.
+constexpr int kXcds = 8;
+
+__device__ __forceinline__ void pair_item(int& patch, int& split)
+{
+    const int total = (int)(gridDim.x * gridDim.y);
+    const int L = (int)(blockIdx.x + gridDim.x * blockIdx.y);
+    const int xcd = L % kXcds, per = total / kXcds, rem = total % kXcds;
+    const int item = xcd * per + min(xcd, rem) + L / kXcds;
+    patch = item % (int)gridDim.x;
+    split = item / (int)gridDim.x;
+}
+
 template <int R, int PX>
 __global__ __launch_bounds__(kThreads) void k_pairs_f64f(Mesh m, PairShape sh,
                                                          const double* __restrict__ z,
@@ -35,7 +52,9 @@ __global__ __launch_bounds__(kThreads) void k_pairs_f64f(Mesh m, PairShape sh,
                                                          const int* __restrict__ fold)
 {
     __shared__ dev::F64Tile lds;
-    dev::pairs_f64f_block<R, PX>(m, sh, z, gam, part, blockIdx.x, blockIdx.y, fold, lds);
+    int patch, split;
+    pair_item(patch, split);
+    dev::pairs_f64f_block<R, PX>(m, sh, z, gam, part, patch, split, fold, lds);
 }
 
 template <int R, int PX>
@@ -46,7 +65,9 @@ __global__ __launch_bounds__(kThreads) void k_pairs_f32(Mesh m, PairShape sh,
                                                         const int* __restrict__ fold)
 {
     __shared__ dev::F32Tile tile;
-    dev::pairs_f32_block<R, PX>(m, sh, z, gam, part, blockIdx.x, blockIdx.y, fold, tile);
+    int patch, split;
+    pair_item(patch, split);
+    dev::pairs_f32_block<R, PX>(m, sh, z, gam, part, patch, split, fold, tile);
 }
 
 // blockIdx.y = pass (0: tie column, 1: tie row); L threads per target
