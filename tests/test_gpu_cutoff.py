@@ -279,3 +279,19 @@ def test_cutoff_stencil_matches_oracle(gpu, n1, n2, rc, seed, bound):
     info = ctx.cutoff_info()
     assert info.pairs_accepted == accepted_pairs(z, rc)
     assert info.pairs_accepted <= info.pairs_tested <= bound * horizontal_pairs(z, rc)
+
+
+@pytest.mark.parametrize("n1,n2,rc", [(128, 96, 0.2), (64, 48, 0.3)])
+def test_cutoff_counted_and_repeated_evaluations_agree_bitwise(gpu, n1, n2, rc):
+    """The pair counters are a variant of the window kernels (whole-wave
+    popcounts): an evaluation with them on gives the same bits as one with
+    them off, and a repeated evaluation gives the same bits again (fixed
+    summation order, no atomics in the sums)."""
+    z, w = drifted_state(n1, n2, 31)
+    p = params(n1, n2, rc)
+    plain, _ = gpu_br(p, z, w, gpu)
+    counted, ctx = gpu_br(p, z, w, gpu, count=True)
+    again, _ = gpu_br(p, z, w, gpu)
+    assert np.array_equal(plain, counted)
+    assert np.array_equal(plain, again)
+    assert ctx.cutoff_info().pairs_accepted == accepted_pairs(z, rc)
