@@ -556,7 +556,8 @@ constexpr int kStCols = kStTX - 2 + kStBw;             // staged source columns
 constexpr int kStHalf = kStCols / 2;                   // entries per parity and row
 constexpr int kStPad = kStHalf + 1;
 constexpr int kStPer = (kStRows * kStCols + kStThreads - 1) / kStThreads;   // staged per lane
-static_assert(kStTX == 32 && kStTY * 16 == kStThreads, "lane layout");
+constexpr int kStPairsX = kStTX / 2;                  // lanes per target row (two targets each)
+static_assert(kStPairsX * kStTY == kStThreads && kStTX % 2 == 0, "lane layout");
 static_assert(kStBw % 2 == 0, "a band starts both parities");
 
 // Index window of one evaluation (the same in every workgroup): alpha radius
@@ -754,6 +755,10 @@ struct StTile {
     dv2 gg[2][kStRows][kStPad];   // (g2, g3)
 };
 
+// Stencil workgroups resident per CU (bounded by the 160 KiB of LDS).
+constexpr long kStGroupsPerCU = (160L * 1024) / (long)sizeof(StTile);
+static_assert(kStGroupsPerCU >= 1, "a staged band must fit the LDS");
+
 // One source against the lane's two targets (cut_pair's sums): a target
 // slot no lane accepts skips its evaluation, and one that every active lane
 // accepts takes the kernel weight without the accept select.
@@ -877,7 +882,7 @@ __global__ __launch_bounds__(kStThreads) void k_cut_sten(Mesh m, CutGrid g,
     const int tx = (blk % blocks1) * kStBlk + in % kStBlk, ty = (blk / blocks1) * kStBlk + in / kStBlk;
     if (tx >= tiles1 || ty >= tiles2) return;     // the ragged edge of the block grid
     const int C0 = tx * kStTX, R0 = ty * kStTY;
-    const int tid = threadIdx.x, a = tid & 15, b = tid >> 4;
+    const int tid = threadIdx.x, a = tid % kStPairsX, b = tid / kStPairsX;
 
     CutTarget t[2];
     int tp[2];
@@ -1008,7 +1013,7 @@ CutGrid make_cut_grid(int n1, int n2, double L1, double L2, double rc, bool peri
     g.planes = g.slots;
     if (periodic) {
         const long tiles = (long)((n1 + kStTX - 1) / kStTX) * ((n2 + kStTY - 1) / kStTY);
-        const long want = (8L * 3L * kCUs + tiles - 1) / tiles;
+        const long want = (8L * kStGroupsPerCU * kCUs + tiles - 1) / tiles;
         g.planes = (int)std::max<long>(g.slots, std::min<long>(want, kMaxPlanes));
     }
     const long N = (long)n1 * n2;
