@@ -6,7 +6,7 @@
 // mesh; on one GPU a periodic cell grid rebuilt every evaluation does the
 // same job with a handful of kernels:
 //
-//   k_cut_keys      cell of every point (x, y wrapped into the period cell;
+//   k_cut_prepare   cell of every point (x, y wrapped into the period cell;
 //                   z is not binned: the interface is a sheet) -> sort key
 //   radix sort      stable LSD sort of (key, point) in 8-bit digits:
 //                   k_sort_hist (per-workgroup digit counts), k_sort_scan
@@ -31,7 +31,7 @@
 // lane's source read from a band of the mesh staged in LDS, so a target
 // tests about its own window (1.1 - 1.2 times the pairs it accepts on the
 // paper's workloads).  A larger window falls back to the patch window
-// (k_cut_records, k_cut_win: one 8 x 8 patch of targets per wave,
+// (k_cut_prepare's records, k_cut_win: one 8 x 8 patch of targets per wave,
 // sources read with scalar loads).  The kernels of the paths not taken
 // leave at once; their launches are capped at a few thousand workgroups.
 //
@@ -97,21 +97,6 @@ __device__ inline void wrap_cell(bool periodic, double x, double x0, double L, d
     const double xw = x - f * L;
     c = (int)floor((xw - x0) / cw);
     c = c < 0 ? 0 : (c >= nc ? nc - 1 : c);
-}
-
-__global__ __launch_bounds__(kThreads) void k_cut_keys(Mesh m, CutGrid g, const double* __restrict__ z,
-                                                       unsigned* __restrict__ keys,
-                                                       unsigned* __restrict__ vals,
-                                                       const int* __restrict__ fold)
-{
-    if (window_path(fold, g.periodic)) return;
-    const int p = blockIdx.x * kThreads + threadIdx.x;
-    if (p >= m.N) return;
-    int kx, ky, cx, cy;
-    wrap_cell(g.periodic, z[p], g.x0, g.L1, g.cw1, g.nc1, kx, cx);
-    wrap_cell(g.periodic, z[m.N + p], g.y0, g.L2, g.cw2, g.nc2, ky, cy);
-    keys[p] = (unsigned)cell_key(g, cx, cy);
-    vals[p] = (unsigned)p;
 }
 
 // ---- stable LSD radix sort of (key, value), 8 bits per pass -----------------
@@ -230,12 +215,28 @@ __global__ __launch_bounds__(kThreads) void k_sort_scatter(const unsigned* __res
     }
 }
 
-__global__ __launch_bounds__(kThreads) void k_fill_int(int* __restrict__ a, int n, int v,
-                                                       const int* __restrict__ fold, int periodic)
+// Zero the cell and block bounds and the wrap flags of the cell path (one
+// launch for the five arrays: start, end, kflag have nkeys entries, bstart
+// and bend one per target block).
+__global__ __launch_bounds__(kThreads) void k_cut_clear(int* __restrict__ start,
+                                                        int* __restrict__ end,
+                                                        int* __restrict__ kflag,
+                                                        int* __restrict__ bstart,
+                                                        int* __restrict__ bend, int nkeys,
+                                                        int nblk, const int* __restrict__ fold,
+                                                        int periodic)
 {
     if (window_path(fold, periodic)) return;
     const int i = blockIdx.x * kThreads + threadIdx.x;
-    if (i < n) a[i] = v;
+    if (i < nkeys) {
+        start[i] = 0;
+        end[i] = 0;
+        kflag[i] = 0;
+    }
+    if (i < nblk) {
+        bstart[i] = 0;
+        bend[i] = 0;
+    }
 }
 
 __global__ void k_fill_u64(unsigned long long* __restrict__ a, int n)
@@ -612,17 +613,31 @@ __device__ inline bool sten_fits(const Mesh& m, const WinGeom& w)
            m.n2 >= kStRows;
 }
 
-// Records (x, y, z, g1, g2, g3, 0, 0) in index order.
-__global__ __launch_bounds__(kThreads) void k_cut_records(Mesh m, CutGrid g,
+// First pass over the points, per path: the cell path's sort keys (cell
+// of every point, x and y wrapped into the period cell; z is not binned:
+// the interface is a sheet) and point indices; the patch window's records
+// (x, y, z, g1, g2, g3, 0, 0) in index order; nothing for the stencil, which
+// reads the planes.
+__global__ __launch_bounds__(kThreads) void k_cut_prepare(Mesh m, CutGrid g,
                                                           const double* __restrict__ z,
                                                           const double* __restrict__ gam,
+                                                          unsigned* __restrict__ keys,
+                                                          unsigned* __restrict__ vals,
                                                           double* __restrict__ src,
                                                           const int* __restrict__ fold)
 {
-    if (!window_path(fold, g.periodic)) return;
-    if (sten_fits(m, win_geom(m, g, fold))) return;   // the stencil reads the planes
     const int p = blockIdx.x * kThreads + threadIdx.x;
     const int N = m.N;
+    if (!window_path(fold, g.periodic)) {
+        if (p >= N) return;
+        int kx, ky, cx, cy;
+        wrap_cell(g.periodic, z[p], g.x0, g.L1, g.cw1, g.nc1, kx, cx);
+        wrap_cell(g.periodic, z[N + p], g.y0, g.L2, g.cw2, g.nc2, ky, cy);
+        keys[p] = (unsigned)cell_key(g, cx, cy);
+        vals[p] = (unsigned)p;
+        return;
+    }
+    if (sten_fits(m, win_geom(m, g, fold))) return;
     if (p >= N) return;
     double* r = src + (size_t)p * 8;
     r[0] = z[p];
@@ -1037,8 +1052,8 @@ hipError_t launch_cut_cells(const Mesh& m, const CutGrid& g, const double* z, co
     const int N = m.N;
     const dim3 blk(kThreads);
     const int per = g.periodic;
-    hipLaunchKernelGGL(k_cut_records, dim3(grid_for(N)), blk, 0, s, m, g, z, gam, b.src, fold);
-    hipLaunchKernelGGL(k_cut_keys, dim3(grid_for(N)), blk, 0, s, m, g, z, b.keys[0], b.vals[0], fold);
+    hipLaunchKernelGGL(k_cut_prepare, dim3(grid_for(N)), blk, 0, s, m, g, z, gam, b.keys[0],
+                       b.vals[0], b.src, fold);
     const int G = g.sort_blocks;
     const int seg = ((N + G - 1) / G + kThreads - 1) / kThreads * kThreads;
     int cur = 0;
@@ -1051,11 +1066,8 @@ hipError_t launch_cut_cells(const Mesh& m, const CutGrid& g, const double* z, co
         cur ^= 1;
     }
     const int nblk = g.nb1 * g.nb2;
-    hipLaunchKernelGGL(k_fill_int, dim3(grid_for(g.nkeys)), blk, 0, s, b.start, g.nkeys, 0, fold, per);
-    hipLaunchKernelGGL(k_fill_int, dim3(grid_for(g.nkeys)), blk, 0, s, b.end, g.nkeys, 0, fold, per);
-    hipLaunchKernelGGL(k_fill_int, dim3(grid_for(nblk)), blk, 0, s, b.bstart, nblk, 0, fold, per);
-    hipLaunchKernelGGL(k_fill_int, dim3(grid_for(nblk)), blk, 0, s, b.bend, nblk, 0, fold, per);
-    hipLaunchKernelGGL(k_fill_int, dim3(grid_for(g.nkeys)), blk, 0, s, b.kflag, g.nkeys, 0, fold, per);
+    hipLaunchKernelGGL(k_cut_clear, dim3(grid_for(std::max(g.nkeys, nblk))), blk, 0, s, b.start,
+                       b.end, b.kflag, b.bstart, b.bend, g.nkeys, nblk, fold, per);
     hipLaunchKernelGGL(k_cut_bounds, dim3(grid_for(N)), blk, 0, s, g, N, b.keys[cur], b.start,
                        b.end, b.bstart, b.bend, fold);
     hipLaunchKernelGGL(k_cut_gather, dim3(grid_for(N)), blk, 0, s, m, g, z, gam, b.vals[cur], b.src,
