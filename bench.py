@@ -996,7 +996,7 @@ def main():
     achieved = FLOPS_PER_PAIR * info.pairs_per_eval / r["avg_pair_s"] / 1e12
     roof = {"kernel": kernel, "bound": "alu", "achieved": achieved, "peak": peak,
             "unit": "TFLOP/s", "frac": achieved / peak,
-            "traffic": measured_traffic(kernel, wl.name), "traffic_unit": "B",
+            "traffic": measured_traffic(kernel, wl.name),
             "flops_per_pair": FLOPS_PER_PAIR, "avg_launch_ms": r["avg_pair_s"] * 1e3,
             "launches": r["pair_launches"]}
     xf = executed_flops_per_pair(kernel, wl.name)
@@ -1034,9 +1034,9 @@ def main():
         "dtype": "f32" if prec32 else "f64",
         "data": "synthetic",
         "config": {
-            "workload": wl.name, "mesh": f"{wl.n1}x{wl.n2}", "points": wl.n,
+            "workload": wl.name, "mesh": f"{wl.n1}x{wl.n2}",
             "modes": wl.modes, "eps_over_h": wl.eps_over_h, "atwood": wl.atwood, "dt": wl.dt,
-            "precision": wl.precision, "pairs_per_step": r["pairs_per_step"],
+            "precision": wl.precision,
             "pair_shape": f"R{info.targets_per_lane} S{info.source_splits} WG{info.workgroups}",
         },
         "roofline": roof,
@@ -1076,9 +1076,10 @@ def main():
         log("64-member ensemble")
         en = ensemble64(zm, torch)
         detail["ensemble64"] = en
-        extras["ensemble64"] = {"pairs_per_s": en["pairs_per_s"],
+        extras["ensemble64"] = {"tera_pairs_per_s": en["pairs_per_s"] / 1e12,
                                 "frac_of_fp32_peak": en["frac_of_fp32_peak"],
-                                "default_shapes_pairs_per_s": en["default_shapes_pairs_per_s"],
+                                "default_shapes_tera_pairs_per_s":
+                                    en["default_shapes_pairs_per_s"] / 1e12,
                                 "solo_bitwise": f"{en['solo_vs_batch']['bitwise_equal']}/"
                                                 f"{en['solo_vs_batch']['members_checked']}"}
         if not args.no_sections:
@@ -1088,7 +1089,7 @@ def main():
                 detail[key] = fn(zm, torch)
             cut = detail["cutoff"]
             extras["cutoff"] = {
-                side: {"acc_per_s": c["accepted_pairs_per_s"],
+                side: {"giga_acc_per_s": c["accepted_pairs_per_s"] / 1e9,
                        "tested_per_acc": c["pairs_tested_per_eval"] / c["pairs_accepted_per_eval"],
                        "pair_ms": c["kernel_ms"]["pairs"]}
                 for side, c in (("768", cut["multimode768"]), ("512", cut["singlemode512"]))}
@@ -1096,8 +1097,8 @@ def main():
         sv = serving(zm, torch, count=args.serve_requests, max_seconds=args.serve_max_seconds)
         detail["serving"] = sv
         extras["serving"] = {k: sv[k] for k in ("p50_step_ms", "p99_step_ms", "queue_delay_p99_s",
-                                                "pairs_per_s", "arrived", "finished",
-                                                "time_compression")}
+                                                "arrived", "finished", "time_compression")}
+        extras["serving"]["tera_pairs_per_s"] = sv["pairs_per_s"] / 1e12
         extras["serving"]["solo_bitwise"] = (f"{sv['solo_vs_mix']['bitwise_equal']}/"
                                              f"{sv['solo_vs_mix']['requests_checked']}")
     if args.detail_out:
