@@ -859,6 +859,13 @@ __device__ __forceinline__ void sten_band(const Mesh& m, const CutGrid& g, const
             step(sx, 1, a + ((sx - dx0) >> 1));
             ++sx;
         }
+        for (; sx + 3 < shi; sx += 4) {   // four steps: two entries of each parity
+            const int hc = a + ((sx - dx0) >> 1);
+            step(sx, 0, hc);
+            step(sx + 1, 1, hc);
+            step(sx + 2, 0, hc + 1);
+            step(sx + 3, 1, hc + 1);
+        }
         for (; sx + 1 < shi; sx += 2) {
             const int hc = a + ((sx - dx0) >> 1);
             step(sx, 0, hc);
