@@ -796,10 +796,8 @@ __device__ __forceinline__ void sten_pair(const Mesh& m, const CutGrid& g, const
         dd[q] = r1[q] * r1[q] + r2[q] * r2[q] + r3[q] * r3[q];
         in[q] = dd[q] < g.rc2;
         any[q] = __builtin_amdgcn_ballot_w64(in[q]) & t[q].amask;
-        if (COUNT) {   // whole-wave counts (scalar work, the same in every lane)
-            tested += (unsigned long long)__popcll(t[q].amask);
-            accepted += (unsigned long long)__popcll(any[q]);
-        }
+        // whole-wave count (scalar work); the tested pairs are counted per row
+        if (COUNT) accepted += (unsigned long long)__popcll(any[q]);
     }
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
@@ -827,6 +825,10 @@ __device__ __forceinline__ void sten_band(const Mesh& m, const CutGrid& g, const
         const int dm = win_chord(m, wg, dy);
         const int slo = max(dx0, -dm), shi = min(dx0 + kStBw, dm + 2);
         if (slo >= shi) continue;
+        // every step of the row tests each active target once
+        if (COUNT)
+            tested += (unsigned long long)(shi - slo) *
+                      (unsigned long long)(__popcll(t[0].amask) + __popcll(t[1].amask));
         const int rr = b + dy - dy0;
         // an active target's source lies less than one period outside the
         // mesh, so its wrap count is -1, 0 or 1 and S L is -L, 0 or L exactly
