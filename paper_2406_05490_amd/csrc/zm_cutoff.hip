@@ -461,6 +461,14 @@ __global__ __launch_bounds__(kCutThreads) void k_cut_pairs(Mesh m, CutGrid g,
     // mostly the same cells) measured 7% slower at 768^2 and 15% at 512^2.
     const int N = m.N;
     const int lane = threadIdx.x;
+    // the reduction sums partial sums [0, planes); this path writes
+    // [0, slots) below and zeroes the rest here
+    {
+        const long nz = (long)(g.planes - g.slots) * 3 * N;
+        double* pz = part + (long)g.slots * 3 * N;
+        for (long i = (long)blockIdx.x * kCutThreads + lane; i < nz; i += (long)gridDim.x * kCutThreads)
+            pz[i] = 0.0;
+    }
     const int nblk = g.nb1 * g.nb2;
     const long items = (long)nblk * g.slots * g.chunks;
     unsigned long long tested = 0, accepted = 0;
@@ -991,19 +999,6 @@ __global__ __launch_bounds__(kStThreads) void k_cut_sten(Mesh m, CutGrid g,
     }
 }
 
-// The cell path writes partial sums [0, slots); the reduction sums
-// [0, planes): zero the rest (the window kernels write every plane).
-__global__ __launch_bounds__(kThreads) void k_cut_zero_planes(Mesh m, CutGrid g,
-                                                              double* __restrict__ part,
-                                                              const int* __restrict__ fold)
-{
-    if (window_path(fold, g.periodic)) return;
-    const long n = (long)(g.planes - g.slots) * 3 * m.N;
-    double* p = part + (long)g.slots * 3 * m.N;
-    for (long i = (long)blockIdx.x * kThreads + threadIdx.x; i < n; i += (long)gridDim.x * kThreads)
-        p[i] = 0.0;
-}
-
 inline unsigned grid_for(long n) { return (unsigned)((n + kThreads - 1) / kThreads); }
 
 }  // namespace
@@ -1101,8 +1096,6 @@ hipError_t launch_cut_pairs(const Mesh& m, const CutGrid& g, const double* z, co
         hipLaunchKernelGGL((k_cut_pairs<false, kCutTargetsPerLane>), grid, dim3(kCutThreads), 0, s,
                            m, g, b.src, b.start, b.end, b.bstart, b.bend, b.kflag, order, part,
                            b.counts, fold);
-    if (g.planes > g.slots)
-        hipLaunchKernelGGL(k_cut_zero_planes, dim3(1024), dim3(kThreads), 0, s, m, g, part, fold);
     // the index-window path: patch window or per-target stencil (the
     // workgroups of the kernels not taking the evaluation leave at once)
     const long win_items = (long)((m.n1 + 7) / 8) * ((m.n2 + 7) / 8) * g.planes;
