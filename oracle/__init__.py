@@ -89,6 +89,8 @@ def _load():
     lib.zmo_rhs.restype = ctypes.c_int
     lib.zmo_rhs_sampled.argtypes = [P, D, D, ctypes.c_int64, I64, D, D, ctypes.c_int]
     lib.zmo_rhs_sampled.restype = ctypes.c_int
+    lib.zmo_wt_sampled.argtypes = [P, D, D, D, ctypes.c_int64, I64, D]
+    lib.zmo_wt_sampled.restype = ctypes.c_int
     lib.zmo_rk3_step.argtypes = [P, D, D, ctypes.c_int, ctypes.c_int]
     lib.zmo_rk3_step.restype = ctypes.c_int
     _lib = lib
@@ -181,6 +183,20 @@ def rhs_sampled(P: Problem, z, w, targets, threads: int = 0):
     if rc:
         raise ValueError("oracle: bad arguments to rhs_sampled")
     return zt, wt
+
+
+def wt_sampled(P: Problem, z, w, u, targets):
+    """The vorticity derivative at the listed point indices, shape (2, nt),
+    with the velocity in V given as the full field ``u`` (shape (3, N)): the
+    medium-order w_t when ``u`` is the FFT velocity."""
+    lib = _load()
+    z = _planes(z, 3, P.n); w = _planes(w, 2, P.n); u = _planes(u, 3, P.n)
+    nt, t, tp = _targets(targets)
+    wt = np.empty((2, nt))
+    rc = lib.zmo_wt_sampled(ctypes.byref(P.c()), _dp(z), _dp(w), _dp(u), nt, tp, _dp(wt))
+    if rc:
+        raise ValueError("oracle: bad arguments to wt_sampled")
+    return wt
 
 
 def rk3(P: Problem, z, w, nsteps: int, threads: int = 0):

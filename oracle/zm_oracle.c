@@ -602,6 +602,34 @@ int zmo_rhs(const zmo_problem *P, const double *z, const double *w,
     return 0;
 }
 
+/* The 9 points the vorticity derivative at a target reads: 0 the centre,
+ * 1..4 axis-1 offsets -2,-1,+1,+2, 5..8 the same along axis 2. */
+static const int stencil_off1[9] = {0, -2, -1, 1, 2, 0, 0, 0, 0};
+static const int stencil_off2[9] = {0, 0, 0, 0, 0, -2, -1, 1, 2};
+
+/* wt[c * ntargets + t] = D_c V + nu Lap(w_c) at point index p, from V at the
+ * 9 stencil points (centred fourth-order differences, as zmo_rhs takes). */
+static void wt_from_stencil(const zmo_problem *P, const double *w, const double V[9],
+                            int64_t p, int64_t ntargets, int64_t t, double *wt)
+{
+    const int n1 = P->n1;
+    const size_t N = (size_t)n1 * P->n2;
+    const double h1 = P->period1 / n1, h2 = P->period2 / P->n2;
+    wt[t] = d1_5pt(V[1], V[2], V[3], V[4], h1);
+    wt[ntargets + t] = d1_5pt(V[5], V[6], V[7], V[8], h2);
+    if (P->nu != 0.0) {
+        const int i1 = (int)(p % n1), i2 = (int)(p / n1);
+        for (int c = 0; c < 2; ++c) {
+            const double *f = w + c * N;
+            double lap = d2_5pt(f_at(P, f, i1 - 2, i2), f_at(P, f, i1 - 1, i2), f_at(P, f, i1, i2),
+                                f_at(P, f, i1 + 1, i2), f_at(P, f, i1 + 2, i2), h1)
+                       + d2_5pt(f_at(P, f, i1, i2 - 2), f_at(P, f, i1, i2 - 1), f_at(P, f, i1, i2),
+                                f_at(P, f, i1, i2 + 1), f_at(P, f, i1, i2 + 2), h2);
+            wt[c * ntargets + t] = wt[c * ntargets + t] + P->nu * lap;
+        }
+    }
+}
+
 /* F at listed targets only.  The BR velocity is evaluated at each target and
  * at its +-1, +-2 stencil neighbours along both axes (V is needed there).
  * zt: 3 planes of length ntargets, wt: 2 planes of length ntargets. */
@@ -614,12 +642,8 @@ int zmo_rhs_sampled(const zmo_problem *P, const double *z, const double *w,
         return -1;
     const int n1 = P->n1, n2 = P->n2;
     const size_t N = (size_t)n1 * n2;
-    const double h1 = P->period1 / n1, h2 = P->period2 / n2;
     for (int64_t t = 0; t < ntargets; ++t)
         if (targets[t] < 0 || (size_t)targets[t] >= N) return -1;
-    /* stencil points: 0 centre, 1..4 axis-1 offsets -2,-1,+1,+2, 5..8 axis-2 */
-    static const int off1[9] = {0, -2, -1, 1, 2, 0, 0, 0, 0};
-    static const int off2[9] = {0, 0, 0, 0, 0, -2, -1, 1, 2};
     const int64_t ns = 9 * ntargets;
     int64_t *pts = (int64_t *)malloc(sizeof(int64_t) * (size_t)(ns > 0 ? ns : 1));
     double *us = (double *)malloc(sizeof(double) * 3 * (size_t)(ns > 0 ? ns : 1));
@@ -629,8 +653,8 @@ int zmo_rhs_sampled(const zmo_problem *P, const double *z, const double *w,
         int i1 = (int)(targets[t] % n1), i2 = (int)(targets[t] / n1);
         for (int k = 0; k < 9; ++k) {
             int w1, w2;
-            int j1 = wrap_index(i1 + off1[k], n1, &w1);
-            int j2 = wrap_index(i2 + off2[k], n2, &w2);
+            int j1 = wrap_index(i1 + stencil_off1[k], n1, &w1);
+            int j2 = wrap_index(i2 + stencil_off2[k], n2, &w2);
             pts[9 * t + k] = (int64_t)j2 * n1 + j1;
         }
     }
@@ -648,21 +672,44 @@ int zmo_rhs_sampled(const zmo_problem *P, const double *z, const double *w,
         zt[t] = us[s0];
         zt[ntargets + t] = us[ns + s0];
         zt[2 * ntargets + t] = us[2 * ns + s0];
-        wt[t] = d1_5pt(V[1], V[2], V[3], V[4], h1);
-        wt[ntargets + t] = d1_5pt(V[5], V[6], V[7], V[8], h2);
-        if (P->nu != 0.0) {
-            int i1 = (int)(targets[t] % n1), i2 = (int)(targets[t] / n1);
-            for (int c = 0; c < 2; ++c) {
-                const double *f = w + c * N;
-                double lap = d2_5pt(f_at(P, f, i1 - 2, i2), f_at(P, f, i1 - 1, i2), f_at(P, f, i1, i2),
-                                    f_at(P, f, i1 + 1, i2), f_at(P, f, i1 + 2, i2), h1)
-                           + d2_5pt(f_at(P, f, i1, i2 - 2), f_at(P, f, i1, i2 - 1), f_at(P, f, i1, i2),
-                                    f_at(P, f, i1, i2 + 1), f_at(P, f, i1, i2 + 2), h2);
-                wt[c * ntargets + t] = wt[c * ntargets + t] + P->nu * lap;
-            }
-        }
+        wt_from_stencil(P, w, V, targets[t], ntargets, t, wt);
     }
     free(pts); free(us); free(buf);
+    return 0;
+}
+
+/* w_t = (D1 V, D2 V) + nu Lap(w) at listed targets, with the velocity in V
+ * supplied as a full field uv (3 planes of length N).  The medium-order model
+ * takes that velocity from the FFT solver (sec. 2; sec. 6), so a caller can
+ * hand in an FFT velocity computed elsewhere where the direct DFT above is
+ * too slow for the mesh.  Periodic sheets only; wt: 2 planes of length
+ * ntargets. */
+int zmo_wt_sampled(const zmo_problem *P, const double *z, const double *w, const double *uv,
+                   int64_t ntargets, const int64_t *targets, double *wt)
+{
+    if (!P || P->n1 < 1 || P->n2 < 1 || ntargets < 0 || !targets || !uv || P->boundary != 0)
+        return -1;
+    const int n1 = P->n1, n2 = P->n2;
+    const size_t N = (size_t)n1 * n2;
+    for (int64_t t = 0; t < ntargets; ++t)
+        if (targets[t] < 0 || (size_t)targets[t] >= N) return -1;
+    double *buf = (double *)malloc(sizeof(double) * 10 * N);
+    if (!buf) return -1;
+    double *t1 = buf, *t2 = buf + 3 * N, *gamma = buf + 6 * N, *q = buf + 9 * N;
+    zmo_surface(P, z, w, t1, t2, gamma, q);
+    for (int64_t t = 0; t < ntargets; ++t) {
+        const int i1 = (int)(targets[t] % n1), i2 = (int)(targets[t] / n1);
+        double V[9];
+        for (int k = 0; k < 9; ++k) {
+            int w1, w2;
+            const int j1 = wrap_index(i1 + stencil_off1[k], n1, &w1);
+            const int j2 = wrap_index(i2 + stencil_off2[k], n2, &w2);
+            const size_t p = (size_t)j2 * n1 + j1;
+            V[k] = bernoulli(P, uv[p], uv[N + p], uv[2 * N + p], q[p], z[2 * N + p]);
+        }
+        wt_from_stencil(P, w, V, targets[t], ntargets, t, wt);
+    }
+    free(buf);
     return 0;
 }
 
@@ -704,4 +751,4 @@ int zmo_rk3_step(const zmo_problem *P, double *z, double *w, int nsteps, int nth
     return 0;
 }
 
-int zmo_abi_version(void) { return 4; }
+int zmo_abi_version(void) { return 5; }

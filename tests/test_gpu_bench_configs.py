@@ -82,9 +82,11 @@ def test_low_order_4096_against_numpy_fft(gpu):
 @pytest.mark.parametrize("n,rc", [(512, 0.0), (1024, 0.2 * 2.0 / 6.0)])
 def test_medium_bench_configs(gpu, n, rc):
     """Medium order at the benchmark sizes: the sheet velocity (= the BR
-    velocity) against the oracle on sampled targets, and the vorticity
-    derivative bit for bit equal to the low-order model's on the same state
-    (both take V from the same FFT velocity)."""
+    velocity) against the oracle on sampled targets; the vorticity derivative
+    against the oracle's V and difference stencil fed numpy's FFT velocity
+    (the oracle's direct DFT would take hours here), and bit for bit equal to
+    the low-order model's on the same state (both take V from the same FFT
+    velocity)."""
     import paper_2406_05490_amd as zm
     z, _ = rr.multi_mode(n, n, 8, seed=1)
     w = rr.synthetic_vorticity(n, n, seed=1)
@@ -93,5 +95,7 @@ def test_medium_bench_configs(gpu, n, rc):
     idx = sampled(n, seed=n + 1)
     ref = oracle.br_velocity(oparams(pm), z, w, targets=idx)
     assert relerr(zt[:, idx], ref) < TOL64
+    wref = oracle.wt_sampled(oparams(pm), z, w, fft_reference(n, n, z, w), idx)
+    assert relerr(wt[:, idx], wref) < TOL64
     _, wt_low = gpu_rhs(zm.Params(n, n, eps=1.0 / n, model=zm.ZM_MODEL_LOW), z, w, gpu)
     assert np.array_equal(wt, wt_low)
