@@ -776,6 +776,7 @@ struct StTile {
     dv2 xy[2][kStRows][kStPad];
     dv2 zg[2][kStRows][kStPad];   // (z, g1)
     dv2 gg[2][kStRows][kStPad];   // (g2, g3)
+    int chord[kStBh];             // win_chord of the band's rows dy0 .. dy0 + kStBh - 1
 };
 
 // Stencil workgroups resident per CU (bounded by the 160 KiB of LDS).
@@ -830,7 +831,8 @@ __device__ __forceinline__ void sten_band(const Mesh& m, const CutGrid& g, const
 {
     const int dyhi = min(dy0 + kStBh, wg.W2 + 1);
     for (int dy = dy0; dy < dyhi; ++dy) {
-        const int dm = win_chord(m, wg, dy);
+        // the same value in every lane (staged with the band)
+        const int dm = __builtin_amdgcn_readfirstlane(T.chord[dy - dy0]);
         const int slo = max(dx0, -dm), shi = min(dx0 + kStBw, dm + 2);
         if (slo >= shi) continue;
         // every step of the row tests each active target once
@@ -972,6 +974,9 @@ __global__ __launch_bounds__(kStThreads) void k_cut_sten(Mesh m, CutGrid g,
                     T.gg[par][rr][hc] = v[i][2];
                 }
             }
+            // the rows' chords (a square root and a division each), once per
+            // band instead of once per row in every wave
+            if (tid < kStBh) T.chord[tid] = win_chord(m, wg, dy0 + tid);
             __syncthreads();
             const bool seam = C0 + dx0 < 0 || C0 + dx0 + kStCols > n1 || R0 + dy0 < 0 ||
                               R0 + dy0 + kStRows > n2;
