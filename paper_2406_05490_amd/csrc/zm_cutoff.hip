@@ -783,9 +783,10 @@ struct StTile {
 constexpr long kStGroupsPerCU = (160L * 1024) / (long)sizeof(StTile);
 static_assert(kStGroupsPerCU >= 1, "a staged band must fit the LDS");
 
-// One source against the lane's two targets (cut_pair's sums): a target
-// slot no lane accepts skips its evaluation, and one that every active lane
-// accepts takes the kernel weight without the accept select.
+// One source against the lane's two targets (cut_pair's sums): a source that
+// no lane accepts for either target is skipped; otherwise both targets take
+// the kernel weight through the accept select in one block (the two
+// reciprocal square roots overlap), an unaccepted pair adding exact zeros.
 template <bool SEAM, bool COUNT>
 __device__ __forceinline__ void sten_pair(const Mesh& m, const CutGrid& g, const CutTarget (&t)[2],
                                           const SrcRec& b, const double (&d1)[2], double SL1,
@@ -808,11 +809,11 @@ __device__ __forceinline__ void sten_pair(const Mesh& m, const CutGrid& g, const
         // whole-wave count (scalar work); the tested pairs are counted per row
         if (COUNT) accepted += (unsigned long long)__popcll(any[q]);
     }
+    if ((any[0] | any[1]) == 0ull) return;
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
-        if (any[q] == 0ull) continue;
         double wgt = dev::inv_cube_sqrt(dd[q] + m.eps2);
-        if (any[q] != t[q].amask) wgt = in[q] ? wgt : 0.0;
+        wgt = in[q] ? wgt : 0.0;
         const double a1 = wgt * b.g1, a2 = wgt * b.g2, a3 = wgt * b.g3;
         acc[q][0] = fma(r2[q], a3, acc[q][0]);
         acc[q][0] = fma(-r3[q], a2, acc[q][0]);
@@ -848,14 +849,16 @@ __device__ __forceinline__ void sten_band(const Mesh& m, const CutGrid& g, const
             const int r = R0 + b + dy;
             SL2 = r < 0 ? -g.L2 : (r >= m.n2 ? g.L2 : 0.0);
         }
-        // offsets o = sx - dx0 in even / odd pairs: both read entry a + o / 2
-        // of the two parity planes (one address, immediate offsets)
-        auto step = [&](int sx, int par, int hc) {
+        // offset o = sx - dx0 reads entry a + o / 2 of parity plane o & 1.
+        // In runs of four steps each step's source is read before the step
+        // ahead of it evaluates, so the LDS latency overlaps arithmetic.
+        struct Rec { dv2 xy, zg, gg; };
+        auto fetch = [&](int par, int hc) {
+            return Rec{T.xy[par][rr][hc], T.zg[par][rr][hc], T.gg[par][rr][hc]};
+        };
+        auto step = [&](int sx, const Rec& r) {
 #pragma clang fp contract(off)
-            const dv2 xy = T.xy[par][rr][hc];
-            const dv2 zg = T.zg[par][rr][hc];
-            const dv2 gg = T.gg[par][rr][hc];
-            const SrcRec rec{xy.x, xy.y, zg.x, zg.y, gg.x, gg.y, 0.0, 0.0};
+            const SrcRec rec{r.xy.x, r.xy.y, r.zg.x, r.zg.y, r.gg.x, r.gg.y, 0.0, 0.0};
             double SL1 = 0.0;
             if (SEAM) {
                 const int c = C0 + 2 * a + sx;
@@ -868,22 +871,28 @@ __device__ __forceinline__ void sten_band(const Mesh& m, const CutGrid& g, const
         };
         int sx = slo;
         if ((sx - dx0) & 1) {
-            step(sx, 1, a + ((sx - dx0) >> 1));
+            step(sx, fetch(1, a + ((sx - dx0) >> 1)));
             ++sx;
         }
-        for (; sx + 3 < shi; sx += 4) {   // four steps: two entries of each parity
+        for (; sx + 3 < shi; sx += 4) {   // two entries of each parity
             const int hc = a + ((sx - dx0) >> 1);
-            step(sx, 0, hc);
-            step(sx + 1, 1, hc);
-            step(sx + 2, 0, hc + 1);
-            step(sx + 3, 1, hc + 1);
+            const Rec r0 = fetch(0, hc);
+            const Rec r1 = fetch(1, hc);
+            step(sx, r0);
+            const Rec r2 = fetch(0, hc + 1);
+            step(sx + 1, r1);
+            const Rec r3 = fetch(1, hc + 1);
+            step(sx + 2, r2);
+            step(sx + 3, r3);
         }
         for (; sx + 1 < shi; sx += 2) {
             const int hc = a + ((sx - dx0) >> 1);
-            step(sx, 0, hc);
-            step(sx + 1, 1, hc);
+            const Rec r0 = fetch(0, hc);
+            const Rec r1 = fetch(1, hc);
+            step(sx, r0);
+            step(sx + 1, r1);
         }
-        if (sx < shi) step(sx, 0, a + ((sx - dx0) >> 1));
+        if (sx < shi) step(sx, fetch(0, a + ((sx - dx0) >> 1)));
     }
 }
 
