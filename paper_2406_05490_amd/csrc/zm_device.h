@@ -276,6 +276,7 @@ __device__ __forceinline__ FoldStat fold_stat(const double T1[3], const double T
     return st;
 }
 
+template <int PER = -1>
 __device__ __forceinline__ FoldStat surface_point(const Mesh& m, int p, const double* __restrict__ z,
                                                   const double* __restrict__ w,
                                                   double* __restrict__ gam, double* __restrict__ q)
@@ -283,7 +284,7 @@ __device__ __forceinline__ FoldStat surface_point(const Mesh& m, int p, const do
     if (p >= m.N) return FoldStat{__builtin_inff(), 0.f, 0.f, 0};
     const int N = m.N;
     double T1[3], T2[3];
-    tangents_at(m, p, z, T1, T2);
+    tangents_at<PER>(m, p, z, T1, T2);
     const double w1 = w[p], w2 = w[N + p];
     const double g1 = w1 * T2[0] - w2 * T1[0];
     const double g2 = w1 * T2[1] - w2 * T1[1];

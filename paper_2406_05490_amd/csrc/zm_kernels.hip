@@ -12,6 +12,9 @@ namespace {
 
 using dev::kThreads;
 
+// PER: 1 periodic sheet, 0 free sheet (the stencils without the other
+// boundary's branches).
+template <int PER>
 __global__ __launch_bounds__(kThreads) void k_surface(Mesh m, const double* __restrict__ z,
                                                       const double* __restrict__ w,
                                                       double* __restrict__ gam,
@@ -23,7 +26,7 @@ __global__ __launch_bounds__(kThreads) void k_surface(Mesh m, const double* __re
     // same words)
     dev::FoldStat st{__builtin_inff(), 0.f, 0.f, 0};
     for (int p = blockIdx.x * kThreads + threadIdx.x; p < m.N; p += gridDim.x * kThreads)
-        st = dev::fold_merge(st, dev::surface_point(m, p, z, w, gam, q));
+        st = dev::fold_merge(st, dev::surface_point<PER>(m, p, z, w, gam, q));
     if (fold) dev::fold_gather(st, fold, gridDim.x);
 }
 
@@ -200,7 +203,10 @@ hipError_t launch_surface(const Mesh& m, const double* z, const double* w, doubl
                           int* fold, hipStream_t s)
 {
     const int groups = std::min(blocks_for(m.N), kSurfaceGroups);
-    hipLaunchKernelGGL(k_surface, dim3(groups), dim3(kThreads), 0, s, m, z, w, gam, q, fold);
+    if (m.periodic)
+        hipLaunchKernelGGL(k_surface<1>, dim3(groups), dim3(kThreads), 0, s, m, z, w, gam, q, fold);
+    else
+        hipLaunchKernelGGL(k_surface<0>, dim3(groups), dim3(kThreads), 0, s, m, z, w, gam, q, fold);
     return hipGetLastError();
 }
 
