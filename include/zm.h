@@ -246,27 +246,42 @@ zm_status zm_profile_read(zm_ctx *ctx, zm_kernel_stats *out);
 /* ---- cutoff solver ---------------------------------------------------------- */
 /*
  * A context with params.cutoff = rc > 0 evaluates the BR velocity with the
- * cutoff solver: points are binned into a grid of cells of side
- * >= rc / cells_per_cutoff in x and y over the period cell [-L_a/2, L_a/2)
- * (z unbinned; periodic sheet: coordinates wrap; free sheet: cells clamp to
- * the box, so points that left it fill the edge cells), sorted by cell (stable,
- * so the source order and every result are deterministic), and each target
- * visits the cells within cells_per_cutoff of its own.  With timing enabled
- * (zm_profile_enable) the pair kernel also counts the pairs it tested and
- * the pairs within rc.
+ * cutoff solver (sec. 3.2.2: only sources within rc of a target contribute;
+ * a pair is in when r1^2 + r2^2 + r3^2 < rc^2 for its image-shifted r).  The
+ * device chooses the path per evaluation from the sheet's tangent map:
+ *  - index window, when the horizontal map alpha -> (x, y) keeps one
+ *    orientation and, on a periodic sheet, has sigma_min(J2) > 0, or, on a
+ *    free sheet, stays within ||J2 - I|| < 1/2 of the identity: every source
+ *    within rc then lies within an index disc around its target, which is
+ *    walked per target (stencil) or, for windows too large for that on a
+ *    periodic sheet, per 8 x 8 patch;
+ *  - cell grid otherwise (folded, overturned or strongly stretched sheets):
+ *    points are binned into cells of side >= rc / cells_per_cutoff in x and
+ *    y over the period cell [-L_a/2, L_a/2) (z unbinned; periodic sheet:
+ *    coordinates wrap; free sheet: cells clamp to the box, so points that
+ *    left it fill the edge cells), sorted by cell (stable), and each target
+ *    visits the cells within cells_per_cutoff of its own.
+ * Every path sums each target's sources in a fixed order into `slots`
+ * partial sums reduced in order, so results are deterministic.  With timing
+ * enabled (zm_profile_enable) the pair kernels also count the pairs they
+ * tested and the pairs within rc, and record the paths taken.
  */
+#define ZM_CUT_PATH_CELLS   1  /* cell grid                                    */
+#define ZM_CUT_PATH_WINDOW  2  /* index window per 8 x 8 patch                 */
+#define ZM_CUT_PATH_STENCIL 4  /* index window per target                      */
+
 typedef struct zm_cutoff_info {
     int32_t cells1, cells2;      /* cell grid along x / y                     */
     int32_t cells_per_cutoff;    /* neighbour reach in cells                  */
     int32_t block_cells;         /* target block side in cells                */
     int32_t slots;               /* partial sums per target (reduced in order)*/
-    int32_t reserved;
+    int32_t paths;               /* ZM_CUT_PATH_* bits of the timed evaluations */
     int64_t pairs_tested;        /* pair evaluations, see below               */
     int64_t pairs_accepted;      /* of those, pairs with |r| < rc             */
 } zm_cutoff_info;
 
-/* Cell grid of a cutoff context and the pair counts the timed evaluations
- * (zm_profile_enable on) accumulated since timing was switched on or since
+/* Cell grid of a cutoff context, and the pair counts and paths of the timed
+ * evaluations (zm_profile_enable on) since timing was switched on or since
  * the previous call, which this call resets.  Waits for the context
  * stream.  ZM_ERR_UNSUPPORTED for an exact (cutoff = 0) context. */
 zm_status zm_cutoff_info_get(zm_ctx *ctx, zm_cutoff_info *out);

@@ -13,7 +13,7 @@ from ._zm import (  # noqa: F401
     ZM_ERR_UNSUPPORTED, ZM_ERR_WORKSPACE, ZM_FLAG_CHECK_FINITE, ZM_FP32_PAIRS,
     ZM_FP64, ZM_OK, ZM_MODEL_HIGH, ZM_MODEL_LOW, ZM_MODEL_MEDIUM, ZM_BOUNDARY_PERIODIC,
     ZM_BOUNDARY_FREE, load, status_string, workspace_bytes, br_velocity_noalloc,
-    NOALLOC_SCRATCH_BYTES,
+    NOALLOC_SCRATCH_BYTES, ZM_CUT_PATH_CELLS, ZM_CUT_PATH_WINDOW, ZM_CUT_PATH_STENCIL,
 )
 
 load()

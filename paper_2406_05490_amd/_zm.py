@@ -32,6 +32,9 @@ ZM_BOUNDARY_PERIODIC = 0
 ZM_BOUNDARY_FREE = 1
 ZM_FLAG_CHECK_FINITE = 0x1
 ZM_FLAG_GRAPH = 0x2
+ZM_CUT_PATH_CELLS = 1
+ZM_CUT_PATH_WINDOW = 2
+ZM_CUT_PATH_STENCIL = 4
 NOALLOC_SCRATCH_BYTES = 64 * 1024 * 1024   # ZM_NOALLOC_SCRATCH_BYTES
 
 KERNELS = ("surface", "pairs", "ties", "reduce", "update", "cells", "fft")
@@ -59,7 +62,7 @@ class zm_params(ctypes.Structure):
 class zm_cutoff_info(ctypes.Structure):
     _fields_ = [("cells1", ctypes.c_int32), ("cells2", ctypes.c_int32),
                 ("cells_per_cutoff", ctypes.c_int32), ("block_cells", ctypes.c_int32),
-                ("slots", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("slots", ctypes.c_int32), ("paths", ctypes.c_int32),
                 ("pairs_tested", ctypes.c_int64), ("pairs_accepted", ctypes.c_int64)]
 
 

@@ -543,7 +543,10 @@ zm_status zm_cutoff_info_get(zm_ctx* c, zm_cutoff_info* out)
     if (!c->cutoff) return fail(c, ZM_ERR_UNSUPPORTED, "not a cutoff context");
     DeviceGuard g(c->device);
     if (!g.ok) return fail(c, ZM_ERR_HIP, "cannot select the context device");
-    unsigned long long h[2] = {0, 0};
+    static_assert(zm::kCutPathCells == ZM_CUT_PATH_CELLS && zm::kCutPathWindow == ZM_CUT_PATH_WINDOW &&
+                      zm::kCutPathStencil == ZM_CUT_PATH_STENCIL,
+                  "path bits");
+    unsigned long long h[zm::kCutCountWords] = {0, 0, 0};
     hipError_t e = hipMemcpyAsync(h, c->cb.counts, sizeof(h), hipMemcpyDeviceToHost, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e == hipSuccess) e = zm::launch_cut_count_reset(c->cb.counts, c->stream);
@@ -553,7 +556,7 @@ zm_status zm_cutoff_info_get(zm_ctx* c, zm_cutoff_info* out)
     out->cells_per_cutoff = c->cut.m;
     out->block_cells = c->cut.B;
     out->slots = c->cut.planes;
-    out->reserved = 0;
+    out->paths = (int32_t)h[2];
     out->pairs_tested = (int64_t)h[0];
     out->pairs_accepted = (int64_t)h[1];
     return ZM_OK;

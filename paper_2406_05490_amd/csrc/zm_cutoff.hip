@@ -63,16 +63,22 @@ __host__ __device__ inline int cell_key(const CutGrid& g, int cx, int cy)
     return ((by * g.nb1 + bx) * g.B + ly) * g.B + lx;
 }
 
-// Whether this evaluation takes the index-window path: a periodic sheet whose
-// tangent map keeps one orientation everywhere (fold[7]: the signs det J2
-// took, bit 0 positive, bit 1 negative, bit 2 zero or not a number) and has
-// a positive sigma_min(J2)^2 (fold[5]).  Every kernel of either path reads
-// it and the other path's kernels leave at once.
+// Largest ||J2 - I||_2 of a free sheet that takes the index window (its
+// window radius is rc / (1 - d), at most twice the radius at d = 0).
+constexpr float kFreeMaxDev2 = 0.25f;
+
+// Whether this evaluation takes the index-window path: a sheet whose tangent
+// map keeps one orientation everywhere (fold[7]: the signs det J2 took, bit 0
+// positive, bit 1 negative, bit 2 zero or not a number) and, periodic, has a
+// positive sigma_min(J2)^2 (fold[5]) or, free, stays within kFreeMaxDev2 of
+// the identity map (fold[9]: max ||J2 - I||^2).  Every kernel of either path
+// reads it and the other path's kernels leave at once.
 __device__ __forceinline__ bool window_path(const int* __restrict__ fold, int periodic)
 {
-    if (!periodic || fold == nullptr) return false;
+    if (fold == nullptr) return false;
     const int sg = fold[7];
-    return (sg == 1 || sg == 2) && __int_as_float(fold[5]) > 0.f;
+    if (sg != 1 && sg != 2) return false;
+    return periodic ? __int_as_float(fold[5]) > 0.f : __int_as_float(fold[9]) < kFreeMaxDev2;
 }
 
 // Periodic grid: wrap count k (x - k L lies in the period cell [x0, x0 + L))
@@ -547,6 +553,7 @@ __global__ __launch_bounds__(kCutThreads) void k_cut_pairs(Mesh m, CutGrid g,
         if (lane == 0) {
             atomicAdd(&counts[0], tested);
             atomicAdd(&counts[1], accepted);
+            atomicOr(&counts[2], kCutPathCells);
         }
     }
 }
@@ -590,15 +597,24 @@ struct WinGeom {
 __device__ inline WinGeom win_geom(const Mesh& m, const CutGrid& g, const int* __restrict__ fold)
 {
     WinGeom w;
-    const double smin = sqrt((double)__int_as_float(fold[5]));
-    const double hmax = sqrt((double)__int_as_float(fold[9]));
+    // the least ratio of horizontal distance to index distance: sigma_min(J2)
+    // on a periodic sheet, 1 - max ||J2 - I|| on a free one
+    const double hdev = sqrt((double)__int_as_float(fold[9]));
+    const double smin = g.periodic ? sqrt((double)__int_as_float(fold[5])) : 1.0 - hdev;
     const double Ra = sqrt(g.rc2) * 1.02 / smin;
     w.Ra2 = Ra * Ra;
     w.W2 = (int)ceil(Ra / m.h2) + 1;
     w.W1 = (int)ceil(Ra / m.h1) + 1;
+    if (!g.periodic) {
+        // no source of a free sheet lies farther than its side in index
+        w.W1 = min(w.W1, m.n1);
+        w.W2 = min(w.W2, m.n2);
+        w.by_seams = true;   // no images: every shift is 0
+        return w;
+    }
     const double dmax = sqrt((double)(w.W1 + 8) * (w.W1 + 8) * m.h1 * m.h1 +
                              (double)(w.W2 + 8) * (w.W2 + 8) * m.h2 * m.h2);
-    w.by_seams = hmax * dmax < 0.45 * fmin(g.L1, g.L2);
+    w.by_seams = hdev * dmax < 0.45 * fmin(g.L1, g.L2);
     return w;
 }
 
@@ -611,12 +627,14 @@ __device__ inline int win_chord(const Mesh& m, const WinGeom& w, int dy)
     return (int)ceil(half / m.h1) + 1;
 }
 
-// Whether the per-target stencil (k_cut_sten) takes the evaluation: the
-// seam counts give the shifts and no target's window holds a source twice
-// (its 2 W1 + 2 columns and 2 W2 + 1 rows fit the period).  Otherwise the
+// Whether the per-target stencil (k_cut_sten) takes the evaluation: on a
+// periodic sheet the seam counts give the shifts and no target's window holds
+// a source twice (its 2 W1 + 2 columns and 2 W2 + 1 rows fit the period);
+// a free sheet has neither images nor wraps, and always fits.  Otherwise the
 // patch-window kernel (k_cut_win) does.
 __device__ inline bool sten_fits(const Mesh& m, const WinGeom& w)
 {
+    if (!m.periodic) return true;
     return w.by_seams && 2 * w.W1 + 2 <= m.n1 && 2 * w.W2 + 1 <= m.n2 && m.n1 >= kStCols &&
            m.n2 >= kStRows;
 }
@@ -748,6 +766,7 @@ __global__ __launch_bounds__(kCutThreads) void k_cut_win(Mesh m, CutGrid g,
         if (lane == 0) {
             atomicAdd(&counts[0], tested);
             atomicAdd(&counts[1], accepted);
+            atomicOr(&counts[2], kCutPathWindow);
         }
     }
 }
@@ -782,6 +801,11 @@ struct StTile {
 // Stencil workgroups resident per CU (bounded by the 160 KiB of LDS).
 constexpr long kStGroupsPerCU = (160L * 1024) / (long)sizeof(StTile);
 static_assert(kStGroupsPerCU >= 1, "a staged band must fit the LDS");
+
+// Coordinate of a free sheet's off-mesh sources in a staged band: far enough
+// that no pair with a mesh point is accepted, small enough that the squared
+// distance stays finite.
+constexpr double kStFar = 1e150;
 
 // One source against the lane's two targets (cut_pair's sums): a source that
 // no lane accepts for either target is skipped; otherwise both targets take
@@ -896,7 +920,9 @@ __device__ __forceinline__ void sten_band(const Mesh& m, const CutGrid& g, const
     }
 }
 
-template <bool COUNT>
+// PER: the boundary kind the launch was chosen for (1 periodic, 0 free), so
+// that each instance stages one kind of band.
+template <bool COUNT, bool PER>
 __global__ __launch_bounds__(kStThreads) void k_cut_sten(Mesh m, CutGrid g,
                                                          const double* __restrict__ z,
                                                          const double* __restrict__ gam,
@@ -909,6 +935,7 @@ __global__ __launch_bounds__(kStThreads) void k_cut_sten(Mesh m, CutGrid g,
     if (!sten_fits(m, wg)) return;                // uniform: the patch window runs instead
     __shared__ StTile T;
     const int n1 = m.n1, n2 = m.n2, N = m.N;
+    constexpr bool periodic = PER;
     const int tiles1 = (n1 + kStTX - 1) / kStTX;
     // workgroups are dealt round-robin to the XCDs: give each XCD one
     // contiguous run of (tile, slot) items so that the windows of the tiles it
@@ -950,13 +977,23 @@ __global__ __launch_bounds__(kStThreads) void k_cut_sten(Mesh m, CutGrid g,
         const int dm = win_chord(m, wg, dyn);
         for (int dx0 = -wg.W1; dx0 <= wg.W1 + 1; dx0 += kStBw) {
             if (max(dx0, -dm) >= min(dx0 + kStBw, dm + 2)) continue;   // outside the disc
+            // a free sheet's bands whose sources all lie off the mesh
+            if (!periodic && (R0 + dy0 + kStRows <= 0 || R0 + dy0 >= n2 ||
+                              C0 + dx0 + kStCols <= 0 || C0 + dx0 >= n1))
+                continue;
             if (band++ % g.planes != slot) continue;
             // stage the band's sources: every load is issued before the
-            // first LDS write (one round trip per band); the band's first
-            // row and column are wrapped once, the rest by subtraction
+            // first LDS write (one round trip per band).  Periodic: the
+            // band's first row and column are wrapped once, the rest by
+            // subtraction.  Free: a source off the mesh is staged as a point
+            // kStFar away with zero strength, which no target accepts (its
+            // squared distance stays finite, its weight is selected away and
+            // its terms add exact zeros)
             int rb = R0 + dy0, cb = C0 + dx0;
-            rb -= floordiv(rb, n2) * n2;
-            cb -= floordiv(cb, n1) * n1;
+            if (periodic) {
+                rb -= floordiv(rb, n2) * n2;
+                cb -= floordiv(cb, n1) * n1;
+            }
             dv2 v[kStPer][3];
 #pragma unroll
             for (int i = 0; i < kStPer; ++i) {
@@ -964,12 +1001,17 @@ __global__ __launch_bounds__(kStThreads) void k_cut_sten(Mesh m, CutGrid g,
                 const int ee = e < kStRows * kStCols ? e : 0;
                 const int rr = ee / kStCols, cr = ee - rr * kStCols;
                 int r = rb + rr, c = cb + cr;
-                r = r >= n2 ? r - n2 : r;   // one period at most: n2 >= kStRows, n1 >= kStCols
-                c = c >= n1 ? c - n1 : c;
-                const int j = r * n1 + c;
-                v[i][0] = dv2{z[j], z[N + j]};
-                v[i][1] = dv2{z[2 * N + j], gam[j]};
-                v[i][2] = dv2{gam[N + j], gam[2 * N + j]};
+                bool on = true;
+                if (periodic) {
+                    r = r >= n2 ? r - n2 : r;   // one period at most: n2 >= kStRows, n1 >= kStCols
+                    c = c >= n1 ? c - n1 : c;
+                } else {
+                    on = r >= 0 && r < n2 && c >= 0 && c < n1;
+                }
+                const int j = on ? r * n1 + c : 0;
+                v[i][0] = on ? dv2{z[j], z[N + j]} : dv2{kStFar, kStFar};
+                v[i][1] = on ? dv2{z[2 * N + j], gam[j]} : dv2{kStFar, 0.0};
+                v[i][2] = on ? dv2{gam[N + j], gam[2 * N + j]} : dv2{0.0, 0.0};
             }
             __syncthreads();   // the previous band's reads are done
 #pragma unroll
@@ -987,8 +1029,8 @@ __global__ __launch_bounds__(kStThreads) void k_cut_sten(Mesh m, CutGrid g,
             // band instead of once per row in every wave
             if (tid < kStBh) T.chord[tid] = win_chord(m, wg, dy0 + tid);
             __syncthreads();
-            const bool seam = C0 + dx0 < 0 || C0 + dx0 + kStCols > n1 || R0 + dy0 < 0 ||
-                              R0 + dy0 + kStRows > n2;
+            const bool seam = periodic && (C0 + dx0 < 0 || C0 + dx0 + kStCols > n1 ||
+                                           R0 + dy0 < 0 || R0 + dy0 + kStRows > n2);
             if (seam)
                 sten_band<true, COUNT>(m, g, wg, T, C0, R0, a, b, dy0, dx0, t, acc, tested,
                                        accepted);
@@ -1009,6 +1051,7 @@ __global__ __launch_bounds__(kStThreads) void k_cut_sten(Mesh m, CutGrid g,
         if ((tid & 63) == 0) {
             atomicAdd(&counts[0], tested);
             atomicAdd(&counts[1], accepted);
+            atomicOr(&counts[2], kCutPathStencil);
         }
     }
 }
@@ -1043,12 +1086,9 @@ CutGrid make_cut_grid(int n1, int n2, double L1, double L2, double rc, bool peri
     // the index-window kernels split each target's sources over more
     // partial sums when the mesh has few stencil tiles, so that a launch
     // holds about eight rounds of resident workgroups (three per CU)
-    g.planes = g.slots;
-    if (periodic) {
-        const long tiles = (long)((n1 + kStTX - 1) / kStTX) * ((n2 + kStTY - 1) / kStTY);
-        const long want = (8L * kStGroupsPerCU * kCUs + tiles - 1) / tiles;
-        g.planes = (int)std::max<long>(g.slots, std::min<long>(want, kMaxPlanes));
-    }
+    const long tiles = (long)((n1 + kStTX - 1) / kStTX) * ((n2 + kStTY - 1) / kStTY);
+    const long want = (8L * kStGroupsPerCU * kCUs + tiles - 1) / tiles;
+    g.planes = (int)std::max<long>(g.slots, std::min<long>(want, kMaxPlanes));
     const long N = (long)n1 * n2;
     const long per_block = (N + (long)g.nb1 * g.nb2 - 1) / ((long)g.nb1 * g.nb2);
     g.tr = kCutTargetsPerLane;
@@ -1123,18 +1163,23 @@ hipError_t launch_cut_pairs(const Mesh& m, const CutGrid& g, const double* z, co
     const int bl1 = ((m.n1 + kStTX - 1) / kStTX + kStBlk - 1) / kStBlk;
     const int bl2 = ((m.n2 + kStTY - 1) / kStTY + kStBlk - 1) / kStBlk;
     const dim3 sgrid((unsigned)(bl1 * bl2 * kStBlk * kStBlk * g.planes));
-    if (count)
-        hipLaunchKernelGGL((k_cut_sten<true>), sgrid, dim3(kStThreads), 0, s, m, g, z, gam, part,
-                           b.counts, fold);
-    else
-        hipLaunchKernelGGL((k_cut_sten<false>), sgrid, dim3(kStThreads), 0, s, m, g, z, gam, part,
-                           b.counts, fold);
+#define ZM_STEN_LAUNCH(C, P)                                                                      \
+    hipLaunchKernelGGL((k_cut_sten<C, P>), sgrid, dim3(kStThreads), 0, s, m, g, z, gam, part,     \
+                       b.counts, fold)
+    if (m.periodic) {
+        if (count) ZM_STEN_LAUNCH(true, true);
+        else ZM_STEN_LAUNCH(false, true);
+    } else {
+        if (count) ZM_STEN_LAUNCH(true, false);
+        else ZM_STEN_LAUNCH(false, false);
+    }
+#undef ZM_STEN_LAUNCH
     return hipGetLastError();
 }
 
 hipError_t launch_cut_count_reset(unsigned long long* counts, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, s, counts, 2);
+    hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, s, counts, kCutCountWords);
     return hipGetLastError();
 }
 

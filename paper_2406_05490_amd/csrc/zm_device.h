@@ -178,14 +178,19 @@ __device__ __forceinline__ void tangents_at(const Mesh& m, int p, const double* 
 //          sigma_max(J3)^2 (float bits) and det J2 signs, kept after the
 //          gathered values are cleared (the cutoff solver's index windows read
 //          fold[5] and fold[7])
-// fold[8]: max of bits(max sigma_max(J2)^2)
-// fold[9]: this evaluation's max sigma_max(J2)^2 (float bits), kept for the
-//          cutoff solver's image-shift rule
+// fold[8]: max of bits(max hdev), where hdev is sigma_max(J2)^2 on a periodic
+//          sheet and ||J2 - I||_2^2 on a free one
+// fold[9]: this evaluation's max hdev (float bits), kept for the cutoff
+//          solver: its image-shift rule (periodic) or its index-window bound
+//          (free sheet: on the convex index rectangle, ||J2 - I|| <= d at
+//          every point gives |x(a) - x(b)| >= (1 - d) |a - b| for the
+//          horizontal map, by integrating J2 along the straight segment)
 // (kFoldWords = 10 ints in all, zm_internal.h)
 constexpr float kFoldMaxStretch2 = 16.f;   // (sigma_max / sigma_min)^2 allowed
 
 struct FoldStat {
-    float smin2, smax2, hmax2;   // sigma_min(J2)^2, sigma_max(J3)^2, sigma_max(J2)^2
+    float smin2, smax2;   // sigma_min(J2)^2, sigma_max(J3)^2
+    float hmax2;          // periodic: sigma_max(J2)^2; free: ||J2 - I||_2^2
     int folded;
 };
 
@@ -259,7 +264,8 @@ __device__ __forceinline__ FoldStat fold_merge(FoldStat a, FoldStat b)
 
 // Tangent-map statistics of one point (identity values for p >= N).
 // folded: bit 0 det J2 > 0, bit 1 det J2 < 0, bit 2 neither (0 or NaN).
-__device__ __forceinline__ FoldStat fold_stat(const double T1[3], const double T2[3], double det2)
+__device__ __forceinline__ FoldStat fold_stat(const double T1[3], const double T2[3], double det2,
+                                              bool periodic)
 {
     const float x1 = (float)T1[0], y1 = (float)T1[1], z1 = (float)T1[2];
     const float x2 = (float)T2[0], y2 = (float)T2[1], z2 = (float)T2[2];
@@ -271,7 +277,15 @@ __device__ __forceinline__ FoldStat fold_stat(const double T1[3], const double T
     FoldStat st;
     st.smin2 = 0.5f * (s2 - __builtin_amdgcn_sqrtf(fmaxf(s2 * s2 - 4.f * det * det, 0.f)));
     st.smax2 = 0.5f * (s3 + __builtin_amdgcn_sqrtf(fmaxf(s3 * s3 - 4.f * nn, 0.f)));
-    st.hmax2 = 0.5f * (s2 + __builtin_amdgcn_sqrtf(fmaxf(s2 * s2 - 4.f * det * det, 0.f)));
+    if (periodic) {
+        st.hmax2 = 0.5f * (s2 + __builtin_amdgcn_sqrtf(fmaxf(s2 * s2 - 4.f * det * det, 0.f)));
+    } else {
+        // J2 - I = [[x1 - 1, x2], [y1, y2 - 1]]: its largest singular value squared
+        const float a11 = x1 - 1.f, a22 = y2 - 1.f;
+        const float f = a11 * a11 + x2 * x2 + y1 * y1 + a22 * a22;
+        const float da = a11 * a22 - x2 * y1;
+        st.hmax2 = 0.5f * (f + __builtin_amdgcn_sqrtf(fmaxf(f * f - 4.f * da * da, 0.f)));
+    }
     st.folded = det2 > 0.0 ? 1 : (det2 < 0.0 ? 2 : 4);
     return st;
 }
@@ -296,7 +310,7 @@ __device__ __forceinline__ FoldStat surface_point(const Mesh& m, int p, const do
     const double c2 = T1[2] * T2[0] - T1[0] * T2[2];
     const double c3 = T1[0] * T2[1] - T1[1] * T2[0];
     q[p] = (g1 * g1 + g2 * g2 + g3 * g3) / (c1 * c1 + c2 * c2 + c3 * c3);
-    return fold_stat(T1, T2, c3);
+    return fold_stat(T1, T2, c3, periodic_of<PER>(m));
 }
 
 // ---------------------------------------------------------------------------

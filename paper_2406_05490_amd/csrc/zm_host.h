@@ -38,7 +38,7 @@ struct Layout {
     size_t cut_start, cut_end;         // nkeys int each
     size_t cut_bstart, cut_bend;       // target blocks, int each
     size_t cut_src;                    // 8N doubles
-    size_t cut_counts;                 // 2 uint64
+    size_t cut_counts;                 // kCutCountWords uint64
     size_t cut_kflag;                  // nkeys int
     // low-order model only (size 0 otherwise)
     size_t lo_a, lo_b;                 // N double2 each
@@ -86,7 +86,7 @@ inline Layout make_layout(const zm_params& p, const zm::PairShape& sh)
     L.cut_bstart = take(cut ? (size_t)g.nb1 * g.nb2 * sizeof(int) : 0);
     L.cut_bend = take(cut ? (size_t)g.nb1 * g.nb2 * sizeof(int) : 0);
     L.cut_src = take(cut ? 8 * N * d : 0);
-    L.cut_counts = take(cut ? 2 * sizeof(unsigned long long) : 0);
+    L.cut_counts = take(cut ? kCutCountWords * sizeof(unsigned long long) : 0);
     L.cut_kflag = take(cut ? (size_t)g.nkeys * sizeof(int) : 0);
     const bool low = p.model == ZM_MODEL_LOW || p.model == ZM_MODEL_MEDIUM;   // FFT buffers
     const size_t c16 = 2 * sizeof(double);

@@ -11,6 +11,11 @@ namespace zm {
 // surface kernel, read by the pair kernels and the cutoff solver).
 constexpr int kFoldWords = 10;
 
+// Cutoff solver counters: pairs tested, pairs accepted, and the paths that
+// took the evaluations (bits, the same values as the public ZM_CUT_PATH_*).
+constexpr int kCutCountWords = 3;
+constexpr unsigned long long kCutPathCells = 1, kCutPathWindow = 2, kCutPathStencil = 4;
+
 // Mesh geometry and model constants, passed by value to every kernel.
 struct Mesh {
     int n1, n2;          // points per axis

@@ -233,16 +233,17 @@ def test_cutoff_below_the_spacing_is_exactly_zero(gpu):
     assert np.all(u == 0.0)
 
 
-@pytest.mark.parametrize("kind,n1,n2,rc", [
-    ("smooth", 64, 48, 0.3),      # index window, seam counts as image shifts
-    ("sheared", 40, 40, 0.4),     # strong horizontal shear: larger window, per-pair images
-    ("folded", 48, 64, 0.3),      # overturned rows: cell grid
+@pytest.mark.parametrize("kind,n1,n2,rc,path", [
+    ("smooth", 64, 48, 0.3, "WINDOW"),    # index window per patch: the seam rule's reach exceeds the period
+    ("sheared", 40, 40, 0.4, "WINDOW"),   # strong shear: larger window, per-pair images
+    ("folded", 48, 64, 0.3, "CELLS"),     # overturned rows: cell grid
 ])
-def test_cutoff_window_and_cell_paths_match_oracle(gpu, kind, n1, n2, rc):
+def test_cutoff_window_and_cell_paths_match_oracle(gpu, kind, n1, n2, rc, path):
     """A periodic sheet whose horizontal map stays one-to-one takes the
     index-window path (no binning), a folded one the cell grid; either way the
     velocity meets the FP64 bar and the accepted-pair count is the
-    definition's exactly."""
+    definition's exactly.  The context reports the path that ran."""
+    import paper_2406_05490_amd as zm
     A1, A2 = rr.grid(n1, n2)
     if kind == "folded":
         z = np.stack([A1, A2 + (1.5 / math.pi) * np.sin(math.pi * A2),
@@ -259,6 +260,7 @@ def test_cutoff_window_and_cell_paths_match_oracle(gpu, kind, n1, n2, rc):
     info = ctx.cutoff_info()
     assert info.pairs_accepted == accepted_pairs(z, rc), kind
     assert info.pairs_tested >= info.pairs_accepted
+    assert info.paths == getattr(zm, "ZM_CUT_PATH_" + path), (kind, info.paths)
 
 
 @pytest.mark.parametrize("n1,n2,rc,seed,bound", [
@@ -272,6 +274,7 @@ def test_cutoff_stencil_matches_oracle(gpu, n1, n2, rc, seed, bound):
     the window is only 10 x 6 spacings) times the pairs whose horizontal
     separation is below rc, well under the 8 x 8 patch window's count; the
     accepted count is the definition's and the velocity meets the FP64 bar."""
+    import paper_2406_05490_amd as zm
     p = params(n1, n2, rc)
     z, w = drifted_state(n1, n2, seed)
     u, ctx = gpu_br(p, z, w, gpu, count=True)
@@ -279,6 +282,7 @@ def test_cutoff_stencil_matches_oracle(gpu, n1, n2, rc, seed, bound):
     info = ctx.cutoff_info()
     assert info.pairs_accepted == accepted_pairs(z, rc)
     assert info.pairs_accepted <= info.pairs_tested <= bound * horizontal_pairs(z, rc)
+    assert info.paths == zm.ZM_CUT_PATH_STENCIL
 
 
 @pytest.mark.parametrize("n1,n2,rc", [(128, 96, 0.2), (64, 48, 0.3)])

@@ -158,6 +158,40 @@ def test_free_cutoff_accepted_pair_count_exact(gpu):
     info = ctx.cutoff_info()
     assert info.pairs_accepted == free_pairs_within(z, rc)
     assert info.pairs_tested >= info.pairs_accepted
+    assert info.paths == zm.ZM_CUT_PATH_STENCIL     # a shifted copy of the index grid
+
+
+@pytest.mark.parametrize("n1,n2,rc,s1,s2,shear,path", [
+    (48, 40, 0.3, 1.0, 1.0, 0.0, "STENCIL"),    # the index grid itself: ||J2 - I|| = 0
+    (45, 37, 0.25, 1.3, 0.85, 0.0, "STENCIL"),  # stretched, ||J2 - I|| = 0.3: window rc / 0.7
+    (24, 16, 0.5, 1.2, 1.0, 0.0, "STENCIL"),    # smaller than a stencil tile, window past the edges
+    (40, 32, 0.3, 1.7, 1.0, 0.0, "CELLS"),      # ||J2 - I|| = 0.7: the cell grid
+    (40, 40, 0.35, 1.0, 1.0, 0.3, "CELLS"),     # shear 0.3 pi cos: ||J2 - I|| up to 0.94
+])
+def test_free_cutoff_paths_match_oracle(gpu, n1, n2, rc, s1, s2, shear, path):
+    """A free sheet whose horizontal map stays within ||J2 - I|| < 1/2 of the
+    index grid takes the per-target stencil (off-mesh sources staged as far
+    points that no target accepts), any other the cell grid; either way the
+    velocity meets the FP64 bar and the accepted-pair count is the
+    definition's exactly."""
+    import math
+    import paper_2406_05490_amd as zm
+    import torch
+    p = cut_params(n1, n2, rc)
+    z, w = rr.random_state(n1, n2, seed=40 + n1, height=0.1)
+    z[0] = s1 * z[0] + shear * np.sin(math.pi * z[1])
+    z[1] = s2 * z[1]
+    ctx = zm.Context(p)
+    ctx.profile_enable(True)
+    ud = torch.empty(3 * p.n, dtype=torch.float64, device=gpu)
+    ctx.br_velocity(to_dev(z, gpu), to_dev(w, gpu), ud)
+    torch.cuda.synchronize()
+    u = to_host(ud, (3, p.n))
+    assert relerr(u, oracle.br_velocity(ocut(p), z, w)) < TOL64
+    info = ctx.cutoff_info()
+    assert info.pairs_accepted == free_pairs_within(z, rc)
+    assert info.pairs_tested >= info.pairs_accepted
+    assert info.paths == getattr(zm, "ZM_CUT_PATH_" + path), info.paths
 
 
 def test_free_cutoff_beyond_diameter_equals_exact(gpu):
