@@ -26,14 +26,17 @@
 // On a periodic sheet whose horizontal map alpha -> (x, y) is one-to-one
 // (the surface kernel's fold statistics: det J2 of one sign at every point)
 // the binning is skipped: every source a target can accept lies within
-// rc / sigma_min(J2) of it in the index torus.  Where that window fits the
-// period, k_cut_sten walks it per target: offsets shared by all lanes, each
-// lane's source read from a band of the mesh staged in LDS, so a target
-// tests about its own window (1.1 - 1.2 times the pairs it accepts on the
-// paper's workloads).  A larger window falls back to the patch window
-// (k_cut_prepare's records, k_cut_win: one 8 x 8 patch of targets per wave,
-// sources read with scalar loads).  The kernels of the paths not taken
-// leave at once; their launches are capped at a few thousand workgroups.
+// rc / sigma_min(J2) of it in the index torus.  On a free sheet the same
+// holds with 1 - max ||J2 - I|| in place of sigma_min while that deviation
+// from the index grid stays below 1/2.  Where the window fits (always on a
+// free sheet), k_cut_sten walks it per target: offsets shared by all lanes,
+// each lane's source read from a band of the mesh staged in LDS, so a
+// target tests about its own window (1.1 - 1.2 times the pairs it accepts
+// on the paper's workloads).  A larger periodic window falls back to the
+// patch window (k_cut_prepare's records, k_cut_win: one 8 x 8 patch of
+// targets per wave, sources read with scalar loads).  The kernels of the
+// paths not taken leave at once; their launches are capped at a few
+// thousand workgroups.
 //
 // The inclusion test is evaluated exactly as the definition writes it
 // (r_a = (z_i,a - z_j,a) - S_a L_a, then r1*r1 + r2*r2 + r3*r3 < rc*rc, no
