@@ -166,13 +166,14 @@ __device__ __forceinline__ void tangents_at(const Mesh& m, int p, const double* 
 // that ratio takes exact r for every pair instead (the same sums with more
 // operations per pair).  The surface kernel gathers min sigma_min(J2)^2,
 // max sigma_max(J3)^2, max sigma_max(J2)^2 and the signs det J2 takes over
-// the mesh; its last workgroup turns them into the flag the pair kernels read
-// and clears the gathered values for the next evaluation.
+// the mesh; a one-thread kernel after it (for a batch: the instance's last
+// workgroup) turns them into the flag the pair kernels read and clears the
+// gathered values for the next evaluation.
 //
 // fold[0]: max of (bits(+inf) - bits(min sigma_min^2)) (0 = nothing seen)
 // fold[1]: max of bits(max sigma_max^2)
 // fold[2]: signs of det J2 seen (bits as in fold_stat)
-// fold[3]: workgroups done
+// fold[3]: workgroups done (batched surface kernel only)
 // fold[4]: 1 = the far forms are off for this evaluation (read by the pair kernels)
 // fold[5], fold[6], fold[7]: this evaluation's min sigma_min(J2)^2 and max
 //          sigma_max(J3)^2 (float bits) and det J2 signs, kept after the
@@ -194,10 +195,12 @@ struct FoldStat {
     int folded;
 };
 
-// Called by every thread of a workgroup (256 threads); the workgroup's
-// points' statistics are combined into fold[], and the last workgroup of
-// the launch (of `groups` in all) writes the flag and clears the rest.
-__device__ __forceinline__ void fold_gather(FoldStat st, int* __restrict__ fold, int groups)
+// Called by every thread of a workgroup (256 threads): the workgroup's
+// points' statistics are combined and added to fold[0], [1], [2] and [8] with
+// atomics, each only where it would change the word (within an evaluation
+// the words only grow, so a value read here is a lower bound of the final
+// one).
+__device__ __forceinline__ void fold_accumulate(FoldStat st, int* __restrict__ fold)
 {
     __shared__ float smin_w[kThreads / 64], smax_w[kThreads / 64], hmax_w[kThreads / 64];
     __shared__ int fold_w[kThreads / 64];
@@ -227,18 +230,20 @@ __device__ __forceinline__ void fold_gather(FoldStat st, int* __restrict__ fold,
         f |= fold_w[k];
     }
     const int inf_bits = __float_as_int(__builtin_inff());
-    // every workgroup adds to the same words: an atomic only where it would
-    // change the word (within an evaluation the words only grow, so a value
-    // read here is a lower bound of the final one)
     auto peek = [&](int i) { return __hip_atomic_load(&fold[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); };
     const int v0 = inf_bits - __float_as_int(a), v1 = __float_as_int(b), v8 = __float_as_int(c);
     if (v0 > peek(0)) atomicMax(&fold[0], v0);   // a, b, c >= 0: bit order = value order
     if (v1 > peek(1)) atomicMax(&fold[1], v1);
     if (v8 > peek(8)) atomicMax(&fold[8], v8);
     if (f & ~peek(2)) atomicOr(&fold[2], f);
-    __threadfence();
-    if (atomicAdd(&fold[3], 1) != groups - 1) return;
-    // last workgroup: every other one has added its values (fenced above)
+}
+
+// One thread, once every workgroup has added its values: the flag the pair
+// kernels read, this evaluation's values, and the gathered words cleared for
+// the next evaluation.
+__device__ __forceinline__ void fold_finish(int* __restrict__ fold)
+{
+    const int inf_bits = __float_as_int(__builtin_inff());
     const float smin2 = __int_as_float(inf_bits - atomicAdd(&fold[0], 0));
     const float smax2 = __int_as_float(atomicAdd(&fold[1], 0));
     const float hmax2 = __int_as_float(atomicAdd(&fold[8], 0));
@@ -254,6 +259,20 @@ __device__ __forceinline__ void fold_gather(FoldStat st, int* __restrict__ fold,
     atomicExch(&fold[2], 0);
     atomicExch(&fold[3], 0);
     atomicExch(&fold[8], 0);
+}
+
+// fold_accumulate and fold_finish in one launch (the batched surface
+// kernel, whose instances each own a range of its workgroups): the last
+// workgroup of an instance (of `groups` in all), counted in fold[3] after a
+// fence, finishes it.
+__device__ __forceinline__ void fold_gather(FoldStat st, int* __restrict__ fold, int groups)
+{
+    fold_accumulate(st, fold);
+    if (threadIdx.x != 0) return;
+    __threadfence();
+    if (atomicAdd(&fold[3], 1) != groups - 1) return;
+    // last workgroup: every other one has added its values (fenced above)
+    fold_finish(fold);
 }
 
 __device__ __forceinline__ FoldStat fold_merge(FoldStat a, FoldStat b)

@@ -12,8 +12,11 @@ namespace {
 
 using dev::kThreads;
 
-// PER: 1 periodic sheet, 0 free sheet (the stencils without the other
-// boundary's branches).
+// One point per thread.  PER: 1 periodic sheet, 0 free sheet (the stencils
+// without the other boundary's branches).  Every workgroup adds its points'
+// tangent-map statistics to the fold words; k_fold_finish, the next launch
+// on the stream, turns them into this evaluation's flag (the kernel boundary
+// orders every workgroup's atomics before its reads).
 template <int PER>
 __global__ __launch_bounds__(kThreads) void k_surface(Mesh m, const double* __restrict__ z,
                                                       const double* __restrict__ w,
@@ -21,13 +24,14 @@ __global__ __launch_bounds__(kThreads) void k_surface(Mesh m, const double* __re
                                                       double* __restrict__ q,
                                                       int* __restrict__ fold)
 {
-    // a few hundred workgroups stride over the mesh, so that the tangent-map
-    // statistics meet in few atomics (every workgroup adds its values to the
-    // same words)
-    dev::FoldStat st{__builtin_inff(), 0.f, 0.f, 0};
-    for (int p = blockIdx.x * kThreads + threadIdx.x; p < m.N; p += gridDim.x * kThreads)
-        st = dev::fold_merge(st, dev::surface_point<PER>(m, p, z, w, gam, q));
-    if (fold) dev::fold_gather(st, fold, gridDim.x);
+    const int p = blockIdx.x * kThreads + threadIdx.x;
+    const dev::FoldStat st = dev::surface_point<PER>(m, p, z, w, gam, q);   // identity past N
+    if (fold) dev::fold_accumulate(st, fold);
+}
+
+__global__ void k_fold_finish(int* __restrict__ fold)
+{
+    if (threadIdx.x == 0) dev::fold_finish(fold);
 }
 
 // Workgroups are dealt round-robin to the 8 XCDs.  The pair kernels give
@@ -129,9 +133,6 @@ __global__ __launch_bounds__(kThreads) void k_tune_init(Mesh m, double* __restri
 
 inline unsigned blocks_for(int n) { return (unsigned)((n + kThreads - 1) / kThreads); }
 
-// Workgroups of the surface kernel at most (two per CU of a 256-CU device).
-constexpr unsigned kSurfaceGroups = 512;
-
 }  // namespace
 
 
@@ -202,11 +203,12 @@ hipError_t launch_tune_init(const Mesh& m, double* z, double* gam, hipStream_t s
 hipError_t launch_surface(const Mesh& m, const double* z, const double* w, double* gam, double* q,
                           int* fold, hipStream_t s)
 {
-    const int groups = std::min(blocks_for(m.N), kSurfaceGroups);
+    const int groups = blocks_for(m.N);
     if (m.periodic)
         hipLaunchKernelGGL(k_surface<1>, dim3(groups), dim3(kThreads), 0, s, m, z, w, gam, q, fold);
     else
         hipLaunchKernelGGL(k_surface<0>, dim3(groups), dim3(kThreads), 0, s, m, z, w, gam, q, fold);
+    if (fold) hipLaunchKernelGGL(k_fold_finish, dim3(1), dim3(64), 0, s, fold);
     return hipGetLastError();
 }
 
