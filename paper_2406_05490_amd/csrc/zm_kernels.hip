@@ -18,7 +18,7 @@ using dev::kThreads;
 // on the stream, turns them into this evaluation's flag (the kernel boundary
 // orders every workgroup's atomics before its reads).
 template <int PER>
-__global__ __launch_bounds__(kThreads) void k_surface(Mesh m, const double* __restrict__ z,
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 4))) void k_surface(Mesh m, const double* __restrict__ z,
                                                       const double* __restrict__ w,
                                                       double* __restrict__ gam,
                                                       double* __restrict__ q,
