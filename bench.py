@@ -25,7 +25,9 @@ import argparse
 import json
 import math
 import os
+import statistics
 import sys
+import threading
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
@@ -214,6 +216,48 @@ def params_of(zm, wl, precision=None, flags=0):
                      precision=prec, flags=flags)
 
 
+class ClockSampler:
+    """Mean GPU core clock (MHz) over a timed region: a background thread
+    reads torch.cuda.clock_rate (amd-smi's current GFX clock) every `period`
+    seconds and prints nothing; mean() is None when the query is not
+    available.  The first query, which loads amd-smi, runs before the region."""
+
+    def __init__(self, torch, period: float = 0.05):
+        self.torch, self.period, self.samples, self.ok = torch, period, [], True
+        self._stop = threading.Event()
+        self._thread = None
+
+    def _run(self):
+        while not self._stop.is_set():
+            try:
+                v = self.torch.cuda.clock_rate(0)
+            except Exception:
+                self.ok = False
+                return
+            if v:
+                self.samples.append(float(v))
+            self._stop.wait(self.period)
+
+    def __enter__(self):
+        try:
+            self.torch.cuda.clock_rate(0)
+        except Exception:
+            self.ok = False
+            return self
+        self._thread = threading.Thread(target=self._run, daemon=True)
+        self._thread.start()
+        return self
+
+    def __exit__(self, *exc):
+        self._stop.set()
+        if self._thread is not None:
+            self._thread.join()
+        return False
+
+    def mean(self):
+        return round(statistics.mean(self.samples)) if self.ok and self.samples else None
+
+
 def trajectory_run(zm, torch, wl, steps: int, warmup: int):
     """The workload's RK3 steps from its initial state: warmup steps, then
     `steps` timed steps with per-kernel HIP events on the context stream."""
@@ -232,12 +276,13 @@ def trajectory_run(zm, torch, wl, steps: int, warmup: int):
     torch.cuda.synchronize()
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
-    t0 = time.perf_counter()
-    ev0.record(stream)
-    ctx.step(steps)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
+    with ClockSampler(torch) as clock:
+        t0 = time.perf_counter()
+        ev0.record(stream)
+        ctx.step(steps)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
     gpu_s = ev0.elapsed_time(ev1) / 1e3
     stats = ctx.profile_read()
     ctx.profile_enable(False)
@@ -246,7 +291,7 @@ def trajectory_run(zm, torch, wl, steps: int, warmup: int):
     launches, pair_ms = stats["pairs"]
     return {"info": info, "elapsed": elapsed, "steps": steps, "stats": stats,
             "pair_launches": launches, "avg_pair_s": pair_ms / 1e3 / max(launches, 1),
-            "pairs_per_step": 3 * info.pairs_per_eval}
+            "pairs_per_step": 3 * info.pairs_per_eval, "clock_mhz": clock.mean()}
 
 
 def br_sweep(zm, torch, wl, reps: int = 2):
@@ -998,7 +1043,7 @@ def main():
             "unit": "TFLOP/s", "frac": achieved / peak,
             "traffic": measured_traffic(kernel, wl.name),
             "flops_per_pair": FLOPS_PER_PAIR, "avg_launch_ms": r["avg_pair_s"] * 1e3,
-            "launches": r["pair_launches"]}
+            "launches": r["pair_launches"], "clock_mhz": r["clock_mhz"]}
     xf = executed_flops_per_pair(kernel, wl.name)
     if xf is not None:
         roof["executed_flops_per_pair"] = xf
