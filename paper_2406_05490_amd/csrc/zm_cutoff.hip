@@ -66,8 +66,9 @@ __host__ __device__ inline int cell_key(const CutGrid& g, int cx, int cy)
     return ((by * g.nb1 + bx) * g.B + ly) * g.B + lx;
 }
 
-// Largest ||J2 - I||_2 of a free sheet that takes the index window (its
-// window radius is rc / (1 - d), at most twice the radius at d = 0).
+// Bound on max ||J2 - I||_2^2 (fold[9]) below which a free sheet takes the
+// index window: d = ||J2 - I|| < 1/2, so its window radius rc / (1 - d) is
+// at most twice the radius at d = 0.
 constexpr float kFreeMaxDev2 = 0.25f;
 
 // Whether this evaluation takes the index-window path: a sheet whose tangent
