@@ -582,7 +582,7 @@ __device__ __forceinline__ void pairs_f32_block(const Mesh& m, const PairShape& 
     const float L1f = (float)m.L1;
     const float eps2f = (float)m.eps2;
     // the sheet's tangent map keeps index distance a bound on distance (see
-    // fold_gather): the far forms may be used this evaluation
+    // the fold statistics above): the far forms may be used this evaluation
     const bool far_ok = fold == nullptr || fold[4] == 0;
 
     // ---- staging: source j relative to the centre, centre's image --------
@@ -937,7 +937,7 @@ __device__ __forceinline__ void pairs_f64f_block(const Mesh& m, const PairShape&
     const int side = 2 * m.K + 1;
     const int total = ntiles * side * side;
     // the sheet's tangent map keeps index distance a bound on distance (see
-    // fold_gather): the expanded far forms may be used this evaluation
+    // the fold statistics above): the expanded far forms may be used this evaluation
     const bool far_ok = fold == nullptr || fold[4] == 0;
 
     double2 st[5];

@@ -59,9 +59,11 @@ bool lookup_tuning(int n1, int n2, int precision, int* R, int* splits);
 
 // Synthetic positions (3 planes) and source strengths (3 planes) for tuning.
 hipError_t launch_tune_init(const Mesh& m, double* z, double* gam, hipStream_t s);
-// fold (5 ints, zero before the first use; may be NULL): the sheet's
-// tangent-map statistics, turned by the launch's last workgroup into the
-// flag fold[4] the pair kernels read (1: use exact r for every pair).
+// fold (kFoldWords ints, zero before the first use; may be NULL): the
+// sheet's tangent-map statistics, gathered by the surface kernel and turned
+// by a one-thread kernel launched after it into the flag fold[4] the pair
+// kernels read (1: use exact r for every pair) and the values the cutoff
+// solver reads.  Two launches.
 hipError_t launch_surface(const Mesh& m, const double* z, const double* w,
                           double* gam, double* q, int* fold, hipStream_t s);
 
