@@ -299,3 +299,24 @@ def test_cutoff_counted_and_repeated_evaluations_agree_bitwise(gpu, n1, n2, rc):
     assert np.array_equal(plain, counted)
     assert np.array_equal(plain, again)
     assert ctx.cutoff_info().pairs_accepted == accepted_pairs(z, rc)
+
+
+@pytest.mark.parametrize("bump", [False, True])
+def test_cutoff_boundary_is_strict_on_the_gpu(gpu, bump):
+    """rc exactly two spacings on a flat 64 x 64 sheet (h a power of two, so
+    the pairs exactly 2h apart have |r|^2 == rc^2 in binary): the index
+    window keeps them out, as the definition's strict inequality does (9
+    accepted sources per target), and takes them in one ulp above (13)."""
+    import paper_2406_05490_amd as zm
+    n = 64
+    rc = 2.0 * (2.0 / n)
+    if bump:
+        rc = float(np.nextafter(rc, np.inf))
+    p = params(n, n, rc)
+    z, _ = rr.flat_state(n, n)
+    w = rr.synthetic_vorticity(n, n, seed=33)
+    u, ctx = gpu_br(p, z, w, gpu, count=True)
+    assert relerr(u, oracle.br_velocity(oparams(p), z, w)) < TOL64
+    info = ctx.cutoff_info()
+    assert info.pairs_accepted == (13 if bump else 9) * n * n
+    assert info.paths == zm.ZM_CUT_PATH_STENCIL

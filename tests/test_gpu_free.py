@@ -255,3 +255,29 @@ def test_free_cutoff_256_sampled(gpu):
     idx = np.unique(np.concatenate([idx, [0, n - 1, n * (n - 1), n * n - 1]]))
     ref = oracle.br_velocity(ocut(p), z, w, targets=idx)
     assert relerr(u[:, idx], ref) < TOL64
+
+
+@pytest.mark.parametrize("bump", [False, True])
+def test_free_cutoff_boundary_is_strict(gpu, bump):
+    """The same boundary on a free flat sheet (64 x 32: h1 = 1/32, h2 = 1/16,
+    so the pairs 2 h1 apart along axis 1 and h2 apart along axis 2 have
+    |r|^2 == rc^2 in binary): the accepted count is the brute-force count with
+    the strict inequality, and one ulp above it takes those pairs in."""
+    import paper_2406_05490_amd as zm
+    import torch
+    n1, n2 = 64, 32
+    rc = 2.0 * (2.0 / n1)
+    if bump:
+        rc = float(np.nextafter(rc, np.inf))
+    p = cut_params(n1, n2, rc)
+    z, _ = rr.flat_state(n1, n2)
+    w = rr.synthetic_vorticity(n1, n2, seed=34)
+    ctx = zm.Context(p)
+    ctx.profile_enable(True)
+    ud = torch.empty(3 * p.n, dtype=torch.float64, device=gpu)
+    ctx.br_velocity(to_dev(z, gpu), to_dev(w, gpu), ud)
+    torch.cuda.synchronize()
+    assert relerr(to_host(ud, (3, p.n)), oracle.br_velocity(ocut(p), z, w)) < TOL64
+    info = ctx.cutoff_info()
+    assert info.pairs_accepted == free_pairs_within(z, rc)
+    assert info.paths == zm.ZM_CUT_PATH_STENCIL

@@ -160,3 +160,30 @@ def test_cutoff_below_the_spacing_leaves_only_the_self_pair():
     z, w = rr.random_state(n, n, seed=21, height=0.05)
     P = oracle.Problem(n, n, eps=1.0 / n, cutoff=0.01)
     assert np.all(oracle.br_velocity(P, z, w) == 0.0)
+
+
+@pytest.mark.parametrize("bump", [False, True])
+def test_cutoff_boundary_is_strict(bump):
+    """rc exactly two spacings on a flat mesh with h a power of two: the pairs
+    exactly 2h apart have |r|^2 == rc^2 in binary and stay out (the strict
+    inequality of the definition); one ulp more takes them in.  The closed
+    form over the lattice disc tells the two apart (9 and 13 points)."""
+    n = 32
+    h = 2.0 / n
+    rc = 2.0 * h
+    if bump:
+        rc = float(np.nextafter(rc, np.inf))
+    eps = 1.0 / n
+    k1, k2 = math.pi, 2 * math.pi
+    P = prob(n, n, eps=eps, cutoff=rc)
+    z, _ = rr.flat_state(n, n)
+    w, mu = mode_w(n, n, k1, k2)
+    u = oracle.br_velocity(P, z, w)
+    m = np.arange(-n, n + 1)
+    R1, R2 = np.meshgrid(m * h, m * h, indexing="xy")
+    rr2 = R1 * R1 + R2 * R2
+    inside = rr2 < rc * rc
+    assert np.count_nonzero(inside) == (13 if bump else 9)
+    kr = k1 * R1 + k2 * R2
+    lam = -(h * h) / (4 * math.pi) * float(np.sum((kr * np.sin(kr) * (rr2 + eps * eps) ** -1.5)[inside]))
+    assert np.max(np.abs(u[2] - lam * mu)) < 1e-12 * abs(lam)
