@@ -51,6 +51,7 @@ MUTANTS = {
                            "const double inv = 1.0 / sqrt(dd + 0.25 * eps_sq);"),
     "cutoff_radius_not_squared": ("const double rc2 = P->cutoff * P->cutoff;",
                                   "const double rc2 = P->cutoff;"),
+    "cutoff_boundary_inclusive": ("if (!(dd < rc2)) continue;", "if (!(dd <= rc2)) continue;"),
     "low_half_dropped": ("const double f = 0.5 * (c1 * w[pj] + c2 * w[N + pj]);",
                          "const double f = (c1 * w[pj] + c2 * w[N + pj]);"),
     "low_symbol_sign": ("c1 = nyq1 ? 0.0 : k1 / kk;", "c1 = nyq1 ? 0.0 : -k1 / kk;"),
